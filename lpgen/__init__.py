@@ -1,0 +1,311 @@
+"""Seeded synthetic standard-form LPs with a planted optimum.
+
+This module only builds inputs.  It holds none of the solver's arithmetic and
+is imported by the tests and the benchmark on behalf of both the CPU oracle and
+the GPU library, which never import each other.
+
+Every instance is ``min c^T x  s.t.  A x = b, x >= 0`` (paper, Section 2).  A
+planted primal-dual pair ``(x*, y*, z*)`` makes the optimum known in closed
+form: ``b = A x*`` and ``c = A^T y* + z*`` with ``x* >= 0``, ``z* >= 0`` and
+``x*_j z*_j = 0``, so ``p* = c^T x* = b^T y*`` (complementarity, Section 2).
+
+Draw order per instance (one PCG64 stream per seed key):
+  1. column nonzero counts, 2. distinct rows per column, 3. values,
+  4. a permutation whose first floor(n/2) entries form supp(x*),
+  5. x*_S ~ U(0,1), 6. y* ~ N(0,1), 7. z* ~ U(0,1) off the support,
+  8. b = A x*, c = A^T y* + z* in float64.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "LP", "rng_for", "planted_from_columns", "uniform_columns", "cfg1", "cfg2",
+    "cfg2_sub", "cfg3", "cfg4_sizes", "cfg4_instance", "cfg4_batch",
+    "cfg5_instance", "cfg5_batch", "cfg5_fd_instance", "tiny", "simplex_lp",
+    "powerlaw_counts", "Batch", "stack_batch",
+]
+
+POWER_ALPHA = 2.1423  # p(k) ~ k^-alpha on [2, 2000] has mean 8.0
+
+
+@dataclass
+class LP:
+    """One standard-form LP in CSR (A) plus a CSR copy of A^T, all float64."""
+    A: sp.csr_matrix
+    AT: sp.csr_matrix
+    b: np.ndarray
+    c: np.ndarray
+    x_star: np.ndarray
+    y_star: np.ndarray
+    z_star: np.ndarray
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.A.nnz)
+
+    @property
+    def p_star(self) -> float:
+        return float(self.c @ self.x_star)
+
+
+def rng_for(*key: int) -> np.random.Generator:
+    """PCG64 stream keyed by a tuple of non-negative integers."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(key))))
+
+
+def _distinct_rows(counts: np.ndarray, m: int, rng: np.random.Generator) -> np.ndarray:
+    """For column j draw counts[j] distinct row indices uniformly from [0, m).
+
+    Returns the row indices in column-major order (column 0's rows first), each
+    column's rows sorted ascending.  Duplicates inside a column are redrawn
+    until none remain; the redraw order is fixed, so the result is a function
+    of the generator state only.
+    """
+    counts = np.asarray(counts, dtype=np.int64)
+    if np.any(counts > m):
+        raise ValueError("a column asks for more distinct rows than m")
+    n = counts.size
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=colptr[1:])
+    nnz = int(colptr[-1])
+    colid = np.repeat(np.arange(n, dtype=np.int64), counts)
+    rows = rng.integers(0, m, size=nnz, dtype=np.int64)
+    while True:
+        order = np.lexsort((rows, colid))
+        rows = rows[order]  # colid is already non-decreasing and stays so
+        dup = np.zeros(nnz, dtype=bool)
+        if nnz > 1:
+            dup[1:] = (rows[1:] == rows[:-1]) & (colid[1:] == colid[:-1])
+        nd = int(dup.sum())
+        if nd == 0:
+            return rows
+        rows[dup] = rng.integers(0, m, size=nd, dtype=np.int64)
+
+
+def _csr_pair_from_columns(m: int, n: int, counts: np.ndarray, rows: np.ndarray,
+                           vals: np.ndarray) -> tuple[sp.csr_matrix, sp.csr_matrix]:
+    """Column-major triplets -> (A in CSR, A^T in CSR), int32 indices, sorted."""
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=colptr[1:])
+    AT = sp.csr_matrix((vals.astype(np.float64), rows.astype(np.int32),
+                        colptr.astype(np.int32)), shape=(n, m))
+    AT.has_sorted_indices = True
+    A = AT.T.tocsr()
+    A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    return A, AT
+
+
+def planted_from_columns(m: int, counts: np.ndarray, rows: np.ndarray,
+                         vals: np.ndarray, rng: np.random.Generator,
+                         name: str = "", meta: dict | None = None) -> LP:
+    """Steps 4-8 of the draw order on a given sparsity pattern and values."""
+    n = counts.size
+    A, AT = _csr_pair_from_columns(m, n, counts, rows, vals)
+    perm = rng.permutation(n)
+    supp = perm[: n // 2]
+    x_star = np.zeros(n)
+    x_star[supp] = rng.uniform(0.0, 1.0, size=supp.size)
+    y_star = rng.standard_normal(m)
+    z_star = np.zeros(n)
+    off = perm[n // 2:]
+    z_star[off] = rng.uniform(0.0, 1.0, size=off.size)
+    b = A @ x_star
+    c = AT @ y_star + z_star
+    return LP(A, AT, b, c, x_star, y_star, z_star, name=name, meta=dict(meta or {}))
+
+
+def uniform_columns(m: int, n: int, per_col: int, rng: np.random.Generator,
+                    name: str = "", meta: dict | None = None) -> LP:
+    """per_col distinct uniform rows in every column, values N(0,1)."""
+    counts = np.full(n, per_col, dtype=np.int64)
+    rows = _distinct_rows(counts, m, rng)
+    vals = rng.standard_normal(rows.size)
+    return planted_from_columns(m, counts, rows, vals, rng, name=name, meta=meta)
+
+
+def cfg1(seed: int = 0) -> LP:
+    """m=200, n=500, 5 nonzeros per column at uniform-random rows, N(0,1)."""
+    return uniform_columns(200, 500, 5, rng_for(1, seed), name=f"cfg1_s{seed}",
+                           meta={"cfg": 1, "seed": seed})
+
+
+def powerlaw_counts(n: int, rng: np.random.Generator, kmin: int = 2, kmax: int = 2000,
+                    alpha: float = POWER_ALPHA) -> np.ndarray:
+    """Discrete truncated power law p(k) ~ k^-alpha on [kmin, kmax]."""
+    k = np.arange(kmin, kmax + 1)
+    p = k.astype(np.float64) ** (-alpha)
+    cdf = np.cumsum(p)
+    cdf /= cdf[-1]
+    u = rng.uniform(0.0, 1.0, size=n)
+    idx = np.minimum(np.searchsorted(cdf, u, side="right"), k.size - 1)
+    return k[idx].astype(np.int64)
+
+
+def _cfg2_like(m: int, n: int, rng: np.random.Generator, kmax: int, name: str,
+               meta: dict) -> LP:
+    counts = powerlaw_counts(n, rng, kmax=min(kmax, m))
+    rows = _distinct_rows(counts, m, rng)
+    vals = rng.standard_normal(rows.size)
+    row_factor = rng.uniform(0.1, 10.0, size=m)
+    vals = vals * row_factor[rows]
+    return planted_from_columns(m, counts, rows, vals, rng, name=name, meta=meta)
+
+
+def cfg2(seed: int = 0) -> LP:
+    """m=100,000, n=400,000, power-law column counts (min 2, mean 8, max 2000),
+    values N(0,1) times a per-row factor U(0.1, 10)."""
+    return _cfg2_like(100_000, 400_000, rng_for(2, seed), 2000, f"cfg2_s{seed}",
+                      {"cfg": 2, "seed": seed})
+
+
+def cfg2_sub(seed: int = 0, scale: int = 100) -> LP:
+    """The cfg2 recipe at 1/scale of its size (column counts capped at m)."""
+    m, n = 100_000 // scale, 400_000 // scale
+    return _cfg2_like(m, n, rng_for(2, 1000 + scale, seed), 2000,
+                      f"cfg2sub{scale}_s{seed}", {"cfg": 2, "seed": seed, "scale": scale})
+
+
+def cfg3(seed: int = 0, nblocks: int = 64, bm: int = 30_000, bn: int = 120_000,
+         per_col: int = 6, nlink: int = 2_000, link_nnz: int = 1_200) -> LP:
+    """Block-angular LP: nblocks diagonal blocks bm x bn (per_col nnz per column
+    inside its block), plus nlink linking rows with link_nnz distinct columns
+    each drawn over all n columns.  Values N(0,1).  The defaults give
+    m = 1,922,000, n = 7,680,000 and about 48.5M nonzeros."""
+    rng = rng_for(3, seed, nblocks, bm)
+    m = nblocks * bm + nlink
+    n = nblocks * bn
+    # block part: column j of block k has per_col distinct rows in [k*bm, (k+1)*bm)
+    parts = [_distinct_rows(np.full(bn, per_col, dtype=np.int64), bm, rng) + k * bm
+             for k in range(nblocks)]
+    block_rows = np.concatenate(parts)
+    del parts
+    # link rows: each picks link_nnz distinct columns among all n
+    lcols = _distinct_rows(np.full(nlink, link_nnz, dtype=np.int64), n, rng)
+    lrow_ids = np.repeat(np.arange(nlink, dtype=np.int64), link_nnz) + nblocks * bm
+    # merge into column-major order
+    all_cols = np.concatenate([np.repeat(np.arange(n, dtype=np.int64), per_col), lcols])
+    all_rows = np.concatenate([block_rows, lrow_ids])
+    order = np.lexsort((all_rows, all_cols))
+    all_cols = all_cols[order]
+    all_rows = all_rows[order]
+    counts = np.bincount(all_cols, minlength=n).astype(np.int64)
+    vals = rng.standard_normal(all_rows.size)
+    return planted_from_columns(m, counts, all_rows, vals, rng, name=f"cfg3_s{seed}",
+                                meta={"cfg": 3, "seed": seed, "nblocks": nblocks,
+                                      "bm": bm, "bn": bn, "nlink": nlink,
+                                      "link_nnz": link_nnz})
+
+
+def cfg4_sizes(count: int = 4096, seed: int = 0) -> np.ndarray:
+    """m_i = round(exp(U(ln 20, ln 2000))) for each instance (log-uniform)."""
+    rng = rng_for(4, seed, 999_999)
+    return np.rint(np.exp(rng.uniform(math.log(20), math.log(2000), size=count))).astype(np.int64)
+
+
+def cfg4_instance(i: int, m: int, seed: int = 0) -> LP:
+    """Instance i of the batched workload: n = round(2.5 m), 4 nnz per column."""
+    n = int(round(2.5 * m))
+    return uniform_columns(int(m), n, 4, rng_for(4, seed, i), name=f"cfg4_{i}",
+                           meta={"cfg": 4, "seed": seed, "inst": i})
+
+
+def cfg4_batch(count: int = 4096, seed: int = 0) -> list[LP]:
+    sizes = cfg4_sizes(count, seed)
+    return [cfg4_instance(i, int(m), seed) for i, m in enumerate(sizes)]
+
+
+def cfg5_instance(i: int, seed: int = 0, m: int = 500, n: int = 1500) -> tuple[LP, np.ndarray]:
+    """Differentiation workload instance and its loss weights w ~ N(0,1)^n."""
+    rng = rng_for(5, seed, i)
+    lp = uniform_columns(m, n, 5, rng, name=f"cfg5_{seed}_{i}",
+                         meta={"cfg": 5, "seed": seed, "inst": i})
+    w = rng.standard_normal(n)
+    return lp, w
+
+
+def cfg5_batch(count: int = 256, seed: int = 0) -> tuple[list[LP], list[np.ndarray]]:
+    lps, ws = [], []
+    for i in range(count):
+        lp, w = cfg5_instance(i, seed)
+        lps.append(lp)
+        ws.append(w)
+    return lps, ws
+
+
+def cfg5_fd_instance(i: int) -> tuple[LP, np.ndarray]:
+    """The small finite-difference set: m=20, n=50, 5 nnz per column."""
+    return cfg5_instance(i, seed=1, m=20, n=50)
+
+
+def tiny(m: int, n: int, per_col: int, seed: int) -> LP:
+    """Small planted LPs for brute-force checks."""
+    return uniform_columns(m, n, min(per_col, m), rng_for(9, m, n, per_col, seed),
+                           name=f"tiny_{m}x{n}_s{seed}")
+
+
+def simplex_lp(c: np.ndarray) -> LP:
+    """m = 1: sum(x) = 1, x >= 0.  The optimum is min_j c_j (textbook)."""
+    n = c.size
+    counts = np.ones(n, dtype=np.int64)
+    rows = np.zeros(n, dtype=np.int64)
+    vals = np.ones(n)
+    A, AT = _csr_pair_from_columns(1, n, counts, rows, vals)
+    j = int(np.argmin(c))
+    x = np.zeros(n)
+    x[j] = 1.0
+    y = np.array([c[j]])
+    z = c - c[j]
+    return LP(A, AT, np.array([1.0]), c.astype(np.float64), x, y, z, name="simplex")
+
+
+@dataclass
+class Batch:
+    """Block-diagonal stacking of independent LPs (global column indices)."""
+    A: sp.csr_matrix
+    AT: sp.csr_matrix
+    b: np.ndarray
+    c: np.ndarray
+    row_off: np.ndarray  # int32 [B+1]
+    col_off: np.ndarray  # int32 [B+1]
+    nnz_off: np.ndarray  # int64 [B+1]
+    lps: list
+
+    @property
+    def B(self) -> int:
+        return len(self.lps)
+
+
+def stack_batch(lps: list[LP]) -> Batch:
+    A = sp.block_diag([lp.A for lp in lps], format="csr")
+    A.sort_indices()
+    AT = sp.block_diag([lp.AT for lp in lps], format="csr")
+    AT.sort_indices()
+    for M in (A, AT):
+        M.indices = M.indices.astype(np.int32)
+        M.indptr = M.indptr.astype(np.int32)
+    row_off = np.zeros(len(lps) + 1, dtype=np.int32)
+    col_off = np.zeros(len(lps) + 1, dtype=np.int32)
+    nnz_off = np.zeros(len(lps) + 1, dtype=np.int64)
+    row_off[1:] = np.cumsum([lp.m for lp in lps])
+    col_off[1:] = np.cumsum([lp.n for lp in lps])
+    nnz_off[1:] = np.cumsum([lp.nnz for lp in lps])
+    b = np.concatenate([lp.b for lp in lps])
+    c = np.concatenate([lp.c for lp in lps])
+    return Batch(A, AT, b, c, row_off, col_off, nnz_off, list(lps))
