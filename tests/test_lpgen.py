@@ -59,6 +59,6 @@ def test_cfg4_sizes_and_instance():
 def test_stack_batch():
     lps = [lpgen.cfg4_instance(i, m) for i, m in enumerate([20, 33, 41])]
     bt = lpgen.stack_batch(lps)
-    assert bt.A.shape == (94, 235) and list(bt.row_off) == [0, 20, 53, 94]
+    assert bt.A.shape == (94, sum(lp.n for lp in lps)) and list(bt.row_off) == [0, 20, 53, 94]
     x = np.concatenate([lp.x_star for lp in lps])
     assert np.abs(bt.A @ x - bt.b).max() < 1e-12
