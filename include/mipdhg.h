@@ -1,0 +1,175 @@
+/*
+ * mipdhg: restarted PDHG for standard-form linear programs on one MI355X.
+ *
+ * Problem (paper, Section 2):  min c^T x  s.t.  A x = b, x >= 0, with A of
+ * size m x n; its dual is max b^T y s.t. A^T y + z = c, z >= 0.  The solver
+ * returns (x, y, z), the residuals r_P = b - A x and r_D = c - A^T y - z, and
+ * stops when the three relative tests of Section 2 hold:
+ *     ||r_P||_2 <= eps (1 + ||b||_2),  ||r_D||_2 <= eps (1 + ||c||_2),
+ *     |c^T x - b^T y| <= eps (1 + |c^T x| + |b^T y|).
+ * The tests and every reported figure are computed in float64 on the original
+ * (unscaled) model, as Sections 2.1 and 4.3 ask, whatever the precision of the
+ * iterations.  z is max(c - A^T y, 0), the z >= 0 that minimises ||r_D||.
+ *
+ * The PDHG itself (Section 4.1 only says it follows cuPDLP+) is: diagonal
+ * scaling (Ruiz infinity-norm passes plus one Pock-Chambolle pass), a constant
+ * step from a power-iteration estimate of ||A||_2, a primal weight re-balanced
+ * at restarts, reflected Halpern iterations, and fixed-point-residual restarts.
+ *
+ * Conventions for every entry point
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch tensors on
+ *    the current HIP device) owned by the caller; the library neither frees nor
+ *    retains them.  Structs (mipdhg_lp, mipdhg_options, mipdhg_info) live in
+ *    host memory.  `stream` is a hipStream_t (NULL = the legacy default
+ *    stream); all device work is enqueued on it.
+ *  - Calls are synchronous with respect to the host: they return when the
+ *    results are in the output buffers.
+ *  - Inputs are float64 with int32 CSR indices (so nnz < 2^31).  A is CSR with
+ *    m rows; the caller also passes A^T as CSR with n rows (the same matrix,
+ *    transposed).  Column indices need not be sorted; duplicates are not
+ *    allowed.
+ *  - Return value >= 0 is a solver status (MIPDHG_OPTIMAL ... NUMERICAL); the
+ *    outputs then hold the last evaluated point and info is filled.  A
+ *    negative value is an error: no output is written, and
+ *    mipdhg_last_error() returns a message (thread-local).
+ *  - Re-entrant for distinct workspaces; two calls that share a workspace must
+ *    not overlap.
+ */
+#ifndef MIPDHG_H
+#define MIPDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* solver status (>= 0) */
+#define MIPDHG_OPTIMAL 0         /* the three tests hold at eps_rel            */
+#define MIPDHG_ITER_LIMIT 1      /* max_iter reached                           */
+#define MIPDHG_TIME_LIMIT 2      /* time_limit_s reached                       */
+#define MIPDHG_NUMERICAL 3       /* a NaN/Inf appeared in an evaluation        */
+/* errors (< 0) */
+#define MIPDHG_ERR_INVALID_ARG -1   /* null pointer, bad size or option       */
+#define MIPDHG_ERR_BAD_CSR -2       /* row pointers or column indices invalid */
+#define MIPDHG_ERR_TRANSPOSE -3     /* A^T is not the transpose of A          */
+#define MIPDHG_ERR_HIP -4           /* a HIP runtime call failed              */
+#define MIPDHG_ERR_WORKSPACE -5     /* workspace smaller than required        */
+#define MIPDHG_ERR_UNSUPPORTED -6   /* option combination not supported       */
+#define MIPDHG_ERR_NONFINITE -7     /* NaN/Inf in A, b or c                   */
+
+/* iteration precision */
+#define MIPDHG_FP64 0        /* everything float64                              */
+#define MIPDHG_FP32 1        /* iterates, scaled A and SpMV accumulation float32 */
+#define MIPDHG_FP32_BF16A 2  /* as FP32, but scaled A values stored as bfloat16 */
+
+/* One LP in the standard form of Section 2.  Device pointers. */
+typedef struct mipdhg_lp {
+    int32_t m, n;            /* rows and columns of A                      */
+    int64_t nnz;             /* nonzeros of A (= of A^T)                   */
+    const int32_t *a_rowptr; /* [m+1], a_rowptr[0] = 0, a_rowptr[m] = nnz  */
+    const int32_t *a_col;    /* [nnz] column index of each entry, in [0,n) */
+    const double *a_val;     /* [nnz]                                      */
+    const int32_t *at_rowptr;/* [n+1] CSR of A^T                           */
+    const int32_t *at_col;   /* [nnz] in [0, m)                            */
+    const double *at_val;    /* [nnz]                                      */
+    const double *b;         /* [m] right-hand side                        */
+    const double *c;         /* [n] objective                              */
+} mipdhg_lp;
+
+/* Options.  Fill with mipdhg_default_options() and change what you need. */
+typedef struct mipdhg_options {
+    int32_t precision;      /* MIPDHG_FP64 / FP32 / FP32_BF16A            [0] */
+    int32_t ruiz_iters;     /* Ruiz infinity-norm passes                  [10] */
+    int32_t pock_chambolle; /* one Pock-Chambolle (alpha=1) pass after     [1] */
+    int32_t power_iters;    /* power iterations for ||A~||_2             [100] */
+    int32_t eval_every;     /* iterations between evaluations             [64] */
+    double step_safety;     /* eta = step_safety / sigma_hat            [0.95] */
+    double reflect_rho;     /* reflection in [0,1]                       [1.0] */
+    int32_t halpern;        /* Halpern anchoring on/off                    [1] */
+    int32_t restarts;       /* restarts on/off                             [1] */
+    double beta_suff;       /* restart if R <= beta_suff R0              [0.2] */
+    double beta_nec;        /* ... or R <= beta_nec R0 and R > R_prev    [0.8] */
+    double beta_art;        /* ... or epoch length >= beta_art t        [0.36] */
+    double pw_theta;        /* primal-weight smoothing                   [0.5] */
+    int64_t max_iter;       /* iteration limit                       [1000000] */
+    double time_limit_s;    /* wall-clock limit, seconds (paper: 1e4)    [1e4] */
+    int32_t validate;       /* check CSR, finiteness and A^T consistency   [1] */
+    int32_t use_graph;      /* replay hipGraphs of eval_every iterations   [1] */
+    int32_t spmv_kind;      /* iteration SpMVs: 0 = nnz-balanced LDS tiles,
+                               1 = lane groups per row (lanes_a/lanes_at)   [0] */
+    int32_t lanes_a;        /* lanes per row for A SpMVs (0 = planner)     [0] */
+    int32_t lanes_at;       /* lanes per row for A^T SpMVs (0 = planner)   [0] */
+    int32_t long_row;       /* rows longer than this use a whole wave (0 = planner) */
+    int32_t kernel_timing;  /* bracket every primal/dual kernel with hipEvents and report
+                               their mean durations in info (disables graphs)  [0] */
+    /* Debug trace of the scaled iterates after each of the first trace_iters
+     * iterations (device float64 arrays, row-major [trace_iters][n or m]):
+     * the state (x, y) after the update and the projected point (x_hat, y_hat).
+     * Any of the four may be NULL.  Tracing disables graphs. */
+    int32_t trace_iters;    /*                                             [0] */
+    double *trace_x, *trace_y, *trace_xhat, *trace_yhat;
+    /* Optional warm start in the original space (device float64, may be NULL). */
+    const double *x_init;   /* [n], must be >= 0 */
+    const double *y_init;   /* [m] */
+} mipdhg_options;
+
+/* Per-solve report (host struct). */
+typedef struct mipdhg_info {
+    int32_t status;
+    int32_t restarts;
+    int64_t iters;          /* iteration t at which the returned point was evaluated */
+    double rp_norm, rd_norm;/* ||r_P||_2, ||r_D||_2 on the original model          */
+    double gap;             /* |c^T x - b^T y|                                      */
+    double pobj, dobj;      /* c^T x, b^T y                                         */
+    double rel_rp, rel_rd, rel_gap; /* the three ratios of Section 2 (<= eps: pass) */
+    double rp_inf, rd_inf;  /* infinity norms                                       */
+    double xz;              /* x^T z                                                */
+    double max_violation;   /* max(rp_inf, rd_inf, xz / (1 + |c^T x|)), Section 4.3 */
+    double b_norm, c_norm;  /* ||b||_2, ||c||_2                                     */
+    double sigma_hat;       /* power-iteration estimate of ||D_r A D_c||_2          */
+    double eta;             /* step, tau * sigma = eta^2                            */
+    double omega0, omega;   /* initial and final primal weight                      */
+    double ms_setup, ms_iter, ms_total; /* wall time: validation+scaling+step, loop, all */
+    double bytes_per_iter;  /* algorithmic bytes of one iteration: A and A^T values and
+                               indices, row pointers, each vector read or written once */
+    double bytes_primal, bytes_dual; /* the same, split by kernel                     */
+    double ms_primal, ms_dual;       /* with kernel_timing: mean duration per launch  */
+    int64_t n_primal, n_dual;        /* with kernel_timing: launches timed            */
+    int32_t lanes_a, lanes_at, long_a, long_at; /* SpMV plan used                   */
+} mipdhg_info;
+
+/* Fill `opt` with the defaults shown in brackets above. */
+void mipdhg_default_options(mipdhg_options *opt);
+
+/* Bytes of device workspace mipdhg_solve needs for this LP and options.
+ * Returns 0 or MIPDHG_ERR_INVALID_ARG. */
+int mipdhg_workspace_size(const mipdhg_lp *lp, const mipdhg_options *opt, size_t *bytes);
+
+/* Solve one LP to eps_rel (Section 2 tests).  Outputs (device float64, all
+ * required): x[n], y[m], z[n], r_p[m], r_d[n] in the original space.
+ * d_row[m], d_col[n] (nullable): the scaling, D_r A D_c being the scaled
+ * matrix the iterations run on; x~ = x / d_col, y~ = y / d_row, z~ = z * d_col
+ * is the solution of the scaled LP that Algorithm 1 (Section 3.1) consumes.
+ * `workspace` is a device buffer of at least mipdhg_workspace_size() bytes,
+ * 256-byte aligned.  `info` (nullable) receives the report. */
+int mipdhg_solve(const mipdhg_lp *lp, const mipdhg_options *opt, double eps_rel,
+                 void *workspace, size_t workspace_bytes, void *stream,
+                 double *x, double *y, double *z, double *r_p, double *r_d,
+                 double *d_row, double *d_col, mipdhg_info *info);
+
+/* sizeof of the public structs, for bindings that mirror them:
+ * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info; 0 for anything else. */
+size_t mipdhg_sizeof(int which);
+
+/* Text for a status or error code. */
+const char *mipdhg_status_string(int code);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char *mipdhg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIPDHG_H */

@@ -1,0 +1,6 @@
+"""MI355X (gfx950) restarted PDHG for standard-form LPs, behind the C ABI of
+include/mipdhg.h.  The Python layer only marshals device pointers."""
+from ._lib import (  # noqa: F401
+    OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, MipdhgError, load,
+)
+from .solver import DeviceLP, Solution, default_options, make_options, solve, workspace_bytes  # noqa: F401

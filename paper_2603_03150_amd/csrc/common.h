@@ -1,0 +1,363 @@
+// Shared device helpers and host plumbing for the mipdhg HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <vector>
+
+#include "mipdhg.h"
+
+namespace mip {
+
+constexpr int kBlock = 256;  // threads per workgroup for the row kernels (4 waves)
+constexpr int kWave = 64;    // CDNA wavefront
+constexpr int kMaxShortBlocks = 2048;  // 8 resident workgroups x 256 CUs
+constexpr int kMaxLongBlocks = 1024;
+constexpr int kMaxRowBlocks = kMaxShortBlocks + kMaxLongBlocks;
+
+// ---------------------------------------------------------------------------
+// host error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define MIP_HIP(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::mip::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                  \
+            return MIPDHG_ERR_HIP;                                                 \
+        }                                                                          \
+    } while (0)
+
+#define MIP_LAUNCH_CHECK()                                                          \
+    do {                                                                            \
+        hipError_t e_ = hipGetLastError();                                          \
+        if (e_ != hipSuccess) {                                                     \
+            ::mip::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                   \
+            return MIPDHG_ERR_HIP;                                                  \
+        }                                                                           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// loads
+// ---------------------------------------------------------------------------
+// Matrix values and column indices are streamed once per SpMV: non-temporal
+// loads keep them from evicting the gathered vector from L2.
+__device__ __forceinline__ double ld_val(const double* p, int64_t k) {
+    return __builtin_nontemporal_load(p + k);
+}
+__device__ __forceinline__ float ld_val(const float* p, int64_t k) {
+    return __builtin_nontemporal_load(p + k);
+}
+// bfloat16 stored as its upper 16 bits
+__device__ __forceinline__ float ld_val(const uint16_t* p, int64_t k) {
+    uint32_t b = __builtin_nontemporal_load(p + k);
+    return __uint_as_float(b << 16);
+}
+__device__ __forceinline__ int32_t ld_idx(const int32_t* p, int64_t k) {
+    return __builtin_nontemporal_load(p + k);
+}
+
+// float -> bfloat16 with round-to-nearest-even (finite inputs)
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+template <typename V> struct ValueOf;
+template <> struct ValueOf<double> { typedef double acc; };
+template <> struct ValueOf<float> { typedef float acc; };
+template <> struct ValueOf<uint16_t> { typedef float acc; };
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum_rt(T v, int L) {
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_max_rt(T v, int L) {
+    for (int o = L / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, L));
+    return v;
+}
+
+// Block-wide reduction of NS sums and NM maxima, in a fixed order, written to
+// out[q] for q in [0, NS+NM) whose bit is set in `mask`.  Every thread of the
+// block must call it.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce_store(double (&s)[NS], double (&mx)[NM > 0 ? NM : 1],
+                                                   double* out, unsigned mask = ~0u) {
+    __shared__ double sh[(NS + NM) > 0 ? (NS + NM) : 1][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double v = group_sum<kWave>(s[q]);
+        if (lane == 0) sh[q][wave] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+        double v = mx[q];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+        if (lane == 0) sh[NS + q][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS + NM) {
+        const int q = threadIdx.x;
+        double v = sh[q][0];
+        for (int w = 1; w < kBlock / kWave; ++w) v = (q < NS) ? v + sh[q][w] : fmax(v, sh[q][w]);
+        if (mask & (1u << q)) out[q] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row plans: which workgroup handles which CSR rows
+// ---------------------------------------------------------------------------
+// Rows no longer than `long_thresh` are handled by groups of `lanes` lanes;
+// each of the first g_short workgroups owns a contiguous chunk of rows.
+// Longer rows (listed in long_rows) are handled one wavefront per row by the
+// g_long workgroups after them.  Workgroups are dispatched round-robin over
+// the 8 XCDs; xcd_virtual_block() gives each XCD a contiguous run of chunks so
+// that the vector entries a chunk gathers stay in that XCD's L2.
+struct RowPlan {
+    const int32_t* rowptr;
+    const int32_t* long_rows;
+    int32_t nrows;
+    int32_t nlong;
+    int32_t long_thresh;
+    int32_t lanes;
+    int32_t chunk;
+    int32_t g_short;
+    int32_t g_long;
+    int32_t pad;
+};
+
+__device__ __forceinline__ int xcd_virtual_block(int b, int G) {
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// Visit every row of the plan.  dot(s, e, lane, L) returns this lane's share of
+// the row's reduction; epi(row, total) runs on the group's first lane.
+template <int L, typename Acc, class Dot, class Epi>
+__device__ __forceinline__ void for_rows(const RowPlan& p, Dot dot, Epi epi) {
+    const int b = blockIdx.x;
+    if (b < p.g_short) {
+        const int vb = xcd_virtual_block(b, p.g_short);
+        const int r0 = vb * p.chunk;
+        const int r1 = min(r0 + p.chunk, p.nrows);
+        constexpr int GPB = kBlock / L;
+        const int grp = threadIdx.x / L;
+        const int lane = threadIdx.x & (L - 1);
+        for (int r = r0 + grp; r < r1; r += GPB) {
+            const int s = p.rowptr[r];
+            const int e = p.rowptr[r + 1];
+            if (e - s > p.long_thresh) continue;
+            Acc acc = dot(s, e, lane, L);
+            acc = group_sum<L>(acc);
+            if (lane == 0) epi(r, acc);
+        }
+    } else {
+        const int lb = b - p.g_short;
+        const int wave = threadIdx.x / kWave;
+        const int lane = threadIdx.x & (kWave - 1);
+        for (int li = lb * (kBlock / kWave) + wave; li < p.nlong; li += p.g_long * (kBlock / kWave)) {
+            const int r = p.long_rows[li];
+            const int s = p.rowptr[r];
+            const int e = p.rowptr[r + 1];
+            Acc acc = dot(s, e, lane, kWave);
+            acc = group_sum<kWave>(acc);
+            if (lane == 0) epi(r, acc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nnz-balanced tiles staged through LDS
+// ---------------------------------------------------------------------------
+// A tile is a run of consecutive rows holding at most kTileNnz nonzeros and
+// kTileRows rows; a row with more than kTileNnz nonzeros is a tile of its own
+// ("huge" row).  One workgroup per tile:
+//   1. the tile's row offsets go to LDS and every product val[k]*x[col[k]] of
+//      the tile is computed with kTileNnz/kBlock independent gathers per
+//      thread and stored in LDS;
+//   2. rows of at most kShortRow products are summed by one thread each (so
+//      the row epilogue reads and writes consecutive vector entries);
+//   3. the longer rows of the tile, listed in row order, are summed by one
+//      wavefront each.
+// Every sum is taken in a fixed order, so results do not depend on timing.
+constexpr int kTileNnz = 2048;
+constexpr int kTileRows = 512;
+constexpr int kShortRow = 32;
+constexpr int kTileLong = kTileNnz / (kShortRow + 1) + 1;
+
+struct TilePlan {
+    const int32_t* rowptr;
+    const int32_t* tile_row;  // [ntiles + 1] first row of each tile
+    int32_t ntiles;
+    int32_t nrows;
+};
+
+template <typename Acc>
+struct TileLds {
+    Acc prod[kTileNnz];
+    int32_t row[kTileRows + 1];
+    int32_t list[kTileLong];
+    int32_t wcount[kBlock / kWave];
+};
+
+template <bool MAXOP, typename Acc>
+__device__ __forceinline__ Acc red_op(Acc a, Acc b) {
+    return MAXOP ? (a > b ? a : b) : a + b;
+}
+
+template <bool MAXOP, typename Acc>
+__device__ __forceinline__ Acc wave_red(Acc v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = red_op<MAXOP>(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// prod(k) -> Acc for a global nonzero index k; epi(row, total) per row.
+template <bool MAXOP, typename Acc, class Prod, class Epi>
+__device__ __forceinline__ void tiled_rows(const TilePlan& p, TileLds<Acc>& L, Prod prod, Epi epi) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int t = xcd_virtual_block(blockIdx.x, gridDim.x);
+    const int r0 = p.tile_row[t];
+    const int r1 = p.tile_row[t + 1];
+    const int s = p.rowptr[r0];
+    const int e = p.rowptr[r1];
+    const int nr = r1 - r0;
+    const int nz = e - s;
+    if (nz > kTileNnz) {  // one huge row: the whole workgroup strides over it
+        Acc a = 0;
+        for (int k = s + tid; k < e; k += kBlock) a = red_op<MAXOP>(a, prod(k));
+        a = wave_red<MAXOP>(a);
+        if (lane == 0) L.prod[wave] = a;
+        __syncthreads();
+        if (tid == 0) {
+            Acc tot = L.prod[0];
+            for (int w = 1; w < kBlock / kWave; ++w) tot = red_op<MAXOP>(tot, L.prod[w]);
+            epi(r0, tot);
+        }
+        return;
+    }
+    for (int i = tid; i <= nr; i += kBlock) L.row[i] = p.rowptr[r0 + i] - s;
+    {
+        int k = tid;
+        for (; k + 3 * kBlock < nz; k += 4 * kBlock) {
+            const Acc a0 = prod(s + k), a1 = prod(s + k + kBlock), a2 = prod(s + k + 2 * kBlock),
+                      a3 = prod(s + k + 3 * kBlock);
+            L.prod[k] = a0;
+            L.prod[k + kBlock] = a1;
+            L.prod[k + 2 * kBlock] = a2;
+            L.prod[k + 3 * kBlock] = a3;
+        }
+        for (; k < nz; k += kBlock) L.prod[k] = prod(s + k);
+    }
+    __syncthreads();
+    int nlist = 0;
+    for (int base = 0; base < nr; base += kBlock) {
+        const int i = base + tid;
+        bool lng = false;
+        if (i < nr) {
+            const int a = L.row[i], b = L.row[i + 1];
+            if (b - a <= kShortRow) {
+                Acc acc = 0;
+                for (int q = a; q < b; ++q) acc = red_op<MAXOP>(acc, L.prod[q]);
+                epi(r0 + i, acc);
+            } else {
+                lng = true;
+            }
+        }
+        // rows too long for one thread, appended to the list in row order
+        const unsigned long long mask = __ballot(lng);
+        if (lane == 0) L.wcount[wave] = __popcll(mask);
+        __syncthreads();
+        int off = nlist;
+        for (int w = 0; w < wave; ++w) off += L.wcount[w];
+        int tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) tot += L.wcount[w];
+        if (lng) L.list[off + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+        nlist += tot;
+        __syncthreads();
+    }
+    for (int j = wave; j < nlist; j += kBlock / kWave) {
+        const int i = L.list[j];
+        const int a = L.row[i], b = L.row[i + 1];
+        Acc acc = 0;
+        for (int q = a + lane; q < b; q += kWave) acc = red_op<MAXOP>(acc, L.prod[q]);
+        acc = wave_red<MAXOP>(acc);
+        if (lane == 0) epi(r0 + i, acc);
+    }
+}
+
+std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows);
+inline int64_t max_tiles(int64_t nrows, int64_t nnz) {
+    return 2 * (nnz / kTileNnz + nrows / kTileRows) + 4;
+}
+
+// Run-time lane count dispatch for the setup kernels.
+#define MIP_DISPATCH_L(LANES, ...)                        \
+    switch (LANES) {                                      \
+        case 2: { constexpr int L = 2; __VA_ARGS__; } break;   \
+        case 4: { constexpr int L = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int L = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int L = 16; __VA_ARGS__; } break; \
+        case 32: { constexpr int L = 32; __VA_ARGS__; } break; \
+        default: { constexpr int L = 64; __VA_ARGS__; } break; \
+    }
+
+// Host-side plan: lane count and long-row list from the row pointers.
+struct HostPlan {
+    int32_t lanes = 8;
+    int32_t long_thresh = 128;
+    int32_t chunk = 0;
+    int32_t g_short = 0;
+    int32_t g_long = 0;
+    std::vector<int32_t> long_rows;
+    int32_t grid() const { return g_short + g_long; }
+};
+
+HostPlan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t lanes_opt,
+                   int32_t long_opt);
+RowPlan device_plan(const HostPlan& hp, const int32_t* rowptr, const int32_t* long_rows_dev,
+                    int32_t nrows);
+
+// workspace carving
+struct Carver {
+    char* base;
+    size_t off = 0;
+    size_t cap;
+    explicit Carver(void* b, size_t c) : base((char*)b), cap(c) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace mip

@@ -1,0 +1,1296 @@
+// Restarted PDHG for one standard-form LP: kernels and host driver.
+//
+// The iteration runs on the scaled problem (Section 2.1 asks for scaling; the
+// scheme is Ruiz + Pock-Chambolle).  Every `eval_every` iterations the
+// projected point is unscaled and measured on the caller's float64 A, and the
+// three relative tests of Section 2 decide termination; restarts and the primal
+// weight follow the cuPDLP+ family that Section 4.1 names.
+//
+// Per iteration two fused kernels run:
+//   primal (rows of A~^T):  g = c~ - A~^T y, x^ = max(x - tau g, 0),
+//                           x_bar = 2 x^ - x, x <- Halpern/reflection update
+//   dual   (rows of A~):    y^ = y + sigma (b~ - A~ x_bar), y <- same update
+// and at the end of a block of iterations: two float64 evaluation kernels, a
+// single-workgroup decide kernel (tests, restart, primal weight) that writes a
+// device-resident control block, and a conditional restart copy.  Blocks are
+// captured once into a hipGraph and replayed; the host reads one status word
+// per block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "plain.h"
+
+namespace mip {
+
+enum : int32_t { ST_RUNNING = -1 };
+enum : int32_t { F_FIRST = 1, F_EVAL = 2, F_HAT = 4 };
+
+// ---------------------------------------------------------------------------
+// small vector kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// partial sums of squares of a float64 vector, one slot per workgroup
+__global__ __launch_bounds__(kBlock) void k_sumsq(const double* v, int64_t n, double* partials) {
+    double s[1] = {0.0};
+    double mx[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        s[0] += v[i] * v[i];
+    block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
+}
+
+// out[q] = fixed-order sum over G partial rows of width W (one workgroup)
+__global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* partials, int G, int W,
+                                                        double* out) {
+    __shared__ double sh[kBlock];
+    for (int q = 0; q < W; ++q) {
+        double s = 0.0;
+        for (int g = threadIdx.x; g < G; g += kBlock) s += partials[(int64_t)g * W + q];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = kBlock / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+// flags: bit0 column index out of range, bit1 non-finite value, bit2 non-finite b/c
+__global__ void k_check_entries(const int32_t* col, const double* val, int64_t nnz, int32_t ncols,
+                                int32_t* flags) {
+    int f = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t j = col[k];
+        if (j < 0 || j >= ncols) f |= 1;
+        if (!isfinite(val[k])) f |= 2;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_check_vec(const double* v, int64_t n, int32_t* flags) {
+    int f = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(v[i])) f |= 4;
+    if (f) atomicOr(flags, f);
+}
+
+__device__ __forceinline__ double hash_unit(uint32_t i, uint32_t seed) {
+    uint32_t h = i * 0x9E3779B1u ^ seed;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (double)h * (2.0 / 4294967296.0) - 1.0;  // [-1, 1)
+}
+
+// Dot-product consistency test of A and A^T: with u = hash(row), v = hash(col),
+// accumulates sum_r u_r (M v)_r and sum |u_r| |M_rc| |v_c| over the rows of M.
+template <int L>
+__global__ __launch_bounds__(kBlock) void k_transpose_dot(RowPlan p, const int32_t* col,
+                                                          const double* val, uint32_t seed_row,
+                                                          uint32_t seed_col, double* partials) {
+    double s[2] = {0.0, 0.0};
+    double mx[1] = {0.0};
+    auto dot = [&](int st, int e, int lane, int LL) {
+        double a = 0.0, b = 0.0;
+        for (int k = st + lane; k < e; k += LL) {
+            double v = hash_unit((uint32_t)col[k], seed_col);
+            a += val[k] * v;
+            b += fabs(val[k] * v);
+        }
+        return double2{a, b};
+    };
+    const int b = blockIdx.x;
+    auto epi = [&](int r, double2 t) {
+        double u = hash_unit((uint32_t)r, seed_row);
+        s[0] += u * t.x;
+        s[1] += fabs(u) * t.y;
+    };
+    if (b < p.g_short) {
+        const int vb = xcd_virtual_block(b, p.g_short);
+        const int r0 = vb * p.chunk, r1 = min(r0 + p.chunk, p.nrows);
+        const int grp = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+        for (int r = r0 + grp; r < r1; r += kBlock / L) {
+            const int st = p.rowptr[r], e = p.rowptr[r + 1];
+            if (e - st > p.long_thresh) continue;
+            double2 t = dot(st, e, lane, L);
+            t.x = group_sum<L>(t.x);
+            t.y = group_sum<L>(t.y);
+            if (lane == 0) epi(r, t);
+        }
+    } else {
+        const int lb = b - p.g_short, wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+        for (int li = lb * 4 + wave; li < p.nlong; li += p.g_long * 4) {
+            const int r = p.long_rows[li];
+            double2 t = dot(p.rowptr[r], p.rowptr[r + 1], lane, kWave);
+            t.x = group_sum<kWave>(t.x);
+            t.y = group_sum<kWave>(t.y);
+            if (lane == 0) epi(r, t);
+        }
+    }
+    block_reduce_store<2, 0>(s, mx, partials + 2 * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// scaling
+// ---------------------------------------------------------------------------
+// stat[r] = d_self[r] * (max or sum over the row of |a_rk| d_other[col_k]),
+// i.e. the row's infinity norm (MAXMODE) or 1-norm of the currently scaled
+// matrix D_r A D_c.
+template <bool MAXMODE>
+__global__ __launch_bounds__(kBlock) void k_scale_stat(TilePlan p, const int32_t* col, const double* val,
+                                                       const double* d_self, const double* d_other,
+                                                       double* stat) {
+    __shared__ TileLds<double> L;
+    auto prod = [&](int k) { return fabs(val[k]) * d_other[col[k]]; };
+    auto epi = [&](int r, double a) { stat[r] = d_self[r] * a; };
+    tiled_rows<MAXMODE>(p, L, prod, epi);
+}
+
+// d[i] *= 1/sqrt(stat[i]) (1 for an empty row or column)
+__global__ void k_scale_update(double* d, const double* stat, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = stat[i];
+        if (s > 0.0) d[i] = d[i] * (1.0 / sqrt(s));
+    }
+}
+
+// out[k] = d_self[r] * val[k] * d_other[col[k]] rounded to V, for every row r
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_scale_values(const int32_t* rowptr, const int32_t* col,
+                                                         const double* val, const double* d_self,
+                                                         const double* d_other, int32_t nrows, V* out) {
+    // one wave per row group of 64 lanes striding the row
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; r < nrows;
+         r += (int64_t)gridDim.x * (kBlock / kWave)) {
+        const int st = rowptr[r], e = rowptr[r + 1];
+        const double ds = d_self[r];
+        for (int k = st + lane; k < e; k += kWave) {
+            double v = ds * val[k] * d_other[col[k]];
+            if constexpr (sizeof(V) == 2) {
+                out[k] = f32_to_bf16_rne((float)v);
+            } else {
+                out[k] = (V)v;
+            }
+        }
+    }
+}
+
+// t[i] = d[i] * v[i] rounded to T; partial sums of squares in float64
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const double* d, int64_t n,
+                                                      T* out, double* partials) {
+    double s[1] = {0.0};
+    double mx[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double t = d[i] * v[i];
+        out[i] = (T)t;
+        s[0] += t * t;
+    }
+    block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// power iteration on D_r A D_c, float64, scaling applied on the fly
+// ---------------------------------------------------------------------------
+// y[r] = d_self[r] * sum_k val[k] d_other[col[k]] x[col[k]]; partial ||y||^2.
+// If `norm_partials` is given, x is first divided by sqrt(sum of those G
+// partials) (the normalisation v = u / ||u|| of the previous half-step).
+__global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_t* col, const double* val,
+                                                        const double* d_self, const double* d_other,
+                                                        const double* x, double* y, double* partials) {
+    __shared__ TileLds<double> L;
+    double s[1] = {0.0};
+    double mx[1] = {0.0};
+    auto prod = [&](int k) {
+        const int j = ld_idx(col, k);
+        return ld_val(val, k) * (d_other[j] * x[j]);
+    };
+    auto epi = [&](int r, double a) {
+        const double t = d_self[r] * a;
+        y[r] = t;
+        s[0] += t * t;
+    };
+    tiled_rows<false>(p, L, prod, epi);
+    block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
+}
+
+// v = u / sqrt(sum of G partials), identical sum order in every workgroup
+__global__ __launch_bounds__(kBlock) void k_normalize(const double* u, double* v, int64_t n,
+                                                      const double* partials, int G) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s += partials[g];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double nrm = sqrt(sh[0]);
+    if (nrm == 0.0) return;  // u = 0: keep v
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        v[i] = u[i] / nrm;
+}
+
+// ---------------------------------------------------------------------------
+// iteration kernels
+// ---------------------------------------------------------------------------
+template <typename T, typename V>
+struct IterArgs {
+    RowPlan p;
+    const int32_t* col;
+    const V* val;
+    const T* gather;   // y (primal) or x_bar (dual)
+    T* state;          // x or y
+    T* bar;            // x_bar (primal only)
+    T* hat;            // x^ or y^
+    const T* anchor;   // Halpern anchor x0 or y0
+    const T* rhs;      // c~ or b~
+    double* out64;     // x or y of the original model, written at evaluations
+    const double* dscale;  // D_c or D_r
+    double* partials;  // [G][3]: ||o - h||^2 at the first iteration, same at the evaluation, ||h - anchor||^2
+    const Ctrl* ctrl;
+    double rho;
+    int32_t halpern;
+    int32_t it;
+    int32_t flags;
+};
+
+// Per-row epilogue of the primal (PRIMAL) or dual step, shared by both SpMV
+// traversals.  q accumulates the three partial sums described in IterArgs.
+template <typename T, typename V, bool PRIMAL>
+struct IterEpi {
+    const IterArgs<T, V>& a;
+    T w, omw, rho, opr, st;
+    int flags;
+    double* q;
+    template <typename Acc>
+    __device__ __forceinline__ void operator()(int r, Acc s) const {
+        const T o = a.state[r];
+        T h;
+        if (PRIMAL) {
+            const T g = a.rhs[r] - (T)s;
+            h = o - st * g;
+            h = h < (T)0 ? (T)0 : h;  // projection onto x >= 0 (NaN propagates)
+            a.bar[r] = (T)2 * h - o;
+        } else {
+            h = o + st * (a.rhs[r] - (T)s);
+        }
+        if (flags & F_HAT) a.hat[r] = h;
+        const T an = a.anchor[r];
+        a.state[r] = w * (opr * h - rho * o) + omw * an;
+        if (flags & (F_FIRST | F_EVAL)) {
+            double d = (double)o - (double)h;
+            d *= d;
+            if (flags & F_FIRST) q[0] += d;
+            if (flags & F_EVAL) q[1] += d;
+        }
+        if (flags & F_EVAL) {
+            const double d = (double)h - (double)an;
+            q[2] += d * d;
+            a.out64[r] = a.dscale[r] * (double)h;
+        }
+    }
+};
+
+template <typename T, typename V, bool PRIMAL>
+__device__ __forceinline__ IterEpi<T, V, PRIMAL> make_epi(const IterArgs<T, V>& a, double* q) {
+    const Ctrl* c = a.ctrl;
+    const int64_t k = c->k_base + a.it;
+    const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
+    IterEpi<T, V, PRIMAL> e{a, (T)w64, (T)(1.0 - w64), (T)a.rho, (T)(1.0 + a.rho),
+                            (T)(PRIMAL ? c->tau : c->sigma), a.flags, q};
+    return e;
+}
+
+__device__ __forceinline__ unsigned iter_store_mask(int flags) {
+    // slot 0 belongs to the block's first iteration, slots 1-2 to its evaluation
+    return ((flags & F_FIRST) ? 1u : 0u) | ((flags & F_EVAL) ? 6u : 0u);
+}
+
+// lane-group traversal (RowPlan)
+template <typename T, typename V, int L, bool PRIMAL>
+__global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    double q[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    typedef typename ValueOf<V>::acc Acc;
+    const auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto dot = [&](int s, int e, int lane, int LL) {
+        Acc acc = 0;
+#pragma unroll 4
+        for (int kk = s + lane; kk < e; kk += LL) acc += ld_val(a.val, kk) * (Acc)a.gather[ld_idx(a.col, kk)];
+        return acc;
+    };
+    for_rows<L, Acc>(a.p, dot, epi);
+    if (a.flags & (F_FIRST | F_EVAL)) block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+}
+
+// LDS-tiled traversal (TilePlan)
+template <typename T, typename V, bool PRIMAL>
+__global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    typedef typename ValueOf<V>::acc Acc;
+    __shared__ TileLds<Acc> L;
+    double q[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    const auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
+    tiled_rows<false>(tp, L, prod, epi);
+    if (a.flags & (F_FIRST | F_EVAL)) block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+}
+
+// ---------------------------------------------------------------------------
+// evaluation on the original model (float64), Section 2 and Section 4.3
+// ---------------------------------------------------------------------------
+// ROWS:  over A's rows, r_p = b - A x; partials: sum r_p^2, sum b.y, -, max |r_p|
+// !ROWS: over A^T's rows, z = max(c - A^T y, 0), r_d = c - A^T y - z;
+//        partials: sum r_d^2, sum c.x, sum x.z, max |r_d|
+struct EvalArgs {
+    RowPlan p;
+    const int32_t* col;
+    const double* val;
+    const double* gather;  // x (ROWS) or y
+    const double* vec;     // b (ROWS) or c
+    const double* own;     // y (ROWS) or x
+    double* out1;          // r_p (ROWS) or z
+    double* out2;          // r_d (!ROWS)
+    double* partials;      // [G][4]
+    const Ctrl* ctrl;
+};
+
+template <bool ROWS>
+__global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    __shared__ TileLds<double> L;
+    double s[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    auto prod = [&](int k) { return ld_val(a.val, k) * a.gather[ld_idx(a.col, k)]; };
+    auto epi = [&](int r, double t) {
+        const double v = a.vec[r];
+        if (ROWS) {
+            const double rp = v - t;
+            a.out1[r] = rp;
+            s[0] += rp * rp;
+            s[1] += v * a.own[r];
+            mx[0] = fmax(mx[0], fabs(rp));
+        } else {
+            const double g = v - t;
+            const double z = g > 0.0 ? g : 0.0;
+            const double rd = g - z;
+            a.out1[r] = z;
+            a.out2[r] = rd;
+            const double x = a.own[r];
+            s[0] += rd * rd;
+            s[1] += v * x;
+            s[2] += x * z;
+            mx[0] = fmax(mx[0], fabs(rd));
+        }
+    };
+    tiled_rows<false>(tp, L, prod, epi);
+    block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// decide: tests, restart, primal weight (one workgroup)
+// ---------------------------------------------------------------------------
+struct DecideArgs {
+    Ctrl* ctrl;
+    const double* pp;  // primal partials [gp][3]
+    const double* pd;  // dual partials [gd][3]
+    const double* per; // eval rows [ger][4]
+    const double* pec; // eval cols [gec][4]
+    int32_t gp, gd, ger, gec;
+    int32_t nit;
+};
+
+__device__ double fixed_sum(const double* p, int G, int W, int q, double* sh) {
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s += p[(int64_t)g * W + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double fixed_max(const double* p, int G, int W, int q, double* sh) {
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s = fmax(s, p[(int64_t)g * W + q]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
+    Ctrl& c = *a.ctrl;
+    if (c.status != ST_RUNNING) return;
+    __shared__ double sh[kBlock];
+    const double px_first = fixed_sum(a.pp, a.gp, 3, 0, sh);
+    const double px_eval = fixed_sum(a.pp, a.gp, 3, 1, sh);
+    const double px_anchor = fixed_sum(a.pp, a.gp, 3, 2, sh);
+    const double py_first = fixed_sum(a.pd, a.gd, 3, 0, sh);
+    const double py_eval = fixed_sum(a.pd, a.gd, 3, 1, sh);
+    const double py_anchor = fixed_sum(a.pd, a.gd, 3, 2, sh);
+    const double rp2 = fixed_sum(a.per, a.ger, 4, 0, sh);
+    const double dobj = fixed_sum(a.per, a.ger, 4, 1, sh);
+    const double rp_inf = fixed_max(a.per, a.ger, 4, 3, sh);
+    const double rd2 = fixed_sum(a.pec, a.gec, 4, 0, sh);
+    const double pobj = fixed_sum(a.pec, a.gec, 4, 1, sh);
+    const double xz = fixed_sum(a.pec, a.gec, 4, 2, sh);
+    const double rd_inf = fixed_max(a.pec, a.gec, 4, 3, sh);
+    if (threadIdx.x != 0) return;
+
+    const double om = c.omega;
+    const int64_t t_end = c.t_base + a.nit;
+    const int64_t k_end = c.k_base + a.nit;
+    if (c.k_base == 0) c.R0 = sqrt(om * px_first + py_first / om);
+    const double R = sqrt(om * px_eval + py_eval / om);
+    c.rp2 = rp2;
+    c.rd2 = rd2;
+    c.pobj = pobj;
+    c.dobj = dobj;
+    c.xz = xz;
+    c.rp_inf = rp_inf;
+    c.rd_inf = rd_inf;
+    c.eval_t = t_end;
+    c.last_R = R;
+    const double rp = sqrt(rp2), rd = sqrt(rd2), gap = fabs(pobj - dobj);
+    int32_t status = ST_RUNNING;
+    if (!(isfinite(rp2) && isfinite(rd2) && isfinite(pobj) && isfinite(dobj))) {
+        status = MIPDHG_NUMERICAL;
+    } else if (rp <= c.eps * (1.0 + c.b_norm) && rd <= c.eps * (1.0 + c.c_norm) &&
+               gap <= c.eps * (1.0 + fabs(pobj) + fabs(dobj))) {
+        status = MIPDHG_OPTIMAL;
+    } else if (t_end >= c.max_iter) {
+        status = MIPDHG_ITER_LIMIT;
+    }
+    c.t_base = t_end;
+    if (status != ST_RUNNING) {
+        c.status = status;
+        c.restart_now = 0;
+        return;
+    }
+    bool restart = false;
+    if (c.do_restarts) {
+        restart = (R <= c.beta_suff * c.R0) || (R <= c.beta_nec * c.R0 && R > c.R_prev) ||
+                  ((double)k_end >= c.beta_art * (double)t_end);
+    }
+    if (restart) {
+        const double dx = sqrt(px_anchor), dy = sqrt(py_anchor);
+        if (dx > 1e-10 && dy > 1e-10) {
+            const double th = c.pw_theta;
+            c.omega = exp(th * log(dy / dx) + (1.0 - th) * log(c.omega));
+            c.tau = c.eta / c.omega;
+            c.sigma = c.eta * c.omega;
+        }
+        c.k_base = 0;
+        c.R_prev = INFINITY;
+        c.restarts += 1;
+        c.restart_now = 1;
+    } else {
+        c.R_prev = R;
+        c.k_base = k_end;
+        c.restart_now = 0;
+    }
+}
+
+// on a restart: state and anchor <- projected point
+template <typename T>
+__global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t n, T* y, T* y0,
+                                const T* yh, int64_t m) {
+    if (!c->restart_now) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T v = xh[i];
+        x[i] = v;
+        x0[i] = v;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T v = yh[i];
+        y[i] = v;
+        y0[i] = v;
+    }
+}
+
+// initial point: state = anchor = init / d (or 0)
+template <typename T>
+__global__ void k_init_state(const double* init, const double* d, int64_t n, T* s, T* s0, T* hat) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T v = init ? (T)(init[i] / d[i]) : (T)0;
+        s[i] = v;
+        s0[i] = v;
+        hat[i] = v;
+    }
+}
+
+template <typename T>
+__global__ void k_export(const T* src, double* dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int pow2_round(double v) {
+    int L = 2;
+    while (L < 64 && (double)L * 1.5 < v) L *= 2;
+    return L;
+}
+
+HostPlan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t lanes_opt, int32_t long_opt) {
+    HostPlan hp;
+    const double mean = nrows > 0 ? (double)(rowptr[nrows] - rowptr[0]) / nrows : 0.0;
+    hp.lanes = lanes_opt > 0 ? lanes_opt : std::min(32, pow2_round(mean));
+    hp.long_thresh = long_opt > 0 ? long_opt : std::max(128, 4 * hp.lanes);
+    for (int32_t r = 0; r < nrows; ++r)
+        if (rowptr[r + 1] - rowptr[r] > hp.long_thresh) hp.long_rows.push_back(r);
+    const int gpb = kBlock / hp.lanes;
+    const int64_t need = (nrows + gpb - 1) / gpb;
+    hp.g_short = (int32_t)std::max<int64_t>(1, std::min<int64_t>(need, kMaxShortBlocks));
+    int64_t chunk = (nrows + hp.g_short - 1) / hp.g_short;
+    chunk = (chunk + gpb - 1) / gpb * gpb;
+    hp.chunk = (int32_t)std::max<int64_t>(chunk, gpb);
+    hp.g_short = (int32_t)std::max<int64_t>(1, (nrows + hp.chunk - 1) / hp.chunk);
+    const int64_t nl = (int64_t)hp.long_rows.size();
+    hp.g_long = nl ? (int32_t)std::min<int64_t>((nl + 3) / 4, kMaxLongBlocks) : 0;
+    return hp;
+}
+
+RowPlan device_plan(const HostPlan& hp, const int32_t* rowptr, const int32_t* long_rows_dev, int32_t nrows) {
+    RowPlan p;
+    p.rowptr = rowptr;
+    p.long_rows = long_rows_dev;
+    p.nrows = nrows;
+    p.nlong = (int32_t)hp.long_rows.size();
+    p.long_thresh = hp.long_thresh;
+    p.lanes = hp.lanes;
+    p.chunk = hp.chunk;
+    p.g_short = hp.g_short;
+    p.g_long = hp.g_long;
+    p.pad = 0;
+    return p;
+}
+
+// Greedy cut of the rows into tiles of at most kTileNnz nonzeros and kTileRows
+// rows; a row longer than kTileNnz is a tile by itself.
+std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows) {
+    std::vector<int32_t> t;
+    t.reserve((size_t)max_tiles(nrows, rowptr[nrows]) + 1);
+    t.push_back(0);
+    int32_t r = 0;
+    while (r < nrows) {
+        const int32_t len = rowptr[r + 1] - rowptr[r];
+        if (len > kTileNnz) {
+            t.push_back(r + 1);
+            ++r;
+            continue;
+        }
+        const int32_t start = r;
+        int64_t nz = 0;
+        while (r < nrows && r - start < kTileRows) {
+            const int32_t l = rowptr[r + 1] - rowptr[r];
+            if (l > kTileNnz || nz + l > kTileNnz) break;
+            nz += l;
+            ++r;
+        }
+        t.push_back(r);
+    }
+    return t;
+}
+
+static inline int grid_for(int64_t n, int cap = 2048) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Workspace layout (identical for the size query and the solve).
+struct PlainWs {
+    Ctrl* ctrl;
+    double *d_row, *d_col, *stat_r, *stat_c, *pv, *pu, *pav, *hist, *red;
+    double *pp, *pd, *per, *pec, *psetup;
+    int64_t gcap;  // partial slots per kernel
+    void *a_vs, *at_vs;
+    void *x, *xbar, *x0, *xhat, *ct, *y, *y0, *yhat, *bt;
+    int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
+    size_t bytes;
+};
+
+static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters) {
+    Carver cv(base, cap);
+    PlainWs w;
+    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32 ? 4 : 2);
+    const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
+    w.gcap = std::max<int64_t>(kMaxRowBlocks, std::max(max_tiles(m, nnz), max_tiles(n, nnz)));
+    w.ctrl = cv.take<Ctrl>(1);
+    w.d_row = cv.take<double>(m);
+    w.d_col = cv.take<double>(n);
+    w.stat_r = cv.take<double>(m);
+    w.stat_c = cv.take<double>(n);
+    w.pv = cv.take<double>(n);
+    w.pu = cv.take<double>(n);
+    w.pav = cv.take<double>(m);
+    w.hist = cv.take<double>(power_iters + 2);
+    w.red = cv.take<double>(16);
+    w.pp = cv.take<double>((size_t)w.gcap * 3);
+    w.pd = cv.take<double>((size_t)w.gcap * 3);
+    w.per = cv.take<double>((size_t)w.gcap * 4);
+    w.pec = cv.take<double>((size_t)w.gcap * 4);
+    w.psetup = cv.take<double>((size_t)w.gcap * 4);
+    w.a_vs = cv.take<char>(nnz * vs);
+    w.at_vs = cv.take<char>(nnz * vs);
+    w.x = cv.take<char>(n * ts);
+    w.xbar = cv.take<char>(n * ts);
+    w.x0 = cv.take<char>(n * ts);
+    w.xhat = cv.take<char>(n * ts);
+    w.ct = cv.take<char>(n * ts);
+    w.y = cv.take<char>(m * ts);
+    w.y0 = cv.take<char>(m * ts);
+    w.yhat = cv.take<char>(m * ts);
+    w.bt = cv.take<char>(m * ts);
+    w.long_a = cv.take<int32_t>(m);
+    w.long_at = cv.take<int32_t>(n);
+    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz) + 1);
+    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz) + 1);
+    w.flags = cv.take<int32_t>(64);
+    w.bytes = (cv.off + 255) & ~size_t(255);
+    return w;
+}
+
+static int check_options(const mipdhg_options* o) {
+    if (o->precision < 0 || o->precision > 2) return set_error("precision must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
+    if (o->ruiz_iters < 0 || o->power_iters < 1 || o->power_iters > 100000)
+        return set_error("ruiz_iters >= 0 and 1 <= power_iters <= 100000 required"), MIPDHG_ERR_INVALID_ARG;
+    if (o->eval_every < 1 || o->eval_every > 4096)
+        return set_error("eval_every must be in [1, 4096]"), MIPDHG_ERR_INVALID_ARG;
+    if (!(o->step_safety > 0.0) || !(o->reflect_rho >= 0.0 && o->reflect_rho <= 1.0))
+        return set_error("step_safety > 0 and reflect_rho in [0,1] required"), MIPDHG_ERR_INVALID_ARG;
+    if (o->max_iter < 1) return set_error("max_iter must be >= 1"), MIPDHG_ERR_INVALID_ARG;
+    if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
+    if (o->spmv_kind != 0 && o->spmv_kind != 1) return set_error("spmv_kind must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    for (int L : {o->lanes_a, o->lanes_at})
+        if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
+            return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
+    if (o->trace_iters < 0) return set_error("trace_iters must be >= 0"), MIPDHG_ERR_INVALID_ARG;
+    return 0;
+}
+
+static int check_lp(const mipdhg_lp* lp) {
+    if (!lp) return set_error("lp is NULL"), MIPDHG_ERR_INVALID_ARG;
+    if (lp->m < 1 || lp->n < 1 || lp->nnz < 0 || lp->nnz >= (int64_t)INT32_MAX)
+        return set_error("need m >= 1, n >= 1 and 0 <= nnz < 2^31 (m=%d n=%d nnz=%lld)", lp->m, lp->n,
+                         (long long)lp->nnz),
+               MIPDHG_ERR_INVALID_ARG;
+    if (!lp->a_rowptr || !lp->at_rowptr || !lp->b || !lp->c ||
+        (lp->nnz > 0 && (!lp->a_col || !lp->a_val || !lp->at_col || !lp->at_val)))
+        return set_error("a required LP pointer is NULL"), MIPDHG_ERR_INVALID_ARG;
+    return 0;
+}
+
+static int check_rowptr(const std::vector<int32_t>& rp, int32_t nrows, int64_t nnz, const char* which) {
+    if (rp[0] != 0 || (int64_t)rp[nrows] != nnz)
+        return set_error("%s row pointer must start at 0 and end at nnz", which), MIPDHG_ERR_BAD_CSR;
+    for (int32_t r = 0; r < nrows; ++r)
+        if (rp[r + 1] < rp[r]) return set_error("%s row pointer decreases at row %d", which, r), MIPDHG_ERR_BAD_CSR;
+    return 0;
+}
+
+}  // namespace mip
+
+using namespace mip;
+
+extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* opt, size_t* bytes) {
+    clear_error();
+    if (!bytes || !opt) return set_error("NULL argument"), MIPDHG_ERR_INVALID_ARG;
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if ((rc = check_options(opt))) return rc;
+    *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters).bytes;
+    return 0;
+}
+
+namespace mip {
+
+template <typename T, typename V>
+struct Solver {
+    const mipdhg_lp& lp;
+    const mipdhg_options& o;
+    hipStream_t stream;
+    PlainWs w;
+    HostPlan hpa, hpat;   // lane-group plans (spmv_kind 1, transpose test)
+    RowPlan pa, pat;
+    TilePlan ta, tat;     // LDS tile plans
+    double *xo, *yo, *zo, *rpo, *rdo;
+    // kernel timing: three events per iteration (before primal, between, after dual)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    double ms_p = 0.0, ms_d = 0.0;
+    int64_t n_p = 0, n_d = 0;
+
+    Solver(const mipdhg_lp& l, const mipdhg_options& op, hipStream_t s) : lp(l), o(op), stream(s) {}
+    ~Solver() {
+        for (auto e : tev) (void)hipEventDestroy(e);
+    }
+    bool tiled() const { return o.spmv_kind == 0; }
+    int grid_primal() const { return tiled() ? tat.ntiles : hpat.grid(); }
+    int grid_dual() const { return tiled() ? ta.ntiles : hpa.grid(); }
+
+    void fill_iter(IterArgs<T, V>& a, bool primal, int it, int flags) {
+        a.p = primal ? pat : pa;
+        a.col = primal ? lp.at_col : lp.a_col;
+        a.val = (const V*)(primal ? w.at_vs : w.a_vs);
+        a.gather = (const T*)(primal ? w.y : w.xbar);
+        a.state = (T*)(primal ? w.x : w.y);
+        a.bar = primal ? (T*)w.xbar : nullptr;
+        a.hat = (T*)(primal ? w.xhat : w.yhat);
+        a.anchor = (const T*)(primal ? w.x0 : w.y0);
+        a.rhs = (const T*)(primal ? w.ct : w.bt);
+        a.out64 = primal ? xo : yo;
+        a.dscale = primal ? w.d_col : w.d_row;
+        a.partials = primal ? w.pp : w.pd;
+        a.ctrl = w.ctrl;
+        a.rho = o.reflect_rho;
+        a.halpern = o.halpern;
+        a.it = it;
+        a.flags = flags;
+    }
+    int launch_primal(int it, int flags) {
+        IterArgs<T, V> a;
+        fill_iter(a, true, it, flags);
+        if (tiled()) {
+            hipLaunchKernelGGL((k_iter_tiled<T, V, true>), dim3(tat.ntiles), dim3(kBlock), 0, stream, a, tat);
+        } else {
+            MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, L, true>), dim3(hpat.grid()), dim3(kBlock),
+                                                         0, stream, a));
+        }
+        MIP_LAUNCH_CHECK();
+        return 0;
+    }
+    int launch_dual(int it, int flags) {
+        IterArgs<T, V> a;
+        fill_iter(a, false, it, flags);
+        if (tiled()) {
+            hipLaunchKernelGGL((k_iter_tiled<T, V, false>), dim3(ta.ntiles), dim3(kBlock), 0, stream, a, ta);
+        } else {
+            MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, L, false>), dim3(hpa.grid()), dim3(kBlock),
+                                                        0, stream, a));
+        }
+        MIP_LAUNCH_CHECK();
+        return 0;
+    }
+    int launch_eval_and_decide(int nit) {
+        EvalArgs er;
+        er.col = lp.a_col;
+        er.val = lp.a_val;
+        er.gather = xo;
+        er.vec = lp.b;
+        er.own = yo;
+        er.out1 = rpo;
+        er.out2 = nullptr;
+        er.partials = w.per;
+        er.ctrl = w.ctrl;
+        hipLaunchKernelGGL((k_eval<true>), dim3(ta.ntiles), dim3(kBlock), 0, stream, er, ta);
+        MIP_LAUNCH_CHECK();
+        EvalArgs ec;
+        ec.col = lp.at_col;
+        ec.val = lp.at_val;
+        ec.gather = yo;
+        ec.vec = lp.c;
+        ec.own = xo;
+        ec.out1 = zo;
+        ec.out2 = rdo;
+        ec.partials = w.pec;
+        ec.ctrl = w.ctrl;
+        hipLaunchKernelGGL((k_eval<false>), dim3(tat.ntiles), dim3(kBlock), 0, stream, ec, tat);
+        MIP_LAUNCH_CHECK();
+        DecideArgs d;
+        d.ctrl = w.ctrl;
+        d.pp = w.pp;
+        d.pd = w.pd;
+        d.per = w.per;
+        d.pec = w.pec;
+        d.gp = grid_primal();
+        d.gd = grid_dual();
+        d.ger = ta.ntiles;
+        d.gec = tat.ntiles;
+        d.nit = nit;
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, stream, d);
+        MIP_LAUNCH_CHECK();
+        const int64_t mx = std::max<int64_t>(lp.m, lp.n);
+        hipLaunchKernelGGL((k_apply_restart<T>), dim3(grid_for(mx)), dim3(kBlock), 0, stream,
+                           (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, (const T*)w.xhat, (int64_t)lp.n,
+                           (T*)w.y, (T*)w.y0, (const T*)w.yhat, (int64_t)lp.m);
+        MIP_LAUNCH_CHECK();
+        return 0;
+    }
+    // One block of nit iterations ending in an evaluation.  With trace, the
+    // scaled iterates after iteration t_first + i are exported.
+    int enqueue_block(int nit, int64_t t_first, bool trace) {
+        int rc;
+        for (int it = 0; it < nit; ++it) {
+            const bool last = it == nit - 1;
+            const int flags = (it == 0 ? F_FIRST : 0) | (last ? (F_EVAL | F_HAT) : 0) | (trace ? F_HAT : 0);
+            if (timing) MIP_HIP(hipEventRecord(tev[3 * it], stream));
+            if ((rc = launch_primal(it, flags))) return rc;
+            if (timing) MIP_HIP(hipEventRecord(tev[3 * it + 1], stream));
+            if ((rc = launch_dual(it, flags))) return rc;
+            if (timing) MIP_HIP(hipEventRecord(tev[3 * it + 2], stream));
+            if (last && (rc = launch_eval_and_decide(nit))) return rc;
+            const int64_t t = t_first + it;  // 1-based iteration number
+            if (trace && t <= o.trace_iters) {
+                const int64_t off_n = (t - 1) * (int64_t)lp.n, off_m = (t - 1) * (int64_t)lp.m;
+                if (o.trace_x)
+                    hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
+                                       (const T*)w.x, o.trace_x + off_n, (int64_t)lp.n);
+                if (o.trace_y)
+                    hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
+                                       (const T*)w.y, o.trace_y + off_m, (int64_t)lp.m);
+                if (o.trace_xhat)
+                    hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
+                                       (const T*)w.xhat, o.trace_xhat + off_n, (int64_t)lp.n);
+                if (o.trace_yhat)
+                    hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
+                                       (const T*)w.yhat, o.trace_yhat + off_m, (int64_t)lp.m);
+                MIP_LAUNCH_CHECK();
+            }
+        }
+        if (timing) {
+            MIP_HIP(hipEventSynchronize(tev[3 * (nit - 1) + 2]));
+            for (int it = 0; it < nit; ++it) {
+                float a = 0.f, b = 0.f;
+                MIP_HIP(hipEventElapsedTime(&a, tev[3 * it], tev[3 * it + 1]));
+                MIP_HIP(hipEventElapsedTime(&b, tev[3 * it + 1], tev[3 * it + 2]));
+                ms_p += a;
+                ms_d += b;
+            }
+            n_p += nit;
+            n_d += nit;
+        }
+        return 0;
+    }
+};
+
+template <typename T, typename V>
+static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, void* ws, size_t ws_bytes,
+                      hipStream_t stream, double* x, double* y, double* z, double* r_p, double* r_d,
+                      double* d_row, double* d_col, mipdhg_info* info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    Solver<T, V> S(lp, o, stream);
+    S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters);
+    if (S.w.bytes > ws_bytes)
+        return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
+               MIPDHG_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
+    S.xo = x;
+    S.yo = y;
+    S.zo = z;
+    S.rpo = r_p;
+    S.rdo = r_d;
+    PlainWs& w = S.w;
+    const int64_t m = lp.m, n = lp.n, nnz = lp.nnz;
+
+    // --- row pointers to the host: validation and SpMV plans
+    std::vector<int32_t> rpa(m + 1), rpat(n + 1);
+    MIP_HIP(hipMemcpyAsync(rpa.data(), lp.a_rowptr, (m + 1) * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipMemcpyAsync(rpat.data(), lp.at_rowptr, (n + 1) * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    int rc;
+    if ((rc = check_rowptr(rpa, lp.m, nnz, "A"))) return rc;
+    if ((rc = check_rowptr(rpat, lp.n, nnz, "A^T"))) return rc;
+    S.hpa = make_plan(rpa, lp.m, o.lanes_a, o.long_row);
+    S.hpat = make_plan(rpat, lp.n, o.lanes_at, o.long_row);
+    if (!S.hpa.long_rows.empty())
+        MIP_HIP(hipMemcpyAsync(w.long_a, S.hpa.long_rows.data(), S.hpa.long_rows.size() * 4,
+                               hipMemcpyHostToDevice, stream));
+    if (!S.hpat.long_rows.empty())
+        MIP_HIP(hipMemcpyAsync(w.long_at, S.hpat.long_rows.data(), S.hpat.long_rows.size() * 4,
+                               hipMemcpyHostToDevice, stream));
+    S.pa = device_plan(S.hpa, lp.a_rowptr, w.long_a, lp.m);
+    S.pat = device_plan(S.hpat, lp.at_rowptr, w.long_at, lp.n);
+    const int ga = S.hpa.grid(), gat = S.hpat.grid();
+    {
+        const std::vector<int32_t> ta = make_tiles(rpa, lp.m), tat = make_tiles(rpat, lp.n);
+        MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
+        MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
+        S.ta = TilePlan{lp.a_rowptr, w.tiles_a, (int32_t)ta.size() - 1, lp.m};
+        S.tat = TilePlan{lp.at_rowptr, w.tiles_at, (int32_t)tat.size() - 1, lp.n};
+        MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
+    }
+    const int gta = S.ta.ntiles, gtat = S.tat.ntiles;
+    const int64_t G = w.gcap;
+
+    // --- validation: indices, finiteness, transpose consistency
+    if (o.validate) {
+        MIP_HIP(hipMemsetAsync(w.flags, 0, 4, stream));
+        if (nnz > 0) {
+            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.a_col, lp.a_val,
+                               nnz, lp.n, w.flags);
+            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.at_col,
+                               lp.at_val, nnz, lp.m, w.flags);
+        }
+        hipLaunchKernelGGL(k_check_vec, dim3(grid_for(m)), dim3(kBlock), 0, stream, lp.b, m, w.flags);
+        hipLaunchKernelGGL(k_check_vec, dim3(grid_for(n)), dim3(kBlock), 0, stream, lp.c, n, w.flags);
+        MIP_LAUNCH_CHECK();
+        int32_t flags = 0;
+        MIP_HIP(hipMemcpyAsync(&flags, w.flags, 4, hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        if (flags & 1) return set_error("column index out of range"), MIPDHG_ERR_BAD_CSR;
+        if (flags & 6) return set_error("NaN or Inf in A, A^T, b or c"), MIPDHG_ERR_NONFINITE;
+        if (nnz > 0) {
+            // u^T (A v) = v^T (A^T u) with hash vectors
+            MIP_DISPATCH_L(S.pa.lanes, hipLaunchKernelGGL((k_transpose_dot<L>), dim3(ga), dim3(kBlock), 0, stream,
+                                                          S.pa, lp.a_col, lp.a_val, 0x1234u, 0xABCDu, w.psetup));
+            hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, ga, 2,
+                               w.red);
+            MIP_DISPATCH_L(S.pat.lanes, hipLaunchKernelGGL((k_transpose_dot<L>), dim3(gat), dim3(kBlock), 0,
+                                                           stream, S.pat, lp.at_col, lp.at_val, 0xABCDu, 0x1234u,
+                                                           w.psetup));
+            hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gat, 2,
+                               w.red + 2);
+            MIP_LAUNCH_CHECK();
+            double red[4];
+            MIP_HIP(hipMemcpyAsync(red, w.red, 4 * 8, hipMemcpyDeviceToHost, stream));
+            MIP_HIP(hipStreamSynchronize(stream));
+            const double scale = std::max(red[1], red[3]);
+            if (!(fabs(red[0] - red[2]) <= 1e-10 * scale + 1e-300))
+                return set_error("A^T does not match A (dot test %.17g vs %.17g)", red[0], red[2]),
+                       MIPDHG_ERR_TRANSPOSE;
+        }
+    }
+
+    // --- norms of the original b and c
+    double bn2 = 0, cn2 = 0;
+    {
+        const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
+        hipLaunchKernelGGL(k_sumsq, dim3(gm), dim3(kBlock), 0, stream, lp.b, m, w.psetup);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gm, 1, w.red);
+        hipLaunchKernelGGL(k_sumsq, dim3(gn), dim3(kBlock), 0, stream, lp.c, n, w.psetup + G);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream,
+                           (const double*)(w.psetup + G), gn, 1, w.red + 1);
+        MIP_LAUNCH_CHECK();
+    }
+
+    // --- scaling: Ruiz passes, then one Pock-Chambolle pass
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.d_row, m, 1.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.d_col, n, 1.0);
+    MIP_LAUNCH_CHECK();
+    const int passes = o.ruiz_iters + (o.pock_chambolle ? 1 : 0);
+    for (int ps = 0; ps < passes; ++ps) {
+        const bool maxmode = ps < o.ruiz_iters;
+        if (maxmode) {
+            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+                               (const double*)w.d_row, (const double*)w.d_col, w.stat_r);
+            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col,
+                               lp.at_val, (const double*)w.d_col, (const double*)w.d_row, w.stat_c);
+        } else {
+            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+                               (const double*)w.d_row, (const double*)w.d_col, w.stat_r);
+            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col,
+                               lp.at_val, (const double*)w.d_col, (const double*)w.d_row, w.stat_c);
+        }
+        hipLaunchKernelGGL(k_scale_update, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.d_row,
+                           (const double*)w.stat_r, m);
+        hipLaunchKernelGGL(k_scale_update, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.d_col,
+                           (const double*)w.stat_c, n);
+        MIP_LAUNCH_CHECK();
+    }
+    // scaled values in the iteration precision, b~ and c~
+    hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(m * kWave, 4096)), dim3(kBlock), 0, stream, lp.a_rowptr,
+                       lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, lp.m, (V*)w.a_vs);
+    hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(n * kWave, 4096)), dim3(kBlock), 0, stream,
+                       lp.at_rowptr, lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.n,
+                       (V*)w.at_vs);
+    {
+        const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
+        hipLaunchKernelGGL((k_scale_vec<T>), dim3(gm), dim3(kBlock), 0, stream, lp.b, (const double*)w.d_row, m,
+                           (T*)w.bt, w.psetup);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gm, 1,
+                           w.red + 2);
+        hipLaunchKernelGGL((k_scale_vec<T>), dim3(gn), dim3(kBlock), 0, stream, lp.c, (const double*)w.d_col, n,
+                           (T*)w.ct, w.psetup + G);
+        hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream,
+                           (const double*)(w.psetup + G), gn, 1, w.red + 3);
+        MIP_LAUNCH_CHECK();
+    }
+
+    // --- power iteration for sigma_hat = ||D_r A D_c||_2
+    {
+        const double v0 = 1.0 / sqrt((double)n);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.pv, n, v0);
+        for (int k = 0; k <= o.power_iters; ++k) {
+            // av = A~ v, hist[k] = ||av||^2
+            hipLaunchKernelGGL(k_spmv_scaled, dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+                               (const double*)w.d_row, (const double*)w.d_col, (const double*)w.pv, w.pav,
+                               w.psetup);
+            hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gta, 1,
+                               w.hist + k);
+            if (k == o.power_iters) break;
+            // u = A~^T av, v = u / ||u||
+            hipLaunchKernelGGL(k_spmv_scaled, dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col, lp.at_val,
+                               (const double*)w.d_col, (const double*)w.d_row, (const double*)w.pav, w.pu,
+                               w.psetup + G);
+            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, 1024)), dim3(kBlock), 0, stream, (const double*)w.pu,
+                               w.pv, n, (const double*)(w.psetup + G), gtat);
+            MIP_LAUNCH_CHECK();
+        }
+        MIP_LAUNCH_CHECK();
+    }
+    std::vector<double> hist(o.power_iters + 1);
+    double red[4];
+    MIP_HIP(hipMemcpyAsync(hist.data(), w.hist, hist.size() * 8, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipMemcpyAsync(red, w.red, 4 * 8, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    bn2 = red[0];
+    cn2 = red[1];
+    for (auto& h : hist) h = sqrt(h);
+    const double sigma_hat = hist.back();
+    double eta;
+    if (sigma_hat <= 0.0) {
+        eta = o.step_safety;
+    } else if (o.pock_chambolle && hist.size() > 10 &&
+               fabs(hist.back() - hist[hist.size() - 11]) > 1e-3 * hist.back()) {
+        eta = o.step_safety;
+    } else {
+        eta = o.step_safety / sigma_hat;
+    }
+    const double nbt = sqrt(red[2]), nct = sqrt(red[3]);
+    const double omega0 = (nbt > 1e-10 && nct > 1e-10) ? nct / nbt : 1.0;
+
+    // --- control block and initial point
+    Ctrl c0;
+    memset(&c0, 0, sizeof(c0));
+    c0.omega = omega0;
+    c0.eta = eta;
+    c0.tau = eta / omega0;
+    c0.sigma = eta * omega0;
+    c0.k_base = 0;
+    c0.t_base = 0;
+    c0.status = ST_RUNNING;
+    c0.restart_now = 0;
+    c0.R0 = NAN;
+    c0.R_prev = INFINITY;
+    c0.eps = eps;
+    c0.b_norm = sqrt(bn2);
+    c0.c_norm = sqrt(cn2);
+    c0.beta_suff = o.beta_suff;
+    c0.beta_nec = o.beta_nec;
+    c0.beta_art = o.beta_art;
+    c0.pw_theta = o.pw_theta;
+    c0.max_iter = o.max_iter;
+    c0.do_restarts = o.restarts;
+    MIP_HIP(hipMemcpyAsync(w.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, o.x_init,
+                       (const double*)w.d_col, n, (T*)w.x, (T*)w.x0, (T*)w.xhat);
+    hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, o.y_init,
+                       (const double*)w.d_row, m, (T*)w.y, (T*)w.y0, (T*)w.yhat);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipStreamSynchronize(stream));
+    const auto t1 = clk::now();
+
+    // --- main loop
+    const int E = o.eval_every;
+    const bool trace = o.trace_iters > 0;
+    const bool graph = o.use_graph && !trace && !o.kernel_timing;
+    if (o.kernel_timing) {
+        S.timing = true;
+        S.tev.resize(3 * (size_t)E);
+        for (auto& e : S.tev) MIP_HIP(hipEventCreate(&e));
+    }
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t g = nullptr;
+    hipStream_t cap = nullptr;
+    if (graph && o.max_iter >= E) {
+        MIP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        S.stream = cap;
+        MIP_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        rc = S.enqueue_block(E, 1, false);
+        hipGraph_t gtmp = nullptr;
+        hipError_t ce = hipStreamEndCapture(cap, &gtmp);
+        S.stream = stream;
+        if (rc) {
+            if (gtmp) (void)hipGraphDestroy(gtmp);
+            (void)hipStreamDestroy(cap);
+            return rc;
+        }
+        if (ce != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            MIP_HIP(ce);
+        }
+        g = gtmp;
+        MIP_HIP(hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0));
+    }
+    // pinned ring of status words, one per block in flight
+    constexpr int kDepth = 3;
+    Ctrl* ring = nullptr;
+    MIP_HIP(hipHostMalloc((void**)&ring, sizeof(Ctrl) * kDepth, hipHostMallocDefault));
+    hipEvent_t ev[kDepth];
+    for (int i = 0; i < kDepth; ++i) MIP_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    int64_t launched = 0;
+    int64_t blocks = 0, checked = 0;
+    bool done = false, timed_out = false;
+    rc = 0;
+    while (!done && launched < o.max_iter) {
+        const int nit = (int)std::min<int64_t>(E, o.max_iter - launched);
+        if (gexec && nit == E) {
+            if (hipGraphLaunch(gexec, stream) != hipSuccess) {
+                set_error("hipGraphLaunch failed");
+                rc = MIPDHG_ERR_HIP;
+                break;
+            }
+        } else if ((rc = S.enqueue_block(nit, launched + 1, trace))) {
+            break;
+        }
+        launched += nit;
+        const int slot = (int)(blocks % kDepth);
+        if (hipMemcpyAsync(ring + slot, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipEventRecord(ev[slot], stream) != hipSuccess) {
+            set_error("status copy failed");
+            rc = MIPDHG_ERR_HIP;
+            break;
+        }
+        ++blocks;
+        // keep kDepth-1 blocks queued; look at the oldest one
+        while (checked < blocks && (blocks - checked >= kDepth || trace || S.timing || launched >= o.max_iter)) {
+            const int cs = (int)(checked % kDepth);
+            if (hipEventSynchronize(ev[cs]) != hipSuccess) {
+                set_error("hipEventSynchronize failed");
+                rc = MIPDHG_ERR_HIP;
+                done = true;
+                break;
+            }
+            ++checked;
+            if (ring[cs].status != ST_RUNNING) {
+                done = true;
+                break;
+            }
+        }
+        if (!done && o.time_limit_s < 1e300 &&
+            std::chrono::duration<double>(clk::now() - t0).count() > o.time_limit_s) {
+            timed_out = true;
+            break;
+        }
+    }
+    hipError_t se = hipStreamSynchronize(stream);
+    const auto t2 = clk::now();
+    for (int i = 0; i < kDepth; ++i) (void)hipEventDestroy(ev[i]);
+    (void)hipHostFree(ring);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (g) (void)hipGraphDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (rc) return rc;
+    MIP_HIP(se);
+
+    Ctrl cf;
+    MIP_HIP(hipMemcpy(&cf, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    int status = cf.status;
+    if (status == ST_RUNNING) status = timed_out ? MIPDHG_TIME_LIMIT : MIPDHG_ITER_LIMIT;
+    if (d_row) MIP_HIP(hipMemcpyAsync(d_row, w.d_row, m * 8, hipMemcpyDeviceToDevice, stream));
+    if (d_col) MIP_HIP(hipMemcpyAsync(d_col, w.d_col, n * 8, hipMemcpyDeviceToDevice, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    const auto t3 = clk::now();
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->status = status;
+        info->restarts = cf.restarts;
+        info->iters = cf.eval_t;
+        info->rp_norm = sqrt(cf.rp2);
+        info->rd_norm = sqrt(cf.rd2);
+        info->pobj = cf.pobj;
+        info->dobj = cf.dobj;
+        info->gap = fabs(cf.pobj - cf.dobj);
+        info->b_norm = c0.b_norm;
+        info->c_norm = c0.c_norm;
+        info->rel_rp = info->rp_norm / (1.0 + c0.b_norm);
+        info->rel_rd = info->rd_norm / (1.0 + c0.c_norm);
+        info->rel_gap = info->gap / (1.0 + fabs(cf.pobj) + fabs(cf.dobj));
+        info->rp_inf = cf.rp_inf;
+        info->rd_inf = cf.rd_inf;
+        info->xz = cf.xz;
+        info->max_violation = std::max(std::max(cf.rp_inf, cf.rd_inf), cf.xz / (1.0 + fabs(cf.pobj)));
+        info->sigma_hat = sigma_hat;
+        info->eta = eta;
+        info->omega0 = omega0;
+        info->omega = cf.omega;
+        info->ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info->ms_iter = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        info->ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
+        const double vs = sizeof(V), ts = sizeof(T);
+        // per iteration: A and A^T values + indices, row pointers, gathers,
+        // streamed vectors (x, x0, c~, x_bar written; y, y0, b~)
+        info->bytes_primal = nnz * (vs + 4.0) + 4.0 * (n + 1) + ts * (double)m + 5.0 * ts * n;
+        info->bytes_dual = nnz * (vs + 4.0) + 4.0 * (m + 1) + ts * (double)n + 4.0 * ts * m;
+        info->bytes_per_iter = info->bytes_primal + info->bytes_dual;
+        info->ms_primal = S.n_p ? S.ms_p / S.n_p : 0.0;
+        info->ms_dual = S.n_d ? S.ms_d / S.n_d : 0.0;
+        info->n_primal = S.n_p;
+        info->n_dual = S.n_d;
+        info->lanes_a = S.hpa.lanes;
+        info->lanes_at = S.hpat.lanes;
+        info->long_a = (int32_t)S.hpa.long_rows.size();
+        info->long_at = (int32_t)S.hpat.long_rows.size();
+    }
+    return status;
+}
+
+}  // namespace mip
+
+extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, double eps_rel, void* workspace,
+                            size_t workspace_bytes, void* stream, double* x, double* y, double* z, double* r_p,
+                            double* r_d, double* d_row, double* d_col, mipdhg_info* info) {
+    clear_error();
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (!opt) return set_error("options are NULL"), MIPDHG_ERR_INVALID_ARG;
+    if ((rc = check_options(opt))) return rc;
+    if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
+    if (!workspace || !x || !y || !z || !r_p || !r_d) return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    switch (opt->precision) {
+        case MIPDHG_FP64:
+            return solve_impl<double, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
+                                              d_row, d_col, info);
+        case MIPDHG_FP32:
+            return solve_impl<float, float>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
+                                            d_row, d_col, info);
+        default:
+            return solve_impl<float, uint16_t>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                               r_d, d_row, d_col, info);
+    }
+}

@@ -1,0 +1,137 @@
+"""Python face of the plain solve: device buffers from torch, then one C call.
+
+Nothing here computes any part of the method; it allocates outputs and the
+workspace with torch and passes raw device pointers and the current stream to
+libmipdhg.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _dev_tensor(a, dtype, device) -> torch.Tensor:
+    t = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype)
+    return t.to(device)
+
+
+class DeviceLP:
+    """A standard-form LP held in device memory: A and A^T in CSR (int32
+    indices, float64 values), b and c in float64."""
+
+    def __init__(self, A, AT, b, c, device: str | torch.device = "cuda"):
+        m, n = A.shape
+        if AT.shape != (n, m):
+            raise ValueError("AT must be n x m")
+        self.m, self.n, self.nnz = int(m), int(n), int(A.nnz)
+        self.device = torch.device(device)
+        d = self.device
+        self.a_rowptr = _dev_tensor(A.indptr, torch.int32, d)
+        self.a_col = _dev_tensor(A.indices, torch.int32, d)
+        self.a_val = _dev_tensor(A.data, torch.float64, d)
+        self.at_rowptr = _dev_tensor(AT.indptr, torch.int32, d)
+        self.at_col = _dev_tensor(AT.indices, torch.int32, d)
+        self.at_val = _dev_tensor(AT.data, torch.float64, d)
+        self.b = _dev_tensor(b, torch.float64, d)
+        self.c = _dev_tensor(c, torch.float64, d)
+
+    @classmethod
+    def from_lp(cls, lp, device="cuda") -> "DeviceLP":
+        return cls(lp.A, lp.AT, lp.b, lp.c, device)
+
+    def struct(self) -> _lib.LPStruct:
+        s = _lib.LPStruct()
+        s.m, s.n, s.nnz = self.m, self.n, self.nnz
+        for name in ("a_rowptr", "a_col", "a_val", "at_rowptr", "at_col", "at_val", "b", "c"):
+            setattr(s, name, getattr(self, name).data_ptr())
+        return s
+
+
+def default_options() -> dict:
+    lib = _lib.load()
+    o = _lib.OptionsStruct()
+    lib.mipdhg_default_options(C.byref(o))
+    return {k: getattr(o, k) for k, _ in _lib.OptionsStruct._fields_
+            if not k.startswith("trace_") and k not in ("x_init", "y_init")}
+
+
+def make_options(precision: str = "fp64", **kw) -> _lib.OptionsStruct:
+    lib = _lib.load()
+    o = _lib.OptionsStruct()
+    lib.mipdhg_default_options(C.byref(o))
+    o.precision = _lib.PRECISION[precision]
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Solution:
+    status: int
+    status_name: str
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    r_p: torch.Tensor
+    r_d: torch.Tensor
+    d_row: torch.Tensor
+    d_col: torch.Tensor
+    info: dict
+    trace: dict = field(default_factory=dict)
+
+
+def workspace_bytes(dlp: DeviceLP, precision: str = "fp64", **opts) -> int:
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_workspace_size(C.byref(dlp.struct()), C.byref(o), C.byref(nb)))
+    return int(nb.value)
+
+
+def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters: int = 0,
+          x_init: torch.Tensor | None = None, y_init: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None, **opts) -> Solution:
+    """Run mipdhg_solve on dlp.  Options are the fields of mipdhg_options."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    d = dlp.device
+    f64 = dict(dtype=torch.float64, device=d)
+    trace = {}
+    if trace_iters:
+        o.trace_iters = int(trace_iters)
+        for key, size in (("x", dlp.n), ("y", dlp.m), ("xhat", dlp.n), ("yhat", dlp.m)):
+            trace[key] = torch.zeros((trace_iters, size), **f64)
+            setattr(o, "trace_" + key, trace[key].data_ptr())
+    if x_init is not None:
+        x_init = x_init.to(**f64).contiguous()
+        o.x_init = x_init.data_ptr()
+    if y_init is not None:
+        y_init = y_init.to(**f64).contiguous()
+        o.y_init = y_init.data_ptr()
+    lps = dlp.struct()
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_workspace_size(C.byref(lps), C.byref(o), C.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    x = torch.empty(dlp.n, **f64)
+    y = torch.empty(dlp.m, **f64)
+    z = torch.empty(dlp.n, **f64)
+    r_p = torch.empty(dlp.m, **f64)
+    r_d = torch.empty(dlp.n, **f64)
+    d_row = torch.empty(dlp.m, **f64)
+    d_col = torch.empty(dlp.n, **f64)
+    info = _lib.InfoStruct()
+    stream = torch.cuda.current_stream(d).cuda_stream
+    rc = lib.mipdhg_solve(C.byref(lps), C.byref(o), float(eps), workspace.data_ptr(), workspace.numel(),
+                          stream, x.data_ptr(), y.data_ptr(), z.data_ptr(), r_p.data_ptr(), r_d.data_ptr(),
+                          d_row.data_ptr(), d_col.data_ptr(), C.byref(info))
+    _lib.check(rc)
+    return Solution(rc, lib.mipdhg_status_string(rc).decode(), x, y, z, r_p, r_d, d_row, d_col,
+                    info.as_dict(), trace)
