@@ -159,8 +159,71 @@ int mipdhg_solve(const mipdhg_lp *lp, const mipdhg_options *opt, double eps_rel,
                  double *x, double *y, double *z, double *r_p, double *r_d,
                  double *d_row, double *d_col, mipdhg_info *info);
 
+/* Many independent LPs, stacked as the diagonal blocks of one block-diagonal
+ * LP: instance i owns rows [row_off[i], row_off[i+1]), columns
+ * [col_off[i], col_off[i+1]) and nonzeros [nnz_off[i], nnz_off[i+1]) of both
+ * A and A^T, whose column indices are global (block-diagonal).  The offset
+ * arrays are HOST arrays of count+1 entries starting at 0 and ending at m, n,
+ * nnz of `whole`; every instance has at least one row and one column. */
+typedef struct mipdhg_batch {
+    int32_t count;
+    const int32_t *row_off;  /* host [count+1] */
+    const int32_t *col_off;  /* host [count+1] */
+    const int64_t *nnz_off;  /* host [count+1] */
+    mipdhg_lp whole;         /* device arrays of the block-diagonal LP */
+} mipdhg_batch;
+
+/* Bytes of device workspace mipdhg_solve_batched needs. */
+int mipdhg_batch_workspace_size(const mipdhg_batch *batch, const mipdhg_options *opt, size_t *bytes);
+
+/* Solve every instance of the batch to eps_rel (the Section 2 tests, each
+ * instance on its own norms), in one persistent kernel launch: one workgroup
+ * per instance at a time, instances taken largest first from a queue, each
+ * with its own scaling, step, primal weight, restarts and termination.
+ * Outputs are the stacked per-instance vectors (device float64, same layout as
+ * the rows/columns of `whole`): x[n], y[m], z[n], r_p[m], r_d[n].  info
+ * (nullable) is a HOST array of `count` reports.  The return value is the
+ * largest status over the instances (0 when all are OPTIMAL) or an error.
+ * An instance needs (m_i + n_i) * sizeof(iterate) bytes of LDS, at most
+ * 150 KiB; larger instances return MIPDHG_ERR_UNSUPPORTED.  Tracing, warm
+ * starts and kernel timing are not available here. */
+int mipdhg_solve_batched(const mipdhg_batch *batch, const mipdhg_options *opt, double eps_rel,
+                         void *workspace, size_t workspace_bytes, void *stream,
+                         double *x, double *y, double *z, double *r_p, double *r_d,
+                         mipdhg_info *info);
+
+/* ---- Differentiable unrolled PDHG (batched) ------------------------------
+ * x_K(c, b): exactly K iterations of the solve's PDHG from (0, 0) on every
+ * instance of `batch` (no termination test), x_K = D_c x_hat of iteration K
+ * in the original space.  Restarts are decided by the usual rule at every
+ * eval_every-th iteration and, with the per-epoch steps, recorded on the tape;
+ * they are constants of the map, which is then piecewise linear in (c, b).
+ * The tape (device, caller-owned, >= mipdhg_unrolled_tape_size bytes, 256-byte
+ * aligned) also holds the scaling, the scaled values and a checkpoint of the
+ * state every ckpt_every iterations; the backward pass recomputes each
+ * checkpoint segment and sweeps it in reverse (the adjoint of the iteration
+ * map, with the projection masks of the recomputed iterations).  b and c are
+ * batch->whole.b / .c.  Instances must fit in LDS as for the batched solve. */
+int mipdhg_unrolled_tape_size(const mipdhg_batch *batch, const mipdhg_options *opt, int32_t K,
+                              int32_t ckpt_every, size_t *bytes);
+
+/* Forward pass; writes x_K (device float64 [n]).  replay = 1 re-runs the map
+ * with the restart schedule and steps already on the tape (for finite
+ * differences of the frozen map) instead of deciding them. */
+int mipdhg_unrolled_forward(const mipdhg_batch *batch, const mipdhg_options *opt, int32_t K,
+                            int32_t ckpt_every, int32_t replay, void *tape, size_t tape_bytes,
+                            void *stream, double *x_K);
+
+/* Backward pass for a loss L with dL/dx_K = grad_xK (device float64 [n]):
+ * writes dL/dc (device float64 [n]) and dL/db ([m]).  Needs the tape of the
+ * forward pass with the same batch, options, K and ckpt_every. */
+int mipdhg_unrolled_backward(const mipdhg_batch *batch, const mipdhg_options *opt, int32_t K,
+                             int32_t ckpt_every, void *tape, size_t tape_bytes, const double *grad_xK,
+                             void *stream, double *grad_c, double *grad_b);
+
 /* sizeof of the public structs, for bindings that mirror them:
- * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info; 0 for anything else. */
+ * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info, 3 mipdhg_batch;
+ * 0 for anything else. */
 size_t mipdhg_sizeof(int which);
 
 /* Text for a status or error code. */

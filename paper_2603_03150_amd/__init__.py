@@ -3,4 +3,8 @@ include/mipdhg.h.  The Python layer only marshals device pointers."""
 from ._lib import (  # noqa: F401
     OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, MipdhgError, load,
 )
-from .solver import DeviceLP, Solution, default_options, make_options, solve, workspace_bytes  # noqa: F401
+from .solver import (  # noqa: F401
+    BatchSolution, DeviceBatch, DeviceLP, Solution, batch_workspace_bytes, default_options, make_options,
+    solve, solve_batched, workspace_bytes,
+)
+from .unrolled import PDHGUnrolled, UnrolledMap  # noqa: F401

@@ -59,12 +59,26 @@ class InfoStruct(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchStruct(C.Structure):
+    _fields_ = [("count", _i32), ("row_off", _p), ("col_off", _p), ("nnz_off", _p), ("whole", LPStruct)]
+
+
 # every symbol include/mipdhg.h declares, with its ctypes signature
 SIGNATURES = {
     "mipdhg_default_options": (None, [C.POINTER(OptionsStruct)]),
     "mipdhg_workspace_size": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), C.POINTER(C.c_size_t)]),
     "mipdhg_solve": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _f64, _p, C.c_size_t, _p,
                                _p, _p, _p, _p, _p, _p, _p, C.POINTER(InfoStruct)]),
+    "mipdhg_batch_workspace_size": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct),
+                                              C.POINTER(C.c_size_t)]),
+    "mipdhg_solve_batched": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _f64, _p, C.c_size_t,
+                                       _p, _p, _p, _p, _p, _p, _p]),
+    "mipdhg_unrolled_tape_size": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32,
+                                            C.POINTER(C.c_size_t)]),
+    "mipdhg_unrolled_forward": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32, _i32,
+                                          _p, C.c_size_t, _p, _p]),
+    "mipdhg_unrolled_backward": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32, _p,
+                                           C.c_size_t, _p, _p, _p, _p]),
     "mipdhg_sizeof": (C.c_size_t, [C.c_int]),
     "mipdhg_status_string": (C.c_char_p, [C.c_int]),
     "mipdhg_last_error": (C.c_char_p, []),
@@ -97,7 +111,7 @@ def load() -> C.CDLL:
     rts = _hip_runtimes()
     if len(rts) > 1:
         raise RuntimeError(f"two HIP runtimes are loaded ({sorted(rts)}); import torch first")
-    for which, cls in ((0, LPStruct), (1, OptionsStruct), (2, InfoStruct)):
+    for which, cls in ((0, LPStruct), (1, OptionsStruct), (2, InfoStruct), (3, BatchStruct)):
         if lib.mipdhg_sizeof(which) != C.sizeof(cls):
             raise RuntimeError(f"ABI mismatch for {cls.__name__}")
     _LIB = lib

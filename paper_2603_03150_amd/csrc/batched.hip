@@ -1,0 +1,553 @@
+// Many independent LPs in one persistent launch.
+//
+// The instances are the diagonal blocks of one block-diagonal CSR pair.  Each
+// workgroup takes instances from an atomic queue (largest first) and runs the
+// whole method of the single solve on its instance: scaling, power iteration,
+// the PDHG iterations, float64 evaluations on the original block and the
+// restart / primal-weight rule, with __syncthreads() as the only phase barrier.
+// The dual iterate y and the extrapolated primal x_bar, the two vectors the
+// SpMVs gather from, live in LDS; everything else stays in L2-resident global
+// memory.  Each thread owns fixed rows and columns of its instance, and every
+// reduction is a fixed-order workgroup reduction whose result every thread
+// holds, so all threads take the same decisions without a broadcast and the
+// results do not depend on which workgroup ran the instance.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+#include "inst_common.h"
+#include "plain.h"
+
+namespace mip {
+
+struct BInst {  // per-instance result, device side
+    int32_t status, restarts;
+    int64_t iters;
+    double rp2, rd2, pobj, dobj, xz, rp_inf, rd_inf;
+    double b_norm, c_norm, sigma_hat, eta, omega0, omega;
+};
+
+template <typename T, typename V>
+struct BArgs {
+    int32_t B;
+    int32_t lds_m, lds_n;
+    const int32_t* order;
+    const int32_t* row_off;
+    const int32_t* col_off;
+    const int32_t *a_rowptr, *a_col;
+    const double* a_val;
+    const int32_t *at_rowptr, *at_col;
+    const double* at_val;
+    const double *b, *c;
+    V *a_vs, *at_vs;
+    T *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
+    double *d_row, *d_col, *pv, *pu, *pav;
+    double *xo, *yo, *zo, *rpo, *rdo;
+    BInst* info;
+    int32_t* counter;
+    double eps, step_safety, rho, beta_suff, beta_nec, beta_art, theta;
+    int64_t max_iter;
+    int32_t ruiz, pc, power_iters, eval_every, halpern, restarts;
+};
+
+template <typename T, typename V>
+__device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, double* sh) {
+    const int tid = threadIdx.x;
+    const int r0 = a.row_off[inst], r1 = a.row_off[inst + 1];
+    const int c0 = a.col_off[inst], c1 = a.col_off[inst + 1];
+    const int m = r1 - r0, n = c1 - c0;
+    double nomax[1] = {0.0};
+    const InstMat M{a.a_rowptr, a.a_col, a.a_val, a.at_rowptr, a.at_col, a.at_val, a.b, a.c};
+    const InstSetup su = inst_setup<T, V>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs, a.at_vs,
+                                          a.bt, a.ct, a.ruiz, a.pc, a.power_iters, a.step_safety, sh);
+    const double b_norm = su.b_norm, c_norm = su.c_norm, sigma_hat = su.sigma_hat, eta = su.eta,
+                 omega0 = su.omega0;
+    double omega = omega0, tau = eta / omega, sig = eta * omega;
+
+    // initial point (0, 0)
+    for (int j = tid; j < n; j += kBatchBlock) {
+        a.x[c0 + j] = (T)0;
+        a.x0[c0 + j] = (T)0;
+    }
+    for (int i = tid; i < m; i += kBatchBlock) {
+        yL[i] = (T)0;
+        a.y0[r0 + i] = (T)0;
+    }
+    __syncthreads();
+
+    const T rho = (T)a.rho, opr = (T)(1.0 + a.rho);
+    const int E = a.eval_every;
+    int64_t k = 0;
+    double R0 = NAN, R_prev = INFINITY;
+    int restarts = 0;
+    int status = -1;
+    int64_t t = 0;
+    double ev[5], evm[2];
+    while (status < 0) {
+        ++t;
+        const bool is_eval = (t % E == 0) || (t == a.max_iter);
+        const bool first = (k == 0);
+        const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
+        const T w = (T)w64, omw = (T)(1.0 - w64), st = (T)tau, sd = (T)sig;
+        double q[4] = {0.0, 0.0, 0.0, 0.0};
+        // primal step over the columns (rows of A^T)
+        for (int j = tid; j < n; j += kBatchBlock) {
+            const int g = c0 + j;
+            typename ValueOf<V>::acc s = 0;
+            for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz)
+                s += ld_val(a.at_vs, kz) * yL[a.at_col[kz] - r0];
+            const T o = a.x[g];
+            T hh = o - st * (a.ct[g] - (T)s);
+            hh = hh < (T)0 ? (T)0 : hh;
+            xbL[j] = (T)2 * hh - o;
+            const T an = a.x0[g];
+            a.x[g] = w * (opr * hh - rho * o) + omw * an;
+            if (first || is_eval) {
+                const double d = (double)o - (double)hh;
+                q[0] += d * d;
+            }
+            if (is_eval) {
+                const double d = (double)hh - (double)an;
+                q[1] += d * d;
+                a.xhat[g] = hh;
+                a.xo[g] = a.d_col[g] * (double)hh;
+            }
+        }
+        __syncthreads();
+        // dual step over the rows of A
+        for (int i = tid; i < m; i += kBatchBlock) {
+            const int g = r0 + i;
+            typename ValueOf<V>::acc s = 0;
+            for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz)
+                s += ld_val(a.a_vs, kz) * xbL[a.a_col[kz] - c0];
+            const T o = yL[i];
+            const T hh = o + sd * (a.bt[g] - (T)s);
+            const T an = a.y0[g];
+            yL[i] = w * (opr * hh - rho * o) + omw * an;
+            if (first || is_eval) {
+                const double d = (double)o - (double)hh;
+                q[2] += d * d;
+            }
+            if (is_eval) {
+                const double d = (double)hh - (double)an;
+                q[3] += d * d;
+                a.yhat[g] = hh;
+                a.yo[g] = a.d_row[g] * (double)hh;
+            }
+        }
+        __syncthreads();
+        if (!(first || is_eval)) {
+            ++k;
+            continue;
+        }
+        wg_reduce<4, 0>(q, nomax, sh);
+        if (first) R0 = sqrt(omega * q[0] + q[2] / omega);
+        ++k;
+        if (!is_eval) continue;
+        const double R = sqrt(omega * q[0] + q[2] / omega);
+        // evaluation on the original block, float64
+        for (int q5 = 0; q5 < 5; ++q5) ev[q5] = 0.0;
+        evm[0] = evm[1] = 0.0;
+        for (int i = tid; i < m; i += kBatchBlock) {
+            const int g = r0 + i;
+            double s = 0.0;
+            for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz) s += a.a_val[kz] * a.xo[a.a_col[kz]];
+            const double rp = a.b[g] - s;
+            a.rpo[g] = rp;
+            ev[0] += rp * rp;
+            ev[1] += a.b[g] * a.yo[g];
+            evm[0] = fmax(evm[0], fabs(rp));
+        }
+        for (int j = tid; j < n; j += kBatchBlock) {
+            const int g = c0 + j;
+            double s = 0.0;
+            for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz) s += a.at_val[kz] * a.yo[a.at_col[kz]];
+            const double gg = a.c[g] - s;
+            const double z = gg > 0.0 ? gg : 0.0;
+            const double rd = gg - z;
+            a.zo[g] = z;
+            a.rdo[g] = rd;
+            const double xv = a.xo[g];
+            ev[2] += rd * rd;
+            ev[3] += a.c[g] * xv;
+            ev[4] += xv * z;
+            evm[1] = fmax(evm[1], fabs(rd));
+        }
+        wg_reduce<5, 2>(ev, evm, sh);
+        const double rp = sqrt(ev[0]), rd = sqrt(ev[2]), pobj = ev[3], dobj = ev[1];
+        const double gap = fabs(pobj - dobj);
+        if (!(isfinite(ev[0]) && isfinite(ev[2]) && isfinite(pobj) && isfinite(dobj))) status = MIPDHG_NUMERICAL;
+        else if (rp <= a.eps * (1.0 + b_norm) && rd <= a.eps * (1.0 + c_norm) &&
+                 gap <= a.eps * (1.0 + fabs(pobj) + fabs(dobj)))
+            status = MIPDHG_OPTIMAL;
+        else if (t >= a.max_iter) status = MIPDHG_ITER_LIMIT;
+        if (status >= 0) break;
+        bool restart = false;
+        if (a.restarts)
+            restart = (R <= a.beta_suff * R0) || (R <= a.beta_nec * R0 && R > R_prev) ||
+                      ((double)k >= a.beta_art * (double)t);
+        if (restart) {
+            const double dx = sqrt(q[1]), dy = sqrt(q[3]);
+            if (dx > 1e-10 && dy > 1e-10) {
+                omega = exp(a.theta * log(dy / dx) + (1.0 - a.theta) * log(omega));
+                tau = eta / omega;
+                sig = eta * omega;
+            }
+            for (int j = tid; j < n; j += kBatchBlock) {
+                const T v = a.xhat[c0 + j];
+                a.x[c0 + j] = v;
+                a.x0[c0 + j] = v;
+            }
+            for (int i = tid; i < m; i += kBatchBlock) {
+                const T v = a.yhat[r0 + i];
+                yL[i] = v;
+                a.y0[r0 + i] = v;
+            }
+            k = 0;
+            R_prev = INFINITY;
+            ++restarts;
+            __syncthreads();
+        } else {
+            R_prev = R;
+        }
+    }
+    if (tid == 0) {
+        BInst& r = a.info[inst];
+        r.status = status;
+        r.restarts = restarts;
+        r.iters = t;
+        r.rp2 = ev[0];
+        r.rd2 = ev[2];
+        r.pobj = ev[3];
+        r.dobj = ev[1];
+        r.xz = ev[4];
+        r.rp_inf = evm[0];
+        r.rd_inf = evm[1];
+        r.b_norm = b_norm;
+        r.c_norm = c_norm;
+        r.sigma_hat = sigma_hat;
+        r.eta = eta;
+        r.omega0 = omega0;
+        r.omega = omega;
+    }
+    __syncthreads();
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kBatchBlock) void k_batched(BArgs<T, V> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* yL = (T*)smem;
+    T* xbL = yL + a.lds_m;
+    __shared__ double sh[8 * (kBatchBlock / kWave)];
+    __shared__ int next;
+    while (true) {
+        if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int qi = next;
+        __syncthreads();
+        if (qi >= a.B) break;  // uniform: every wave leaves once the queue is empty
+        solve_instance<T, V>(a, a.order[qi], yL, xbL, sh);
+    }
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// block-diagonal structure: every entry of instance i's rows lies in its columns
+__global__ void k_check_blockdiag(const int32_t* rowptr, const int32_t* col, const int32_t* row_off,
+                                  const int32_t* col_off, int B, int32_t nrows, int32_t* flags) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = B;  // instance: row_off[lo] <= r < row_off[lo+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (row_off[mid] <= r) lo = mid;
+            else hi = mid;
+        }
+        const int c0 = col_off[lo], c1 = col_off[lo + 1];
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+            if (col[k] < c0 || col[k] >= c1) {
+                atomicOr(flags, 8);
+                break;
+            }
+    }
+}
+
+struct BatchWs {
+    int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
+    BInst* info;
+    double *d_row, *d_col, *pv, *pu, *pav, *partials, *red;
+    void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
+    size_t bytes;
+};
+
+static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t n, int64_t nnz, int prec) {
+    Carver cv(base, cap);
+    BatchWs w;
+    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32 ? 4 : 2);
+    const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
+    w.order = cv.take<int32_t>(B);
+    w.row_off = cv.take<int32_t>(B + 1);
+    w.col_off = cv.take<int32_t>(B + 1);
+    w.counter = cv.take<int32_t>(64);
+    w.flags = cv.take<int32_t>(64);
+    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz) + 1);
+    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz) + 1);
+    w.info = cv.take<BInst>(B);
+    w.d_row = cv.take<double>(m);
+    w.d_col = cv.take<double>(n);
+    w.pv = cv.take<double>(n);
+    w.pu = cv.take<double>(n);
+    w.pav = cv.take<double>(m);
+    w.partials = cv.take<double>((size_t)std::max(max_tiles(m, nnz), max_tiles(n, nnz)) + 16);
+    w.red = cv.take<double>(16);
+    w.a_vs = cv.take<char>(nnz * vs);
+    w.at_vs = cv.take<char>(nnz * vs);
+    w.x = cv.take<char>(n * ts);
+    w.x0 = cv.take<char>(n * ts);
+    w.xhat = cv.take<char>(n * ts);
+    w.ct = cv.take<char>(n * ts);
+    w.y0 = cv.take<char>(m * ts);
+    w.yhat = cv.take<char>(m * ts);
+    w.bt = cv.take<char>(m * ts);
+    w.bytes = (cv.off + 255) & ~size_t(255);
+    return w;
+}
+
+static int check_batch(const mipdhg_batch* bt) {
+    if (!bt) return set_error("batch is NULL"), MIPDHG_ERR_INVALID_ARG;
+    if (bt->count < 1) return set_error("batch count must be >= 1"), MIPDHG_ERR_INVALID_ARG;
+    if (!bt->row_off || !bt->col_off || !bt->nnz_off)
+        return set_error("row_off, col_off and nnz_off are required"), MIPDHG_ERR_INVALID_ARG;
+    int rc = check_lp(&bt->whole);
+    if (rc) return rc;
+    const int B = bt->count;
+    if (bt->row_off[0] != 0 || bt->col_off[0] != 0 || bt->nnz_off[0] != 0 || bt->row_off[B] != bt->whole.m ||
+        bt->col_off[B] != bt->whole.n || bt->nnz_off[B] != bt->whole.nnz)
+        return set_error("instance offsets must start at 0 and end at m, n, nnz"), MIPDHG_ERR_INVALID_ARG;
+    for (int i = 0; i < B; ++i)
+        if (bt->row_off[i + 1] <= bt->row_off[i] || bt->col_off[i + 1] <= bt->col_off[i] ||
+            bt->nnz_off[i + 1] < bt->nnz_off[i])
+            return set_error("instance %d is empty or its offsets decrease", i), MIPDHG_ERR_INVALID_ARG;
+    return 0;
+}
+
+static int lds_bytes_for(int max_m, int max_n, size_t ts) {
+    return (int)(((size_t)max_m + (size_t)max_n) * ts + 16);
+}
+
+template <typename T, typename V>
+static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double eps, void* ws, size_t ws_bytes,
+                        hipStream_t stream, double* x, double* y, double* z, double* r_p, double* r_d,
+                        mipdhg_info* info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const mipdhg_lp& lp = bt.whole;
+    const int B = bt.count;
+    BatchWs w = carve_batch(ws, ws_bytes, B, lp.m, lp.n, lp.nnz, o.precision);
+    if (w.bytes > ws_bytes)
+        return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, w.bytes), MIPDHG_ERR_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
+    int max_m = 0, max_n = 0;
+    for (int i = 0; i < B; ++i) {
+        max_m = std::max(max_m, bt.row_off[i + 1] - bt.row_off[i]);
+        max_n = std::max(max_n, bt.col_off[i + 1] - bt.col_off[i]);
+    }
+    const int lds = lds_bytes_for(max_m, max_n, sizeof(T));
+    if (lds > 150 * 1024)
+        return set_error("largest instance needs %d bytes of LDS (limit 150 KiB): m + n too large", lds),
+               MIPDHG_ERR_UNSUPPORTED;
+    // host checks of the row pointers against the instance offsets
+    std::vector<int32_t> rpa(lp.m + 1), rpat(lp.n + 1);
+    MIP_HIP(hipMemcpyAsync(rpa.data(), lp.a_rowptr, (lp.m + 1) * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipMemcpyAsync(rpat.data(), lp.at_rowptr, (lp.n + 1) * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    int rc;
+    if ((rc = check_rowptr(rpa, lp.m, lp.nnz, "A"))) return rc;
+    if ((rc = check_rowptr(rpat, lp.n, lp.nnz, "A^T"))) return rc;
+    for (int i = 0; i <= B; ++i)
+        if (rpa[bt.row_off[i]] != bt.nnz_off[i] || rpat[bt.col_off[i]] != bt.nnz_off[i])
+            return set_error("nnz_off does not match the row pointers at instance %d", i), MIPDHG_ERR_BAD_CSR;
+    // largest instances first
+    std::vector<int32_t> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
+        return bt.nnz_off[p + 1] - bt.nnz_off[p] > bt.nnz_off[q + 1] - bt.nnz_off[q];
+    });
+    MIP_HIP(hipMemcpyAsync(w.order, order.data(), B * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
+    if (o.validate) {
+        const std::vector<int32_t> ta = make_tiles(rpa, lp.m), tat = make_tiles(rpat, lp.n);
+        MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
+        MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
+        const TilePlan pa{lp.a_rowptr, w.tiles_a, (int32_t)ta.size() - 1, lp.m};
+        const TilePlan pat{lp.at_rowptr, w.tiles_at, (int32_t)tat.size() - 1, lp.n};
+        if ((rc = validate_device(lp, pa, pat, w.flags, w.partials, w.red, stream))) return rc;
+        MIP_HIP(hipMemsetAsync(w.flags, 0, 4, stream));
+        hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.a_rowptr, lp.a_col,
+                           (const int32_t*)w.row_off, (const int32_t*)w.col_off, B, lp.m, w.flags);
+        hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.at_rowptr,
+                           lp.at_col, (const int32_t*)w.col_off, (const int32_t*)w.row_off, B, lp.n, w.flags);
+        MIP_LAUNCH_CHECK();
+        int32_t f = 0;
+        MIP_HIP(hipMemcpyAsync(&f, w.flags, 4, hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        if (f & 8) return set_error("an entry lies outside its instance's diagonal block"), MIPDHG_ERR_BAD_CSR;
+    }
+    BArgs<T, V> a;
+    a.B = B;
+    a.lds_m = max_m;
+    a.lds_n = max_n;
+    a.order = w.order;
+    a.row_off = w.row_off;
+    a.col_off = w.col_off;
+    a.a_rowptr = lp.a_rowptr;
+    a.a_col = lp.a_col;
+    a.a_val = lp.a_val;
+    a.at_rowptr = lp.at_rowptr;
+    a.at_col = lp.at_col;
+    a.at_val = lp.at_val;
+    a.b = lp.b;
+    a.c = lp.c;
+    a.a_vs = (V*)w.a_vs;
+    a.at_vs = (V*)w.at_vs;
+    a.x = (T*)w.x;
+    a.x0 = (T*)w.x0;
+    a.xhat = (T*)w.xhat;
+    a.ct = (T*)w.ct;
+    a.y0 = (T*)w.y0;
+    a.yhat = (T*)w.yhat;
+    a.bt = (T*)w.bt;
+    a.d_row = w.d_row;
+    a.d_col = w.d_col;
+    a.pv = w.pv;
+    a.pu = w.pu;
+    a.pav = w.pav;
+    a.xo = x;
+    a.yo = y;
+    a.zo = z;
+    a.rpo = r_p;
+    a.rdo = r_d;
+    a.info = w.info;
+    a.counter = w.counter;
+    a.eps = eps;
+    a.step_safety = o.step_safety;
+    a.rho = o.reflect_rho;
+    a.beta_suff = o.beta_suff;
+    a.beta_nec = o.beta_nec;
+    a.beta_art = o.beta_art;
+    a.theta = o.pw_theta;
+    a.max_iter = o.max_iter;
+    a.ruiz = o.ruiz_iters;
+    a.pc = o.pock_chambolle;
+    a.power_iters = o.power_iters;
+    a.eval_every = o.eval_every;
+    a.halpern = o.halpern;
+    a.restarts = o.restarts;
+    // persistent grid: as many workgroups as fit, never more than instances
+    int dev = 0, cus = 256, per_cu = 1;
+    MIP_HIP(hipGetDevice(&dev));
+    MIP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MIP_HIP(hipFuncSetAttribute((const void*)k_batched<T, V>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V>, kBatchBlock, lds));
+    const int grid = std::max(1, std::min(B, cus * std::max(per_cu, 1)));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, w.counter, 64);
+    const auto t1 = clk::now();
+    hipEvent_t e0, e1;
+    MIP_HIP(hipEventCreate(&e0));
+    MIP_HIP(hipEventCreate(&e1));
+    MIP_HIP(hipEventRecord(e0, stream));
+    hipLaunchKernelGGL((k_batched<T, V>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipEventRecord(e1, stream));
+    std::vector<BInst> res(B);
+    MIP_HIP(hipMemcpyAsync(res.data(), w.info, sizeof(BInst) * B, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    float kms = 0.f;
+    MIP_HIP(hipEventElapsedTime(&kms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const auto t2 = clk::now();
+    int worst = MIPDHG_OPTIMAL;
+    for (int i = 0; i < B; ++i) worst = std::max(worst, res[i].status);
+    if (info) {
+        for (int i = 0; i < B; ++i) {
+            const BInst& r = res[i];
+            mipdhg_info& f = info[i];
+            memset(&f, 0, sizeof(f));
+            f.status = r.status;
+            f.restarts = r.restarts;
+            f.iters = r.iters;
+            f.rp_norm = sqrt(r.rp2);
+            f.rd_norm = sqrt(r.rd2);
+            f.pobj = r.pobj;
+            f.dobj = r.dobj;
+            f.gap = fabs(r.pobj - r.dobj);
+            f.b_norm = r.b_norm;
+            f.c_norm = r.c_norm;
+            f.rel_rp = f.rp_norm / (1.0 + r.b_norm);
+            f.rel_rd = f.rd_norm / (1.0 + r.c_norm);
+            f.rel_gap = f.gap / (1.0 + fabs(r.pobj) + fabs(r.dobj));
+            f.rp_inf = r.rp_inf;
+            f.rd_inf = r.rd_inf;
+            f.xz = r.xz;
+            f.max_violation = std::max(std::max(r.rp_inf, r.rd_inf), r.xz / (1.0 + fabs(r.pobj)));
+            f.sigma_hat = r.sigma_hat;
+            f.eta = r.eta;
+            f.omega0 = r.omega0;
+            f.omega = r.omega;
+            f.ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            f.ms_iter = kms;
+            f.ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
+        }
+    }
+    return worst;
+}
+
+}  // namespace mip
+
+using namespace mip;
+
+extern "C" int mipdhg_batch_workspace_size(const mipdhg_batch* bt, const mipdhg_options* opt, size_t* bytes) {
+    clear_error();
+    if (!bytes || !opt) return set_error("NULL argument"), MIPDHG_ERR_INVALID_ARG;
+    int rc = check_batch(bt);
+    if (rc) return rc;
+    if ((rc = check_options(opt))) return rc;
+    *bytes = carve_batch(nullptr, 0, bt->count, bt->whole.m, bt->whole.n, bt->whole.nnz, opt->precision).bytes;
+    return 0;
+}
+
+extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options* opt, double eps_rel,
+                                    void* workspace, size_t workspace_bytes, void* stream, double* x, double* y,
+                                    double* z, double* r_p, double* r_d, mipdhg_info* info) {
+    clear_error();
+    int rc = check_batch(bt);
+    if (rc) return rc;
+    if (!opt) return set_error("options are NULL"), MIPDHG_ERR_INVALID_ARG;
+    if ((rc = check_options(opt))) return rc;
+    if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
+    if (!workspace || !x || !y || !z || !r_p || !r_d)
+        return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
+    if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing)
+        return set_error("tracing, warm starts and kernel timing are single-LP options"), MIPDHG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    switch (opt->precision) {
+        case MIPDHG_FP64:
+            return batched_impl<double, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
+                                                info);
+        case MIPDHG_FP32:
+            return batched_impl<float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
+                                              info);
+        default:
+            return batched_impl<float, uint16_t>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                 r_d, info);
+    }
+}

@@ -66,6 +66,7 @@ extern "C" size_t mipdhg_sizeof(int which) {
         case 0: return sizeof(mipdhg_lp);
         case 1: return sizeof(mipdhg_options);
         case 2: return sizeof(mipdhg_info);
+        case 3: return sizeof(mipdhg_batch);
         default: return 0;
     }
 }

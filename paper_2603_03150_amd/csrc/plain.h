@@ -2,6 +2,11 @@
 #pragma once
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
 namespace mip {
 
 // Written by the setup code and by the decide kernel at the end of every
@@ -23,5 +28,19 @@ struct Ctrl {
     double rp2, rd2, pobj, dobj, xz, rp_inf, rd_inf;
     int64_t eval_t;
 };
+
+// shared host helpers (plain.hip, validate.hip)
+int check_lp(const mipdhg_lp* lp);
+int check_options(const mipdhg_options* o);
+int check_rowptr(const std::vector<int32_t>& rp, int32_t nrows, int64_t nnz, const char* which);
+// Checks column ranges, finiteness of A, A^T, b, c, and A^T against A by a
+// dot-product test.  flags: 4 ints, partials: >= 2 * max tiles doubles, red: 4.
+int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat, int32_t* flags,
+                    double* partials, double* red, hipStream_t stream);
+
+inline int grid_for(int64_t n, int cap = 2048) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
 
 }  // namespace mip

@@ -69,88 +69,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* partials, 
 }
 
 // ---------------------------------------------------------------------------
-// validation
-// ---------------------------------------------------------------------------
-// flags: bit0 column index out of range, bit1 non-finite value, bit2 non-finite b/c
-__global__ void k_check_entries(const int32_t* col, const double* val, int64_t nnz, int32_t ncols,
-                                int32_t* flags) {
-    int f = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int32_t j = col[k];
-        if (j < 0 || j >= ncols) f |= 1;
-        if (!isfinite(val[k])) f |= 2;
-    }
-    if (f) atomicOr(flags, f);
-}
-
-__global__ void k_check_vec(const double* v, int64_t n, int32_t* flags) {
-    int f = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (!isfinite(v[i])) f |= 4;
-    if (f) atomicOr(flags, f);
-}
-
-__device__ __forceinline__ double hash_unit(uint32_t i, uint32_t seed) {
-    uint32_t h = i * 0x9E3779B1u ^ seed;
-    h ^= h >> 16;
-    h *= 0x85EBCA6Bu;
-    h ^= h >> 13;
-    h *= 0xC2B2AE35u;
-    h ^= h >> 16;
-    return (double)h * (2.0 / 4294967296.0) - 1.0;  // [-1, 1)
-}
-
-// Dot-product consistency test of A and A^T: with u = hash(row), v = hash(col),
-// accumulates sum_r u_r (M v)_r and sum |u_r| |M_rc| |v_c| over the rows of M.
-template <int L>
-__global__ __launch_bounds__(kBlock) void k_transpose_dot(RowPlan p, const int32_t* col,
-                                                          const double* val, uint32_t seed_row,
-                                                          uint32_t seed_col, double* partials) {
-    double s[2] = {0.0, 0.0};
-    double mx[1] = {0.0};
-    auto dot = [&](int st, int e, int lane, int LL) {
-        double a = 0.0, b = 0.0;
-        for (int k = st + lane; k < e; k += LL) {
-            double v = hash_unit((uint32_t)col[k], seed_col);
-            a += val[k] * v;
-            b += fabs(val[k] * v);
-        }
-        return double2{a, b};
-    };
-    const int b = blockIdx.x;
-    auto epi = [&](int r, double2 t) {
-        double u = hash_unit((uint32_t)r, seed_row);
-        s[0] += u * t.x;
-        s[1] += fabs(u) * t.y;
-    };
-    if (b < p.g_short) {
-        const int vb = xcd_virtual_block(b, p.g_short);
-        const int r0 = vb * p.chunk, r1 = min(r0 + p.chunk, p.nrows);
-        const int grp = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-        for (int r = r0 + grp; r < r1; r += kBlock / L) {
-            const int st = p.rowptr[r], e = p.rowptr[r + 1];
-            if (e - st > p.long_thresh) continue;
-            double2 t = dot(st, e, lane, L);
-            t.x = group_sum<L>(t.x);
-            t.y = group_sum<L>(t.y);
-            if (lane == 0) epi(r, t);
-        }
-    } else {
-        const int lb = b - p.g_short, wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-        for (int li = lb * 4 + wave; li < p.nlong; li += p.g_long * 4) {
-            const int r = p.long_rows[li];
-            double2 t = dot(p.rowptr[r], p.rowptr[r + 1], lane, kWave);
-            t.x = group_sum<kWave>(t.x);
-            t.y = group_sum<kWave>(t.y);
-            if (lane == 0) epi(r, t);
-        }
-    }
-    block_reduce_store<2, 0>(s, mx, partials + 2 * blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
 // scaling
 // ---------------------------------------------------------------------------
 // stat[r] = d_self[r] * (max or sum over the row of |a_rk| d_other[col_k]),
@@ -635,10 +553,6 @@ std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrow
     return t;
 }
 
-static inline int grid_for(int64_t n, int cap = 2048) {
-    int64_t g = (n + kBlock - 1) / kBlock;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
-}
 
 // Workspace layout (identical for the size query and the solve).
 struct PlainWs {
@@ -693,7 +607,7 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     return w;
 }
 
-static int check_options(const mipdhg_options* o) {
+int check_options(const mipdhg_options* o) {
     if (o->precision < 0 || o->precision > 2) return set_error("precision must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->ruiz_iters < 0 || o->power_iters < 1 || o->power_iters > 100000)
         return set_error("ruiz_iters >= 0 and 1 <= power_iters <= 100000 required"), MIPDHG_ERR_INVALID_ARG;
@@ -711,7 +625,7 @@ static int check_options(const mipdhg_options* o) {
     return 0;
 }
 
-static int check_lp(const mipdhg_lp* lp) {
+int check_lp(const mipdhg_lp* lp) {
     if (!lp) return set_error("lp is NULL"), MIPDHG_ERR_INVALID_ARG;
     if (lp->m < 1 || lp->n < 1 || lp->nnz < 0 || lp->nnz >= (int64_t)INT32_MAX)
         return set_error("need m >= 1, n >= 1 and 0 <= nnz < 2^31 (m=%d n=%d nnz=%lld)", lp->m, lp->n,
@@ -723,7 +637,7 @@ static int check_lp(const mipdhg_lp* lp) {
     return 0;
 }
 
-static int check_rowptr(const std::vector<int32_t>& rp, int32_t nrows, int64_t nnz, const char* which) {
+int check_rowptr(const std::vector<int32_t>& rp, int32_t nrows, int64_t nnz, const char* which) {
     if (rp[0] != 0 || (int64_t)rp[nrows] != nnz)
         return set_error("%s row pointer must start at 0 and end at nnz", which), MIPDHG_ERR_BAD_CSR;
     for (int32_t r = 0; r < nrows; ++r)
@@ -957,43 +871,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const int64_t G = w.gcap;
 
     // --- validation: indices, finiteness, transpose consistency
-    if (o.validate) {
-        MIP_HIP(hipMemsetAsync(w.flags, 0, 4, stream));
-        if (nnz > 0) {
-            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.a_col, lp.a_val,
-                               nnz, lp.n, w.flags);
-            hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.at_col,
-                               lp.at_val, nnz, lp.m, w.flags);
-        }
-        hipLaunchKernelGGL(k_check_vec, dim3(grid_for(m)), dim3(kBlock), 0, stream, lp.b, m, w.flags);
-        hipLaunchKernelGGL(k_check_vec, dim3(grid_for(n)), dim3(kBlock), 0, stream, lp.c, n, w.flags);
-        MIP_LAUNCH_CHECK();
-        int32_t flags = 0;
-        MIP_HIP(hipMemcpyAsync(&flags, w.flags, 4, hipMemcpyDeviceToHost, stream));
-        MIP_HIP(hipStreamSynchronize(stream));
-        if (flags & 1) return set_error("column index out of range"), MIPDHG_ERR_BAD_CSR;
-        if (flags & 6) return set_error("NaN or Inf in A, A^T, b or c"), MIPDHG_ERR_NONFINITE;
-        if (nnz > 0) {
-            // u^T (A v) = v^T (A^T u) with hash vectors
-            MIP_DISPATCH_L(S.pa.lanes, hipLaunchKernelGGL((k_transpose_dot<L>), dim3(ga), dim3(kBlock), 0, stream,
-                                                          S.pa, lp.a_col, lp.a_val, 0x1234u, 0xABCDu, w.psetup));
-            hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, ga, 2,
-                               w.red);
-            MIP_DISPATCH_L(S.pat.lanes, hipLaunchKernelGGL((k_transpose_dot<L>), dim3(gat), dim3(kBlock), 0,
-                                                           stream, S.pat, lp.at_col, lp.at_val, 0xABCDu, 0x1234u,
-                                                           w.psetup));
-            hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gat, 2,
-                               w.red + 2);
-            MIP_LAUNCH_CHECK();
-            double red[4];
-            MIP_HIP(hipMemcpyAsync(red, w.red, 4 * 8, hipMemcpyDeviceToHost, stream));
-            MIP_HIP(hipStreamSynchronize(stream));
-            const double scale = std::max(red[1], red[3]);
-            if (!(fabs(red[0] - red[2]) <= 1e-10 * scale + 1e-300))
-                return set_error("A^T does not match A (dot test %.17g vs %.17g)", red[0], red[2]),
-                       MIPDHG_ERR_TRANSPOSE;
-        }
-    }
+    if (o.validate && (rc = validate_device(lp, S.ta, S.tat, w.flags, w.psetup, w.red, stream))) return rc;
 
     // --- norms of the original b and c
     double bn2 = 0, cn2 = 0;

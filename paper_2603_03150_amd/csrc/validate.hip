@@ -1,0 +1,122 @@
+// Input validation shared by the single and batched solves: column ranges,
+// finiteness, and a dot-product test that A^T is the transpose of A.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "plain.h"
+
+namespace mip {
+
+// flags: bit0 column index out of range, bit1 non-finite value, bit2 non-finite b/c
+__global__ void k_check_entries(const int32_t* col, const double* val, int64_t nnz, int32_t ncols,
+                                int32_t* flags) {
+    int f = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t j = col[k];
+        if (j < 0 || j >= ncols) f |= 1;
+        if (!isfinite(val[k])) f |= 2;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_check_vec(const double* v, int64_t n, int32_t* flags) {
+    int f = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(v[i])) f |= 4;
+    if (f) atomicOr(flags, f);
+}
+
+__device__ __forceinline__ double hash_unit(uint32_t i, uint32_t seed) {
+    uint32_t h = i * 0x9E3779B1u ^ seed;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (double)h * (2.0 / 4294967296.0) - 1.0;  // [-1, 1)
+}
+
+// With u = hash(row), v = hash(col): partial sums of u_r (M v)_r (ABS = false)
+// or of |u_r| sum_c |M_rc v_c| (ABS = true) over the rows of M.
+template <bool ABS>
+__global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int32_t* col, const double* val,
+                                                          uint32_t seed_row, uint32_t seed_col, double* partials) {
+    __shared__ TileLds<double> L;
+    double s[1] = {0.0};
+    double mx[1] = {0.0};
+    auto prod = [&](int k) {
+        const double t = val[k] * hash_unit((uint32_t)col[k], seed_col);
+        return ABS ? fabs(t) : t;
+    };
+    auto epi = [&](int r, double t) {
+        const double u = hash_unit((uint32_t)r, seed_row);
+        s[0] += (ABS ? fabs(u) : u) * t;
+    };
+    tiled_rows<false>(p, L, prod, epi);
+    block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partials, int G, double* out) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s += partials[g];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat, int32_t* flags,
+                    double* partials, double* red, hipStream_t stream) {
+    const int64_t nnz = lp.nnz;
+    MIP_HIP(hipMemsetAsync(flags, 0, 4, stream));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.a_col, lp.a_val, nnz,
+                           lp.n, flags);
+        hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, lp.at_col, lp.at_val,
+                           nnz, lp.m, flags);
+    }
+    hipLaunchKernelGGL(k_check_vec, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.b, (int64_t)lp.m, flags);
+    hipLaunchKernelGGL(k_check_vec, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.c, (int64_t)lp.n, flags);
+    MIP_LAUNCH_CHECK();
+    int32_t f = 0;
+    MIP_HIP(hipMemcpyAsync(&f, flags, 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    if (f & 1) return set_error("column index out of range"), MIPDHG_ERR_BAD_CSR;
+    if (f & 6) return set_error("NaN or Inf in A, A^T, b or c"), MIPDHG_ERR_NONFINITE;
+    if (nnz == 0) return 0;
+    // u^T (A v) against v^T (A^T u), and the scale sum |u||A||v|
+    const uint32_t su = 0x1234u, sv = 0xABCDu;
+    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(ta.ntiles), dim3(kBlock), 0, stream, ta, lp.a_col,
+                       lp.a_val, su, sv, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, ta.ntiles, red);
+    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(ta.ntiles), dim3(kBlock), 0, stream, ta, lp.a_col,
+                       lp.a_val, su, sv, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, ta.ntiles,
+                       red + 1);
+    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(tat.ntiles), dim3(kBlock), 0, stream, tat, lp.at_col,
+                       lp.at_val, sv, su, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, tat.ntiles,
+                       red + 2);
+    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(tat.ntiles), dim3(kBlock), 0, stream, tat, lp.at_col,
+                       lp.at_val, sv, su, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, tat.ntiles,
+                       red + 3);
+    MIP_LAUNCH_CHECK();
+    double r[4];
+    MIP_HIP(hipMemcpyAsync(r, red, 4 * 8, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    const double scale = std::max(r[1], r[3]);
+    if (!(fabs(r[0] - r[2]) <= 1e-10 * scale + 1e-300))
+        return set_error("A^T does not match A (dot test %.17g vs %.17g)", r[0], r[2]), MIPDHG_ERR_TRANSPOSE;
+    return 0;
+}
+
+}  // namespace mip

@@ -135,3 +135,86 @@ def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters
     _lib.check(rc)
     return Solution(rc, lib.mipdhg_status_string(rc).decode(), x, y, z, r_p, r_d, d_row, d_col,
                     info.as_dict(), trace)
+
+
+class DeviceBatch:
+    """Independent LPs stacked block-diagonally in device memory, with the
+    host offset arrays the batched entry point needs."""
+
+    def __init__(self, A, AT, b, c, row_off, col_off, nnz_off, device="cuda"):
+        self.lp = DeviceLP(A, AT, b, c, device)
+        self.row_off = np.ascontiguousarray(row_off, dtype=np.int32)
+        self.col_off = np.ascontiguousarray(col_off, dtype=np.int32)
+        self.nnz_off = np.ascontiguousarray(nnz_off, dtype=np.int64)
+        self.count = int(self.row_off.size - 1)
+
+    @classmethod
+    def from_lps(cls, lps, device="cuda") -> "DeviceBatch":
+        import scipy.sparse as sp
+        A = sp.block_diag([lp.A for lp in lps], format="csr")
+        AT = sp.block_diag([lp.AT for lp in lps], format="csr")
+        A.sort_indices()
+        AT.sort_indices()
+        row_off = np.concatenate([[0], np.cumsum([lp.A.shape[0] for lp in lps])])
+        col_off = np.concatenate([[0], np.cumsum([lp.A.shape[1] for lp in lps])])
+        nnz_off = np.concatenate([[0], np.cumsum([lp.A.nnz for lp in lps])])
+        return cls(A, AT, np.concatenate([lp.b for lp in lps]), np.concatenate([lp.c for lp in lps]),
+                   row_off, col_off, nnz_off, device)
+
+    def struct(self) -> _lib.BatchStruct:
+        s = _lib.BatchStruct()
+        s.count = self.count
+        s.row_off = self.row_off.ctypes.data
+        s.col_off = self.col_off.ctypes.data
+        s.nnz_off = self.nnz_off.ctypes.data
+        s.whole = self.lp.struct()
+        return s
+
+
+@dataclass
+class BatchSolution:
+    status: int
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    r_p: torch.Tensor
+    r_d: torch.Tensor
+    infos: list
+
+    def split(self, batch: DeviceBatch, i: int) -> dict:
+        r0, r1 = batch.row_off[i], batch.row_off[i + 1]
+        c0, c1 = batch.col_off[i], batch.col_off[i + 1]
+        return {"x": self.x[c0:c1], "y": self.y[r0:r1], "z": self.z[c0:c1], "r_p": self.r_p[r0:r1],
+                "r_d": self.r_d[c0:c1], "info": self.infos[i]}
+
+
+def solve_batched(batch: DeviceBatch, eps: float = 1e-4, precision: str = "fp32",
+                  workspace: torch.Tensor | None = None, **opts) -> BatchSolution:
+    """Run mipdhg_solve_batched on every instance of the batch."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    st = batch.struct()
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_batch_workspace_size(C.byref(st), C.byref(o), C.byref(nb)))
+    d = batch.lp.device
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    f64 = dict(dtype=torch.float64, device=d)
+    m, n = batch.lp.m, batch.lp.n
+    x, y, z = torch.empty(n, **f64), torch.empty(m, **f64), torch.empty(n, **f64)
+    r_p, r_d = torch.empty(m, **f64), torch.empty(n, **f64)
+    infos = (_lib.InfoStruct * batch.count)()
+    stream = torch.cuda.current_stream(d).cuda_stream
+    rc = lib.mipdhg_solve_batched(C.byref(st), C.byref(o), float(eps), workspace.data_ptr(), workspace.numel(),
+                                  stream, x.data_ptr(), y.data_ptr(), z.data_ptr(), r_p.data_ptr(),
+                                  r_d.data_ptr(), infos)
+    _lib.check(rc)
+    return BatchSolution(rc, x, y, z, r_p, r_d, [infos[i].as_dict() for i in range(batch.count)])
+
+
+def batch_workspace_bytes(batch: DeviceBatch, precision: str = "fp32", **opts) -> int:
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_batch_workspace_size(C.byref(batch.struct()), C.byref(o), C.byref(nb)))
+    return int(nb.value)

@@ -1,0 +1,116 @@
+"""GPU parity of the batched persistent solve against the float64 oracle.
+
+FP64: every instance matches the oracle run on that instance alone: status,
+iteration count, restart count, and the returned point to 1e-8.  FP32: every
+instance that reports OPTIMAL satisfies the Section 2 tests when re-measured
+in float64 on the host, and its objective is within 1e-4 relative of the
+oracle's.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import lpgen
+import oracle
+from oracle.pdhg import OracleOptions
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_03150_amd")
+torch = pytest.importorskip("torch")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b)) / max(1.0, float(np.linalg.norm(b)))
+
+
+def _sizes(count, lo=20, hi=300, seed=0):
+    rng = lpgen.rng_for(44, seed)
+    return np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))).astype(int)
+
+
+def _tests_hold(lp, x, y, eps):
+    z = np.maximum(lp.c - lp.AT @ y, 0.0)
+    rp = lp.b - lp.A @ x
+    rd = lp.c - lp.AT @ y - z
+    p, d = lp.c @ x, lp.b @ y
+    return (np.linalg.norm(rp) <= eps * (1 + np.linalg.norm(lp.b))
+            and np.linalg.norm(rd) <= eps * (1 + np.linalg.norm(lp.c))
+            and abs(p - d) <= eps * (1 + abs(p) + abs(d)))
+
+
+def test_batched_fp64_matches_oracle_per_instance():
+    lps = [lpgen.cfg4_instance(i, m) for i, m in enumerate(_sizes(24))]
+    batch = P.DeviceBatch.from_lps(lps)
+    eps = 1e-6
+    sol = P.solve_batched(batch, eps, "fp64", max_iter=100_000)
+    for i, lp in enumerate(lps):
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, eps, opts=OracleOptions(max_iter=100_000))
+        got = sol.split(batch, i)
+        assert got["info"]["status"] == ref.status == 0, i
+        assert got["info"]["iters"] == ref.iters, (i, got["info"]["iters"], ref.iters)
+        assert got["info"]["restarts"] == ref.restarts, i
+        assert _rel(_np(got["x"]), ref.meas.x) <= 1e-8, i
+        assert _rel(_np(got["y"]), ref.meas.y) <= 1e-8, i
+        assert abs(got["info"]["sigma_hat"] - ref.sigma_hat) <= 1e-12 * ref.sigma_hat
+        assert np.allclose(_np(got["r_p"]), ref.meas.r_p, rtol=0, atol=1e-9)
+
+
+def test_batched_fp64_iteration_limit_and_options():
+    # a tail evaluation at max_iter, no Halpern, no restarts, rho = 0.5
+    lps = [lpgen.cfg4_instance(100 + i, m) for i, m in enumerate([20, 37, 64])]
+    batch = P.DeviceBatch.from_lps(lps)
+    kw = dict(max_iter=150, halpern=0, restarts=0, reflect_rho=0.5)
+    sol = P.solve_batched(batch, 1e-12, "fp64", **kw)
+    for i, lp in enumerate(lps):
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12,
+                           opts=OracleOptions(max_iter=150, halpern=False, restarts=False, reflect_rho=0.5))
+        got = sol.split(batch, i)
+        assert got["info"]["status"] == ref.status == 1 and got["info"]["iters"] == 150
+        assert _rel(_np(got["x"]), ref.meas.x) <= 1e-10
+
+
+def test_batched_fp32_reaches_tolerance():
+    lps = [lpgen.cfg4_instance(200 + i, m) for i, m in enumerate(_sizes(64, 20, 2000, seed=1))]
+    batch = P.DeviceBatch.from_lps(lps)
+    eps = 1e-4
+    sol = P.solve_batched(batch, eps, "fp32", max_iter=200_000)
+    assert sol.status == 0
+    for i in range(0, len(lps), 7):
+        lp = lps[i]
+        got = sol.split(batch, i)
+        x, y = _np(got["x"]), _np(got["y"])
+        assert _tests_hold(lp, x, y, eps), i
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-8)
+        assert abs(lp.c @ x - ref.meas.pobj) <= 1e-4 * max(1, abs(ref.meas.pobj)), i
+
+
+def test_batched_single_instance_equals_plain_solve():
+    lp = lpgen.cfg1(0)
+    b = P.solve_batched(P.DeviceBatch.from_lps([lp]), 1e-6, "fp64")
+    p = P.solve(P.DeviceLP.from_lp(lp), 1e-6, "fp64")
+    assert b.infos[0]["iters"] == p.info["iters"]
+    assert _rel(_np(b.x), _np(p.x)) <= 1e-10
+
+
+def test_batched_deterministic():
+    lps = [lpgen.cfg4_instance(300 + i, m) for i, m in enumerate(_sizes(40, seed=2))]
+    batch = P.DeviceBatch.from_lps(lps)
+    a = P.solve_batched(batch, 1e-4, "fp32")
+    b = P.solve_batched(batch, 1e-4, "fp32")
+    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
+    assert [i["iters"] for i in a.infos] == [i["iters"] for i in b.infos]
+
+
+def test_batched_rejects_off_block_entry():
+    lps = [lpgen.cfg4_instance(400 + i, 30) for i in range(2)]
+    batch = P.DeviceBatch.from_lps(lps)
+    # move one entry of instance 0 into instance 1's columns
+    batch.lp.a_col[0] = int(batch.col_off[1]) + 1
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp64")
+    assert e.value.code in (-2, -3)

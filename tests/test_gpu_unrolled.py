@@ -1,0 +1,152 @@
+"""GPU unrolled PDHG map and its hand-written adjoint against the oracle.
+
+FP64: x_K and (dL/dc, dL/db) match the oracle's forward and reverse mode per
+instance; finite differences of the GPU map with the recorded schedule
+(replay) agree with the GPU gradient away from projection-mask flips (flips
+detected with the oracle); the gradient does not depend on the checkpoint
+interval.  FP32: the error against the FP64 oracle gradient is reported.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from oracle.pdhg import OracleOptions
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_03150_amd")
+torch = pytest.importorskip("torch")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b)) / max(1e-300, float(np.linalg.norm(b)))
+
+
+def _fd_set(count=16):
+    pairs = [lpgen.cfg5_fd_instance(i) for i in range(count)]
+    return [p[0] for p in pairs], [p[1] for p in pairs]
+
+
+def _seg(batch, v, i, rows=False):
+    off = batch.row_off if rows else batch.col_off
+    return v[off[i]:off[i + 1]]
+
+
+@pytest.mark.parametrize("K,ckpt", [(300, 50), (257, 64)])
+def test_fp64_forward_and_gradient_match_oracle(K, ckpt):
+    lps, ws = _fd_set(16)
+    batch = P.DeviceBatch.from_lps(lps)
+    umap = P.UnrolledMap(batch, K=K, ckpt_every=ckpt, precision="fp64")
+    c = batch.lp.c.clone()
+    b = batch.lp.b.clone()
+    xK, tape = umap.forward_raw(c, b)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    gc, gb = umap.backward_raw(c, b, tape, w)
+    xK, gc, gb = _np(xK), _np(gc), _np(gb)
+    for i, lp in enumerate(lps):
+        rc, rb, rx, _ = oracle.unrolled_grad(lp.A, lp.b, lp.c, K, ws[i], OracleOptions())
+        assert _rel(_seg(batch, xK, i), rx) <= 1e-10, i
+        assert _rel(_seg(batch, gc, i), rc) <= 1e-8, i
+        assert _rel(_seg(batch, gb, i, rows=True), rb) <= 1e-8, i
+
+
+def test_fp64_finite_differences_with_replay():
+    lps, ws = _fd_set(4)
+    batch = P.DeviceBatch.from_lps(lps)
+    K, h = 300, 1e-6
+    umap = P.UnrolledMap(batch, K=K, ckpt_every=100, precision="fp64")
+    c0, b0 = batch.lp.c.clone(), batch.lp.b.clone()
+    x0, tape = umap.forward_raw(c0, b0)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    gc, gb = umap.backward_raw(c0, b0, tape, w)
+    gc, gb = _np(gc), _np(gb)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for i, lp in enumerate(lps):
+        _, sched, tape0 = oracle.unrolled_forward(lp.A, lp.b, lp.c, K, keep_masks=True)
+        base = np.array(tape0["masks"])
+        for which in ("c", "b"):
+            size = lp.n if which == "c" else lp.m
+            for j in rng.choice(size, size=4, replace=False):
+                e = np.zeros(size)
+                e[j] = h
+                flips = False
+                for sgn in (1, -1):
+                    cc, bb = (lp.c + sgn * e, lp.b) if which == "c" else (lp.c, lp.b + sgn * e)
+                    _, _, tp = oracle.unrolled_forward(lp.A, bb, cc, K, schedule=sched, keep_masks=True)
+                    flips |= not np.array_equal(np.array(tp["masks"]), base)
+                if flips:
+                    continue
+                vals = []
+                for sgn in (1, -1):
+                    c1, b1 = c0.clone(), b0.clone()
+                    if which == "c":
+                        c1[batch.col_off[i] + j] += sgn * h
+                    else:
+                        b1[batch.row_off[i] + j] += sgn * h
+                    xp, _ = umap.forward_raw(c1, b1, tape=tape.clone(), replay=True)
+                    vals.append(float(w @ xp))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                g = gc[batch.col_off[i] + j] if which == "c" else gb[batch.row_off[i] + j]
+                assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)) + 1e-8, (i, which, j, fd, g)
+                checked += 1
+    assert checked >= 16
+
+
+def test_gradient_independent_of_checkpoint_interval():
+    lps, ws = _fd_set(8)
+    batch = P.DeviceBatch.from_lps(lps)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    out = []
+    for ck in (1, 37, 200):
+        umap = P.UnrolledMap(batch, K=200, ckpt_every=ck, precision="fp64")
+        xK, tape = umap.forward_raw(batch.lp.c, batch.lp.b)
+        out.append((xK,) + umap.backward_raw(batch.lp.c, batch.lp.b, tape, w))
+    for o in out[1:]:
+        for u, v in zip(out[0], o):
+            assert torch.equal(u, v)
+
+
+def test_autograd_function():
+    lps, ws = _fd_set(4)
+    batch = P.DeviceBatch.from_lps(lps)
+    umap = P.UnrolledMap(batch, K=150, ckpt_every=50, precision="fp64")
+    c = batch.lp.c.clone().requires_grad_(True)
+    b = batch.lp.b.clone().requires_grad_(True)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    xK = umap.apply(c, b)
+    (w * xK).sum().backward()
+    x2, tape = umap.forward_raw(c, b)
+    gc, gb = umap.backward_raw(c, b, tape, w)
+    assert torch.equal(xK.detach(), x2)
+    assert torch.equal(c.grad, gc) and torch.equal(b.grad, gb)
+
+
+def test_fp32_gradient_error_vs_fp64_oracle():
+    lps, ws = [], []
+    for i in range(4):
+        lp, w = lpgen.cfg5_instance(i)
+        lps.append(lp)
+        ws.append(w)
+    batch = P.DeviceBatch.from_lps(lps)
+    K = 2000
+    umap = P.UnrolledMap(batch, K=K, ckpt_every=100, precision="fp32")
+    xK, tape = umap.forward_raw(batch.lp.c, batch.lp.b)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    gc, gb = umap.backward_raw(batch.lp.c, batch.lp.b, tape, w)
+    gc, xK = _np(gc), _np(xK)
+    errs = []
+    for i in range(2):
+        lp = lps[i]
+        rc, rb, rx, _ = oracle.unrolled_grad(lp.A, lp.b, lp.c, K, ws[i], OracleOptions())
+        ex = _rel(_seg(batch, xK, i), rx)
+        eg = _rel(_seg(batch, gc, i), rc)
+        errs.append((ex, eg))
+        assert np.all(np.isfinite(_seg(batch, gc, i)))
+        assert ex <= 1e-2, (i, ex)
+    print("fp32 unrolled relative errors (x_K, dL/dc):", errs)
