@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-iters", type=int, default=1024,
                     help="iterations of the per-kernel HIP-event timing leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-LP leg")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=32,
+                    help="instances of the batch solved one at a time by the plain FP64 path")
     return ap.parse_args()
 
 
@@ -76,6 +80,48 @@ def cpu_baseline(lp, gpu_iters: int, eps: float) -> dict:
     return {"value": value, "unit": "iter/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle capped at 64 and 192 iterations on the same LP: setup {setup:.2f} s, "
                        f"{per_iter * 1e3:.1f} ms/iteration, rate quoted for a {gpu_iters}-iteration solve")}
+
+
+def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
+    """4,096 LPs (m log-uniform on [20, 2000], n = 2.5 m, 4 nonzeros per
+    column) in one persistent launch, FP32 iterates with FP64 per-instance
+    tests, against the plain FP64 single-LP path on a stratified sample."""
+    import numpy as np
+
+    import lpgen
+    t0 = time.perf_counter()
+    sizes = lpgen.cfg4_sizes(count)
+    lps = [lpgen.cfg4_instance(i, int(m)) for i, m in enumerate(sizes)]
+    batch = P.DeviceBatch.from_lps(lps, "cuda:0")
+    gen_s = time.perf_counter() - t0
+    ws = torch.empty(P.batch_workspace_bytes(batch, "fp32"), dtype=torch.uint8, device="cuda:0")
+    P.solve_batched(batch, eps, "fp32", workspace=ws, max_iter=100_000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = P.solve_batched(batch, eps, "fp32", workspace=ws, max_iter=100_000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = np.array([inf["iters"] for inf in sol.infos])
+    solved = sum(1 for inf in sol.infos if inf["status"] == 0)
+    # plain FP64 path, one LP at a time, on every (count/sample)-th instance by size
+    order = np.argsort(sizes, kind="stable")
+    pick = order[np.linspace(0, count - 1, sample).round().astype(int)]
+    t_plain = 0.0
+    for i in pick:
+        dl = P.DeviceLP.from_lp(lps[i], "cuda:0")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.solve(dl, eps, "fp64", max_iter=100_000)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+    plain_lps = sample / t_plain
+    return {"metric": "batched LPs/s to eps_rel=1e-4", "value": count / dt, "unit": "LPs/s",
+            "count": count, "solved": solved, "seconds": dt,
+            "iters_p50": float(np.percentile(iters, 50)), "iters_p99": float(np.percentile(iters, 99)),
+            "plain_fp64_lps_per_s": plain_lps, "plain_sample": int(sample),
+            "speedup_vs_plain": (count / dt) / plain_lps, "generate_s": gen_s,
+            "workload": "4096 LPs, m log-uniform [20,2000], n=2.5m, 4 nnz/col, N(0,1), planted optima, "
+                        "FP32 iterates, FP64 per-instance tests"}
 
 
 def main() -> int:
@@ -159,6 +205,9 @@ def main() -> int:
                   "iter_only_rate": int(last.info["iters"]) / (last.info["ms_iter"] * 1e-3),
                   "plan": {k: last.info[k] for k in ("lanes_a", "lanes_at", "long_a", "long_at")}},
     }
+    if not args.no_batched:
+        print("# batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(P, torch, args.batch_count, args.plain_sample, args.eps)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(lp, int(last.info["iters"]), args.eps)

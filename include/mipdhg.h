@@ -221,6 +221,28 @@ int mipdhg_unrolled_backward(const mipdhg_batch *batch, const mipdhg_options *op
                              int32_t ckpt_every, void *tape, size_t tape_bytes, const double *grad_xK,
                              void *stream, double *grad_c, double *grad_b);
 
+/* ---- Centered warm start (Algorithm 1, Section 3.1) ----------------------
+ * Maps a PDHG solution of the SCALED LP to the interior-point start (x', z')
+ * (y passes through unchanged): mu_target = max(x^T z / n, mu_min); each pair
+ * is lifted to alpha_min, then the smaller of x_j, z_j moves toward
+ * mu_target / (the other) and the other toward mu_target / (the new value),
+ * each by at most delta_max.  The paper's settings are mu_min = 1e-6,
+ * delta_max = 1e-4, alpha_min = 1e-6.  If d_col (device [n]) is given, x and z
+ * are original-space outputs of mipdhg_solve and are first scaled
+ * (x~ = x / d_col, z~ = z * d_col); otherwise they are already scaled.
+ * Outputs x_out, z_out (device [n]) are in the scaled space; mu_target (host,
+ * nullable) receives the target.  workspace: device, 256-byte aligned, at
+ * least mipdhg_center_workspace_size(n) bytes. */
+size_t mipdhg_center_workspace_size(int32_t n);
+int mipdhg_center_start(int32_t n, const double *x, const double *z, const double *d_col, double mu_min,
+                        double delta_max, double alpha_min, void *workspace, size_t workspace_bytes,
+                        void *stream, double *x_out, double *z_out, double *mu_target);
+
+/* The re-clamp of Algorithm 1's recovery loop (run after the caller has
+ * raised alpha_min tenfold because the interior-point step was too small):
+ * x_j <- max(x_j, alpha_min), z_j <- max(z_j, alpha_min), in place. */
+int mipdhg_center_reclamp(int32_t n, double alpha_min, void *stream, double *x_io, double *z_io);
+
 /* sizeof of the public structs, for bindings that mirror them:
  * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info, 3 mipdhg_batch;
  * 0 for anything else. */

@@ -1,0 +1,125 @@
+// Centered start point of Algorithm 1 (Section 3.1): the map from a PDHG
+// solution of the scaled LP to the interior-point warm start, and the
+// alpha_min re-clamp of its step-recovery loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "plain.h"
+
+namespace mip {
+
+// Optionally scales an original-space (x, z) to the scaled LP
+// (x~ = x / d_col, z~ = z * d_col) into xs/zs; partial sums of x~_j z~_j.
+__global__ __launch_bounds__(kBlock) void k_center_dot(const double* x, const double* z, const double* d_col,
+                                                       int64_t n, double* xs, double* zs, double* partials) {
+    double s[1] = {0.0};
+    double mx[1] = {0.0};
+    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        double xv = x[j], zv = z[j];
+        if (d_col) {
+            xv = xv / d_col[j];
+            zv = zv * d_col[j];
+        }
+        xs[j] = xv;
+        zs[j] = zv;
+        s[0] += xv * zv;
+    }
+    block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
+}
+
+// mu_target = max(sum(partials) / n, mu_min), fixed-order sum in one workgroup
+__global__ __launch_bounds__(kBlock) void k_center_mu(const double* partials, int G, int64_t n, double mu_min,
+                                                      double* mu) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s += partials[g];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *mu = fmax(sh[0] / (double)n, mu_min);
+}
+
+__device__ __forceinline__ double clamp_move(double target, double from, double delta) {
+    return fmin(fmax(target, from - delta), from + delta);
+}
+
+// the per-pair map: lift to alpha_min, move the smaller toward mu/other,
+// then the other toward mu/(new smaller), each by at most delta_max
+__global__ void k_center_map(const double* xs, const double* zs, int64_t n, const double* mu_p, double delta,
+                             double alpha, double* xo, double* zo) {
+    const double mu = *mu_p;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double a = fmax(xs[j], alpha);
+        double b = fmax(zs[j], alpha);
+        if (a < b) {
+            a = clamp_move(mu / b, a, delta);
+            b = clamp_move(mu / a, b, delta);
+        } else {
+            b = clamp_move(mu / a, b, delta);
+            a = clamp_move(mu / b, a, delta);
+        }
+        xo[j] = a;
+        zo[j] = b;
+    }
+}
+
+__global__ void k_reclamp(double* x, double* z, int64_t n, double alpha) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        x[j] = fmax(x[j], alpha);
+        z[j] = fmax(z[j], alpha);
+    }
+}
+
+}  // namespace mip
+
+using namespace mip;
+
+extern "C" size_t mipdhg_center_workspace_size(int32_t n) {
+    const int G = grid_for(n, 1024);
+    return ((size_t)G * 8 + 255) / 256 * 256 + 256 + 2 * (((size_t)n * 8 + 255) / 256 * 256);
+}
+
+extern "C" int mipdhg_center_start(int32_t n, const double* x, const double* z, const double* d_col, double mu_min,
+                                   double delta_max, double alpha_min, void* workspace, size_t workspace_bytes,
+                                   void* stream, double* x_out, double* z_out, double* mu_target) {
+    clear_error();
+    if (n < 1 || !x || !z || !x_out || !z_out || !workspace)
+        return set_error("n >= 1 and non-NULL x, z, x_out, z_out, workspace are required"), MIPDHG_ERR_INVALID_ARG;
+    if (!(mu_min > 0.0) || !(delta_max >= 0.0) || !(alpha_min >= 0.0) || !std::isfinite(mu_min) ||
+        !std::isfinite(delta_max) || !std::isfinite(alpha_min))
+        return set_error("need mu_min > 0, delta_max >= 0, alpha_min >= 0, all finite"), MIPDHG_ERR_INVALID_ARG;
+    if (workspace_bytes < mipdhg_center_workspace_size(n))
+        return set_error("workspace too small"), MIPDHG_ERR_WORKSPACE;
+    if (((uintptr_t)workspace & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    Carver cv(workspace, workspace_bytes);
+    const int G = grid_for(n, 1024);
+    double* partials = cv.take<double>(G);
+    double* mu = cv.take<double>(32);
+    double* xs = cv.take<double>(n);
+    double* zs = cv.take<double>(n);
+    hipLaunchKernelGGL(k_center_dot, dim3(G), dim3(kBlock), 0, s, x, z, d_col, (int64_t)n, xs, zs, partials);
+    hipLaunchKernelGGL(k_center_mu, dim3(1), dim3(kBlock), 0, s, (const double*)partials, G, (int64_t)n, mu_min, mu);
+    hipLaunchKernelGGL(k_center_map, dim3(grid_for(n)), dim3(kBlock), 0, s, (const double*)xs, (const double*)zs,
+                       (int64_t)n, (const double*)mu, delta_max, alpha_min, x_out, z_out);
+    MIP_LAUNCH_CHECK();
+    if (mu_target) MIP_HIP(hipMemcpyAsync(mu_target, mu, 8, hipMemcpyDeviceToHost, s));
+    MIP_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+extern "C" int mipdhg_center_reclamp(int32_t n, double alpha_min, void* stream, double* x_io, double* z_io) {
+    clear_error();
+    if (n < 1 || !x_io || !z_io || !(alpha_min >= 0.0) || !std::isfinite(alpha_min))
+        return set_error("n >= 1, non-NULL vectors and a finite alpha_min >= 0 are required"), MIPDHG_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_reclamp, dim3(grid_for(n)), dim3(kBlock), 0, s, x_io, z_io, (int64_t)n, alpha_min);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipStreamSynchronize(s));
+    return 0;
+}

@@ -150,14 +150,22 @@ class DeviceBatch:
 
     @classmethod
     def from_lps(cls, lps, device="cuda") -> "DeviceBatch":
+        """Stack LPs (objects with A, AT, b, c) into one block-diagonal pair."""
         import scipy.sparse as sp
-        A = sp.block_diag([lp.A for lp in lps], format="csr")
-        AT = sp.block_diag([lp.AT for lp in lps], format="csr")
-        A.sort_indices()
-        AT.sort_indices()
-        row_off = np.concatenate([[0], np.cumsum([lp.A.shape[0] for lp in lps])])
-        col_off = np.concatenate([[0], np.cumsum([lp.A.shape[1] for lp in lps])])
-        nnz_off = np.concatenate([[0], np.cumsum([lp.A.nnz for lp in lps])])
+        row_off = np.concatenate([[0], np.cumsum([lp.A.shape[0] for lp in lps])]).astype(np.int64)
+        col_off = np.concatenate([[0], np.cumsum([lp.A.shape[1] for lp in lps])]).astype(np.int64)
+        nnz_off = np.concatenate([[0], np.cumsum([lp.A.nnz for lp in lps])]).astype(np.int64)
+
+        def stack(mats, off_minor, off_major):
+            indptr = np.concatenate([mat.indptr[:-1].astype(np.int64) + nnz_off[i] for i, mat in enumerate(mats)]
+                                    + [nnz_off[-1:]])
+            indices = np.concatenate([mat.indices.astype(np.int64) + off_minor[i] for i, mat in enumerate(mats)])
+            data = np.concatenate([mat.data for mat in mats])
+            shape = (int(off_major[-1]), int(off_minor[-1]))
+            return sp.csr_matrix((data, indices.astype(np.int32), indptr.astype(np.int32)), shape=shape)
+
+        A = stack([lp.A for lp in lps], col_off, row_off)
+        AT = stack([lp.AT for lp in lps], row_off, col_off)
         return cls(A, AT, np.concatenate([lp.b for lp in lps]), np.concatenate([lp.c for lp in lps]),
                    row_off, col_off, nnz_off, device)
 
@@ -218,3 +226,33 @@ def batch_workspace_bytes(batch: DeviceBatch, precision: str = "fp32", **opts) -
     nb = C.c_size_t(0)
     _lib.check(lib.mipdhg_batch_workspace_size(C.byref(batch.struct()), C.byref(o), C.byref(nb)))
     return int(nb.value)
+
+
+def center_start(x: torch.Tensor, z: torch.Tensor, d_col: torch.Tensor | None = None, mu_min: float = 1e-6,
+                 delta_max: float = 1e-4, alpha_min: float = 1e-6):
+    """Algorithm 1's centered start (x', z', mu_target) from a PDHG solution;
+    pass d_col to scale an original-space (x, z) first."""
+    lib = _lib.load()
+    n = int(x.numel())
+    d = x.device
+    x = x.to(torch.float64).contiguous()
+    z = z.to(torch.float64).contiguous()
+    ws = torch.empty(int(lib.mipdhg_center_workspace_size(n)), dtype=torch.uint8, device=d)
+    xo = torch.empty(n, dtype=torch.float64, device=d)
+    zo = torch.empty(n, dtype=torch.float64, device=d)
+    mu = C.c_double(0.0)
+    dc = d_col.to(torch.float64).contiguous() if d_col is not None else None
+    rc = lib.mipdhg_center_start(n, x.data_ptr(), z.data_ptr(), dc.data_ptr() if dc is not None else None,
+                                 mu_min, delta_max, alpha_min, ws.data_ptr(), ws.numel(),
+                                 torch.cuda.current_stream(d).cuda_stream, xo.data_ptr(), zo.data_ptr(),
+                                 C.byref(mu))
+    _lib.check(rc)
+    return xo, zo, mu.value
+
+
+def center_reclamp(xp: torch.Tensor, zp: torch.Tensor, alpha_min: float) -> None:
+    """In-place lift of both vectors to alpha_min (Algorithm 1 recovery loop)."""
+    lib = _lib.load()
+    _lib.check(lib.mipdhg_center_reclamp(int(xp.numel()), float(alpha_min),
+                                         torch.cuda.current_stream(xp.device).cuda_stream,
+                                         xp.data_ptr(), zp.data_ptr()))
