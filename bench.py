@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16", "fp32acc32"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-iters", type=int, default=1024,
@@ -190,7 +190,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16(A)"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16(A)", "fp32acc32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "seed": args.seed,
                    "eps_rel": args.eps, "precision": args.precision},

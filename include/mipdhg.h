@@ -59,10 +59,13 @@ extern "C" {
 #define MIPDHG_ERR_UNSUPPORTED -6   /* option combination not supported       */
 #define MIPDHG_ERR_NONFINITE -7     /* NaN/Inf in A, b or c                   */
 
-/* iteration precision */
-#define MIPDHG_FP64 0        /* everything float64                              */
-#define MIPDHG_FP32 1        /* iterates, scaled A and SpMV accumulation float32 */
-#define MIPDHG_FP32_BF16A 2  /* as FP32, but scaled A values stored as bfloat16 */
+/* iteration precision (storage of the scaled A values and of the iterate
+ * vectors; the termination tests are float64 in every mode) */
+#define MIPDHG_FP64 0        /* everything float64                                    */
+#define MIPDHG_FP32 1        /* A values, x, y stored in float32; SpMV sums and the
+                                per-row updates computed in float64, rounded once   */
+#define MIPDHG_FP32_BF16A 2  /* as FP32, but the scaled A values stored as bfloat16   */
+#define MIPDHG_FP32_ACC32 3  /* float32 storage AND float32 SpMV sums and updates     */
 
 /* One LP in the standard form of Section 2.  Device pointers. */
 typedef struct mipdhg_lp {
@@ -80,7 +83,7 @@ typedef struct mipdhg_lp {
 
 /* Options.  Fill with mipdhg_default_options() and change what you need. */
 typedef struct mipdhg_options {
-    int32_t precision;      /* MIPDHG_FP64 / FP32 / FP32_BF16A            [0] */
+    int32_t precision;      /* MIPDHG_FP64 / FP32 / FP32_BF16A / FP32_ACC32 [0] */
     int32_t ruiz_iters;     /* Ruiz infinity-norm passes                  [10] */
     int32_t pock_chambolle; /* one Pock-Chambolle (alpha=1) pass after     [1] */
     int32_t power_iters;    /* power iterations for ||A~||_2             [100] */
@@ -99,6 +102,9 @@ typedef struct mipdhg_options {
     int32_t use_graph;      /* replay hipGraphs of eval_every iterations   [1] */
     int32_t spmv_kind;      /* iteration SpMVs: 0 = nnz-balanced LDS tiles,
                                1 = lane groups per row (lanes_a/lanes_at)   [0] */
+    int32_t tile_nnz;       /* LDS tiles: nonzeros per tile, 256..8192 (0 = 2048) */
+    int32_t tile_rows;      /* LDS tiles: rows per tile, 1..512 (0 = 512)           */
+    int32_t short_row;      /* LDS tiles: longer rows are summed by a wavefront (0 = 32) */
     int32_t lanes_a;        /* lanes per row for A SpMVs (0 = planner)     [0] */
     int32_t lanes_at;       /* lanes per row for A^T SpMVs (0 = planner)   [0] */
     int32_t long_row;       /* rows longer than this use a whole wave (0 = planner) */

@@ -80,11 +80,23 @@ def _distinct_rows(counts: np.ndarray, m: int, rng: np.random.Generator) -> np.n
     if np.any(counts > m):
         raise ValueError("a column asks for more distinct rows than m")
     n = counts.size
-    colptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=colptr[1:])
-    nnz = int(colptr[-1])
-    colid = np.repeat(np.arange(n, dtype=np.int64), counts)
+    nnz = int(counts.sum())
     rows = rng.integers(0, m, size=nnz, dtype=np.int64)
+    if n and np.all(counts == counts[0]):
+        # equal counts: sort each column's rows as a row of an (n, k) array,
+        # which gives the same order as the general (column, row) sort below
+        k = int(counts[0])
+        r2 = rows.reshape(n, k)
+        while True:
+            r2.sort(axis=1)
+            dup = np.zeros_like(r2, dtype=bool)
+            if k > 1:
+                dup[:, 1:] = r2[:, 1:] == r2[:, :-1]
+            nd = int(dup.sum())
+            if nd == 0:
+                return r2.reshape(-1)
+            r2[dup] = rng.integers(0, m, size=nd, dtype=np.int64)
+    colid = np.repeat(np.arange(n, dtype=np.int64), counts)
     while True:
         order = np.lexsort((rows, colid))
         rows = rows[order]  # colid is already non-decreasing and stays so
@@ -199,13 +211,22 @@ def cfg3(seed: int = 0, nblocks: int = 64, bm: int = 30_000, bn: int = 120_000,
     # link rows: each picks link_nnz distinct columns among all n
     lcols = _distinct_rows(np.full(nlink, link_nnz, dtype=np.int64), n, rng)
     lrow_ids = np.repeat(np.arange(nlink, dtype=np.int64), link_nnz) + nblocks * bm
-    # merge into column-major order
-    all_cols = np.concatenate([np.repeat(np.arange(n, dtype=np.int64), per_col), lcols])
-    all_rows = np.concatenate([block_rows, lrow_ids])
-    order = np.lexsort((all_rows, all_cols))
-    all_cols = all_cols[order]
-    all_rows = all_rows[order]
-    counts = np.bincount(all_cols, minlength=n).astype(np.int64)
+    # merge into column-major order: each column's block rows (sorted, all
+    # below nblocks*bm) followed by its link rows in increasing order
+    lcount = np.bincount(lcols, minlength=n).astype(np.int64)
+    counts = per_col + lcount
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=colptr[1:])
+    all_rows = np.empty(int(colptr[-1]), dtype=np.int64)
+    pos = np.repeat(colptr[:-1], per_col) + np.tile(np.arange(per_col, dtype=np.int64), n)
+    all_rows[pos] = block_rows
+    del pos, block_rows
+    o = np.argsort(lcols, kind="stable")
+    scols = lcols[o]
+    lstart = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lcount, out=lstart[1:])
+    within = np.arange(scols.size, dtype=np.int64) - lstart[scols]
+    all_rows[colptr[scols] + per_col + within] = lrow_ids[o]
     vals = rng.standard_normal(all_rows.size)
     return planted_from_columns(m, counts, all_rows, vals, rng, name=f"cfg3_s{seed}",
                                 meta={"cfg": 3, "seed": seed, "nblocks": nblocks,

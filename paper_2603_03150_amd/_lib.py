@@ -19,7 +19,7 @@ OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_BAD_CSR, ERR_TRANSPOSE, ERR_HIP = -1, -2, -3, -4
 ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_NONFINITE = -5, -6, -7
 
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32acc32": 3}
 
 _i32, _i64, _f64, _p = C.c_int32, C.c_int64, C.c_double, C.c_void_p
 
@@ -38,7 +38,8 @@ class OptionsStruct(C.Structure):
                 ("halpern", _i32), ("restarts", _i32),
                 ("beta_suff", _f64), ("beta_nec", _f64), ("beta_art", _f64), ("pw_theta", _f64),
                 ("max_iter", _i64), ("time_limit_s", _f64),
-                ("validate", _i32), ("use_graph", _i32), ("spmv_kind", _i32), ("lanes_a", _i32), ("lanes_at", _i32),
+                ("validate", _i32), ("use_graph", _i32), ("spmv_kind", _i32), ("tile_nnz", _i32), ("tile_rows", _i32),
+                ("short_row", _i32), ("lanes_a", _i32), ("lanes_at", _i32),
                 ("long_row", _i32), ("kernel_timing", _i32), ("trace_iters", _i32),
                 ("trace_x", _p), ("trace_y", _p), ("trace_xhat", _p), ("trace_yhat", _p),
                 ("x_init", _p), ("y_init", _p)]

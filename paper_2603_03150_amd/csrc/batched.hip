@@ -55,7 +55,7 @@ struct BArgs {
     int32_t ruiz, pc, power_iters, eval_every, halpern, restarts;
 };
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, double* sh) {
     const int tid = threadIdx.x;
     const int r0 = a.row_off[inst], r1 = a.row_off[inst + 1];
@@ -80,7 +80,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     }
     __syncthreads();
 
-    const T rho = (T)a.rho, opr = (T)(1.0 + a.rho);
+    const double rho = a.rho, opr = 1.0 + a.rho;
     const int E = a.eval_every;
     int64_t k = 0;
     double R0 = NAN, R_prev = INFINITY;
@@ -92,52 +92,53 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         ++t;
         const bool is_eval = (t % E == 0) || (t == a.max_iter);
         const bool first = (k == 0);
-        const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
-        const T w = (T)w64, omw = (T)(1.0 - w64), st = (T)tau, sd = (T)sig;
+        const double w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
+        const double omw = 1.0 - w;
         double q[4] = {0.0, 0.0, 0.0, 0.0};
-        // primal step over the columns (rows of A^T)
+        // primal step over the columns (rows of A^T); float64 arithmetic,
+        // stored in T
         for (int j = tid; j < n; j += kBatchBlock) {
             const int g = c0 + j;
-            typename ValueOf<V>::acc s = 0;
+            Acc s = 0;
             for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz)
-                s += ld_val(a.at_vs, kz) * yL[a.at_col[kz] - r0];
-            const T o = a.x[g];
-            T hh = o - st * (a.ct[g] - (T)s);
-            hh = hh < (T)0 ? (T)0 : hh;
-            xbL[j] = (T)2 * hh - o;
-            const T an = a.x0[g];
-            a.x[g] = w * (opr * hh - rho * o) + omw * an;
+                s += (Acc)ld_val(a.at_vs, kz) * (Acc)yL[a.at_col[kz] - r0];
+            const double o = (double)a.x[g];
+            double hh = o - tau * ((double)a.ct[g] - (double)s);
+            hh = hh < 0.0 ? 0.0 : hh;
+            xbL[j] = (T)(2.0 * hh - o);
+            const double an = (double)a.x0[g];
+            a.x[g] = (T)(w * (opr * hh - rho * o) + omw * an);
             if (first || is_eval) {
-                const double d = (double)o - (double)hh;
+                const double d = o - hh;
                 q[0] += d * d;
             }
             if (is_eval) {
-                const double d = (double)hh - (double)an;
+                const double d = hh - an;
                 q[1] += d * d;
-                a.xhat[g] = hh;
-                a.xo[g] = a.d_col[g] * (double)hh;
+                a.xhat[g] = (T)hh;
+                a.xo[g] = a.d_col[g] * hh;
             }
         }
         __syncthreads();
         // dual step over the rows of A
         for (int i = tid; i < m; i += kBatchBlock) {
             const int g = r0 + i;
-            typename ValueOf<V>::acc s = 0;
+            Acc s = 0;
             for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz)
-                s += ld_val(a.a_vs, kz) * xbL[a.a_col[kz] - c0];
-            const T o = yL[i];
-            const T hh = o + sd * (a.bt[g] - (T)s);
-            const T an = a.y0[g];
-            yL[i] = w * (opr * hh - rho * o) + omw * an;
+                s += (Acc)ld_val(a.a_vs, kz) * (Acc)xbL[a.a_col[kz] - c0];
+            const double o = (double)yL[i];
+            const double hh = o + sig * ((double)a.bt[g] - (double)s);
+            const double an = (double)a.y0[g];
+            yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
             if (first || is_eval) {
-                const double d = (double)o - (double)hh;
+                const double d = o - hh;
                 q[2] += d * d;
             }
             if (is_eval) {
-                const double d = (double)hh - (double)an;
+                const double d = hh - an;
                 q[3] += d * d;
-                a.yhat[g] = hh;
-                a.yo[g] = a.d_row[g] * (double)hh;
+                a.yhat[g] = (T)hh;
+                a.yo[g] = a.d_row[g] * hh;
             }
         }
         __syncthreads();
@@ -238,7 +239,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     __syncthreads();
 }
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 __global__ __launch_bounds__(kBatchBlock) void k_batched(BArgs<T, V> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* yL = (T*)smem;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batched(BArgs<T, V> a) {
         const int qi = next;
         __syncthreads();
         if (qi >= a.B) break;  // uniform: every wave leaves once the queue is empty
-        solve_instance<T, V>(a, a.order[qi], yL, xbL, sh);
+        solve_instance<T, V, Acc>(a, a.order[qi], yL, xbL, sh);
     }
 }
 
@@ -280,7 +281,7 @@ __global__ void k_check_blockdiag(const int32_t* rowptr, const int32_t* col, con
 }
 
 struct BatchWs {
-    int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
+    int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at, *tnz_a, *tnz_at;
     BInst* info;
     double *d_row, *d_col, *pv, *pu, *pav, *partials, *red;
     void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
@@ -290,22 +291,24 @@ struct BatchWs {
 static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t n, int64_t nnz, int prec) {
     Carver cv(base, cap);
     BatchWs w;
-    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32 ? 4 : 2);
+    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
     const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
     w.order = cv.take<int32_t>(B);
     w.row_off = cv.take<int32_t>(B + 1);
     w.col_off = cv.take<int32_t>(B + 1);
     w.counter = cv.take<int32_t>(64);
     w.flags = cv.take<int32_t>(64);
-    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz) + 1);
-    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz) + 1);
+    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
+    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
+    w.tnz_a = cv.take<int32_t>(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
+    w.tnz_at = cv.take<int32_t>(max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
     w.info = cv.take<BInst>(B);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
     w.pv = cv.take<double>(n);
     w.pu = cv.take<double>(n);
     w.pav = cv.take<double>(m);
-    w.partials = cv.take<double>((size_t)std::max(max_tiles(m, nnz), max_tiles(n, nnz)) + 16);
+    w.partials = cv.take<double>((size_t)std::max(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault), max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault)) + 16);
     w.red = cv.take<double>(16);
     w.a_vs = cv.take<char>(nnz * vs);
     w.at_vs = cv.take<char>(nnz * vs);
@@ -342,7 +345,7 @@ static int lds_bytes_for(int max_m, int max_n, size_t ts) {
     return (int)(((size_t)max_m + (size_t)max_n) * ts + 16);
 }
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double eps, void* ws, size_t ws_bytes,
                         hipStream_t stream, double* x, double* y, double* z, double* r_p, double* r_d,
                         mipdhg_info* info) {
@@ -384,11 +387,18 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     if (o.validate) {
-        const std::vector<int32_t> ta = make_tiles(rpa, lp.m), tat = make_tiles(rpat, lp.n);
+        const std::vector<int32_t> ta = make_tiles(rpa, lp.m, kTileNnzDefault, kTileRowsDefault),
+                                   tat = make_tiles(rpat, lp.n, kTileNnzDefault, kTileRowsDefault);
+        const std::vector<int32_t> za = tile_offsets(ta, rpa), zat = tile_offsets(tat, rpat);
         MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
-        const TilePlan pa{lp.a_rowptr, w.tiles_a, (int32_t)ta.size() - 1, lp.m};
-        const TilePlan pat{lp.at_rowptr, w.tiles_at, (int32_t)tat.size() - 1, lp.n};
+        MIP_HIP(hipMemcpyAsync(w.tnz_a, za.data(), za.size() * 4, hipMemcpyHostToDevice, stream));
+        MIP_HIP(hipMemcpyAsync(w.tnz_at, zat.data(), zat.size() * 4, hipMemcpyHostToDevice, stream));
+        const TilePlan pa = make_tile_plan(lp.a_rowptr, w.tiles_a, w.tnz_a, (int32_t)ta.size() - 1, lp.m,
+                                           kTileNnzDefault, kTileRowsDefault, kShortRowDefault);
+        const TilePlan pat = make_tile_plan(lp.at_rowptr, w.tiles_at, w.tnz_at, (int32_t)tat.size() - 1, lp.n,
+                                            kTileNnzDefault, kTileRowsDefault, kShortRowDefault);
+        if ((rc = allow_validate_lds((int)std::max(tile_lds_bytes(pa, 8), tile_lds_bytes(pat, 8))))) return rc;
         if ((rc = validate_device(lp, pa, pat, w.flags, w.partials, w.red, stream))) return rc;
         MIP_HIP(hipMemsetAsync(w.flags, 0, 4, stream));
         hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.a_rowptr, lp.a_col,
@@ -455,8 +465,8 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     int dev = 0, cus = 256, per_cu = 1;
     MIP_HIP(hipGetDevice(&dev));
     MIP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MIP_HIP(hipFuncSetAttribute((const void*)k_batched<T, V>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V>, kBatchBlock, lds));
+    MIP_HIP(hipFuncSetAttribute((const void*)k_batched<T, V, Acc>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V, Acc>, kBatchBlock, lds));
     const int grid = std::max(1, std::min(B, cus * std::max(per_cu, 1)));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, w.counter, 64);
     const auto t1 = clk::now();
@@ -464,7 +474,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     MIP_HIP(hipEventCreate(&e0));
     MIP_HIP(hipEventCreate(&e1));
     MIP_HIP(hipEventRecord(e0, stream));
-    hipLaunchKernelGGL((k_batched<T, V>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
     MIP_LAUNCH_CHECK();
     MIP_HIP(hipEventRecord(e1, stream));
     std::vector<BInst> res(B);
@@ -541,13 +551,16 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
-            return batched_impl<double, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
-                                                info);
+            return batched_impl<double, double, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
+                                                        r_p, r_d, info);
         case MIPDHG_FP32:
-            return batched_impl<float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
-                                              info);
+            return batched_impl<float, float, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                      r_d, info);
+        case MIPDHG_FP32_BF16A:
+            return batched_impl<float, uint16_t, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
+                                                         r_p, r_d, info);
         default:
-            return batched_impl<float, uint16_t>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
-                                                 r_d, info);
+            return batched_impl<float, float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                     r_d, info);
     }
 }

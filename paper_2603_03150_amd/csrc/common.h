@@ -194,36 +194,64 @@ __device__ __forceinline__ void for_rows(const RowPlan& p, Dot dot, Epi epi) {
 // ---------------------------------------------------------------------------
 // nnz-balanced tiles staged through LDS
 // ---------------------------------------------------------------------------
-// A tile is a run of consecutive rows holding at most kTileNnz nonzeros and
-// kTileRows rows; a row with more than kTileNnz nonzeros is a tile of its own
+// A tile is a run of consecutive rows holding at most tile_nnz nonzeros and
+// tile_rows rows; a row with more than tile_nnz nonzeros is a tile of its own
 // ("huge" row).  One workgroup per tile:
+//   0. the epilogue's per-row vector reads for the tile's rows are issued
+//      (Epi::load) so that their latency overlaps the products;
 //   1. the tile's row offsets go to LDS and every product val[k]*x[col[k]] of
-//      the tile is computed with kTileNnz/kBlock independent gathers per
+//      the tile is computed with tile_nnz/kBlock independent gathers per
 //      thread and stored in LDS;
-//   2. rows of at most kShortRow products are summed by one thread each (so
-//      the row epilogue reads and writes consecutive vector entries);
-//   3. the longer rows of the tile, listed in row order, are summed by one
-//      wavefront each.
+//   2. rows of at most short_row products are summed by one thread each, the
+//      longer rows (listed in row order) by one wavefront each; sums go to LDS;
+//   3. the epilogue runs for all rows in parallel, one thread per row, so its
+//      vector reads and writes are coalesced.
 // Every sum is taken in a fixed order, so results do not depend on timing.
-constexpr int kTileNnz = 2048;
-constexpr int kTileRows = 512;
-constexpr int kShortRow = 32;
-constexpr int kTileLong = kTileNnz / (kShortRow + 1) + 1;
+// `active` (uniform) is checked after the products, before anything is
+// written: a kernel can load its control word early and still be a no-op.
+constexpr int kTileNnzDefault = 2048;
+constexpr int kTileRowsDefault = 512;
+constexpr int kShortRowDefault = 32;
+constexpr int kMaxTileRows = 512;   // bound of the per-thread prefetch
+constexpr int kMaxTileNnz = 8192;
+constexpr int kRowsPerThread = kMaxTileRows / kBlock;
 
 struct TilePlan {
     const int32_t* rowptr;
     const int32_t* tile_row;  // [ntiles + 1] first row of each tile
+    const int32_t* tile_nz;   // [ntiles + 1] rowptr[tile_row[t]]
     int32_t ntiles;
     int32_t nrows;
+    int32_t tile_nnz;   // nonzeros per tile (LDS products)
+    int32_t tile_rows;  // rows per tile, <= kMaxTileRows
+    int32_t short_row;  // rows up to this length are summed by one thread
+    int32_t max_long;   // tile_nnz / (short_row + 1) + 1
+};
+
+// The tile's LDS, carved from dynamic shared memory.
+template <typename Acc>
+struct TileLds {
+    Acc* prod;
+    Acc* sum;
+    int32_t* row;
+    int32_t* list;
+    int32_t* wcount;
 };
 
 template <typename Acc>
-struct TileLds {
-    Acc prod[kTileNnz];
-    int32_t row[kTileRows + 1];
-    int32_t list[kTileLong];
-    int32_t wcount[kBlock / kWave];
-};
+__device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const TilePlan& p) {
+    TileLds<Acc> L;
+    L.prod = (Acc*)smem;
+    L.sum = L.prod + p.tile_nnz;
+    L.row = (int32_t*)(L.sum + p.tile_rows);
+    L.list = L.row + p.tile_rows + 1;
+    L.wcount = L.list + p.max_long;
+    return L;
+}
+
+inline size_t tile_lds_bytes(const TilePlan& p, size_t acc) {
+    return acc * (size_t)(p.tile_nnz + p.tile_rows) + 4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) + 16;
+}
 
 template <bool MAXOP, typename Acc>
 __device__ __forceinline__ Acc red_op(Acc a, Acc b) {
@@ -237,31 +265,58 @@ __device__ __forceinline__ Acc wave_red(Acc v) {
     return v;
 }
 
-// prod(k) -> Acc for a global nonzero index k; epi(row, total) per row.
+// Epilogue without prefetched values, from a lambda f(row, sum).
+struct NoPre {};
+template <class F>
+struct LambdaEpi {
+    F f;
+    typedef NoPre Pre;
+    __device__ __forceinline__ NoPre load(int) const { return NoPre{}; }
+    template <class A>
+    __device__ __forceinline__ void apply(int r, const NoPre&, A s) const {
+        f(r, s);
+    }
+};
+template <class F>
+__device__ __forceinline__ LambdaEpi<F> lepi(F f) {
+    return LambdaEpi<F>{f};
+}
+
+// prod(k) -> Acc for a global nonzero index k.  Epi provides
+// Pre load(row) and apply(row, pre, total).
 template <bool MAXOP, typename Acc, class Prod, class Epi>
-__device__ __forceinline__ void tiled_rows(const TilePlan& p, TileLds<Acc>& L, Prod prod, Epi epi) {
+__device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>& L, Prod prod, const Epi& epi,
+                                           bool active = true) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     const int t = xcd_virtual_block(blockIdx.x, gridDim.x);
     const int r0 = p.tile_row[t];
     const int r1 = p.tile_row[t + 1];
-    const int s = p.rowptr[r0];
-    const int e = p.rowptr[r1];
+    const int s = p.tile_nz[t];
+    const int e = p.tile_nz[t + 1];
     const int nr = r1 - r0;
     const int nz = e - s;
-    if (nz > kTileNnz) {  // one huge row: the whole workgroup strides over it
+    if (nz > p.tile_nnz) {  // one huge row: the whole workgroup strides over it
+        typename Epi::Pre pre0;
+        if (tid == 0) pre0 = epi.load(r0);
         Acc a = 0;
         for (int k = s + tid; k < e; k += kBlock) a = red_op<MAXOP>(a, prod(k));
         a = wave_red<MAXOP>(a);
         if (lane == 0) L.prod[wave] = a;
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && active) {
             Acc tot = L.prod[0];
             for (int w = 1; w < kBlock / kWave; ++w) tot = red_op<MAXOP>(tot, L.prod[w]);
-            epi(r0, tot);
+            epi.apply(r0, pre0, tot);
         }
         return;
+    }
+    typename Epi::Pre pre[kRowsPerThread];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int i = tid + q * kBlock;
+        if (i < nr) pre[q] = epi.load(r0 + i);
     }
     for (int i = tid; i <= nr; i += kBlock) L.row[i] = p.rowptr[r0 + i] - s;
     {
@@ -277,16 +332,17 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, TileLds<Acc>& L, P
         for (; k < nz; k += kBlock) L.prod[k] = prod(s + k);
     }
     __syncthreads();
+    if (!active) return;  // uniform
     int nlist = 0;
     for (int base = 0; base < nr; base += kBlock) {
         const int i = base + tid;
         bool lng = false;
         if (i < nr) {
             const int a = L.row[i], b = L.row[i + 1];
-            if (b - a <= kShortRow) {
+            if (b - a <= p.short_row) {
                 Acc acc = 0;
                 for (int q = a; q < b; ++q) acc = red_op<MAXOP>(acc, L.prod[q]);
-                epi(r0 + i, acc);
+                L.sum[i] = acc;
             } else {
                 lng = true;
             }
@@ -309,13 +365,21 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, TileLds<Acc>& L, P
         Acc acc = 0;
         for (int q = a + lane; q < b; q += kWave) acc = red_op<MAXOP>(acc, L.prod[q]);
         acc = wave_red<MAXOP>(acc);
-        if (lane == 0) epi(r0 + i, acc);
+        if (lane == 0) L.sum[i] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int i = tid + q * kBlock;
+        if (i < nr) epi.apply(r0 + i, pre[q], L.sum[i]);
     }
 }
 
-std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows);
-inline int64_t max_tiles(int64_t nrows, int64_t nnz) {
-    return 2 * (nnz / kTileNnz + nrows / kTileRows) + 4;
+std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
+                                int32_t tile_rows);
+std::vector<int32_t> tile_offsets(const std::vector<int32_t>& tiles, const std::vector<int32_t>& rowptr);
+inline int64_t max_tiles(int64_t nrows, int64_t nnz, int64_t tile_nnz, int64_t tile_rows) {
+    return 2 * (nnz / tile_nnz + nrows / tile_rows) + 4;
 }
 
 // Run-time lane count dispatch for the setup kernels.

@@ -78,10 +78,11 @@ template <bool MAXMODE>
 __global__ __launch_bounds__(kBlock) void k_scale_stat(TilePlan p, const int32_t* col, const double* val,
                                                        const double* d_self, const double* d_other,
                                                        double* stat) {
-    __shared__ TileLds<double> L;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, p);
     auto prod = [&](int k) { return fabs(val[k]) * d_other[col[k]]; };
     auto epi = [&](int r, double a) { stat[r] = d_self[r] * a; };
-    tiled_rows<MAXMODE>(p, L, prod, epi);
+    tiled_rows<MAXMODE>(p, L, prod, lepi(epi));
 }
 
 // d[i] *= 1/sqrt(stat[i]) (1 for an empty row or column)
@@ -138,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const dou
 __global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_t* col, const double* val,
                                                         const double* d_self, const double* d_other,
                                                         const double* x, double* y, double* partials) {
-    __shared__ TileLds<double> L;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
     auto prod = [&](int k) {
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_
         y[r] = t;
         s[0] += t * t;
     };
-    tiled_rows<false>(p, L, prod, epi);
+    tiled_rows<false>(p, L, prod, lepi(epi));
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
@@ -198,38 +200,61 @@ struct IterArgs {
 
 // Per-row epilogue of the primal (PRIMAL) or dual step, shared by both SpMV
 // traversals.  q accumulates the three partial sums described in IterArgs.
+// load() fetches the row's vector entries ahead of the SpMV; apply() finishes.
+template <typename T>
+struct IterPre {
+    T o, an, rhs;
+    double ds;
+};
+
 template <typename T, typename V, bool PRIMAL>
 struct IterEpi {
     const IterArgs<T, V>& a;
-    T w, omw, rho, opr, st;
+    double w, omw, rho, opr, st;
     int flags;
     double* q;
+    typedef IterPre<T> Pre;
+    __device__ __forceinline__ Pre load(int r) const {
+        Pre p;
+        p.o = a.state[r];
+        p.an = a.anchor[r];
+        p.rhs = a.rhs[r];
+        p.ds = (flags & F_EVAL) ? a.dscale[r] : 0.0;
+        return p;
+    }
+    // The arithmetic is float64 whatever the storage type T: the stored
+    // iterates are rounded once, at the store.
     template <typename Acc>
-    __device__ __forceinline__ void operator()(int r, Acc s) const {
-        const T o = a.state[r];
-        T h;
+    __device__ __forceinline__ void apply(int r, const Pre& p, Acc s) const {
+        const double o = (double)p.o;
+        double h;
         if (PRIMAL) {
-            const T g = a.rhs[r] - (T)s;
+            const double g = (double)p.rhs - (double)s;
             h = o - st * g;
-            h = h < (T)0 ? (T)0 : h;  // projection onto x >= 0 (NaN propagates)
-            a.bar[r] = (T)2 * h - o;
+            h = h < 0.0 ? 0.0 : h;  // projection onto x >= 0 (NaN propagates)
+            a.bar[r] = (T)(2.0 * h - o);
         } else {
-            h = o + st * (a.rhs[r] - (T)s);
+            h = o + st * ((double)p.rhs - (double)s);
         }
-        if (flags & F_HAT) a.hat[r] = h;
-        const T an = a.anchor[r];
-        a.state[r] = w * (opr * h - rho * o) + omw * an;
+        if (flags & F_HAT) a.hat[r] = (T)h;
+        const double an = (double)p.an;
+        a.state[r] = (T)(w * (opr * h - rho * o) + omw * an);
         if (flags & (F_FIRST | F_EVAL)) {
-            double d = (double)o - (double)h;
+            double d = o - h;
             d *= d;
             if (flags & F_FIRST) q[0] += d;
             if (flags & F_EVAL) q[1] += d;
         }
         if (flags & F_EVAL) {
-            const double d = (double)h - (double)an;
+            const double d = h - an;
             q[2] += d * d;
-            a.out64[r] = a.dscale[r] * (double)h;
+            a.out64[r] = p.ds * h;
         }
+    }
+    // lane-group traversal: load and apply at once
+    template <typename Acc>
+    __device__ __forceinline__ void operator()(int r, Acc s) const {
+        apply(r, load(r), s);
     }
 };
 
@@ -238,8 +263,7 @@ __device__ __forceinline__ IterEpi<T, V, PRIMAL> make_epi(const IterArgs<T, V>& 
     const Ctrl* c = a.ctrl;
     const int64_t k = c->k_base + a.it;
     const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
-    IterEpi<T, V, PRIMAL> e{a, (T)w64, (T)(1.0 - w64), (T)a.rho, (T)(1.0 + a.rho),
-                            (T)(PRIMAL ? c->tau : c->sigma), a.flags, q};
+    IterEpi<T, V, PRIMAL> e{a, w64, 1.0 - w64, a.rho, 1.0 + a.rho, PRIMAL ? c->tau : c->sigma, a.flags, q};
     return e;
 }
 
@@ -248,13 +272,12 @@ __device__ __forceinline__ unsigned iter_store_mask(int flags) {
     return ((flags & F_FIRST) ? 1u : 0u) | ((flags & F_EVAL) ? 6u : 0u);
 }
 
-// lane-group traversal (RowPlan)
-template <typename T, typename V, int L, bool PRIMAL>
+// lane-group traversal (RowPlan); SpMV accumulated in Acc
+template <typename T, typename V, typename Acc, int L, bool PRIMAL>
 __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
     if (a.ctrl->status != ST_RUNNING) return;
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    typedef typename ValueOf<V>::acc Acc;
     const auto epi = make_epi<T, V, PRIMAL>(a, q);
     auto dot = [&](int s, int e, int lane, int LL) {
         Acc acc = 0;
@@ -266,18 +289,20 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
     if (a.flags & (F_FIRST | F_EVAL)) block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
 
-// LDS-tiled traversal (TilePlan)
-template <typename T, typename V, bool PRIMAL>
+// LDS-tiled traversal (TilePlan).  The control word is loaded up front and
+// only checked once the products are in LDS.
+template <typename T, typename V, typename Acc, bool PRIMAL>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
-    if (a.ctrl->status != ST_RUNNING) return;
-    typedef typename ValueOf<V>::acc Acc;
-    __shared__ TileLds<Acc> L;
+    const bool active = a.ctrl->status == ST_RUNNING;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
     const auto epi = make_epi<T, V, PRIMAL>(a, q);
     auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
-    tiled_rows<false>(tp, L, prod, epi);
-    if (a.flags & (F_FIRST | F_EVAL)) block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+    tiled_rows<false>(tp, L, prod, epi, active);
+    if (active && (a.flags & (F_FIRST | F_EVAL)))
+        block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
 
 // ---------------------------------------------------------------------------
@@ -301,8 +326,9 @@ struct EvalArgs {
 
 template <bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
-    if (a.ctrl->status != ST_RUNNING) return;
-    __shared__ TileLds<double> L;
+    const bool active = a.ctrl->status == ST_RUNNING;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, tp);
     double s[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
     auto prod = [&](int k) { return ld_val(a.val, k) * a.gather[ld_idx(a.col, k)]; };
@@ -327,8 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
             mx[0] = fmax(mx[0], fabs(rd));
         }
     };
-    tiled_rows<false>(tp, L, prod, epi);
-    block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
+    tiled_rows<false>(tp, L, prod, lepi(epi), active);
+    if (active) block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -526,25 +552,32 @@ RowPlan device_plan(const HostPlan& hp, const int32_t* rowptr, const int32_t* lo
     return p;
 }
 
-// Greedy cut of the rows into tiles of at most kTileNnz nonzeros and kTileRows
-// rows; a row longer than kTileNnz is a tile by itself.
-std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows) {
+// Greedy cut of the rows into tiles of at most tile_nnz nonzeros and tile_rows
+// rows; a row longer than tile_nnz is a tile by itself.
+std::vector<int32_t> tile_offsets(const std::vector<int32_t>& tiles, const std::vector<int32_t>& rowptr) {
+    std::vector<int32_t> z(tiles.size());
+    for (size_t i = 0; i < tiles.size(); ++i) z[i] = rowptr[tiles[i]];
+    return z;
+}
+
+std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
+                                int32_t tile_rows) {
     std::vector<int32_t> t;
-    t.reserve((size_t)max_tiles(nrows, rowptr[nrows]) + 1);
+    t.reserve((size_t)max_tiles(nrows, rowptr[nrows], tile_nnz, tile_rows) + 1);
     t.push_back(0);
     int32_t r = 0;
     while (r < nrows) {
         const int32_t len = rowptr[r + 1] - rowptr[r];
-        if (len > kTileNnz) {
+        if (len > tile_nnz) {
             t.push_back(r + 1);
             ++r;
             continue;
         }
         const int32_t start = r;
         int64_t nz = 0;
-        while (r < nrows && r - start < kTileRows) {
+        while (r < nrows && r - start < tile_rows) {
             const int32_t l = rowptr[r + 1] - rowptr[r];
-            if (l > kTileNnz || nz + l > kTileNnz) break;
+            if (l > tile_nnz || nz + l > tile_nnz) break;
             nz += l;
             ++r;
         }
@@ -554,6 +587,25 @@ std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrow
 }
 
 
+int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
+int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
+int32_t short_row_of(const mipdhg_options& o) { return o.short_row > 0 ? o.short_row : kShortRowDefault; }
+
+TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* tile_row, const int32_t* tile_nz, int32_t ntiles,
+                        int32_t nrows, int32_t tnz, int32_t trows, int32_t srow) {
+    TilePlan p;
+    p.rowptr = rowptr;
+    p.tile_row = tile_row;
+    p.tile_nz = tile_nz;
+    p.ntiles = ntiles;
+    p.nrows = nrows;
+    p.tile_nnz = tnz;
+    p.tile_rows = trows;
+    p.short_row = srow;
+    p.max_long = tnz / (srow + 1) + 1;
+    return p;
+}
+
 // Workspace layout (identical for the size query and the solve).
 struct PlainWs {
     Ctrl* ctrl;
@@ -562,16 +614,17 @@ struct PlainWs {
     int64_t gcap;  // partial slots per kernel
     void *a_vs, *at_vs;
     void *x, *xbar, *x0, *xhat, *ct, *y, *y0, *yhat, *bt;
-    int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
+    int32_t *long_a, *long_at, *tiles_a, *tiles_at, *tnz_a, *tnz_at, *flags;
     size_t bytes;
 };
 
-static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters) {
+static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
+                     int64_t tnz, int64_t trows) {
     Carver cv(base, cap);
     PlainWs w;
-    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32 ? 4 : 2);
+    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
     const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
-    w.gcap = std::max<int64_t>(kMaxRowBlocks, std::max(max_tiles(m, nnz), max_tiles(n, nnz)));
+    w.gcap = std::max<int64_t>(kMaxRowBlocks, std::max(max_tiles(m, nnz, tnz, trows), max_tiles(n, nnz, tnz, trows)));
     w.ctrl = cv.take<Ctrl>(1);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
@@ -600,15 +653,17 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.bt = cv.take<char>(m * ts);
     w.long_a = cv.take<int32_t>(m);
     w.long_at = cv.take<int32_t>(n);
-    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz) + 1);
-    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz) + 1);
+    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz, tnz, trows) + 1);
+    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz, tnz, trows) + 1);
+    w.tnz_a = cv.take<int32_t>(max_tiles(m, nnz, tnz, trows) + 1);
+    w.tnz_at = cv.take<int32_t>(max_tiles(n, nnz, tnz, trows) + 1);
     w.flags = cv.take<int32_t>(64);
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
 
 int check_options(const mipdhg_options* o) {
-    if (o->precision < 0 || o->precision > 2) return set_error("precision must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
+    if (o->precision < 0 || o->precision > 3) return set_error("precision must be 0, 1, 2 or 3"), MIPDHG_ERR_INVALID_ARG;
     if (o->ruiz_iters < 0 || o->power_iters < 1 || o->power_iters > 100000)
         return set_error("ruiz_iters >= 0 and 1 <= power_iters <= 100000 required"), MIPDHG_ERR_INVALID_ARG;
     if (o->eval_every < 1 || o->eval_every > 4096)
@@ -618,6 +673,11 @@ int check_options(const mipdhg_options* o) {
     if (o->max_iter < 1) return set_error("max_iter must be >= 1"), MIPDHG_ERR_INVALID_ARG;
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
     if (o->spmv_kind != 0 && o->spmv_kind != 1) return set_error("spmv_kind must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->tile_nnz != 0 && (o->tile_nnz < 256 || o->tile_nnz > kMaxTileNnz))
+        return set_error("tile_nnz must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
+    if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
+        return set_error("tile_rows must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
+    if (o->short_row < 0) return set_error("short_row must be >= 0"), MIPDHG_ERR_INVALID_ARG;
     for (int L : {o->lanes_a, o->lanes_at})
         if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
             return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
@@ -655,13 +715,14 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     int rc = check_lp(lp);
     if (rc) return rc;
     if ((rc = check_options(opt))) return rc;
-    *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters).bytes;
+    *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
+                   tile_rows_of(*opt)).bytes;
     return 0;
 }
 
 namespace mip {
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 struct Solver {
     const mipdhg_lp& lp;
     const mipdhg_options& o;
@@ -682,6 +743,20 @@ struct Solver {
         for (auto e : tev) (void)hipEventDestroy(e);
     }
     bool tiled() const { return o.spmv_kind == 0; }
+    // dynamic LDS beyond 64 KiB must be allowed per kernel
+    int allow_tile_lds() {
+        const size_t need = std::max(tile_lds_bytes(ta, 8), tile_lds_bytes(tat, 8));
+        if (need <= 65536) return 0;
+        const int lim = (int)need;
+        const void* ks[] = {(const void*)k_iter_tiled<T, V, Acc, true>, (const void*)k_iter_tiled<T, V, Acc, false>,
+                            (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
+                            (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
+        for (const void* k : ks)
+            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+                return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
+                       MIPDHG_ERR_UNSUPPORTED;
+        return allow_validate_lds(lim);
+    }
     int grid_primal() const { return tiled() ? tat.ntiles : hpat.grid(); }
     int grid_dual() const { return tiled() ? ta.ntiles : hpa.grid(); }
 
@@ -708,9 +783,10 @@ struct Solver {
         IterArgs<T, V> a;
         fill_iter(a, true, it, flags);
         if (tiled()) {
-            hipLaunchKernelGGL((k_iter_tiled<T, V, true>), dim3(tat.ntiles), dim3(kBlock), 0, stream, a, tat);
+            hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, sizeof(Acc)),
+                               stream, a, tat);
         } else {
-            MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, L, true>), dim3(hpat.grid()), dim3(kBlock),
+            MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, true>), dim3(hpat.grid()), dim3(kBlock),
                                                          0, stream, a));
         }
         MIP_LAUNCH_CHECK();
@@ -720,9 +796,10 @@ struct Solver {
         IterArgs<T, V> a;
         fill_iter(a, false, it, flags);
         if (tiled()) {
-            hipLaunchKernelGGL((k_iter_tiled<T, V, false>), dim3(ta.ntiles), dim3(kBlock), 0, stream, a, ta);
+            hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, sizeof(Acc)),
+                               stream, a, ta);
         } else {
-            MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, L, false>), dim3(hpa.grid()), dim3(kBlock),
+            MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, false>), dim3(hpa.grid()), dim3(kBlock),
                                                         0, stream, a));
         }
         MIP_LAUNCH_CHECK();
@@ -739,7 +816,7 @@ struct Solver {
         er.out2 = nullptr;
         er.partials = w.per;
         er.ctrl = w.ctrl;
-        hipLaunchKernelGGL((k_eval<true>), dim3(ta.ntiles), dim3(kBlock), 0, stream, er, ta);
+        hipLaunchKernelGGL((k_eval<true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, er, ta);
         MIP_LAUNCH_CHECK();
         EvalArgs ec;
         ec.col = lp.at_col;
@@ -751,7 +828,7 @@ struct Solver {
         ec.out2 = rdo;
         ec.partials = w.pec;
         ec.ctrl = w.ctrl;
-        hipLaunchKernelGGL((k_eval<false>), dim3(tat.ntiles), dim3(kBlock), 0, stream, ec, tat);
+        hipLaunchKernelGGL((k_eval<false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, ec, tat);
         MIP_LAUNCH_CHECK();
         DecideArgs d;
         d.ctrl = w.ctrl;
@@ -820,14 +897,14 @@ struct Solver {
     }
 };
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, void* ws, size_t ws_bytes,
                       hipStream_t stream, double* x, double* y, double* z, double* r_p, double* r_d,
                       double* d_row, double* d_col, mipdhg_info* info) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
-    Solver<T, V> S(lp, o, stream);
-    S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters);
+    Solver<T, V, Acc> S(lp, o, stream);
+    S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o));
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -860,11 +937,16 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     S.pat = device_plan(S.hpat, lp.at_rowptr, w.long_at, lp.n);
     const int ga = S.hpa.grid(), gat = S.hpat.grid();
     {
-        const std::vector<int32_t> ta = make_tiles(rpa, lp.m), tat = make_tiles(rpat, lp.n);
+        const int32_t tnz = tile_nnz_of(o), trows = tile_rows_of(o), srow = short_row_of(o);
+        const std::vector<int32_t> ta = make_tiles(rpa, lp.m, tnz, trows), tat = make_tiles(rpat, lp.n, tnz, trows);
+        const std::vector<int32_t> za = tile_offsets(ta, rpa), zat = tile_offsets(tat, rpat);
         MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
-        S.ta = TilePlan{lp.a_rowptr, w.tiles_a, (int32_t)ta.size() - 1, lp.m};
-        S.tat = TilePlan{lp.at_rowptr, w.tiles_at, (int32_t)tat.size() - 1, lp.n};
+        MIP_HIP(hipMemcpyAsync(w.tnz_a, za.data(), za.size() * 4, hipMemcpyHostToDevice, stream));
+        MIP_HIP(hipMemcpyAsync(w.tnz_at, zat.data(), zat.size() * 4, hipMemcpyHostToDevice, stream));
+        S.ta = make_tile_plan(lp.a_rowptr, w.tiles_a, w.tnz_a, (int32_t)ta.size() - 1, lp.m, tnz, trows, srow);
+        S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, w.tnz_at, (int32_t)tat.size() - 1, lp.n, tnz, trows, srow);
+        if ((rc = S.allow_tile_lds())) return rc;
         MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
     }
     const int gta = S.ta.ntiles, gtat = S.tat.ntiles;
@@ -893,14 +975,14 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     for (int ps = 0; ps < passes; ++ps) {
         const bool maxmode = ps < o.ruiz_iters;
         if (maxmode) {
-            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta, lp.a_col, lp.a_val,
                                (const double*)w.d_row, (const double*)w.d_col, w.stat_r);
-            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col,
+            hipLaunchKernelGGL((k_scale_stat<true>), dim3(gtat), dim3(kBlock), tile_lds_bytes(S.tat, 8), stream, S.tat, lp.at_col,
                                lp.at_val, (const double*)w.d_col, (const double*)w.d_row, w.stat_c);
         } else {
-            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta, lp.a_col, lp.a_val,
                                (const double*)w.d_row, (const double*)w.d_col, w.stat_r);
-            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col,
+            hipLaunchKernelGGL((k_scale_stat<false>), dim3(gtat), dim3(kBlock), tile_lds_bytes(S.tat, 8), stream, S.tat, lp.at_col,
                                lp.at_val, (const double*)w.d_col, (const double*)w.d_row, w.stat_c);
         }
         hipLaunchKernelGGL(k_scale_update, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.d_row,
@@ -934,14 +1016,14 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.pv, n, v0);
         for (int k = 0; k <= o.power_iters; ++k) {
             // av = A~ v, hist[k] = ||av||^2
-            hipLaunchKernelGGL(k_spmv_scaled, dim3(gta), dim3(kBlock), 0, stream, S.ta, lp.a_col, lp.a_val,
+            hipLaunchKernelGGL(k_spmv_scaled, dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta, lp.a_col, lp.a_val,
                                (const double*)w.d_row, (const double*)w.d_col, (const double*)w.pv, w.pav,
                                w.psetup);
             hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gta, 1,
                                w.hist + k);
             if (k == o.power_iters) break;
             // u = A~^T av, v = u / ||u||
-            hipLaunchKernelGGL(k_spmv_scaled, dim3(gtat), dim3(kBlock), 0, stream, S.tat, lp.at_col, lp.at_val,
+            hipLaunchKernelGGL(k_spmv_scaled, dim3(gtat), dim3(kBlock), tile_lds_bytes(S.tat, 8), stream, S.tat, lp.at_col, lp.at_val,
                                (const double*)w.d_col, (const double*)w.d_row, (const double*)w.pav, w.pu,
                                w.psetup + G);
             hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, 1024)), dim3(kBlock), 0, stream, (const double*)w.pu,
@@ -1162,13 +1244,16 @@ extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, doub
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
-            return solve_impl<double, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
-                                              d_row, d_col, info);
+            return solve_impl<double, double, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                      r_d, d_row, d_col, info);
         case MIPDHG_FP32:
-            return solve_impl<float, float>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p, r_d,
-                                            d_row, d_col, info);
+            return solve_impl<float, float, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                    r_d, d_row, d_col, info);
+        case MIPDHG_FP32_BF16A:
+            return solve_impl<float, uint16_t, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
+                                                       r_p, r_d, d_row, d_col, info);
         default:
-            return solve_impl<float, uint16_t>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
-                                               r_d, d_row, d_col, info);
+            return solve_impl<float, float, float>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                   r_d, d_row, d_col, info);
     }
 }

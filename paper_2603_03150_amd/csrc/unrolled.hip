@@ -77,54 +77,52 @@ struct UInst {
 // weight from k.  With masks != nullptr the projection masks are stored.
 // Returns q = (||x-x^||^2, ||x^-x0||^2, ||y-y^||^2, ||y^-y0||^2) partials of
 // this thread when `want_q`.
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V>& u, T* yL, T* xbL, int64_t k,
                                           double tau, double sig, bool want_q, bool keep_hat, bool last,
                                           uint64_t* maskrow, double (&q)[4]) {
     const int tid = threadIdx.x;
-    const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
-    const T w = (T)w64, omw = (T)(1.0 - w64), st = (T)tau, sd = (T)sig;
-    const T rho = (T)a.rho, opr = (T)(1.0 + a.rho);
-    typedef typename ValueOf<V>::acc Acc;
+    const double w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
+    const double omw = 1.0 - w, rho = a.rho, opr = 1.0 + a.rho;
     for (int j = tid; j < u.n; j += kBatchBlock) {
         const int g = u.c0 + j;
         Acc s = 0;
         for (int kz = a.M.at_rowptr[g]; kz < a.M.at_rowptr[g + 1]; ++kz)
-            s += ld_val(a.at_vs, kz) * (Acc)yL[a.M.at_col[kz] - u.r0];
-        const T o = a.x[g];
-        const T v = o - st * (a.ct[g] - (T)s);
-        const T hh = v < (T)0 ? (T)0 : v;
+            s += (Acc)ld_val(a.at_vs, kz) * (Acc)yL[a.M.at_col[kz] - u.r0];
+        const double o = (double)a.x[g];
+        const double v = o - tau * ((double)a.ct[g] - (double)s);
+        const double hh = v < 0.0 ? 0.0 : v;
         if (maskrow) {
-            const unsigned long long bits = __ballot(v > (T)0);
+            const unsigned long long bits = __ballot(v > 0.0);
             if ((tid & (kWave - 1)) == 0) maskrow[j >> 6] = bits;
         }
-        xbL[j] = (T)2 * hh - o;
-        const T an = a.x0[g];
-        a.x[g] = w * (opr * hh - rho * o) + omw * an;
+        xbL[j] = (T)(2.0 * hh - o);
+        const double an = (double)a.x0[g];
+        a.x[g] = (T)(w * (opr * hh - rho * o) + omw * an);
         if (want_q) {
-            const double d = (double)o - (double)hh, e = (double)hh - (double)an;
+            const double d = o - hh, e = hh - an;
             q[0] += d * d;
             q[1] += e * e;
         }
-        if (keep_hat) a.xhat[g] = hh;
-        if (last) a.xK[g] = a.d_col[g] * (double)hh;
+        if (keep_hat) a.xhat[g] = (T)hh;
+        if (last) a.xK[g] = a.d_col[g] * hh;
     }
     __syncthreads();
     for (int i = tid; i < u.m; i += kBatchBlock) {
         const int g = u.r0 + i;
         Acc s = 0;
         for (int kz = a.M.a_rowptr[g]; kz < a.M.a_rowptr[g + 1]; ++kz)
-            s += ld_val(a.a_vs, kz) * (Acc)xbL[a.M.a_col[kz] - u.c0];
-        const T o = yL[i];
-        const T hh = o + sd * (a.bt[g] - (T)s);
-        const T an = a.y0[g];
-        yL[i] = w * (opr * hh - rho * o) + omw * an;
+            s += (Acc)ld_val(a.a_vs, kz) * (Acc)xbL[a.M.a_col[kz] - u.c0];
+        const double o = (double)yL[i];
+        const double hh = o + sig * ((double)a.bt[g] - (double)s);
+        const double an = (double)a.y0[g];
+        yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
         if (want_q) {
-            const double d = (double)o - (double)hh, e = (double)hh - (double)an;
+            const double d = o - hh, e = hh - an;
             q[2] += d * d;
             q[3] += e * e;
         }
-        if (keep_hat) a.yhat[g] = hh;
+        if (keep_hat) a.yhat[g] = (T)hh;
     }
     __syncthreads();
 }
@@ -145,7 +143,7 @@ __device__ __forceinline__ void u_restart(const UArgs<T, V>& a, const UInst<T, V
     __syncthreads();
 }
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 __device__ void forward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* yL, T* xbL, double* sh) {
     const int tid = threadIdx.x, i = u.inst, B = a.B;
     const InstSetup su = inst_setup<T, V>(a.M, u.r0, u.r1, u.c0, u.c1, a.d_row, a.d_col, a.pv, a.pu, a.pav,
@@ -199,7 +197,7 @@ __device__ void forward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* 
         const bool first = k == 0;
         const bool need_q = !a.replay && (first || at_eval);
         double q[4] = {0.0, 0.0, 0.0, 0.0};
-        u_iterate<T, V>(a, u, yL, xbL, k, tau, sig, need_q, at_eval, t == a.K, nullptr, q);
+        u_iterate<T, V, Acc>(a, u, yL, xbL, k, tau, sig, need_q, at_eval, t == a.K, nullptr, q);
         if (need_q) wg_reduce<4, 0>(q, nomax, sh);
         if (!a.replay && first) R0 = sqrt(omega * q[0] + q[2] / omega);
         ++k;
@@ -240,10 +238,9 @@ __device__ void forward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* 
     }
 }
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* yL, T* xbL) {
     const int tid = threadIdx.x, i = u.inst, B = a.B;
-    typedef typename ValueOf<V>::acc Acc;
     for (int j = tid; j < u.n; j += kBatchBlock) {
         const int g = u.c0 + j;
         a.lx[g] = (T)0;
@@ -256,7 +253,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
         a.ly0[g] = (T)0;
         a.lbt[g] = 0.0;
     }
-    const T rho = (T)a.rho, opr = (T)(1.0 + a.rho);
+    const double rho = a.rho, opr = 1.0 + a.rho;
     double qd[4];
     for (int seg = a.nseg - 1; seg >= 0; --seg) {
         const int tb = seg * a.ckpt, te = min(a.K, tb + a.ckpt);
@@ -281,7 +278,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
                 a.sbuf[(int64_t)it * B + i] = sig;
             }
             const bool rs = a.restart[(int64_t)(t - 1) * B + i] != 0;
-            u_iterate<T, V>(a, u, yL, xbL, k, tau, sig, false, rs, false,
+            u_iterate<T, V, Acc>(a, u, yL, xbL, k, tau, sig, false, rs, false,
                             a.masks + (int64_t)it * a.W + a.word_off[i], qd);
             ++k;
             if (rs) {
@@ -298,18 +295,18 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
             const int it = t - tb - 1;
             const bool rs = a.restart[(int64_t)(t - 1) * B + i] != 0;
             const int64_t kt = a.kbuf[(int64_t)it * B + i];
-            const double w64 = a.halpern ? (double)(kt + 1) / (double)(kt + 2) : 1.0;
-            const T w = (T)w64, omw = (T)(1.0 - w64);
-            const T tau = (T)a.tbuf[(int64_t)it * B + i], sig = (T)a.sbuf[(int64_t)it * B + i];
+            const double w = a.halpern ? (double)(kt + 1) / (double)(kt + 2) : 1.0;
+            const double omw = 1.0 - w;
+            const double tau = a.tbuf[(int64_t)it * B + i], sig = a.sbuf[(int64_t)it * B + i];
             // (R1) rows: adjoint of y_hat, of the previous y (partial) and anchor
             for (int r = tid; r < u.m; r += kBatchBlock) {
                 const int g = u.r0 + r;
-                const T ly = a.ly[g], ly0 = a.ly0[g];
-                const T lyh = rs ? ly + ly0 : w * opr * ly;
-                lyhL[r] = lyh;
-                a.ly[g] = (rs ? (T)0 : -w * rho * ly) + lyh;
-                a.ly0[g] = rs ? (T)0 : ly0 + omw * ly;
-                a.lbt[g] += (double)sig * (double)lyh;
+                const double ly = (double)a.ly[g], ly0 = (double)a.ly0[g];
+                const double lyh = rs ? ly + ly0 : w * opr * ly;
+                lyhL[r] = (T)lyh;
+                a.ly[g] = (T)((rs ? 0.0 : -w * rho * ly) + lyh);
+                a.ly0[g] = (T)(rs ? 0.0 : ly0 + omw * ly);
+                a.lbt[g] += sig * lyh;
             }
             __syncthreads();
             // (C) columns: lam_xbar = -sigma A~^T lam_yhat, then extrapolation,
@@ -319,18 +316,18 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
                 const int g = u.c0 + j;
                 Acc s = 0;
                 for (int kz = a.M.at_rowptr[g]; kz < a.M.at_rowptr[g + 1]; ++kz)
-                    s += ld_val(a.at_vs, kz) * (Acc)lyhL[a.M.at_col[kz] - u.r0];
-                const T lxbar = -sig * (T)s;
-                const T lx = a.lx[g], lx0 = a.lx0[g];
-                T lxh = (rs ? lx + lx0 : w * opr * lx) + (T)2 * lxbar;
-                if (t == a.K) lxh += (T)(a.d_col[g] * a.gx[g]);
+                    s += (Acc)ld_val(a.at_vs, kz) * (Acc)lyhL[a.M.at_col[kz] - u.r0];
+                const double lxbar = -sig * (double)s;
+                const double lx = (double)a.lx[g], lx0 = (double)a.lx0[g];
+                double lxh = (rs ? lx + lx0 : w * opr * lx) + 2.0 * lxbar;
+                if (t == a.K) lxh += a.d_col[g] * a.gx[g];
                 const bool on = (mrow[j >> 6] >> (j & 63)) & 1ull;
-                const T lv = on ? lxh : (T)0;
-                const T lg = -tau * lv;
-                a.lx[g] = (rs ? (T)0 : -w * rho * lx) - lxbar + lv;
-                a.lx0[g] = rs ? (T)0 : lx0 + omw * lx;
-                a.lct[g] += (double)lg;
-                lgL[j] = lg;
+                const double lv = on ? lxh : 0.0;
+                const double lg = -tau * lv;
+                a.lx[g] = (T)((rs ? 0.0 : -w * rho * lx) - lxbar + lv);
+                a.lx0[g] = (T)(rs ? 0.0 : lx0 + omw * lx);
+                a.lct[g] += lg;
+                lgL[j] = (T)lg;
             }
             __syncthreads();
             // (R2) rows: lam_y -= A~ lam_g
@@ -338,8 +335,8 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
                 const int g = u.r0 + r;
                 Acc s = 0;
                 for (int kz = a.M.a_rowptr[g]; kz < a.M.a_rowptr[g + 1]; ++kz)
-                    s += ld_val(a.a_vs, kz) * (Acc)lgL[a.M.a_col[kz] - u.c0];
-                a.ly[g] -= (T)s;
+                    s += (Acc)ld_val(a.a_vs, kz) * (Acc)lgL[a.M.a_col[kz] - u.c0];
+                a.ly[g] = (T)((double)a.ly[g] - (double)s);
             }
             __syncthreads();
         }
@@ -349,7 +346,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
     __syncthreads();
 }
 
-template <typename T, typename V, bool BACKWARD>
+template <typename T, typename V, typename Acc, bool BACKWARD>
 __global__ __launch_bounds__(kBatchBlock) void k_unrolled(UArgs<T, V> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* yL = (T*)smem;
@@ -370,8 +367,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_unrolled(UArgs<T, V> a) {
         u.c1 = a.col_off[qi + 1];
         u.m = u.r1 - u.r0;
         u.n = u.c1 - u.c0;
-        if (BACKWARD) backward_instance<T, V>(a, u, yL, xbL);
-        else forward_instance<T, V>(a, u, yL, xbL, sh);
+        if (BACKWARD) backward_instance<T, V, Acc>(a, u, yL, xbL);
+        else forward_instance<T, V, Acc>(a, u, yL, xbL, sh);
     }
 }
 
@@ -404,7 +401,7 @@ static TapeLayout carve_tape(void* base, size_t cap, const mipdhg_batch& bt, int
     Carver cv(base, cap);
     TapeLayout t;
     const int64_t B = bt.count, m = bt.whole.m, n = bt.whole.n, nnz = bt.whole.nnz;
-    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32 ? 4 : 2);
+    const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
     const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
     int64_t W = 0;
     for (int64_t i = 0; i < B; ++i) W += (bt.col_off[i + 1] - bt.col_off[i] + 63) / 64;
@@ -472,7 +469,7 @@ static int check_unrolled(const mipdhg_batch* bt, const mipdhg_options* o, int K
     return 0;
 }
 
-template <typename T, typename V>
+template <typename T, typename V, typename Acc>
 static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K, int ckpt, void* tape,
                          size_t tape_bytes, hipStream_t stream, bool backward, int replay, const double* gx,
                          double* out1, double* out2) {
@@ -583,20 +580,20 @@ static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K,
     MIP_HIP(hipGetDevice(&dev));
     MIP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (backward) {
-        MIP_HIP(hipFuncSetAttribute((const void*)k_unrolled<T, V, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        MIP_HIP(hipFuncSetAttribute((const void*)k_unrolled<T, V, Acc, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     lds));
-        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_unrolled<T, V, true>, kBatchBlock, lds));
+        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_unrolled<T, V, Acc, true>, kBatchBlock, lds));
     } else {
-        MIP_HIP(hipFuncSetAttribute((const void*)k_unrolled<T, V, false>,
+        MIP_HIP(hipFuncSetAttribute((const void*)k_unrolled<T, V, Acc, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_unrolled<T, V, false>, kBatchBlock, lds));
+        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_unrolled<T, V, Acc, false>, kBatchBlock, lds));
     }
     const int grid = std::max(1, std::min(B, cus * std::max(per_cu, 1)));
     hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(64), 0, stream, (uint8_t*)t.counter, (int64_t)256);
     if (backward)
-        hipLaunchKernelGGL((k_unrolled<T, V, true>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+        hipLaunchKernelGGL((k_unrolled<T, V, Acc, true>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
     else
-        hipLaunchKernelGGL((k_unrolled<T, V, false>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+        hipLaunchKernelGGL((k_unrolled<T, V, Acc, false>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
     MIP_LAUNCH_CHECK();
     MIP_HIP(hipStreamSynchronize(stream));
     return 0;
@@ -626,14 +623,17 @@ extern "C" int mipdhg_unrolled_forward(const mipdhg_batch* bt, const mipdhg_opti
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
-            return unrolled_impl<double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay, nullptr,
-                                                 x_K, nullptr);
+            return unrolled_impl<double, double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay,
+                                                         nullptr, x_K, nullptr);
         case MIPDHG_FP32:
-            return unrolled_impl<float, float>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay, nullptr,
-                                               x_K, nullptr);
+            return unrolled_impl<float, float, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay,
+                                                       nullptr, x_K, nullptr);
+        case MIPDHG_FP32_BF16A:
+            return unrolled_impl<float, uint16_t, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false,
+                                                          replay, nullptr, x_K, nullptr);
         default:
-            return unrolled_impl<float, uint16_t>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay,
-                                                  nullptr, x_K, nullptr);
+            return unrolled_impl<float, float, float>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay,
+                                                      nullptr, x_K, nullptr);
     }
 }
 
@@ -648,13 +648,16 @@ extern "C" int mipdhg_unrolled_backward(const mipdhg_batch* bt, const mipdhg_opt
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
-            return unrolled_impl<double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1, grad_xK,
-                                                 grad_c, grad_b);
+            return unrolled_impl<double, double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1,
+                                                         grad_xK, grad_c, grad_b);
         case MIPDHG_FP32:
-            return unrolled_impl<float, float>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1, grad_xK,
-                                               grad_c, grad_b);
+            return unrolled_impl<float, float, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1, grad_xK,
+                                                       grad_c, grad_b);
+        case MIPDHG_FP32_BF16A:
+            return unrolled_impl<float, uint16_t, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1,
+                                                          grad_xK, grad_c, grad_b);
         default:
-            return unrolled_impl<float, uint16_t>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1, grad_xK,
-                                                  grad_c, grad_b);
+            return unrolled_impl<float, float, float>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1, grad_xK,
+                                                      grad_c, grad_b);
     }
 }

@@ -45,7 +45,8 @@ __device__ __forceinline__ double hash_unit(uint32_t i, uint32_t seed) {
 template <bool ABS>
 __global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int32_t* col, const double* val,
                                                           uint32_t seed_row, uint32_t seed_col, double* partials) {
-    __shared__ TileLds<double> L;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
     auto prod = [&](int k) {
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int3
         const double u = hash_unit((uint32_t)r, seed_row);
         s[0] += (ABS ? fabs(u) : u) * t;
     };
-    tiled_rows<false>(p, L, prod, epi);
+    tiled_rows<false>(p, L, prod, lepi(epi));
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
@@ -71,6 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partials,
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = sh[0];
+}
+
+int allow_validate_lds(int bytes) {
+    if (bytes <= 65536) return 0;
+    if (hipFuncSetAttribute((const void*)k_transpose_dot<false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_transpose_dot<true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+            hipSuccess)
+        return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", bytes),
+               MIPDHG_ERR_UNSUPPORTED;
+    return 0;
 }
 
 int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat, int32_t* flags,
@@ -94,18 +106,18 @@ int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat
     if (nnz == 0) return 0;
     // u^T (A v) against v^T (A^T u), and the scale sum |u||A||v|
     const uint32_t su = 0x1234u, sv = 0xABCDu;
-    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(ta.ntiles), dim3(kBlock), 0, stream, ta, lp.a_col,
+    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, ta, lp.a_col,
                        lp.a_val, su, sv, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, ta.ntiles, red);
-    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(ta.ntiles), dim3(kBlock), 0, stream, ta, lp.a_col,
+    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, ta, lp.a_col,
                        lp.a_val, su, sv, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, ta.ntiles,
                        red + 1);
-    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(tat.ntiles), dim3(kBlock), 0, stream, tat, lp.at_col,
+    hipLaunchKernelGGL((k_transpose_dot<false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, tat, lp.at_col,
                        lp.at_val, sv, su, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, tat.ntiles,
                        red + 2);
-    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(tat.ntiles), dim3(kBlock), 0, stream, tat, lp.at_col,
+    hipLaunchKernelGGL((k_transpose_dot<true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, tat, lp.at_col,
                        lp.at_val, sv, su, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, stream, (const double*)partials, tat.ntiles,
                        red + 3);
