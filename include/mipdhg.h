@@ -254,6 +254,19 @@ int mipdhg_center_reclamp(int32_t n, double alpha_min, void *stream, double *x_i
  * 0 for anything else. */
 size_t mipdhg_sizeof(int which);
 
+/* Times every candidate shape of the two iteration SpMVs on this LP (lane
+ * groups; LDS tiles of 512..4096 nonzeros, 256 or 512 rows, short-row limit
+ * 32 or 128) for `iters` iterations each, with per-kernel hipEvents, and
+ * writes the fastest into opt (spmv_kind, tile_nnz, tile_rows, short_row).
+ * best_ms (host, nullable) receives its mean primal + dual time per
+ * iteration.  Arguments as for mipdhg_solve, whose output buffers are used as
+ * scratch; the workspace must be large enough for the smallest tiles, i.e. at
+ * least mipdhg_workspace_size() of opt with tile_nnz = 512, tile_rows = 256.
+ * Candidates that do not fit are skipped. */
+int mipdhg_autotune(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, void *workspace,
+                    size_t workspace_bytes, void *stream, double *x, double *y, double *z, double *r_p,
+                    double *r_d, double *best_ms);
+
 /* Text for a status or error code. */
 const char *mipdhg_status_string(int code);
 

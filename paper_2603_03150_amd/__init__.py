@@ -4,7 +4,7 @@ from ._lib import (  # noqa: F401
     OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, MipdhgError, load,
 )
 from .solver import (  # noqa: F401
-    BatchSolution, DeviceBatch, DeviceLP, Solution, batch_workspace_bytes, default_options, make_options,
+    BatchSolution, DeviceBatch, autotune, DeviceLP, Solution, batch_workspace_bytes, default_options, make_options,
     center_reclamp, center_start, solve, solve_batched, workspace_bytes,
 )
 from .unrolled import PDHGUnrolled, UnrolledMap  # noqa: F401

@@ -215,6 +215,7 @@ constexpr int kShortRowDefault = 32;
 constexpr int kMaxTileRows = 512;   // bound of the per-thread prefetch
 constexpr int kMaxTileNnz = 8192;
 constexpr int kRowsPerThread = kMaxTileRows / kBlock;
+constexpr int kProdUnroll = 8;  // products in flight per thread
 
 struct TilePlan {
     const int32_t* rowptr;
@@ -242,7 +243,7 @@ template <typename Acc>
 __device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const TilePlan& p) {
     TileLds<Acc> L;
     L.prod = (Acc*)smem;
-    L.sum = L.prod + p.tile_nnz;
+    L.sum = L.prod + p.tile_nnz + 1;  // prod[tile_nnz] is a dummy slot
     L.row = (int32_t*)(L.sum + p.tile_rows);
     L.list = L.row + p.tile_rows + 1;
     L.wcount = L.list + p.max_long;
@@ -250,7 +251,8 @@ __device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const Tile
 }
 
 inline size_t tile_lds_bytes(const TilePlan& p, size_t acc) {
-    return acc * (size_t)(p.tile_nnz + p.tile_rows) + 4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) + 16;
+    return acc * (size_t)(p.tile_nnz + 1 + p.tile_rows) + 4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) +
+           16;
 }
 
 template <bool MAXOP, typename Acc>
@@ -312,25 +314,32 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>
         }
         return;
     }
+    // Every load that does not depend on another is issued here, branch-free
+    // (indices clamped into the tile), so that their latencies overlap: the
+    // epilogue's vector entries, the row offsets, and the matrix entries of
+    // the first products.
     typename Epi::Pre pre[kRowsPerThread];
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
-        const int i = tid + q * kBlock;
-        if (i < nr) pre[q] = epi.load(r0 + i);
-    }
-    for (int i = tid; i <= nr; i += kBlock) L.row[i] = p.rowptr[r0 + i] - s;
-    {
-        int k = tid;
-        for (; k + 3 * kBlock < nz; k += 4 * kBlock) {
-            const Acc a0 = prod(s + k), a1 = prod(s + k + kBlock), a2 = prod(s + k + 2 * kBlock),
-                      a3 = prod(s + k + 3 * kBlock);
-            L.prod[k] = a0;
-            L.prod[k + kBlock] = a1;
-            L.prod[k + 2 * kBlock] = a2;
-            L.prod[k + 3 * kBlock] = a3;
+    for (int q = 0; q < kRowsPerThread; ++q) pre[q] = epi.load(r0 + min(tid + q * kBlock, nr - 1));
+    int rp[kRowsPerThread + 1];
+#pragma unroll
+    for (int q = 0; q <= kRowsPerThread; ++q) rp[q] = p.rowptr[r0 + min(tid + q * kBlock, nr)];
+    // products, kProdUnroll per thread in flight
+    for (int base = 0; base < nz; base += kProdUnroll * kBlock) {
+        Acc v[kProdUnroll];
+#pragma unroll
+        for (int u = 0; u < kProdUnroll; ++u) v[u] = prod(s + min(base + tid + u * kBlock, nz - 1));
+        // out-of-range lanes store to the dummy slot prod[tile_nnz], so the
+        // stores need no branch
+#pragma unroll
+        for (int u = 0; u < kProdUnroll; ++u) {
+            const int k = base + tid + u * kBlock;
+            L.prod[k < nz ? k : p.tile_nnz] = v[u];
         }
-        for (; k < nz; k += kBlock) L.prod[k] = prod(s + k);
     }
+#pragma unroll
+    for (int q = 0; q <= kRowsPerThread; ++q)
+        if (tid + q * kBlock <= nr) L.row[tid + q * kBlock] = rp[q] - s;
     __syncthreads();
     if (!active) return;  // uniform
     int nlist = 0;

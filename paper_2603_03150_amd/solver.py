@@ -95,6 +95,26 @@ def workspace_bytes(dlp: DeviceLP, precision: str = "fp64", **opts) -> int:
     return int(nb.value)
 
 
+def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -> dict:
+    """Pick the fastest SpMV shape for this LP (mipdhg_autotune); returns the
+    option fields to pass to solve()."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    small = make_options(precision, **dict(opts, tile_nnz=512, tile_rows=256))
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_workspace_size(C.byref(dlp.struct()), C.byref(small), C.byref(nb)))
+    d = dlp.device
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    f64 = dict(dtype=torch.float64, device=d)
+    bufs = [torch.empty(k, **f64) for k in (dlp.n, dlp.m, dlp.n, dlp.m, dlp.n)]
+    best = C.c_double(0.0)
+    rc = lib.mipdhg_autotune(C.byref(dlp.struct()), C.byref(o), int(iters), ws.data_ptr(), ws.numel(),
+                             torch.cuda.current_stream(d).cuda_stream, *[b.data_ptr() for b in bufs], C.byref(best))
+    _lib.check(rc)
+    return {"spmv_kind": o.spmv_kind, "tile_nnz": o.tile_nnz, "tile_rows": o.tile_rows, "short_row": o.short_row,
+            "ms_per_iter": best.value}
+
+
 def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters: int = 0,
           x_init: torch.Tensor | None = None, y_init: torch.Tensor | None = None,
           workspace: torch.Tensor | None = None, **opts) -> Solution:

@@ -280,3 +280,28 @@ def _small_ws(dlp):
                           torch.cuda.current_stream().cuda_stream, *[t.data_ptr() for t in out], None, None, None)
     assert rc == -5
     _lib.check(rc)
+
+
+def test_autotune_picks_a_valid_shape_with_identical_results():
+    lp = lpgen.cfg2_sub(3, scale=100)
+    dlp = P.DeviceLP.from_lp(lp)
+    best = P.autotune(dlp, "fp64", iters=64)
+    assert best["ms_per_iter"] > 0
+    shape = {k: best[k] for k in ("spmv_kind", "tile_nnz", "tile_rows", "short_row")}
+    a = P.solve(dlp, 1e-6, "fp64", **shape)
+    b = P.solve(dlp, 1e-6, "fp64")
+    assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]
+    assert _rel(_np(a.x), _np(b.x)) <= 1e-9
+
+
+@pytest.mark.parametrize("tile_nnz,tile_rows,short_row", [(256, 64, 4), (512, 512, 200), (8192, 37, 32)])
+def test_trace_parity_tile_shapes(tile_nnz, tile_rows, short_row):
+    lp = lpgen.cfg2_sub(4, scale=200)
+    dlp = P.DeviceLP.from_lp(lp)
+    T = 70
+    sol = P.solve(dlp, 1e-12, "fp64", trace_iters=T, max_iter=T, tile_nnz=tile_nnz, tile_rows=tile_rows,
+                  short_row=short_row)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, opts=_oracle_opts(max_iter=T), trace_iters=T)
+    for t in range(1, T + 1):
+        assert _rel(_np(sol.trace["x"][t - 1]), ref.trace[t][0]) <= 1e-10, t
+        assert _rel(_np(sol.trace["y"][t - 1]), ref.trace[t][1]) <= 1e-10, t
