@@ -281,7 +281,7 @@ __global__ void k_check_blockdiag(const int32_t* rowptr, const int32_t* col, con
 }
 
 struct BatchWs {
-    int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at, *tnz_a, *tnz_at;
+    int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
     double *d_row, *d_col, *pv, *pu, *pav, *partials, *red;
     void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
@@ -298,10 +298,8 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.col_off = cv.take<int32_t>(B + 1);
     w.counter = cv.take<int32_t>(64);
     w.flags = cv.take<int32_t>(64);
-    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
-    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
-    w.tnz_a = cv.take<int32_t>(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
-    w.tnz_at = cv.take<int32_t>(max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault) + 1);
+    w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault));
+    w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault));
     w.info = cv.take<BInst>(B);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
@@ -387,16 +385,16 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     if (o.validate) {
-        const std::vector<int32_t> ta = make_tiles(rpa, lp.m, kTileNnzDefault, kTileRowsDefault),
-                                   tat = make_tiles(rpat, lp.n, kTileNnzDefault, kTileRowsDefault);
-        const std::vector<int32_t> za = tile_offsets(ta, rpa), zat = tile_offsets(tat, rpat);
+        const std::vector<int32_t> ta = make_tile_desc(rpa, lp.m, kTileNnzDefault, kTileRowsDefault),
+                                   tat = make_tile_desc(rpat, lp.n, kTileNnzDefault, kTileRowsDefault);
+        if (!tile_desc_ok(ta, rpa, lp.m, kTileNnzDefault, kTileRowsDefault) ||
+            !tile_desc_ok(tat, rpat, lp.n, kTileNnzDefault, kTileRowsDefault))
+            return set_error("internal: tile plan does not cover the rows"), MIPDHG_ERR_UNSUPPORTED;
         MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
-        MIP_HIP(hipMemcpyAsync(w.tnz_a, za.data(), za.size() * 4, hipMemcpyHostToDevice, stream));
-        MIP_HIP(hipMemcpyAsync(w.tnz_at, zat.data(), zat.size() * 4, hipMemcpyHostToDevice, stream));
-        const TilePlan pa = make_tile_plan(lp.a_rowptr, w.tiles_a, w.tnz_a, (int32_t)ta.size() - 1, lp.m,
-                                           kTileNnzDefault, kTileRowsDefault, kShortRowDefault);
-        const TilePlan pat = make_tile_plan(lp.at_rowptr, w.tiles_at, w.tnz_at, (int32_t)tat.size() - 1, lp.n,
+        const TilePlan pa = make_tile_plan(lp.a_rowptr, w.tiles_a, (int32_t)(ta.size() / 4), lp.m, kTileNnzDefault,
+                                           kTileRowsDefault, kShortRowDefault);
+        const TilePlan pat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n,
                                             kTileNnzDefault, kTileRowsDefault, kShortRowDefault);
         if ((rc = allow_validate_lds((int)std::max(tile_lds_bytes(pa, 8), tile_lds_bytes(pat, 8))))) return rc;
         if ((rc = validate_device(lp, pa, pat, w.flags, w.partials, w.red, stream))) return rc;

@@ -215,12 +215,11 @@ constexpr int kShortRowDefault = 32;
 constexpr int kMaxTileRows = 512;   // bound of the per-thread prefetch
 constexpr int kMaxTileNnz = 8192;
 constexpr int kRowsPerThread = kMaxTileRows / kBlock;
-constexpr int kProdUnroll = 8;  // products in flight per thread
 
 struct TilePlan {
     const int32_t* rowptr;
-    const int32_t* tile_row;  // [ntiles + 1] first row of each tile
-    const int32_t* tile_nz;   // [ntiles + 1] rowptr[tile_row[t]]
+    const int4* desc;  // [ntiles] {first row, end row, first nonzero, end nonzero},
+                       // in the order the workgroups take them (see make_tile_desc)
     int32_t ntiles;
     int32_t nrows;
     int32_t tile_nnz;   // nonzeros per tile (LDS products)
@@ -286,17 +285,14 @@ __device__ __forceinline__ LambdaEpi<F> lepi(F f) {
 
 // prod(k) -> Acc for a global nonzero index k.  Epi provides
 // Pre load(row) and apply(row, pre, total).
-template <bool MAXOP, typename Acc, class Prod, class Epi>
+template <bool MAXOP, typename Acc, int U = 8, class Prod, class Epi>
 __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>& L, Prod prod, const Epi& epi,
                                            bool active = true) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int t = xcd_virtual_block(blockIdx.x, gridDim.x);
-    const int r0 = p.tile_row[t];
-    const int r1 = p.tile_row[t + 1];
-    const int s = p.tile_nz[t];
-    const int e = p.tile_nz[t + 1];
+    const int4 d = p.desc[xcd_virtual_block(blockIdx.x, gridDim.x)];
+    const int r0 = d.x, r1 = d.y, s = d.z, e = d.w;
     const int nr = r1 - r0;
     const int nz = e - s;
     if (nz > p.tile_nnz) {  // one huge row: the whole workgroup strides over it
@@ -324,15 +320,15 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>
     int rp[kRowsPerThread + 1];
 #pragma unroll
     for (int q = 0; q <= kRowsPerThread; ++q) rp[q] = p.rowptr[r0 + min(tid + q * kBlock, nr)];
-    // products, kProdUnroll per thread in flight
-    for (int base = 0; base < nz; base += kProdUnroll * kBlock) {
-        Acc v[kProdUnroll];
+    // products, U per thread in flight
+    for (int base = 0; base < nz; base += U * kBlock) {
+        Acc v[U];
 #pragma unroll
-        for (int u = 0; u < kProdUnroll; ++u) v[u] = prod(s + min(base + tid + u * kBlock, nz - 1));
+        for (int u = 0; u < U; ++u) v[u] = prod(s + min(base + tid + u * kBlock, nz - 1));
         // out-of-range lanes store to the dummy slot prod[tile_nnz], so the
         // stores need no branch
 #pragma unroll
-        for (int u = 0; u < kProdUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int k = base + tid + u * kBlock;
             L.prod[k < nz ? k : p.tile_nnz] = v[u];
         }
@@ -384,9 +380,11 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>
     }
 }
 
-std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
-                                int32_t tile_rows);
-std::vector<int32_t> tile_offsets(const std::vector<int32_t>& tiles, const std::vector<int32_t>& rowptr);
+// Tiles of the rows, as 4 ints per tile in workgroup order (see plain.hip).
+std::vector<int32_t> make_tile_desc(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
+                                    int32_t tile_rows);
+bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& rowptr, int32_t nrows,
+                  int32_t tile_nnz, int32_t tile_rows);
 inline int64_t max_tiles(int64_t nrows, int64_t nnz, int64_t tile_nnz, int64_t tile_rows) {
     return 2 * (nnz / tile_nnz + nrows / tile_rows) + 4;
 }

@@ -41,8 +41,8 @@ int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat
 int32_t tile_nnz_of(const mipdhg_options& o);
 int32_t tile_rows_of(const mipdhg_options& o);
 int32_t short_row_of(const mipdhg_options& o);
-TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* tile_row, const int32_t* tile_nz, int32_t ntiles,
-                        int32_t nrows, int32_t tnz, int32_t trows, int32_t srow);
+TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,
+                        int32_t trows, int32_t srow);
 int allow_validate_lds(int bytes);
 
 inline int grid_for(int64_t n, int cap = 2048) {

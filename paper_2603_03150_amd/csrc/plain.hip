@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 
 // LDS-tiled traversal (TilePlan).  The control word is loaded up front and
 // only checked once the products are in LDS.
-template <typename T, typename V, typename Acc, bool PRIMAL>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
     const bool active = a.ctrl->status == ST_RUNNING;
     extern __shared__ __align__(16) unsigned char smem_t[];
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePla
     double mx[1] = {0.0};
     const auto epi = make_epi<T, V, PRIMAL>(a, q);
     auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
-    tiled_rows<false>(tp, L, prod, epi, active);
+    tiled_rows<false, Acc, U>(tp, L, prod, epi, active);
     if (active && (a.flags & (F_FIRST | F_EVAL)))
         block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
@@ -553,50 +553,101 @@ RowPlan device_plan(const HostPlan& hp, const int32_t* rowptr, const int32_t* lo
 }
 
 // Greedy cut of the rows into tiles of at most tile_nnz nonzeros and tile_rows
-// rows; a row longer than tile_nnz is a tile by itself.
-std::vector<int32_t> tile_offsets(const std::vector<int32_t>& tiles, const std::vector<int32_t>& rowptr) {
-    std::vector<int32_t> z(tiles.size());
-    for (size_t i = 0; i < tiles.size(); ++i) z[i] = rowptr[tiles[i]];
-    return z;
-}
+// rows (a row longer than tile_nnz is a tile by itself), then ordered for the
+// hardware: workgroup b runs on XCD b % 8, and xcd_virtual_block() gives each
+// XCD a contiguous range of descriptor slots.  "Heavy" tiles (holding a row
+// of more than kHeavyRow nonzeros, whose gathers reach far across the vector)
+// are dealt round-robin over the XCDs, first in each XCD's range; the light
+// tiles fill the remaining slots in row order, so each XCD gathers from a
+// contiguous stretch of rows.
+constexpr int32_t kHeavyRow = 256;
 
-std::vector<int32_t> make_tiles(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
-                                int32_t tile_rows) {
-    std::vector<int32_t> t;
-    t.reserve((size_t)max_tiles(nrows, rowptr[nrows], tile_nnz, tile_rows) + 1);
-    t.push_back(0);
+std::vector<int32_t> make_tile_desc(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz,
+                                    int32_t tile_rows) {
+    std::vector<int32_t> bounds;
+    std::vector<char> heavy;
+    bounds.reserve((size_t)max_tiles(nrows, rowptr[nrows], tile_nnz, tile_rows) + 1);
+    bounds.push_back(0);
     int32_t r = 0;
     while (r < nrows) {
         const int32_t len = rowptr[r + 1] - rowptr[r];
         if (len > tile_nnz) {
-            t.push_back(r + 1);
+            bounds.push_back(r + 1);
+            heavy.push_back(1);
             ++r;
             continue;
         }
         const int32_t start = r;
         int64_t nz = 0;
+        bool h = false;
         while (r < nrows && r - start < tile_rows) {
             const int32_t l = rowptr[r + 1] - rowptr[r];
             if (l > tile_nnz || nz + l > tile_nnz) break;
             nz += l;
+            h |= l > kHeavyRow;
             ++r;
         }
-        t.push_back(r);
+        bounds.push_back(r);
+        heavy.push_back(h ? 1 : 0);
     }
-    return t;
+    const int64_t G = (int64_t)heavy.size();
+    const int64_t q = G / 8, rem = G % 8;
+    std::vector<int64_t> start(9, 0), fill(8, 0);
+    for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + q + (x < rem ? 1 : 0);
+    std::vector<int64_t> slot_of(G, -1);
+    int64_t nh = 0;
+    for (int64_t i = 0; i < G; ++i)
+        if (heavy[i]) {
+            const int x = (int)(nh++ % 8);
+            slot_of[i] = start[x] + fill[x]++;
+        }
+    int x = 0;
+    for (int64_t i = 0; i < G; ++i) {
+        if (heavy[i]) continue;
+        while (start[x] + fill[x] >= start[x + 1]) ++x;
+        slot_of[i] = start[x] + fill[x]++;
+    }
+    std::vector<int32_t> desc(4 * G);
+    for (int64_t i = 0; i < G; ++i) {
+        int32_t* d = &desc[4 * slot_of[i]];
+        d[0] = bounds[i];
+        d[1] = bounds[i + 1];
+        d[2] = rowptr[bounds[i]];
+        d[3] = rowptr[bounds[i + 1]];
+    }
+    return desc;
 }
 
+// The descriptors must cover every row exactly once with matching nonzero
+// ranges and respect the tile limits; checked on the host before any launch.
+bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& rowptr, int32_t nrows,
+                  int32_t tile_nnz, int32_t tile_rows) {
+    const size_t G = desc.size() / 4;
+    std::vector<std::pair<int32_t, int32_t>> ranges(G);
+    for (size_t t = 0; t < G; ++t) {
+        const int32_t r0 = desc[4 * t], r1 = desc[4 * t + 1], s = desc[4 * t + 2], e = desc[4 * t + 3];
+        if (r0 < 0 || r1 <= r0 || r1 > nrows || s != rowptr[r0] || e != rowptr[r1]) return false;
+        if (r1 - r0 > tile_rows || (e - s > tile_nnz && r1 - r0 != 1)) return false;
+        ranges[t] = {r0, r1};
+    }
+    std::sort(ranges.begin(), ranges.end());
+    int32_t next = 0;
+    for (const auto& rg : ranges) {
+        if (rg.first != next) return false;
+        next = rg.second;
+    }
+    return next == nrows;
+}
 
 int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
 int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
 int32_t short_row_of(const mipdhg_options& o) { return o.short_row > 0 ? o.short_row : kShortRowDefault; }
 
-TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* tile_row, const int32_t* tile_nz, int32_t ntiles,
-                        int32_t nrows, int32_t tnz, int32_t trows, int32_t srow) {
+TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,
+                        int32_t trows, int32_t srow) {
     TilePlan p;
     p.rowptr = rowptr;
-    p.tile_row = tile_row;
-    p.tile_nz = tile_nz;
+    p.desc = (const int4*)desc;
     p.ntiles = ntiles;
     p.nrows = nrows;
     p.tile_nnz = tnz;
@@ -614,7 +665,7 @@ struct PlainWs {
     int64_t gcap;  // partial slots per kernel
     void *a_vs, *at_vs;
     void *x, *xbar, *x0, *xhat, *ct, *y, *y0, *yhat, *bt;
-    int32_t *long_a, *long_at, *tiles_a, *tiles_at, *tnz_a, *tnz_at, *flags;
+    int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
     size_t bytes;
 };
 
@@ -653,10 +704,8 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.bt = cv.take<char>(m * ts);
     w.long_a = cv.take<int32_t>(m);
     w.long_at = cv.take<int32_t>(n);
-    w.tiles_a = cv.take<int32_t>(max_tiles(m, nnz, tnz, trows) + 1);
-    w.tiles_at = cv.take<int32_t>(max_tiles(n, nnz, tnz, trows) + 1);
-    w.tnz_a = cv.take<int32_t>(max_tiles(m, nnz, tnz, trows) + 1);
-    w.tnz_at = cv.take<int32_t>(max_tiles(n, nnz, tnz, trows) + 1);
+    w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, tnz, trows));
+    w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, tnz, trows));
     w.flags = cv.take<int32_t>(64);
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
@@ -748,7 +797,9 @@ struct Solver {
         const size_t need = std::max(tile_lds_bytes(ta, 8), tile_lds_bytes(tat, 8));
         if (need <= 65536) return 0;
         const int lim = (int)need;
-        const void* ks[] = {(const void*)k_iter_tiled<T, V, Acc, true>, (const void*)k_iter_tiled<T, V, Acc, false>,
+        const void* ks[] = {(const void*)k_iter_tiled<T, V, Acc, true, 8>, (const void*)k_iter_tiled<T, V, Acc, false, 8>,
+                            (const void*)k_iter_tiled<T, V, Acc, true, 16>,
+                            (const void*)k_iter_tiled<T, V, Acc, false, 16>,
                             (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
                             (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
         for (const void* k : ks)
@@ -783,8 +834,12 @@ struct Solver {
         IterArgs<T, V> a;
         fill_iter(a, true, it, flags);
         if (tiled()) {
-            hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, sizeof(Acc)),
-                               stream, a, tat);
+            if (tat.tile_nnz > 8 * kBlock)
+                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 16>), dim3(tat.ntiles), dim3(kBlock),
+                                   tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+            else
+                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 8>), dim3(tat.ntiles), dim3(kBlock),
+                                   tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
         } else {
             MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, true>), dim3(hpat.grid()), dim3(kBlock),
                                                          0, stream, a));
@@ -796,8 +851,12 @@ struct Solver {
         IterArgs<T, V> a;
         fill_iter(a, false, it, flags);
         if (tiled()) {
-            hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, sizeof(Acc)),
-                               stream, a, ta);
+            if (ta.tile_nnz > 8 * kBlock)
+                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 16>), dim3(ta.ntiles), dim3(kBlock),
+                                   tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+            else
+                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 8>), dim3(ta.ntiles), dim3(kBlock),
+                                   tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
         } else {
             MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, false>), dim3(hpa.grid()), dim3(kBlock),
                                                         0, stream, a));
@@ -938,14 +997,14 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const int ga = S.hpa.grid(), gat = S.hpat.grid();
     {
         const int32_t tnz = tile_nnz_of(o), trows = tile_rows_of(o), srow = short_row_of(o);
-        const std::vector<int32_t> ta = make_tiles(rpa, lp.m, tnz, trows), tat = make_tiles(rpat, lp.n, tnz, trows);
-        const std::vector<int32_t> za = tile_offsets(ta, rpa), zat = tile_offsets(tat, rpat);
+        const std::vector<int32_t> ta = make_tile_desc(rpa, lp.m, tnz, trows),
+                                   tat = make_tile_desc(rpat, lp.n, tnz, trows);
+        if (!tile_desc_ok(ta, rpa, lp.m, tnz, trows) || !tile_desc_ok(tat, rpat, lp.n, tnz, trows))
+            return set_error("internal: tile plan does not cover the rows"), MIPDHG_ERR_UNSUPPORTED;
         MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
-        MIP_HIP(hipMemcpyAsync(w.tnz_a, za.data(), za.size() * 4, hipMemcpyHostToDevice, stream));
-        MIP_HIP(hipMemcpyAsync(w.tnz_at, zat.data(), zat.size() * 4, hipMemcpyHostToDevice, stream));
-        S.ta = make_tile_plan(lp.a_rowptr, w.tiles_a, w.tnz_a, (int32_t)ta.size() - 1, lp.m, tnz, trows, srow);
-        S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, w.tnz_at, (int32_t)tat.size() - 1, lp.n, tnz, trows, srow);
+        S.ta = make_tile_plan(lp.a_rowptr, w.tiles_a, (int32_t)(ta.size() / 4), lp.m, tnz, trows, srow);
+        S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n, tnz, trows, srow);
         if ((rc = S.allow_tile_lds())) return rc;
         MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
     }
