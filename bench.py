@@ -49,6 +49,14 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=32,
                     help="instances of the batch solved one at a time by the plain FP64 path")
+    ap.add_argument("--no-block-angular", action="store_true", help="skip the block-angular LP leg")
+    ap.add_argument("--no-ratios", action="store_true", help="skip the tolerance-ratio leg")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
+    ap.add_argument("--profile", action="store_true",
+                    help="only a short capped solve (256 iterations) of --profile-workload (for hardware counters)")
+    ap.add_argument("--profile-workload", default="power_law", choices=["power_law", "block_angular"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only a plain device copy of known size (to calibrate hardware byte counters)")
     return ap.parse_args()
 
 
@@ -80,6 +88,136 @@ def cpu_baseline(lp, gpu_iters: int, eps: float) -> dict:
     return {"value": value, "unit": "iter/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle capped at 64 and 192 iterations on the same LP: setup {setup:.2f} s, "
                        f"{per_iter * 1e3:.1f} ms/iteration, rate quoted for a {gpu_iters}-iteration solve")}
+
+
+KERNEL_SOURCES = ("paper_2603_03150_amd/csrc/common.h", "paper_2603_03150_amd/csrc/plain.h",
+                  "paper_2603_03150_amd/csrc/plain.hip")
+
+
+def kernel_source_sha() -> str:
+    """Hash of the sources that define the iteration kernels: a stored
+    hardware-counter record is used only while they are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(workload_key: str, kernel: str):
+    """Measured HBM bytes per launch of `kernel` on `workload_key`, from the
+    committed counter summary (profiles/traffic_<workload_key>.json), or None
+    if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_key}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_sha() or rec.get("kernel") != kernel:
+        return None
+    return rec
+
+
+def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str) -> dict:
+    """Algorithmic bytes per launch of the slower iteration kernel over its
+    mean launch time, from HIP events around every launch on the solver's
+    stream, against the 8 TB/s HBM peak."""
+    tsol = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=iters, kernel_timing=1, validate=0)
+    ti = tsol.info
+    kern = {"primal": (ti["bytes_primal"], ti["ms_primal"]), "dual": (ti["bytes_dual"], ti["ms_dual"])}
+    dom = max(kern, key=lambda k: kern[k][1])
+    b, ms = kern[dom]
+    achieved = b / (ms * 1e-3) / 1e9
+    name = f"k_iter_tiled<{dom}>"
+    rec = traffic_record(workload_key, name)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": rec["bytes_per_launch"] if rec else None,
+            "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": iters,
+            "traffic_source": f"profiles/traffic_{workload_key}.json" if rec else None,
+            "other_kernel": {k: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9}
+                             for k, v in kern.items() if k != dom}}
+
+
+def block_angular_leg(P, torch, eps: float, precision: str, timing_iters: int) -> dict:
+    """The block-angular LP (64 blocks 30,000 x 120,000, 6 nonzeros per
+    column, plus 2,000 linking rows of 1,200 nonzeros; 48.5M nonzeros), the
+    one workload whose matrix does not fit the 256 MB last-level cache: a
+    solve to eps and the per-kernel HBM roofline."""
+    import lpgen
+    t0 = time.perf_counter()
+    lp = lpgen.cfg3(0)
+    gen_s = time.perf_counter() - t0
+    dlp = P.DeviceLP.from_lp(lp, "cuda:0")
+    ws = torch.empty(P.workspace_bytes(dlp, precision), dtype=torch.uint8, device="cuda:0")
+    P.solve(dlp, eps, precision, workspace=ws, max_iter=64)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = P.solve(dlp, eps, precision, workspace=ws, max_iter=30_000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf = sol.info
+    roof = kernel_roofline(P, dlp, ws, precision, timing_iters, "block_angular")
+    out = {"workload": "block-angular LP, 64 blocks 30000x120000 (6 nnz/col) + 2000 link rows x 1200 nnz, "
+                       "planted optimum", "m": lp.m, "n": lp.n, "nnz": lp.nnz, "precision": precision,
+           "eps_rel": eps, "status": sol.status_name, "iters": int(inf["iters"]), "restarts": int(inf["restarts"]),
+           "seconds": dt, "iter_per_s": int(inf["iters"]) / dt,
+           "iter_only_rate": int(inf["iters"]) / (inf["ms_iter"] * 1e-3), "ms_setup": inf["ms_setup"],
+           "bytes_per_iter": inf["bytes_per_iter"],
+           "iter_only_GBs": inf["bytes_per_iter"] * int(inf["iters"]) / (inf["ms_iter"] * 1e-3) / 1e9,
+           "rel_obj_err_vs_planted": abs(inf["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star)),
+           "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof}
+    del dlp, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def ratio_leg(P, torch, dlp2, ws2, precision: str, t_main: float, iters_main: int) -> dict:
+    """Solve time at a tighter tolerance over solve time at 1e-4: the small
+    LP in FP64 at 1e-8, the power-law LP in the bench precision at 1e-6."""
+    import lpgen
+    d1 = P.DeviceLP.from_lp(lpgen.cfg1(0), "cuda:0")
+
+    def timed(dlp, eps, prec, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = P.solve(dlp, eps, prec, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, s
+
+    timed(d1, 1e-4, "fp64")
+    a_t, a = timed(d1, 1e-4, "fp64")
+    b_t, b = timed(d1, 1e-8, "fp64", max_iter=1_000_000)
+    c_t, c = timed(dlp2, 1e-6, precision, workspace=ws2, max_iter=200_000)
+    return {"small_fp64": {"t_1e-4_s": a_t, "t_1e-8_s": b_t, "ratio": b_t / a_t, "iters_1e-4": int(a.info["iters"]),
+                           "iters_1e-8": int(b.info["iters"]), "status_1e-8": b.status_name},
+            "power_law": {"t_1e-4_s": t_main, "t_1e-6_s": c_t, "ratio": c_t / t_main, "iters_1e-4": iters_main,
+                          "iters_1e-6": int(c.info["iters"]), "status_1e-6": c.status_name},
+            "paper_context": "geomean runtime ratios over its LP set: 2.29 (1e-6), 3.56 (1e-8)"}
+
+
+def diff_leg(P, torch) -> dict:
+    """256 LPs (m=500, n=1,500, 5 nonzeros per column): K=2,000 unrolled FP32
+    iterations with checkpoints every 100, forward and hand-written backward."""
+    import numpy as np
+
+    import lpgen
+    lps, ws = lpgen.cfg5_batch(256)
+    batch = P.DeviceBatch.from_lps(lps, "cuda:0")
+    umap = P.UnrolledMap(batch, K=2000, ckpt_every=100, precision="fp32")
+    w = torch.tensor(np.concatenate(ws), device="cuda:0")
+    xk, tape = umap.forward_raw(batch.lp.c, batch.lp.b)
+    umap.backward_raw(batch.lp.c, batch.lp.b, tape, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xk, tape = umap.forward_raw(batch.lp.c, batch.lp.b, tape=tape)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    umap.backward_raw(batch.lp.c, batch.lp.b, tape, w)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"instances": 256, "K": 2000, "ckpt_every": 100, "precision": "fp32", "forward_s": t1 - t0,
+            "backward_s": t2 - t1, "tape_bytes": umap.tape_bytes}
 
 
 def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
@@ -139,8 +277,18 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # 1 GiB read + 1 GiB written per copy, four copies
+        a = torch.empty(256 * 2**20, dtype=torch.float32, device="cuda:0")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 4}))
+        return 0
     t0 = time.perf_counter()
-    lp = lpgen.cfg2(args.seed)
+    lp = lpgen.cfg3(args.seed) if args.profile and args.profile_workload == "block_angular" else lpgen.cfg2(args.seed)
     gen_s = time.perf_counter() - t0
     print(f"# generated m={lp.m} n={lp.n} nnz={lp.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     dlp = P.DeviceLP.from_lp(lp, "cuda:0")
@@ -148,6 +296,12 @@ def main() -> int:
 
     def step():
         return P.solve(dlp, args.eps, args.precision, workspace=ws, max_iter=200_000)
+
+    if args.profile:
+        s = P.solve(dlp, 0.0, args.precision, workspace=ws, max_iter=256)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_solve_iters": int(s.info["iters"]), "precision": args.precision}))
+        return 0
 
     for i in range(args.warmup):
         s = step()
@@ -166,18 +320,7 @@ def main() -> int:
     value = iters / elapsed
 
     # per-kernel timing leg: HIP events around every primal and dual launch
-    tsol = P.solve(dlp, 0.0, args.precision, workspace=ws, max_iter=args.timing_iters, kernel_timing=1)
-    ti = tsol.info
-    kern = {"primal": (ti["bytes_primal"], ti["ms_primal"]), "dual": (ti["bytes_dual"], ti["ms_dual"])}
-    dom = max(kern, key=lambda k: kern[k][1])
-    b, ms = kern[dom]
-    achieved = b / (ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": f"k_iter<{'dual' if dom == 'dual' else 'primal'}>",
-                "bytes_per_launch": b, "ms_per_launch": ms,
-                "other_kernel": {k: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9}
-                                 for k, v in kern.items() if k != dom}}
+    roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, "power_law")
 
     out = {
         "metric": "PDHG iter/s (plain solve to eps_rel=1e-4)",
@@ -205,6 +348,18 @@ def main() -> int:
                   "iter_only_rate": int(last.info["iters"]) / (last.info["ms_iter"] * 1e-3),
                   "plan": {k: last.info[k] for k in ("lanes_a", "lanes_at", "long_a", "long_at")}},
     }
+    if not args.no_ratios:
+        print("# tolerance ratios", file=sys.stderr, flush=True)
+        out["tolerance_ratios"] = ratio_leg(P, torch, dlp, ws, args.precision, elapsed / args.steps,
+                                            int(last.info["iters"]))
+    if not args.no_diff:
+        print("# differentiation leg", file=sys.stderr, flush=True)
+        out["differentiation"] = diff_leg(P, torch)
+    if not args.no_block_angular:
+        print("# block-angular leg", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+        out["block_angular"] = block_angular_leg(P, torch, args.eps, args.precision, 256)
     if not args.no_batched:
         print("# batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(P, torch, args.batch_count, args.plain_sample, args.eps)

@@ -100,8 +100,10 @@ typedef struct mipdhg_options {
     double time_limit_s;    /* wall-clock limit, seconds (paper: 1e4)    [1e4] */
     int32_t validate;       /* check CSR, finiteness and A^T consistency   [1] */
     int32_t use_graph;      /* replay hipGraphs of eval_every iterations   [1] */
-    int32_t spmv_kind;      /* iteration SpMVs: 0 = nnz-balanced LDS tiles,
-                               1 = lane groups per row (lanes_a/lanes_at)   [0] */
+    int32_t spmv_kind;      /* iteration SpMVs: 0 = nnz-balanced LDS tiles, one
+                               workgroup per tile; 1 = lane groups per row
+                               (lanes_a/lanes_at); 2 = the same LDS tiles walked
+                               by a persistent grid of resident workgroups   [0] */
     int32_t tile_nnz;       /* LDS tiles: nonzeros per tile, 256..8192 (0 = 2048) */
     int32_t tile_rows;      /* LDS tiles: rows per tile, 1..512 (0 = 512)           */
     int32_t short_row;      /* LDS tiles: longer rows are summed by a wavefront (0 = 32) */

@@ -21,9 +21,10 @@ struct Cand {
 std::vector<Cand> candidates() {
     std::vector<Cand> c;
     c.push_back({1, 0, 0, 0});  // lane groups with the planner's lane counts
-    for (int tn : {512, 1024, 2048, 4096})
-        for (int tr : {256, 512})
-            for (int sr : {32, 128}) c.push_back({0, tn, tr, sr});
+    for (int kind : {0, 2})
+        for (int tn : {512, 1024, 2048, 4096})
+            for (int tr : {256, 512})
+                for (int sr : {32, 128}) c.push_back({kind, tn, tr, sr});
     return c;
 }
 

@@ -156,6 +156,23 @@ __device__ __forceinline__ int xcd_virtual_block(int b, int G) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// The tile of a launch with one workgroup per tile.
+__device__ __forceinline__ int own_tile() { return xcd_virtual_block(blockIdx.x, gridDim.x); }
+
+// The tiles of a persistent launch: the descriptors form 8 contiguous runs,
+// one per XCD (workgroup b runs on XCD b mod 8), and the workgroups of an XCD
+// stride over its run.  Covers [0, ntiles) exactly once for any grid that
+// has at least min(8, ntiles) workgroups.
+struct TileRange {
+    int first, end, step;
+};
+__device__ __forceinline__ TileRange persistent_tiles(int ntiles) {
+    const int G = gridDim.x, b = blockIdx.x, x = b & 7;
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int t0 = x * q + min(x, r);
+    return TileRange{t0 + (b >> 3), t0 + q + (x < r ? 1 : 0), (G >> 3) + (x < (G & 7) ? 1 : 0)};
+}
+
 // Visit every row of the plan.  dot(s, e, lane, L) returns this lane's share of
 // the row's reduction; epi(row, total) runs on the group's first lane.
 template <int L, typename Acc, class Dot, class Epi>
@@ -233,6 +250,7 @@ template <typename Acc>
 struct TileLds {
     Acc* prod;
     Acc* sum;
+    Acc* wsum;  // per-wave scan totals of the chunked reduction
     int32_t* row;
     int32_t* list;
     int32_t* wcount;
@@ -243,15 +261,16 @@ __device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const Tile
     TileLds<Acc> L;
     L.prod = (Acc*)smem;
     L.sum = L.prod + p.tile_nnz + 1;  // prod[tile_nnz] is a dummy slot
-    L.row = (int32_t*)(L.sum + p.tile_rows);
+    L.wsum = L.sum + p.tile_rows;
+    L.row = (int32_t*)(L.wsum + kBlock / kWave);
     L.list = L.row + p.tile_rows + 1;
     L.wcount = L.list + p.max_long;
     return L;
 }
 
 inline size_t tile_lds_bytes(const TilePlan& p, size_t acc) {
-    return acc * (size_t)(p.tile_nnz + 1 + p.tile_rows) + 4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) +
-           16;
+    return acc * (size_t)(p.tile_nnz + 1 + p.tile_rows + kBlock / kWave) +
+           4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) + 16;
 }
 
 template <bool MAXOP, typename Acc>
@@ -283,15 +302,84 @@ __device__ __forceinline__ LambdaEpi<F> lepi(F f) {
     return LambdaEpi<F>{f};
 }
 
+// Row totals of a tile whose products are in L.prod and whose row offsets
+// (relative to the tile) are in L.row[0..nr].  Every thread reduces one
+// contiguous chunk of ceil(nz / 256) products: rows that end inside the chunk
+// after its first row end are complete and written at once; the part of the
+// first row that ends in the chunk needs what earlier threads hold of that
+// row, which a segmented scan over the threads supplies (a chunk with a row
+// end starts a new segment of the scan).  Empty rows keep the 0 written to
+// L.sum beforehand.  The work per thread does not depend on the row lengths.
+template <bool MAXOP, typename Acc>
+__device__ __forceinline__ void chunk_row_sums(const TileLds<Acc>& L, int nz, int nr) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int C = (nz + kBlock - 1) / kBlock;
+    const int p0 = tid * C, p1 = min(p0 + C, nz);
+    bool ends = false;  // a row ends inside this chunk
+    Acc head = 0, acc = 0;
+    int rfirst = 0;
+    if (p0 < nz) {
+        int lo = 0, hi = nr;  // row[lo] <= p0 < row[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (L.row[mid] <= p0) lo = mid;
+            else hi = mid;
+        }
+        int r = lo, end = L.row[lo + 1];
+        rfirst = r;
+        for (int k = p0; k < p1; ++k) {
+            acc = red_op<MAXOP>(acc, L.prod[k]);
+            if (k + 1 == end) {
+                if (ends) L.sum[r] = acc;
+                else head = acc;
+                ends = true;
+                acc = 0;
+                do {  // next non-empty row
+                    ++r;
+                    end = r < nr ? L.row[r + 1] : 0x7fffffff;
+                } while (end == k + 1);
+            }
+        }
+    }
+    // inclusive segmented scan of (ends, open tail) over the wave; the
+    // earlier operand is always on the left
+    Acc v = acc;
+    int f = ends ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const Acc v2 = __shfl_up(v, d, kWave);
+        const int f2 = __shfl_up(f, d, kWave);
+        if (lane >= d) {
+            if (!f) v = red_op<MAXOP>(v2, v);
+            f |= f2;
+        }
+    }
+    if (lane == kWave - 1) {
+        L.wsum[wave] = v;
+        L.wcount[wave] = f;
+    }
+    Acc ev = __shfl_up(v, 1, kWave);
+    int ef = __shfl_up(f, 1, kWave);
+    if (lane == 0) {
+        ev = 0;
+        ef = 0;
+    }
+    __syncthreads();
+    Acc pv = 0;  // the waves before this one
+    for (int w = 0; w < wave; ++w) pv = L.wcount[w] ? L.wsum[w] : red_op<MAXOP>(pv, L.wsum[w]);
+    const Acc carry = ef ? ev : red_op<MAXOP>(pv, ev);
+    if (ends) L.sum[rfirst] = red_op<MAXOP>(carry, head);
+}
+
 // prod(k) -> Acc for a global nonzero index k.  Epi provides
 // Pre load(row) and apply(row, pre, total).
 template <bool MAXOP, typename Acc, int U = 8, class Prod, class Epi>
-__device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>& L, Prod prod, const Epi& epi,
-                                           bool active = true) {
+__device__ __forceinline__ void tiled_rows(const TilePlan& p, int tile, const TileLds<Acc>& L, Prod prod,
+                                           const Epi& epi, bool active = true) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int4 d = p.desc[xcd_virtual_block(blockIdx.x, gridDim.x)];
+    const int4 d = p.desc[tile];
     const int r0 = d.x, r1 = d.y, s = d.z, e = d.w;
     const int nr = r1 - r0;
     const int nz = e - s;
@@ -336,8 +424,23 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>
 #pragma unroll
     for (int q = 0; q <= kRowsPerThread; ++q)
         if (tid + q * kBlock <= nr) L.row[tid + q * kBlock] = rp[q] - s;
+    const bool chunked = p.short_row < 0;
+    if (chunked)
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q)
+            if (tid + q * kBlock < nr) L.sum[tid + q * kBlock] = 0;
     __syncthreads();
     if (!active) return;  // uniform
+    if (chunked) {
+        chunk_row_sums<MAXOP>(L, nz, nr);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int i = tid + q * kBlock;
+            if (i < nr) epi.apply(r0 + i, pre[q], L.sum[i]);
+        }
+        return;
+    }
     int nlist = 0;
     for (int base = 0; base < nr; base += kBlock) {
         const int i = base + tid;
@@ -345,8 +448,17 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, const TileLds<Acc>
         if (i < nr) {
             const int a = L.row[i], b = L.row[i + 1];
             if (b - a <= p.short_row) {
+                // each lane starts at its own offset inside the row and wraps
+                // around: row starts that differ by a multiple of the bank
+                // count would otherwise hit one LDS bank on every step
+                const int len = b - a;
+                const int j0 = len > 0 ? (lane & ((1 << (31 - __clz(len))) - 1)) : 0;
                 Acc acc = 0;
-                for (int q = a; q < b; ++q) acc = red_op<MAXOP>(acc, L.prod[q]);
+                int q = a + j0;
+                for (int c = 0; c < len; ++c) {
+                    acc = red_op<MAXOP>(acc, L.prod[q]);
+                    q = (q + 1 == b) ? a : q + 1;
+                }
                 L.sum[i] = acc;
             } else {
                 lng = true;

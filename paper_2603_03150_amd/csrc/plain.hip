@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_stat(TilePlan p, const int32_t
     const auto L = tile_lds<double>(smem_t, p);
     auto prod = [&](int k) { return fabs(val[k]) * d_other[col[k]]; };
     auto epi = [&](int r, double a) { stat[r] = d_self[r] * a; };
-    tiled_rows<MAXMODE>(p, L, prod, lepi(epi));
+    tiled_rows<MAXMODE>(p, own_tile(), L, prod, lepi(epi));
 }
 
 // d[i] *= 1/sqrt(stat[i]) (1 for an empty row or column)
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_
         y[r] = t;
         s[0] += t * t;
     };
-    tiled_rows<false>(p, L, prod, lepi(epi));
+    tiled_rows<false>(p, own_tile(), L, prod, lepi(epi));
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
@@ -300,8 +300,30 @@ __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePla
     double mx[1] = {0.0};
     const auto epi = make_epi<T, V, PRIMAL>(a, q);
     auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
-    tiled_rows<false, Acc, U>(tp, L, prod, epi, active);
+    tiled_rows<false, Acc, U>(tp, own_tile(), L, prod, epi, active);
     if (active && (a.flags & (F_FIRST | F_EVAL)))
+        block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+}
+
+// The same step as a persistent launch: about one workgroup per resident slot,
+// each walking its XCD's run of tiles, so that no time goes to dispatching a
+// workgroup per tile.  The norm partials cover all tiles of a workgroup.
+template <typename T, typename V, typename Acc, bool PRIMAL, int U>
+__global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TilePlan tp) {
+    const bool active = a.ctrl->status == ST_RUNNING;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<Acc>(smem_t, tp);
+    double q[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    const auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
+    const TileRange tr = persistent_tiles(tp.ntiles);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        tiled_rows<false, Acc, U>(tp, t, L, prod, epi, active);
+        if (!active) return;
+        __syncthreads();  // the next tile reuses the LDS
+    }
+    if (a.flags & (F_FIRST | F_EVAL))
         block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
 
@@ -353,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
             mx[0] = fmax(mx[0], fabs(rd));
         }
     };
-    tiled_rows<false>(tp, L, prod, lepi(epi), active);
+    tiled_rows<false>(tp, own_tile(), L, prod, lepi(epi), active);
     if (active) block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
 }
 
@@ -641,7 +663,7 @@ bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& 
 
 int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
 int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
-int32_t short_row_of(const mipdhg_options& o) { return o.short_row > 0 ? o.short_row : kShortRowDefault; }
+int32_t short_row_of(const mipdhg_options& o) { return o.short_row != 0 ? o.short_row : kShortRowDefault; }
 
 TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,
                         int32_t trows, int32_t srow) {
@@ -653,7 +675,7 @@ TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntil
     p.tile_nnz = tnz;
     p.tile_rows = trows;
     p.short_row = srow;
-    p.max_long = tnz / (srow + 1) + 1;
+    p.max_long = srow < 0 ? 1 : tnz / (srow + 1) + 1;
     return p;
 }
 
@@ -721,12 +743,12 @@ int check_options(const mipdhg_options* o) {
         return set_error("step_safety > 0 and reflect_rho in [0,1] required"), MIPDHG_ERR_INVALID_ARG;
     if (o->max_iter < 1) return set_error("max_iter must be >= 1"), MIPDHG_ERR_INVALID_ARG;
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
-    if (o->spmv_kind != 0 && o->spmv_kind != 1) return set_error("spmv_kind must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->spmv_kind < 0 || o->spmv_kind > 2) return set_error("spmv_kind must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_nnz != 0 && (o->tile_nnz < 256 || o->tile_nnz > kMaxTileNnz))
         return set_error("tile_nnz must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
         return set_error("tile_rows must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
-    if (o->short_row < 0) return set_error("short_row must be >= 0"), MIPDHG_ERR_INVALID_ARG;
+    if (o->short_row < -1) return set_error("short_row must be >= -1"), MIPDHG_ERR_INVALID_ARG;
     for (int L : {o->lanes_a, o->lanes_at})
         if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
             return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
@@ -791,7 +813,9 @@ struct Solver {
     ~Solver() {
         for (auto e : tev) (void)hipEventDestroy(e);
     }
-    bool tiled() const { return o.spmv_kind == 0; }
+    bool tiled() const { return o.spmv_kind != 1; }
+    bool persistent() const { return o.spmv_kind == 2; }
+    int gp_persist = 0, gd_persist = 0;  // persistent grids (resident slots, capped by the tile count)
     // dynamic LDS beyond 64 KiB must be allowed per kernel
     int allow_tile_lds() {
         const size_t need = std::max(tile_lds_bytes(ta, 8), tile_lds_bytes(tat, 8));
@@ -800,6 +824,10 @@ struct Solver {
         const void* ks[] = {(const void*)k_iter_tiled<T, V, Acc, true, 8>, (const void*)k_iter_tiled<T, V, Acc, false, 8>,
                             (const void*)k_iter_tiled<T, V, Acc, true, 16>,
                             (const void*)k_iter_tiled<T, V, Acc, false, 16>,
+                            (const void*)k_iter_persist<T, V, Acc, true, 8>,
+                            (const void*)k_iter_persist<T, V, Acc, false, 8>,
+                            (const void*)k_iter_persist<T, V, Acc, true, 16>,
+                            (const void*)k_iter_persist<T, V, Acc, false, 16>,
                             (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
                             (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
         for (const void* k : ks)
@@ -808,8 +836,33 @@ struct Solver {
                        MIPDHG_ERR_UNSUPPORTED;
         return allow_validate_lds(lim);
     }
-    int grid_primal() const { return tiled() ? tat.ntiles : hpat.grid(); }
-    int grid_dual() const { return tiled() ? ta.ntiles : hpa.grid(); }
+    int grid_primal() const { return persistent() ? gp_persist : tiled() ? tat.ntiles : hpat.grid(); }
+    int grid_dual() const { return persistent() ? gd_persist : tiled() ? ta.ntiles : hpa.grid(); }
+    // Resident workgroups of the persistent kernel over all CUs, at least
+    // min(8, ntiles) so that every XCD's run of tiles has a workgroup.
+    template <bool PRIMAL>
+    int persist_grid(const TilePlan& tp) {
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
+        const hipError_t e =
+            tp.tile_nnz > 8 * kBlock
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 16>, kBlock, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 8>, kBlock, lds);
+        if (e != hipSuccess || occ < 1) return 0;
+        const int64_t g = std::min<int64_t>((int64_t)cus * occ, tp.ntiles);
+        return (int)std::max<int64_t>(g, std::min<int64_t>(8, tp.ntiles));
+    }
+    int plan_persistent() {
+        if (!persistent()) return 0;
+        gp_persist = persist_grid<true>(tat);
+        gd_persist = persist_grid<false>(ta);
+        if (gp_persist < 1 || gd_persist < 1)
+            return set_error("could not size the persistent grid (occupancy query failed)"), MIPDHG_ERR_HIP;
+        return 0;
+    }
 
     void fill_iter(IterArgs<T, V>& a, bool primal, int it, int flags) {
         a.p = primal ? pat : pa;
@@ -835,11 +888,23 @@ struct Solver {
         fill_iter(a, true, it, flags);
         if (tiled()) {
             if (tat.tile_nnz > 8 * kBlock)
-                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 16>), dim3(tat.ntiles), dim3(kBlock),
-                                   tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+                {
+                if (persistent())
+                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, true, 16>), dim3(gp_persist), dim3(kBlock),
+                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+                else
+                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 16>), dim3(tat.ntiles), dim3(kBlock),
+                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+            }
             else
-                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 8>), dim3(tat.ntiles), dim3(kBlock),
-                                   tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+                {
+                if (persistent())
+                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, true, 8>), dim3(gp_persist), dim3(kBlock),
+                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+                else
+                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 8>), dim3(tat.ntiles), dim3(kBlock),
+                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
+            }
         } else {
             MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, true>), dim3(hpat.grid()), dim3(kBlock),
                                                          0, stream, a));
@@ -852,11 +917,23 @@ struct Solver {
         fill_iter(a, false, it, flags);
         if (tiled()) {
             if (ta.tile_nnz > 8 * kBlock)
-                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 16>), dim3(ta.ntiles), dim3(kBlock),
-                                   tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+                {
+                if (persistent())
+                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, false, 16>), dim3(gd_persist), dim3(kBlock),
+                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+                else
+                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 16>), dim3(ta.ntiles), dim3(kBlock),
+                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+            }
             else
-                hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 8>), dim3(ta.ntiles), dim3(kBlock),
-                                   tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+                {
+                if (persistent())
+                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, false, 8>), dim3(gd_persist), dim3(kBlock),
+                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+                else
+                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 8>), dim3(ta.ntiles), dim3(kBlock),
+                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
+            }
         } else {
             MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, false>), dim3(hpa.grid()), dim3(kBlock),
                                                         0, stream, a));
@@ -1006,6 +1083,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         S.ta = make_tile_plan(lp.a_rowptr, w.tiles_a, (int32_t)(ta.size() / 4), lp.m, tnz, trows, srow);
         S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n, tnz, trows, srow);
         if ((rc = S.allow_tile_lds())) return rc;
+        if ((rc = S.plan_persistent())) return rc;
         MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
     }
     const int gta = S.ta.ntiles, gtat = S.tat.ntiles;

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int3
         const double u = hash_unit((uint32_t)r, seed_row);
         s[0] += (ABS ? fabs(u) : u) * t;
     };
-    tiled_rows<false>(p, L, prod, lepi(epi));
+    tiled_rows<false>(p, own_tile(), L, prod, lepi(epi));
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 

@@ -43,10 +43,10 @@ def _oracle_opts(**kw):
     return OracleOptions(**kw)
 
 
-def _trace_parity(lp, T=100, lanes_a=0, lanes_at=0, long_row=0, eval_every=64, spmv_kind=0):
+def _trace_parity(lp, T=100, lanes_a=0, lanes_at=0, long_row=0, eval_every=64, spmv_kind=0, short_row=0):
     dlp = P.DeviceLP.from_lp(lp)
     sol = P.solve(dlp, 1e-12, "fp64", trace_iters=T, max_iter=T, lanes_a=lanes_a, lanes_at=lanes_at,
-                  long_row=long_row, eval_every=eval_every, spmv_kind=spmv_kind)
+                  long_row=long_row, eval_every=eval_every, spmv_kind=spmv_kind, short_row=short_row)
     ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12,
                        opts=_oracle_opts(max_iter=T, eval_every=eval_every), trace_iters=T)
     assert sol.status == ref.status
@@ -99,12 +99,12 @@ def _huge_row_lp(m, n, extra, seed):
     return lpgen.planted_from_columns(m, np.array(counts), rows, vals, rng)
 
 
-@pytest.mark.parametrize("spmv_kind", [0, 1])
-def test_trace_parity_huge_rows_and_empty_rows(spmv_kind):
+@pytest.mark.parametrize("spmv_kind,short_row", [(0, 0), (1, 0), (2, 0), (0, -1), (2, -1)])
+def test_trace_parity_huge_rows_and_empty_rows(spmv_kind, short_row):
     lp = _huge_row_lp(m=3000, n=5000, extra=3, seed=0)
     assert np.diff(lp.A.indptr).max() > 2048 and np.diff(lp.AT.indptr).max() == 3000
     assert (np.diff(lp.A.indptr)[1500:] <= 1).all()
-    _trace_parity(lp, T=70, spmv_kind=spmv_kind)
+    _trace_parity(lp, T=70, spmv_kind=spmv_kind, short_row=short_row)
 
 
 def test_tiled_and_lane_kernels_agree():
@@ -112,8 +112,17 @@ def test_tiled_and_lane_kernels_agree():
     dlp = P.DeviceLP.from_lp(lp)
     a = P.solve(dlp, 1e-6, "fp64", spmv_kind=0)
     b = P.solve(dlp, 1e-6, "fp64", spmv_kind=1)
-    assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]
+    c = P.solve(dlp, 1e-6, "fp64", spmv_kind=2)
+    assert a.status == b.status == c.status == 0 and a.info["iters"] == b.info["iters"] == c.info["iters"]
     assert _rel(_np(a.x), _np(b.x)) <= 1e-9
+    # the persistent grid sums the same tiles in the same order
+    assert torch.equal(a.x, c.x) and torch.equal(a.y, c.y)
+
+
+@pytest.mark.parametrize("lp_fn", [lambda: lpgen.tiny(6, 15, 3, 2), lambda: lpgen.cfg1(1)])
+def test_trace_parity_persistent_grid(lp_fn):
+    # one tile (fewer tiles than XCDs) and a few hundred tiles
+    _trace_parity(lp_fn(), T=70, eval_every=1, spmv_kind=2)
 
 
 def test_trace_parity_eval_every_one():
@@ -294,13 +303,15 @@ def test_autotune_picks_a_valid_shape_with_identical_results():
     assert _rel(_np(a.x), _np(b.x)) <= 1e-9
 
 
-@pytest.mark.parametrize("tile_nnz,tile_rows,short_row", [(256, 64, 4), (512, 512, 200), (8192, 37, 32)])
-def test_trace_parity_tile_shapes(tile_nnz, tile_rows, short_row):
+@pytest.mark.parametrize("spmv_kind", [0, 2])
+@pytest.mark.parametrize("tile_nnz,tile_rows,short_row", [(256, 64, 4), (512, 512, 200), (8192, 37, 32),
+                                                        (256, 64, -1), (2048, 512, -1), (8192, 37, -1)])
+def test_trace_parity_tile_shapes(tile_nnz, tile_rows, short_row, spmv_kind):
     lp = lpgen.cfg2_sub(4, scale=200)
     dlp = P.DeviceLP.from_lp(lp)
     T = 70
     sol = P.solve(dlp, 1e-12, "fp64", trace_iters=T, max_iter=T, tile_nnz=tile_nnz, tile_rows=tile_rows,
-                  short_row=short_row)
+                  short_row=short_row, spmv_kind=spmv_kind)
     ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, opts=_oracle_opts(max_iter=T), trace_iters=T)
     for t in range(1, T + 1):
         assert _rel(_np(sol.trace["x"][t - 1]), ref.trace[t][0]) <= 1e-10, t
