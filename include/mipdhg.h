@@ -106,7 +106,10 @@ typedef struct mipdhg_options {
                                by a persistent grid of resident workgroups   [0] */
     int32_t tile_nnz;       /* LDS tiles: nonzeros per tile, 256..8192 (0 = 2048) */
     int32_t tile_rows;      /* LDS tiles: rows per tile, 1..512 (0 = 512)           */
-    int32_t short_row;      /* LDS tiles: longer rows are summed by a wavefront (0 = 32) */
+    int32_t short_row;      /* LDS tile row sums: 0 or -1 = every thread reduces an equal chunk of
+                               the tile's products with a segmented scan across threads (default);
+                               > 0 = rows up to this length summed by one thread each, longer
+                               rows by a wavefront each */
     int32_t lanes_a;        /* lanes per row for A SpMVs (0 = planner)     [0] */
     int32_t lanes_at;       /* lanes per row for A^T SpMVs (0 = planner)   [0] */
     int32_t long_row;       /* rows longer than this use a whole wave (0 = planner) */
@@ -121,6 +124,11 @@ typedef struct mipdhg_options {
     /* Optional warm start in the original space (device float64, may be NULL). */
     const double *x_init;   /* [n], must be >= 0 */
     const double *y_init;   /* [m] */
+    /* Order of the nonzeros inside each LDS tile of the iteration's scaled
+     * copies (spmv_kind 0 and 2): 0 = sorted by gather index, so that the
+     * lanes of a load fall on few cache lines (costs 6 more workspace bytes
+     * per nonzero and copy); 1 = row-major.  Results are bitwise identical. [0] */
+    int32_t gather_order;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */

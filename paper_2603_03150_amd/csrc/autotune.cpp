@@ -22,9 +22,9 @@ std::vector<Cand> candidates() {
     std::vector<Cand> c;
     c.push_back({1, 0, 0, 0});  // lane groups with the planner's lane counts
     for (int kind : {0, 2})
-        for (int tn : {512, 1024, 2048, 4096})
+        for (int tn : {1024, 2048, 4096, 8192})
             for (int tr : {256, 512})
-                for (int sr : {32, 128}) c.push_back({kind, tn, tr, sr});
+                for (int sr : {-1, 32}) c.push_back({kind, tn, tr, sr});
     return c;
 }
 

@@ -63,6 +63,36 @@ __device__ __forceinline__ int32_t ld_idx(const int32_t* p, int64_t k) {
     return __builtin_nontemporal_load(p + k);
 }
 
+// Element i of an array whose base the whole wavefront shares, addressed as
+// that base plus a 32-bit byte offset (the offset must stay below 4 GiB):
+// one vector register per address instead of two.
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t i) {
+    return (const T*)((const char*)base + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t i) {
+    return (T*)((char*)base + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t i) {
+    return *at(base, i);
+}
+template <typename T>
+__device__ __forceinline__ T ld_at_nt(const T* base, uint32_t i) {
+    return __builtin_nontemporal_load(at(base, i));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, uint32_t i, T v) {
+    *at(base, i) = v;
+}
+__device__ __forceinline__ double ld_val_at(const double* p, uint32_t i) { return ld_at_nt(p, i); }
+__device__ __forceinline__ float ld_val_at(const float* p, uint32_t i) { return ld_at_nt(p, i); }
+__device__ __forceinline__ float ld_val_at(const uint16_t* p, uint32_t i) {
+    const uint32_t b = ld_at_nt(p, i);
+    return __uint_as_float(b << 16);
+}
+
 // float -> bfloat16 with round-to-nearest-even (finite inputs)
 __host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
     uint32_t u;
@@ -228,7 +258,7 @@ __device__ __forceinline__ void for_rows(const RowPlan& p, Dot dot, Epi epi) {
 // written: a kernel can load its control word early and still be a no-op.
 constexpr int kTileNnzDefault = 2048;
 constexpr int kTileRowsDefault = 512;
-constexpr int kShortRowDefault = 32;
+constexpr int kShortRowDefault = -1;  // chunked segmented row sums
 constexpr int kMaxTileRows = 512;   // bound of the per-thread prefetch
 constexpr int kMaxTileNnz = 8192;
 constexpr int kRowsPerThread = kMaxTileRows / kBlock;
@@ -243,7 +273,16 @@ struct TilePlan {
     int32_t tile_rows;  // rows per tile, <= kMaxTileRows
     int32_t short_row;  // rows up to this length are summed by one thread
     int32_t max_long;   // tile_nnz / (short_row + 1) + 1
+    // Sorted layout: nonzero k of a tile (other than a one-row tile) holds the
+    // product whose row-major position in the tile is slot[k]; nullptr for
+    // the row-major layout.
+    const uint16_t* slot;
 };
+
+// Product slots of a tile: tile_nnz rounded up to a whole number of the
+// largest chunk (32), so that rotated chunks stay inside; one more slot
+// after them is a dummy target for out-of-range lanes.
+__host__ __device__ inline int prod_cap(const TilePlan& p) { return (p.tile_nnz + 31) & ~31; }
 
 // The tile's LDS, carved from dynamic shared memory.
 template <typename Acc>
@@ -260,7 +299,7 @@ template <typename Acc>
 __device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const TilePlan& p) {
     TileLds<Acc> L;
     L.prod = (Acc*)smem;
-    L.sum = L.prod + p.tile_nnz + 1;  // prod[tile_nnz] is a dummy slot
+    L.sum = L.prod + prod_cap(p) + 1;  // prod[prod_cap] is a dummy slot
     L.wsum = L.sum + p.tile_rows;
     L.row = (int32_t*)(L.wsum + kBlock / kWave);
     L.list = L.row + p.tile_rows + 1;
@@ -269,7 +308,7 @@ __device__ __forceinline__ TileLds<Acc> tile_lds(unsigned char* smem, const Tile
 }
 
 inline size_t tile_lds_bytes(const TilePlan& p, size_t acc) {
-    return acc * (size_t)(p.tile_nnz + 1 + p.tile_rows + kBlock / kWave) +
+    return acc * (size_t)(prod_cap(p) + 1 + p.tile_rows + kBlock / kWave) +
            4 * (size_t)(p.tile_rows + 1 + p.max_long + kBlock / kWave) + 16;
 }
 
@@ -291,10 +330,12 @@ template <class F>
 struct LambdaEpi {
     F f;
     typedef NoPre Pre;
-    __device__ __forceinline__ NoPre load(int) const { return NoPre{}; }
+    __device__ __forceinline__ void ready() {}
+    __device__ __forceinline__ bool running() const { return true; }
+    __device__ __forceinline__ NoPre load(int, int) const { return NoPre{}; }
     template <class A>
-    __device__ __forceinline__ void apply(int r, const NoPre&, A s) const {
-        f(r, s);
+    __device__ __forceinline__ void apply(int r0, int i, const NoPre&, A s) const {
+        f(r0 + i, s);
     }
 };
 template <class F>
@@ -304,17 +345,36 @@ __device__ __forceinline__ LambdaEpi<F> lepi(F f) {
 
 // Row totals of a tile whose products are in L.prod and whose row offsets
 // (relative to the tile) are in L.row[0..nr].  Every thread reduces one
-// contiguous chunk of ceil(nz / 256) products: rows that end inside the chunk
+// contiguous chunk of C = 2^lgc >= nz / 256 products, stored swizzled inside
+// the chunk (chunk_slot) so that the lanes, which read their chunks in step,
+// fall on different LDS banks.  Rows that end inside the chunk
 // after its first row end are complete and written at once; the part of the
 // first row that ends in the chunk needs what earlier threads hold of that
 // row, which a segmented scan over the threads supplies (a chunk with a row
 // end starts a new segment of the scan).  Empty rows keep the 0 written to
 // L.sum beforehand.  The work per thread does not depend on the row lengths.
+// log2 of the chunk length for nz products over the 256 threads
+__device__ __forceinline__ int chunk_lg(int nz) {
+    const int c = (nz + kBlock - 1) / kBlock;
+    return c <= 1 ? 0 : 32 - __clz(c - 1);
+}
+
+// LDS position of product k: inside its chunk of 2^lgc products the
+// position is XORed with bits of the chunk number, so that the lanes of a
+// wavefront, which read their chunks in step, are spread evenly over the LDS
+// banks (the chunk of thread t starts at double 2^lgc t; lanes whose chunks
+// start on the same bank get different XOR values).  Identity for lgc = 0.
+__device__ __forceinline__ int chunk_slot(int k, int lgc) {
+    return k ^ ((k >> 5) & ((1 << lgc) - 1));
+}
+
 template <bool MAXOP, typename Acc>
-__device__ __forceinline__ void chunk_row_sums(const TileLds<Acc>& L, int nz, int nr) {
+__device__ __forceinline__ void chunk_row_sums(const TileLds<Acc>& L, int nz, int nr, int lgc) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int C = (nz + kBlock - 1) / kBlock;
+    const int C = 1 << lgc;
     const int p0 = tid * C, p1 = min(p0 + C, nz);
+    const Acc* mine = L.prod + p0;  // product k at mine[(k - p0) ^ x]
+    const int x = (p0 >> 5) & (C - 1);
     bool ends = false;  // a row ends inside this chunk
     Acc head = 0, acc = 0;
     int rfirst = 0;
@@ -328,7 +388,7 @@ __device__ __forceinline__ void chunk_row_sums(const TileLds<Acc>& L, int nz, in
         int r = lo, end = L.row[lo + 1];
         rfirst = r;
         for (int k = p0; k < p1; ++k) {
-            acc = red_op<MAXOP>(acc, L.prod[k]);
+            acc = red_op<MAXOP>(acc, mine[(k - p0) ^ x]);
             if (k + 1 == end) {
                 if (ends) L.sum[r] = acc;
                 else head = acc;
@@ -371,11 +431,12 @@ __device__ __forceinline__ void chunk_row_sums(const TileLds<Acc>& L, int nz, in
     if (ends) L.sum[rfirst] = red_op<MAXOP>(carry, head);
 }
 
-// prod(k) -> Acc for a global nonzero index k.  Epi provides
-// Pre load(row) and apply(row, pre, total).
-template <bool MAXOP, typename Acc, int U = 8, class Prod, class Epi>
+// prod(b, j) -> Acc for nonzero b + j, with b the same in the whole
+// workgroup and 0 <= j < 65536.  Epi provides Pre load(r0, i) and
+// apply(r0, i, pre, total) for row r0 + i of a tile starting at row r0.
+template <bool MAXOP, typename Acc, int U = 8, bool SORTED = false, class Prod, class Epi>
 __device__ __forceinline__ void tiled_rows(const TilePlan& p, int tile, const TileLds<Acc>& L, Prod prod,
-                                           const Epi& epi, bool active = true) {
+                                           Epi& epi, bool active = true) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -385,16 +446,18 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, int tile, const Ti
     const int nz = e - s;
     if (nz > p.tile_nnz) {  // one huge row: the whole workgroup strides over it
         typename Epi::Pre pre0;
-        if (tid == 0) pre0 = epi.load(r0);
+        if (tid == 0) pre0 = epi.load(r0, 0);
         Acc a = 0;
-        for (int k = s + tid; k < e; k += kBlock) a = red_op<MAXOP>(a, prod(k));
+        for (int k0 = s; k0 < e; k0 += kBlock)
+            if (k0 + tid < e) a = red_op<MAXOP>(a, prod(k0, tid));
         a = wave_red<MAXOP>(a);
         if (lane == 0) L.prod[wave] = a;
+        epi.ready();
         __syncthreads();
-        if (tid == 0 && active) {
+        if (tid == 0 && active && epi.running()) {
             Acc tot = L.prod[0];
             for (int w = 1; w < kBlock / kWave; ++w) tot = red_op<MAXOP>(tot, L.prod[w]);
-            epi.apply(r0, pre0, tot);
+            epi.apply(r0, 0, pre0, tot);
         }
         return;
     }
@@ -404,40 +467,47 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, int tile, const Ti
     // the first products.
     typename Epi::Pre pre[kRowsPerThread];
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) pre[q] = epi.load(r0 + min(tid + q * kBlock, nr - 1));
+    for (int q = 0; q < kRowsPerThread; ++q) pre[q] = epi.load(r0, min(tid + q * kBlock, nr - 1));
     int rp[kRowsPerThread + 1];
 #pragma unroll
-    for (int q = 0; q <= kRowsPerThread; ++q) rp[q] = p.rowptr[r0 + min(tid + q * kBlock, nr)];
+    for (int q = 0; q <= kRowsPerThread; ++q) rp[q] = ld_at(p.rowptr + r0, min(tid + q * kBlock, nr));
     // products, U per thread in flight
+    const bool chunked = p.short_row < 0;
+    const int lgc = chunked ? chunk_lg(nz) : 0;  // 0: no rotation
     for (int base = 0; base < nz; base += U * kBlock) {
         Acc v[U];
+        int sl[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = prod(s + min(base + tid + u * kBlock, nz - 1));
-        // out-of-range lanes store to the dummy slot prod[tile_nnz], so the
+        for (int u = 0; u < U; ++u) {
+            const int j = min(base + tid + u * kBlock, nz - 1);
+            v[u] = prod(s, j);
+            sl[u] = SORTED ? (int)ld_at_nt(p.slot + s, j) : j;
+        }
+        // out-of-range lanes store to the dummy slot prod[prod_cap], so the
         // stores need no branch
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = base + tid + u * kBlock;
-            L.prod[k < nz ? k : p.tile_nnz] = v[u];
+            L.prod[k < nz ? chunk_slot(sl[u], lgc) : prod_cap(p)] = v[u];
         }
     }
 #pragma unroll
     for (int q = 0; q <= kRowsPerThread; ++q)
         if (tid + q * kBlock <= nr) L.row[tid + q * kBlock] = rp[q] - s;
-    const bool chunked = p.short_row < 0;
+    epi.ready();
     if (chunked)
 #pragma unroll
         for (int q = 0; q < kRowsPerThread; ++q)
             if (tid + q * kBlock < nr) L.sum[tid + q * kBlock] = 0;
     __syncthreads();
-    if (!active) return;  // uniform
+    if (!active || !epi.running()) return;  // uniform
     if (chunked) {
-        chunk_row_sums<MAXOP>(L, nz, nr);
+        chunk_row_sums<MAXOP>(L, nz, nr, lgc);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kRowsPerThread; ++q) {
             const int i = tid + q * kBlock;
-            if (i < nr) epi.apply(r0 + i, pre[q], L.sum[i]);
+            if (i < nr) epi.apply(r0, i, pre[q], L.sum[i]);
         }
         return;
     }
@@ -488,7 +558,7 @@ __device__ __forceinline__ void tiled_rows(const TilePlan& p, int tile, const Ti
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
         const int i = tid + q * kBlock;
-        if (i < nr) epi.apply(r0 + i, pre[q], L.sum[i]);
+        if (i < nr) epi.apply(r0, i, pre[q], L.sum[i]);
     }
 }
 

@@ -80,9 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_scale_stat(TilePlan p, const int32_t
                                                        double* stat) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, p);
-    auto prod = [&](int k) { return fabs(val[k]) * d_other[col[k]]; };
+    auto prod = [&](int b, int j) {
+        const int64_t k = (int64_t)b + j;
+        return fabs(val[k]) * d_other[col[k]];
+    };
     auto epi = [&](int r, double a) { stat[r] = d_self[r] * a; };
-    tiled_rows<MAXMODE>(p, own_tile(), L, prod, lepi(epi));
+    auto le = lepi(epi);
+    tiled_rows<MAXMODE>(p, own_tile(), L, prod, le);
 }
 
 // d[i] *= 1/sqrt(stat[i]) (1 for an empty row or column)
@@ -116,6 +120,85 @@ __global__ __launch_bounds__(kBlock) void k_scale_values(const int32_t* rowptr, 
     }
 }
 
+template <typename V>
+__device__ __forceinline__ void store_scaled(V* out, int64_t k, double v) {
+    if constexpr (sizeof(V) == 2) {
+        out[k] = f32_to_bf16_rne((float)v);
+    } else {
+        out[k] = (V)v;
+    }
+}
+
+// Sorted tile layout of one scaled copy.  Inside every tile (one workgroup
+// per tile) the nonzeros are ordered by column with an LDS bitonic sort of
+// (column, position) keys, which are unique, so the order is deterministic.
+// Written per sorted position k: the column, the 16-bit row-major position
+// in the tile (slot), and the scaled value d_self[row] * val * d_other[col]
+// in the iteration precision (the same expression as k_scale_values).  A
+// tile holding one row longer than tile_nnz keeps the row-major order.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_sort_scale_tiles(TilePlan p, const int32_t* col, const double* val,
+                                                             const double* d_self, const double* d_other,
+                                                             int32_t* col_s, uint16_t* slot_s, V* out) {
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    int pw = 1;
+    while (pw < p.tile_nnz) pw <<= 1;
+    unsigned long long* key = (unsigned long long*)smem_t;
+    int32_t* rows = (int32_t*)(key + pw);
+    const int tid = threadIdx.x;
+    const int4 d = p.desc[blockIdx.x];
+    const int r0 = d.x, nr = d.y - d.x, s = d.z, e = d.w, nz = e - s;
+    if (nz > p.tile_nnz) {
+        const double ds = d_self[r0];
+        for (int k = s + tid; k < e; k += kBlock) {
+            const int c = col[k];
+            col_s[k] = c;
+            slot_s[k] = 0;
+            store_scaled(out, k, ds * val[k] * d_other[c]);
+        }
+        return;
+    }
+    int P = 1;
+    while (P < nz) P <<= 1;
+    for (int i = tid; i < P; i += kBlock)
+        key[i] = i < nz ? ((unsigned long long)(uint32_t)col[s + i] << 16) | (unsigned)i : ~0ull;
+    for (int i = tid; i <= nr; i += kBlock) rows[i] = p.rowptr[r0 + i] - s;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += kBlock) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < nz; i += kBlock) {
+        const unsigned long long kv = key[i];
+        const int c = (int)(kv >> 16), src = (int)(kv & 0xffffu);
+        int lo = 0, hi = nr;  // rows[lo] <= src < rows[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rows[mid] <= src) lo = mid;
+            else hi = mid;
+        }
+        col_s[s + i] = c;
+        slot_s[s + i] = (uint16_t)src;
+        store_scaled(out, s + i, d_self[r0 + lo] * val[s + src] * d_other[c]);
+    }
+}
+
+inline size_t sort_lds_bytes(const TilePlan& p) {
+    size_t pw = 1;
+    while (pw < (size_t)p.tile_nnz) pw <<= 1;
+    return 8 * pw + 4 * (size_t)(p.tile_rows + 1);
+}
+
 // t[i] = d[i] * v[i] rounded to T; partial sums of squares in float64
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const double* d, int64_t n,
@@ -143,7 +226,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_
     const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
-    auto prod = [&](int k) {
+    auto prod = [&](int b, int jj) {
+        const int64_t k = (int64_t)b + jj;
         const int j = ld_idx(col, k);
         return ld_val(val, k) * (d_other[j] * x[j]);
     };
@@ -152,7 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_
         y[r] = t;
         s[0] += t * t;
     };
-    tiled_rows<false>(p, own_tile(), L, prod, lepi(epi));
+    auto le = lepi(epi);
+    tiled_rows<false>(p, own_tile(), L, prod, le);
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
@@ -204,7 +289,6 @@ struct IterArgs {
 template <typename T>
 struct IterPre {
     T o, an, rhs;
-    double ds;
 };
 
 template <typename T, typename V, bool PRIMAL>
@@ -213,32 +297,46 @@ struct IterEpi {
     double w, omw, rho, opr, st;
     int flags;
     double* q;
+    bool run;
     typedef IterPre<T> Pre;
-    __device__ __forceinline__ Pre load(int r) const {
+    // The run flag, the Halpern weight and the step come from the device
+    // control block; they are read here, once the tile's independent loads
+    // are in flight.
+    __device__ __forceinline__ bool running() const { return run; }
+    __device__ __forceinline__ void ready() {
+        const Ctrl* c = a.ctrl;
+        run = c->status == ST_RUNNING;
+        const int64_t k = c->k_base + a.it;
+        w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
+        omw = 1.0 - w;
+        st = PRIMAL ? c->tau : c->sigma;
+    }
+    // branch-free, so that the loads of all rows of a thread are in flight
+    // together (the scaling factor is fetched by apply() on evaluations only)
+    __device__ __forceinline__ Pre load(int r0, int i) const {
         Pre p;
-        p.o = a.state[r];
-        p.an = a.anchor[r];
-        p.rhs = a.rhs[r];
-        p.ds = (flags & F_EVAL) ? a.dscale[r] : 0.0;
+        p.o = ld_at(a.state + r0, i);
+        p.an = ld_at(a.anchor + r0, i);
+        p.rhs = ld_at(a.rhs + r0, i);
         return p;
     }
     // The arithmetic is float64 whatever the storage type T: the stored
     // iterates are rounded once, at the store.
     template <typename Acc>
-    __device__ __forceinline__ void apply(int r, const Pre& p, Acc s) const {
+    __device__ __forceinline__ void apply(int r0, int i, const Pre& p, Acc s) const {
         const double o = (double)p.o;
         double h;
         if (PRIMAL) {
             const double g = (double)p.rhs - (double)s;
             h = o - st * g;
             h = h < 0.0 ? 0.0 : h;  // projection onto x >= 0 (NaN propagates)
-            a.bar[r] = (T)(2.0 * h - o);
+            st_at(a.bar + r0, i, (T)(2.0 * h - o));
         } else {
             h = o + st * ((double)p.rhs - (double)s);
         }
-        if (flags & F_HAT) a.hat[r] = (T)h;
+        if (flags & F_HAT) st_at(a.hat + r0, i, (T)h);
         const double an = (double)p.an;
-        a.state[r] = (T)(w * (opr * h - rho * o) + omw * an);
+        st_at(a.state + r0, i, (T)(w * (opr * h - rho * o) + omw * an));
         if (flags & (F_FIRST | F_EVAL)) {
             double d = o - h;
             d *= d;
@@ -248,22 +346,19 @@ struct IterEpi {
         if (flags & F_EVAL) {
             const double d = h - an;
             q[2] += d * d;
-            a.out64[r] = p.ds * h;
+            st_at(a.out64 + r0, i, ld_at(a.dscale + r0, i) * h);
         }
     }
     // lane-group traversal: load and apply at once
     template <typename Acc>
     __device__ __forceinline__ void operator()(int r, Acc s) const {
-        apply(r, load(r), s);
+        apply(r, 0, load(r, 0), s);
     }
 };
 
 template <typename T, typename V, bool PRIMAL>
 __device__ __forceinline__ IterEpi<T, V, PRIMAL> make_epi(const IterArgs<T, V>& a, double* q) {
-    const Ctrl* c = a.ctrl;
-    const int64_t k = c->k_base + a.it;
-    const double w64 = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
-    IterEpi<T, V, PRIMAL> e{a, w64, 1.0 - w64, a.rho, 1.0 + a.rho, PRIMAL ? c->tau : c->sigma, a.flags, q};
+    IterEpi<T, V, PRIMAL> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
     return e;
 }
 
@@ -278,7 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
     if (a.ctrl->status != ST_RUNNING) return;
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    const auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto epi = make_epi<T, V, PRIMAL>(a, q);
+    epi.ready();
     auto dot = [&](int s, int e, int lane, int LL) {
         Acc acc = 0;
 #pragma unroll 4
@@ -291,36 +387,38 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 
 // LDS-tiled traversal (TilePlan).  The control word is loaded up front and
 // only checked once the products are in LDS.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
-    const bool active = a.ctrl->status == ST_RUNNING;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    const auto epi = make_epi<T, V, PRIMAL>(a, q);
-    auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
-    tiled_rows<false, Acc, U>(tp, own_tile(), L, prod, epi, active);
-    if (active && (a.flags & (F_FIRST | F_EVAL)))
+    auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto prod = [&](int b, int j) {
+        return ld_val_at(a.val + b, j) * (Acc)ld_at(a.gather, (uint32_t)ld_at_nt(a.col + b, j));
+    };
+    tiled_rows<false, Acc, U, SORTED>(tp, own_tile(), L, prod, epi);
+    if (epi.running() && (a.flags & (F_FIRST | F_EVAL)))
         block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
 
 // The same step as a persistent launch: about one workgroup per resident slot,
 // each walking its XCD's run of tiles, so that no time goes to dispatching a
 // workgroup per tile.  The norm partials cover all tiles of a workgroup.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED>
 __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TilePlan tp) {
-    const bool active = a.ctrl->status == ST_RUNNING;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    const auto epi = make_epi<T, V, PRIMAL>(a, q);
-    auto prod = [&](int k) { return ld_val(a.val, k) * (Acc)a.gather[ld_idx(a.col, k)]; };
+    auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto prod = [&](int b, int j) {
+        return ld_val_at(a.val + b, j) * (Acc)ld_at(a.gather, (uint32_t)ld_at_nt(a.col + b, j));
+    };
     const TileRange tr = persistent_tiles(tp.ntiles);
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        tiled_rows<false, Acc, U>(tp, t, L, prod, epi, active);
-        if (!active) return;
+        tiled_rows<false, Acc, U, SORTED>(tp, t, L, prod, epi);
+        if (!epi.running()) return;
         __syncthreads();  // the next tile reuses the LDS
     }
     if (a.flags & (F_FIRST | F_EVAL))
@@ -353,7 +451,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     const auto L = tile_lds<double>(smem_t, tp);
     double s[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    auto prod = [&](int k) { return ld_val(a.val, k) * a.gather[ld_idx(a.col, k)]; };
+    auto prod = [&](int b, int j) {
+        const int64_t k = (int64_t)b + j;
+        return ld_val(a.val, k) * a.gather[ld_idx(a.col, k)];
+    };
     auto epi = [&](int r, double t) {
         const double v = a.vec[r];
         if (ROWS) {
@@ -375,7 +476,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
             mx[0] = fmax(mx[0], fabs(rd));
         }
     };
-    tiled_rows<false>(tp, own_tile(), L, prod, lepi(epi), active);
+    auto le = lepi(epi);
+    tiled_rows<false>(tp, own_tile(), L, prod, le, active);
     if (active) block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
 }
 
@@ -664,6 +766,16 @@ bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& 
 int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
 int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
 int32_t short_row_of(const mipdhg_options& o) { return o.short_row != 0 ? o.short_row : kShortRowDefault; }
+// The tile kernels address the gathered vector with 32-bit byte offsets; a
+// vector of 4 GiB or more makes the iteration use the lane-group kernels.
+int iter_kind(const mipdhg_options& o, int64_t m, int64_t n) {
+    const int64_t ts = o.precision == MIPDHG_FP64 ? 8 : 4;
+    if (std::max(m, n) * ts >= (int64_t(1) << 32)) return 1;
+    return o.spmv_kind;
+}
+bool sorted_layout(const mipdhg_options& o, int64_t m, int64_t n) {
+    return o.gather_order == 0 && iter_kind(o, m, n) != 1;
+}
 
 TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,
                         int32_t trows, int32_t srow) {
@@ -676,6 +788,7 @@ TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntil
     p.tile_rows = trows;
     p.short_row = srow;
     p.max_long = srow < 0 ? 1 : tnz / (srow + 1) + 1;
+    p.slot = nullptr;
     return p;
 }
 
@@ -688,11 +801,13 @@ struct PlainWs {
     void *a_vs, *at_vs;
     void *x, *xbar, *x0, *xhat, *ct, *y, *y0, *yhat, *bt;
     int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
+    int32_t *col_a, *col_at;    // sorted layout: column copies in tile order
+    uint16_t *slot_a, *slot_at; // sorted layout: row-major position in the tile
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
-                     int64_t tnz, int64_t trows) {
+                     int64_t tnz, int64_t trows, bool sorted) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -729,6 +844,10 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, tnz, trows));
     w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, tnz, trows));
     w.flags = cv.take<int32_t>(64);
+    w.col_a = sorted ? cv.take<int32_t>(nnz) : nullptr;
+    w.col_at = sorted ? cv.take<int32_t>(nnz) : nullptr;
+    w.slot_a = sorted ? cv.take<uint16_t>(nnz) : nullptr;
+    w.slot_at = sorted ? cv.take<uint16_t>(nnz) : nullptr;
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -744,6 +863,7 @@ int check_options(const mipdhg_options* o) {
     if (o->max_iter < 1) return set_error("max_iter must be >= 1"), MIPDHG_ERR_INVALID_ARG;
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
     if (o->spmv_kind < 0 || o->spmv_kind > 2) return set_error("spmv_kind must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
+    if (o->gather_order < 0 || o->gather_order > 1) return set_error("gather_order must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_nnz != 0 && (o->tile_nnz < 256 || o->tile_nnz > kMaxTileNnz))
         return set_error("tile_nnz must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
@@ -787,7 +907,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if (rc) return rc;
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
-                   tile_rows_of(*opt)).bytes;
+                   tile_rows_of(*opt), sorted_layout(*opt, lp->m, lp->n)).bytes;
     return 0;
 }
 
@@ -813,29 +933,45 @@ struct Solver {
     ~Solver() {
         for (auto e : tev) (void)hipEventDestroy(e);
     }
-    bool tiled() const { return o.spmv_kind != 1; }
-    bool persistent() const { return o.spmv_kind == 2; }
+    bool tiled() const { return iter_kind(o, lp.m, lp.n) != 1; }
+    bool persistent() const { return iter_kind(o, lp.m, lp.n) == 2; }
     int gp_persist = 0, gd_persist = 0;  // persistent grids (resident slots, capped by the tile count)
     // dynamic LDS beyond 64 KiB must be allowed per kernel
     int allow_tile_lds() {
         const size_t need = std::max(tile_lds_bytes(ta, 8), tile_lds_bytes(tat, 8));
-        if (need <= 65536) return 0;
-        const int lim = (int)need;
-        const void* ks[] = {(const void*)k_iter_tiled<T, V, Acc, true, 8>, (const void*)k_iter_tiled<T, V, Acc, false, 8>,
-                            (const void*)k_iter_tiled<T, V, Acc, true, 16>,
-                            (const void*)k_iter_tiled<T, V, Acc, false, 16>,
-                            (const void*)k_iter_persist<T, V, Acc, true, 8>,
-                            (const void*)k_iter_persist<T, V, Acc, false, 8>,
-                            (const void*)k_iter_persist<T, V, Acc, true, 16>,
-                            (const void*)k_iter_persist<T, V, Acc, false, 16>,
-                            (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
-                            (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
-        for (const void* k : ks)
-            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
-                return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
-                       MIPDHG_ERR_UNSUPPORTED;
-        return allow_validate_lds(lim);
+        if (need > 65536) {
+            const int lim = (int)need;
+            const void* ks[] = {
+                (const void*)k_iter_tiled<T, V, Acc, true, 8, false>, (const void*)k_iter_tiled<T, V, Acc, false, 8, false>,
+                (const void*)k_iter_tiled<T, V, Acc, true, 16, false>, (const void*)k_iter_tiled<T, V, Acc, false, 16, false>,
+                (const void*)k_iter_tiled<T, V, Acc, true, 8, true>, (const void*)k_iter_tiled<T, V, Acc, false, 8, true>,
+                (const void*)k_iter_tiled<T, V, Acc, true, 16, true>, (const void*)k_iter_tiled<T, V, Acc, false, 16, true>,
+                (const void*)k_iter_persist<T, V, Acc, true, 8, false>,
+                (const void*)k_iter_persist<T, V, Acc, false, 8, false>,
+                (const void*)k_iter_persist<T, V, Acc, true, 16, false>,
+                (const void*)k_iter_persist<T, V, Acc, false, 16, false>,
+                (const void*)k_iter_persist<T, V, Acc, true, 8, true>,
+                (const void*)k_iter_persist<T, V, Acc, false, 8, true>,
+                (const void*)k_iter_persist<T, V, Acc, true, 16, true>,
+                (const void*)k_iter_persist<T, V, Acc, false, 16, true>,
+                (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
+                (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
+            for (const void* k : ks)
+                if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+                    return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
+                           MIPDHG_ERR_UNSUPPORTED;
+            int rc = allow_validate_lds(lim);
+            if (rc) return rc;
+        }
+        const size_t sneed = std::max(sort_lds_bytes(ta), sort_lds_bytes(tat));
+        if (sorted() && sneed > 65536 &&
+            hipFuncSetAttribute((const void*)k_sort_scale_tiles<V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sneed) != hipSuccess)
+            return set_error("tile sort needs %zu bytes of LDS per workgroup, more than the device allows", sneed),
+                   MIPDHG_ERR_UNSUPPORTED;
+        return 0;
     }
+    bool sorted() const { return sorted_layout(o, lp.m, lp.n); }
     int grid_primal() const { return persistent() ? gp_persist : tiled() ? tat.ntiles : hpat.grid(); }
     int grid_dual() const { return persistent() ? gd_persist : tiled() ? ta.ntiles : hpa.grid(); }
     // Resident workgroups of the persistent kernel over all CUs, at least
@@ -847,10 +983,17 @@ struct Solver {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
         const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
-        const hipError_t e =
-            tp.tile_nnz > 8 * kBlock
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 16>, kBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 8>, kBlock, lds);
+        hipError_t e;
+        if (tp.tile_nnz > 8 * kBlock)
+            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 16, true>,
+                                                                       kBlock, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 16, false>, kBlock, lds);
+        else
+            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 8, true>,
+                                                                       kBlock, lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 8, false>, kBlock, lds);
         if (e != hipSuccess || occ < 1) return 0;
         const int64_t g = std::min<int64_t>((int64_t)cus * occ, tp.ntiles);
         return (int)std::max<int64_t>(g, std::min<int64_t>(8, tp.ntiles));
@@ -866,7 +1009,7 @@ struct Solver {
 
     void fill_iter(IterArgs<T, V>& a, bool primal, int it, int flags) {
         a.p = primal ? pat : pa;
-        a.col = primal ? lp.at_col : lp.a_col;
+        a.col = primal ? (sorted() ? w.col_at : lp.at_col) : (sorted() ? w.col_a : lp.a_col);
         a.val = (const V*)(primal ? w.at_vs : w.a_vs);
         a.gather = (const T*)(primal ? w.y : w.xbar);
         a.state = (T*)(primal ? w.x : w.y);
@@ -883,28 +1026,39 @@ struct Solver {
         a.it = it;
         a.flags = flags;
     }
+    // One of the tile kernels: one workgroup per tile or persistent, 8 or 16
+    // products in flight per thread, row-major or sorted layout.
+    template <bool PRIMAL>
+    void launch_tiles(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
+        const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
+        const bool big = tp.tile_nnz > 8 * kBlock;
+        const dim3 grid(persistent() ? gpersist : tp.ntiles);
+        if (sorted()) tp.slot = PRIMAL ? w.slot_at : w.slot_a;
+#define MIP_TILE_LAUNCH(K, U, SRT) hipLaunchKernelGGL((K<T, V, Acc, PRIMAL, U, SRT>), grid, dim3(kBlock), lds, stream, a, tp)
+        if (persistent()) {
+            if (big) {
+                if (sorted()) MIP_TILE_LAUNCH(k_iter_persist, 16, true);
+                else MIP_TILE_LAUNCH(k_iter_persist, 16, false);
+            } else {
+                if (sorted()) MIP_TILE_LAUNCH(k_iter_persist, 8, true);
+                else MIP_TILE_LAUNCH(k_iter_persist, 8, false);
+            }
+        } else {
+            if (big) {
+                if (sorted()) MIP_TILE_LAUNCH(k_iter_tiled, 16, true);
+                else MIP_TILE_LAUNCH(k_iter_tiled, 16, false);
+            } else {
+                if (sorted()) MIP_TILE_LAUNCH(k_iter_tiled, 8, true);
+                else MIP_TILE_LAUNCH(k_iter_tiled, 8, false);
+            }
+        }
+#undef MIP_TILE_LAUNCH
+    }
     int launch_primal(int it, int flags) {
         IterArgs<T, V> a;
         fill_iter(a, true, it, flags);
         if (tiled()) {
-            if (tat.tile_nnz > 8 * kBlock)
-                {
-                if (persistent())
-                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, true, 16>), dim3(gp_persist), dim3(kBlock),
-                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
-                else
-                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 16>), dim3(tat.ntiles), dim3(kBlock),
-                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
-            }
-            else
-                {
-                if (persistent())
-                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, true, 8>), dim3(gp_persist), dim3(kBlock),
-                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
-                else
-                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, true, 8>), dim3(tat.ntiles), dim3(kBlock),
-                                       tile_lds_bytes(tat, sizeof(Acc)), stream, a, tat);
-            }
+            launch_tiles<true>(a, tat, gp_persist);
         } else {
             MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, true>), dim3(hpat.grid()), dim3(kBlock),
                                                          0, stream, a));
@@ -916,24 +1070,7 @@ struct Solver {
         IterArgs<T, V> a;
         fill_iter(a, false, it, flags);
         if (tiled()) {
-            if (ta.tile_nnz > 8 * kBlock)
-                {
-                if (persistent())
-                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, false, 16>), dim3(gd_persist), dim3(kBlock),
-                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
-                else
-                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 16>), dim3(ta.ntiles), dim3(kBlock),
-                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
-            }
-            else
-                {
-                if (persistent())
-                    hipLaunchKernelGGL((k_iter_persist<T, V, Acc, false, 8>), dim3(gd_persist), dim3(kBlock),
-                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
-                else
-                    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, false, 8>), dim3(ta.ntiles), dim3(kBlock),
-                                       tile_lds_bytes(ta, sizeof(Acc)), stream, a, ta);
-            }
+            launch_tiles<false>(a, ta, gd_persist);
         } else {
             MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, false>), dim3(hpa.grid()), dim3(kBlock),
                                                         0, stream, a));
@@ -1040,7 +1177,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     Solver<T, V, Acc> S(lp, o, stream);
-    S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o));
+    S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
+                sorted_layout(o, lp.m, lp.n));
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1128,12 +1266,23 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
                            (const double*)w.stat_c, n);
         MIP_LAUNCH_CHECK();
     }
-    // scaled values in the iteration precision, b~ and c~
-    hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(m * kWave, 4096)), dim3(kBlock), 0, stream, lp.a_rowptr,
-                       lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, lp.m, (V*)w.a_vs);
-    hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(n * kWave, 4096)), dim3(kBlock), 0, stream,
-                       lp.at_rowptr, lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.n,
-                       (V*)w.at_vs);
+    // scaled values in the iteration precision (sorted or row-major tile
+    // layout), b~ and c~
+    if (S.sorted()) {
+        hipLaunchKernelGGL((k_sort_scale_tiles<V>), dim3(gta), dim3(kBlock), sort_lds_bytes(S.ta), stream, S.ta,
+                           lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, w.col_a, w.slot_a,
+                           (V*)w.a_vs);
+        hipLaunchKernelGGL((k_sort_scale_tiles<V>), dim3(gtat), dim3(kBlock), sort_lds_bytes(S.tat), stream, S.tat,
+                           lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, w.col_at, w.slot_at,
+                           (V*)w.at_vs);
+    } else {
+        hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(m * kWave, 4096)), dim3(kBlock), 0, stream,
+                           lp.a_rowptr, lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, lp.m,
+                           (V*)w.a_vs);
+        hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(n * kWave, 4096)), dim3(kBlock), 0, stream,
+                           lp.at_rowptr, lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.n,
+                           (V*)w.at_vs);
+    }
     {
         const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
         hipLaunchKernelGGL((k_scale_vec<T>), dim3(gm), dim3(kBlock), 0, stream, lp.b, (const double*)w.d_row, m,

@@ -49,7 +49,8 @@ __global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int3
     const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
-    auto prod = [&](int k) {
+    auto prod = [&](int b, int j) {
+        const int64_t k = (int64_t)b + j;
         const double t = val[k] * hash_unit((uint32_t)col[k], seed_col);
         return ABS ? fabs(t) : t;
     };
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(kBlock) void k_transpose_dot(TilePlan p, const int3
         const double u = hash_unit((uint32_t)r, seed_row);
         s[0] += (ABS ? fabs(u) : u) * t;
     };
-    tiled_rows<false>(p, own_tile(), L, prod, lepi(epi));
+    auto le = lepi(epi);
+    tiled_rows<false>(p, own_tile(), L, prod, le);
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 

@@ -119,6 +119,28 @@ def test_tiled_and_lane_kernels_agree():
     assert torch.equal(a.x, c.x) and torch.equal(a.y, c.y)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kw", [dict(), dict(tile_nnz=8192, tile_rows=37), dict(tile_nnz=256, tile_rows=64, short_row=-1),
+                                dict(spmv_kind=2, tile_nnz=4096)])
+def test_sorted_layout_bitwise_equal_to_row_major(prec, kw):
+    # the sorted layout changes only the order of the loads: every product
+    # lands in the same LDS slot, so the iterates are bitwise identical
+    lp = lpgen.cfg2_sub(5, scale=100)
+    dlp = P.DeviceLP.from_lp(lp)
+    a = P.solve(dlp, 1e-6, prec, gather_order=0, **kw)
+    b = P.solve(dlp, 1e-6, prec, gather_order=1, **kw)
+    assert a.status == b.status and a.info["iters"] == b.info["iters"]
+    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
+
+
+def test_sorted_layout_huge_and_empty_rows_bitwise():
+    lp = _huge_row_lp(m=3000, n=5000, extra=3, seed=1)
+    dlp = P.DeviceLP.from_lp(lp)
+    a = P.solve(dlp, 1e-12, "fp64", max_iter=200, gather_order=0)
+    b = P.solve(dlp, 1e-12, "fp64", max_iter=200, gather_order=1)
+    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
+
+
 @pytest.mark.parametrize("lp_fn", [lambda: lpgen.tiny(6, 15, 3, 2), lambda: lpgen.cfg1(1)])
 def test_trace_parity_persistent_grid(lp_fn):
     # one tile (fewer tiles than XCDs) and a few hundred tiles
