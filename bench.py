@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """PDHG iterations per second on one MI355X.
 
-Workload: a plain PDHG solve to eps_rel = 1e-4 of the power-law LP with
-m = 100,000, n = 400,000 (column counts p(k) ~ k^-2.1423 on [2, 2000], about
-3.2M nonzeros, values N(0,1) times a per-row factor U(0.1, 10), planted
-optimum), float32 iterates and SpMV accumulation, float64 termination tests on
-the original model.  One step is one whole solve from device-resident inputs:
-validation, scaling, power iteration, the iterations, and the final
-evaluation.  value = iterations / second over the K timed steps.
+Workload (default, --workload power_law): a plain PDHG solve to
+eps_rel = 1e-4 of the power-law LP with m = 100,000, n = 400,000 (column
+counts p(k) ~ k^-2.1423 on [2, 2000], about 3.2M nonzeros, values N(0,1) times
+a per-row factor U(0.1, 10), planted optimum), float32 iterates with float64
+SpMV sums, float64 termination tests on the original model.  One step is one
+whole solve from device-resident inputs: validation, scaling, power
+iteration, the iterations, and the final evaluation.  value = iterations /
+second over the K timed steps.  --workload block_angular puts the 48.5M-nonzero
+block-angular LP on the main line instead.
 
 Also reported, on the same JSON line:
-  roofline      the dominant kernel's algorithmic bytes per launch over its
-                mean launch time (HIP events on the solver's stream), against
-                MI355X's 8 TB/s HBM peak;
-  cpu_baseline  the float64 NumPy/SciPy oracle on the host, single thread, on
-                a bounded sample of the same workload.
+  roofline          the slower iteration kernel's algorithmic bytes per launch
+                    over its mean launch time (HIP events on the solver's
+                    stream around 256 back-to-back launches), against MI355X's
+                    8 TB/s HBM peak; traffic = measured HBM-side bytes per
+                    launch from the committed counter record, while the kernel
+                    sources match it;
+  cpu_baseline      the float64 NumPy/SciPy oracle on the host, single thread,
+                    on a bounded sample of the same workload;
+  block_angular, tolerance_ratios, differentiation, batched: the other
+                    workloads (see their docstrings below).
 """
 from __future__ import annotations
 
@@ -29,9 +36,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = ("power-law LP m=100000 n=400000 (~3.2M nnz, column counts k^-2.1423 on [2,2000], "
-            "N(0,1) x row factor U(0.1,10), planted optimum), plain PDHG, FP32 iterates, "
-            "FP64 termination tests, eps_rel=1e-4")
+WORKLOADS = {
+    "power_law": ("power-law LP m=100000 n=400000 (~3.2M nnz, column counts k^-2.1423 on [2,2000], "
+                  "N(0,1) x row factor U(0.1,10), planted optimum), plain PDHG, FP32 iterates, "
+                  "FP64 termination tests, eps_rel=1e-4"),
+    "block_angular": ("block-angular LP m=1922000 n=7680000 (64 blocks 30000x120000 with 6 nnz/col, "
+                      "2000 link rows x 1200 nnz, ~48.5M nnz, planted optimum), plain PDHG, FP32 iterates, "
+                      "FP64 termination tests, eps_rel=1e-4"),
+}
 
 
 def parse():
@@ -54,7 +66,8 @@ def parse():
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--profile", action="store_true",
                     help="only a short capped solve (256 iterations) of --profile-workload (for hardware counters)")
-    ap.add_argument("--profile-workload", default="power_law", choices=["power_law", "block_angular"])
+    ap.add_argument("--workload", default="power_law", choices=["power_law", "block_angular"],
+                    help="LP of the main line (the block-angular leg is skipped when it is the main one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only a plain device copy of known size (to calibrate hardware byte counters)")
     return ap.parse_args()
@@ -121,10 +134,14 @@ def traffic_record(workload_key: str, kernel: str):
 
 def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str) -> dict:
     """Algorithmic bytes per launch of the slower iteration kernel over its
-    mean launch time, from HIP events around every launch on the solver's
-    stream, against the 8 TB/s HBM peak."""
-    tsol = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=iters, kernel_timing=1, validate=0)
+    mean launch time, against the 8 TB/s HBM peak.  The launch time is from
+    HIP events on the solver's stream around 256 back-to-back launches of each
+    kernel (kernel_timing=2); the mean with events around every launch of a
+    solve (kernel_timing=1, which adds the event cost to each launch) is
+    reported beside it."""
+    tsol = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=64, kernel_timing=2, validate=0)
     ti = tsol.info
+    each = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=iters, kernel_timing=1, validate=0).info
     kern = {"primal": (ti["bytes_primal"], ti["ms_primal"]), "dual": (ti["bytes_dual"], ti["ms_dual"])}
     dom = max(kern, key=lambda k: kern[k][1])
     b, ms = kern[dom]
@@ -133,7 +150,8 @@ def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str) -
     rec = traffic_record(workload_key, name)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec["bytes_per_launch"] if rec else None,
-            "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": iters,
+            "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": int(ti["n_primal"]),
+            "ms_per_launch_events_each": each["ms_" + dom],
             "traffic_source": f"profiles/traffic_{workload_key}.json" if rec else None,
             "other_kernel": {k: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9}
                              for k, v in kern.items() if k != dom}}
@@ -188,7 +206,7 @@ def ratio_leg(P, torch, dlp2, ws2, precision: str, t_main: float, iters_main: in
     timed(d1, 1e-4, "fp64")
     a_t, a = timed(d1, 1e-4, "fp64")
     b_t, b = timed(d1, 1e-8, "fp64", max_iter=1_000_000)
-    c_t, c = timed(dlp2, 1e-6, precision, workspace=ws2, max_iter=200_000)
+    c_t, c = timed(dlp2, 1e-6, precision, workspace=ws2, max_iter=40_000)
     return {"small_fp64": {"t_1e-4_s": a_t, "t_1e-8_s": b_t, "ratio": b_t / a_t, "iters_1e-4": int(a.info["iters"]),
                            "iters_1e-8": int(b.info["iters"]), "status_1e-8": b.status_name},
             "power_law": {"t_1e-4_s": t_main, "t_1e-6_s": c_t, "ratio": c_t / t_main, "iters_1e-4": iters_main,
@@ -288,7 +306,7 @@ def main() -> int:
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 4}))
         return 0
     t0 = time.perf_counter()
-    lp = lpgen.cfg3(args.seed) if args.profile and args.profile_workload == "block_angular" else lpgen.cfg2(args.seed)
+    lp = lpgen.cfg3(args.seed) if args.workload == "block_angular" else lpgen.cfg2(args.seed)
     gen_s = time.perf_counter() - t0
     print(f"# generated m={lp.m} n={lp.n} nnz={lp.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     dlp = P.DeviceLP.from_lp(lp, "cuda:0")
@@ -320,7 +338,7 @@ def main() -> int:
     value = iters / elapsed
 
     # per-kernel timing leg: HIP events around every primal and dual launch
-    roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, "power_law")
+    roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, args.workload)
 
     out = {
         "metric": "PDHG iter/s (plain solve to eps_rel=1e-4)",
@@ -335,7 +353,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16(A)", "fp32acc32": "f32"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "seed": args.seed,
+        "config": {"workload": WORKLOADS[args.workload], "m": lp.m, "n": lp.n, "nnz": lp.nnz, "seed": args.seed,
                    "eps_rel": args.eps, "precision": args.precision},
         "roofline": roofline,
         "solve": {"status": last.status_name, "iters": int(last.info["iters"]),
@@ -355,7 +373,7 @@ def main() -> int:
     if not args.no_diff:
         print("# differentiation leg", file=sys.stderr, flush=True)
         out["differentiation"] = diff_leg(P, torch)
-    if not args.no_block_angular:
+    if not args.no_block_angular and args.workload != "block_angular":
         print("# block-angular leg", file=sys.stderr, flush=True)
         del ws
         torch.cuda.empty_cache()

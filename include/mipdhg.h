@@ -113,8 +113,11 @@ typedef struct mipdhg_options {
     int32_t lanes_a;        /* lanes per row for A SpMVs (0 = planner)     [0] */
     int32_t lanes_at;       /* lanes per row for A^T SpMVs (0 = planner)   [0] */
     int32_t long_row;       /* rows longer than this use a whole wave (0 = planner) */
-    int32_t kernel_timing;  /* bracket every primal/dual kernel with hipEvents and report
-                               their mean durations in info (disables graphs)  [0] */
+    int32_t kernel_timing;  /* per-launch durations of the primal/dual kernels in info:
+                               1 = hipEvents around every launch of the solve (disables
+                               graphs); 2 = after the solve, 256 back-to-back launches of
+                               each kernel between two events (no per-launch event cost;
+                               the solve's outputs are not changed)             [0] */
     /* Debug trace of the scaled iterates after each of the first trace_iters
      * iterations (device float64 arrays, row-major [trace_iters][n or m]):
      * the state (x, y) after the update and the projected point (x_hat, y_hat).

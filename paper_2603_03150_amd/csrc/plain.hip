@@ -214,30 +214,30 @@ __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const dou
 }
 
 // ---------------------------------------------------------------------------
-// power iteration on D_r A D_c, float64, scaling applied on the fly
+// power iteration on D_r A D_c, float64 vectors and sums
 // ---------------------------------------------------------------------------
-// y[r] = d_self[r] * sum_k val[k] d_other[col[k]] x[col[k]]; partial ||y||^2.
-// If `norm_partials` is given, x is first divided by sqrt(sum of those G
-// partials) (the normalisation v = u / ||u|| of the previous half-step).
-__global__ __launch_bounds__(kBlock) void k_spmv_scaled(TilePlan p, const int32_t* col, const double* val,
-                                                        const double* d_self, const double* d_other,
-                                                        const double* x, double* y, double* partials) {
+// y[r] = sum_k a~_k x[col[k]] over the iteration's scaled copy (values
+// already D_r A D_c in the iteration precision, sorted or row-major tile
+// layout), partial ||y||^2: the power iteration measures the matrix the
+// iteration actually applies, with one gather per nonzero (scaling the
+// float64 original on the fly would gather the column factor as well).
+// Products and sums in float64.
+template <typename V, bool SORTED>
+__global__ __launch_bounds__(kBlock) void k_spmv_copy(TilePlan p, const int32_t* col, const V* vals,
+                                                      const double* x, double* y, double* partials) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
-    auto prod = [&](int b, int jj) {
-        const int64_t k = (int64_t)b + jj;
-        const int j = ld_idx(col, k);
-        return ld_val(val, k) * (d_other[j] * x[j]);
+    auto prod = [&](int b, int j) {
+        return (double)ld_val_at(vals + b, j) * x[ld_at_nt(col + b, j)];
     };
     auto epi = [&](int r, double a) {
-        const double t = d_self[r] * a;
-        y[r] = t;
-        s[0] += t * t;
+        y[r] = a;
+        s[0] += a * a;
     };
     auto le = lepi(epi);
-    tiled_rows<false>(p, own_tile(), L, prod, le);
+    tiled_rows<false, double, 8, SORTED>(p, own_tile(), L, prod, le);
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
@@ -864,6 +864,8 @@ int check_options(const mipdhg_options* o) {
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
     if (o->spmv_kind < 0 || o->spmv_kind > 2) return set_error("spmv_kind must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->gather_order < 0 || o->gather_order > 1) return set_error("gather_order must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->kernel_timing < 0 || o->kernel_timing > 2)
+        return set_error("kernel_timing must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_nnz != 0 && (o->tile_nnz < 256 || o->tile_nnz > kMaxTileNnz))
         return set_error("tile_nnz must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
@@ -955,7 +957,8 @@ struct Solver {
                 (const void*)k_iter_persist<T, V, Acc, true, 16, true>,
                 (const void*)k_iter_persist<T, V, Acc, false, 16, true>,
                 (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
-                (const void*)k_scale_stat<false>, (const void*)k_spmv_scaled};
+                (const void*)k_scale_stat<false>, (const void*)k_spmv_copy<V, true>,
+                (const void*)k_spmv_copy<V, false>};
             for (const void* k : ks)
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
                     return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
@@ -1300,18 +1303,32 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     {
         const double v0 = 1.0 / sqrt((double)n);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.pv, n, v0);
+        // on the scaled iteration copies (tile plans with their layout)
+        TilePlan pa = S.ta, pat = S.tat;
+        const bool srt = S.sorted();
+        if (srt) {
+            pa.slot = w.slot_a;
+            pat.slot = w.slot_at;
+        }
+        const int32_t* ca = srt ? w.col_a : lp.a_col;
+        const int32_t* cat = srt ? w.col_at : lp.at_col;
+        auto spmv = [&](const TilePlan& tp, const int32_t* col, const void* vals, const double* x, double* y,
+                        double* part) {
+            if (srt)
+                hipLaunchKernelGGL((k_spmv_copy<V, true>), dim3(tp.ntiles), dim3(kBlock), tile_lds_bytes(tp, 8), stream,
+                                   tp, col, (const V*)vals, x, y, part);
+            else
+                hipLaunchKernelGGL((k_spmv_copy<V, false>), dim3(tp.ntiles), dim3(kBlock), tile_lds_bytes(tp, 8),
+                                   stream, tp, col, (const V*)vals, x, y, part);
+        };
         for (int k = 0; k <= o.power_iters; ++k) {
             // av = A~ v, hist[k] = ||av||^2
-            hipLaunchKernelGGL(k_spmv_scaled, dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta, lp.a_col, lp.a_val,
-                               (const double*)w.d_row, (const double*)w.d_col, (const double*)w.pv, w.pav,
-                               w.psetup);
+            spmv(pa, ca, w.a_vs, (const double*)w.pv, w.pav, w.psetup);
             hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gta, 1,
                                w.hist + k);
             if (k == o.power_iters) break;
             // u = A~^T av, v = u / ||u||
-            hipLaunchKernelGGL(k_spmv_scaled, dim3(gtat), dim3(kBlock), tile_lds_bytes(S.tat, 8), stream, S.tat, lp.at_col, lp.at_val,
-                               (const double*)w.d_col, (const double*)w.d_row, (const double*)w.pav, w.pu,
-                               w.psetup + G);
+            spmv(pat, cat, w.at_vs, (const double*)w.pav, w.pu, w.psetup + G);
             hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, 1024)), dim3(kBlock), 0, stream, (const double*)w.pu,
                                w.pv, n, (const double*)(w.psetup + G), gtat);
             MIP_LAUNCH_CHECK();
@@ -1373,8 +1390,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     // --- main loop
     const int E = o.eval_every;
     const bool trace = o.trace_iters > 0;
-    const bool graph = o.use_graph && !trace && !o.kernel_timing;
-    if (o.kernel_timing) {
+    const bool graph = o.use_graph && !trace && o.kernel_timing != 1;
+    if (o.kernel_timing == 1) {
         S.timing = true;
         S.tev.resize(3 * (size_t)E);
         for (auto& e : S.tev) MIP_HIP(hipEventCreate(&e));
@@ -1465,6 +1482,32 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
 
     Ctrl cf;
     MIP_HIP(hipMemcpy(&cf, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (o.kernel_timing == 2) {
+        // back-to-back runs of each iteration kernel between two events; the
+        // control word is set to running for the runs (a finished solve makes
+        // the kernels skip their row sums) and restored afterwards
+        constexpr int R = 256;
+        hipEvent_t te[3];
+        for (auto& e : te) MIP_HIP(hipEventCreate(&e));
+        const int32_t running = ST_RUNNING;
+        MIP_HIP(hipMemcpyAsync(&w.ctrl->status, &running, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        S.stream = stream;
+        MIP_HIP(hipEventRecord(te[0], stream));
+        for (int r = 0; r < R && !rc; ++r) rc = S.launch_primal(1, 0);
+        MIP_HIP(hipEventRecord(te[1], stream));
+        for (int r = 0; r < R && !rc; ++r) rc = S.launch_dual(1, 0);
+        MIP_HIP(hipEventRecord(te[2], stream));
+        MIP_HIP(hipMemcpyAsync(&w.ctrl->status, &cf.status, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        float a = 0.f, b = 0.f;
+        MIP_HIP(hipEventElapsedTime(&a, te[0], te[1]));
+        MIP_HIP(hipEventElapsedTime(&b, te[1], te[2]));
+        for (auto e : te) (void)hipEventDestroy(e);
+        if (rc) return rc;
+        S.ms_p = a;
+        S.ms_d = b;
+        S.n_p = S.n_d = R;
+    }
     int status = cf.status;
     if (status == ST_RUNNING) status = timed_out ? MIPDHG_TIME_LIMIT : MIPDHG_ITER_LIMIT;
     if (d_row) MIP_HIP(hipMemcpyAsync(d_row, w.d_row, m * 8, hipMemcpyDeviceToDevice, stream));

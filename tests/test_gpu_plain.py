@@ -133,6 +133,20 @@ def test_sorted_layout_bitwise_equal_to_row_major(prec, kw):
     assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
 
 
+def test_back_to_back_kernel_timing_leaves_the_solve_unchanged():
+    lp = lpgen.cfg2_sub(6, scale=100)
+    dlp = P.DeviceLP.from_lp(lp)
+    a = P.solve(dlp, 1e-6, "fp32")
+    b = P.solve(dlp, 1e-6, "fp32", kernel_timing=2)
+    assert a.status == b.status and a.info["iters"] == b.info["iters"]
+    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y) and torch.equal(a.z, b.z)
+    assert b.info["n_primal"] == b.info["n_dual"] == 256
+    assert b.info["ms_primal"] > 0 and b.info["ms_dual"] > 0
+    # a second solve on the same workspace still starts from scratch
+    c = P.solve(dlp, 1e-6, "fp32")
+    assert torch.equal(a.x, c.x)
+
+
 def test_sorted_layout_huge_and_empty_rows_bitwise():
     lp = _huge_row_lp(m=3000, n=5000, extra=3, seed=1)
     dlp = P.DeviceLP.from_lp(lp)
