@@ -66,6 +66,10 @@ extern "C" {
                                 per-row updates computed in float64, rounded once   */
 #define MIPDHG_FP32_BF16A 2  /* as FP32, but the scaled A values stored as bfloat16   */
 #define MIPDHG_FP32_ACC32 3  /* float32 storage AND float32 SpMV sums and updates     */
+#define MIPDHG_FP32_A 4      /* A values stored in float32, iterate vectors, sums and
+                                updates in float64 (reaches tighter tolerances than
+                                FP32 at 4 more bytes per vector entry); single-LP
+                                solve only                                           */
 
 /* One LP in the standard form of Section 2.  Device pointers. */
 typedef struct mipdhg_lp {

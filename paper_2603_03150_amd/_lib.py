@@ -19,7 +19,7 @@ OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_BAD_CSR, ERR_TRANSPOSE, ERR_HIP = -1, -2, -3, -4
 ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_NONFINITE = -5, -6, -7
 
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32acc32": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32acc32": 3, "fp32a": 4}
 
 _i32, _i64, _f64, _p = C.c_int32, C.c_int64, C.c_double, C.c_void_p
 

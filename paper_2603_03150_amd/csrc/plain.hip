@@ -769,7 +769,7 @@ int32_t short_row_of(const mipdhg_options& o) { return o.short_row != 0 ? o.shor
 // The tile kernels address the gathered vector with 32-bit byte offsets; a
 // vector of 4 GiB or more makes the iteration use the lane-group kernels.
 int iter_kind(const mipdhg_options& o, int64_t m, int64_t n) {
-    const int64_t ts = o.precision == MIPDHG_FP64 ? 8 : 4;
+    const int64_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
     if (std::max(m, n) * ts >= (int64_t(1) << 32)) return 1;
     return o.spmv_kind;
 }
@@ -811,7 +811,7 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
-    const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
+    const size_t ts = (prec == MIPDHG_FP64 || prec == MIPDHG_FP32_A) ? 8 : 4;
     w.gcap = std::max<int64_t>(kMaxRowBlocks, std::max(max_tiles(m, nnz, tnz, trows), max_tiles(n, nnz, tnz, trows)));
     w.ctrl = cv.take<Ctrl>(1);
     w.d_row = cv.take<double>(m);
@@ -853,7 +853,7 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
 }
 
 int check_options(const mipdhg_options* o) {
-    if (o->precision < 0 || o->precision > 3) return set_error("precision must be 0, 1, 2 or 3"), MIPDHG_ERR_INVALID_ARG;
+    if (o->precision < 0 || o->precision > 4) return set_error("precision must be 0 to 4"), MIPDHG_ERR_INVALID_ARG;
     if (o->ruiz_iters < 0 || o->power_iters < 1 || o->power_iters > 100000)
         return set_error("ruiz_iters >= 0 and 1 <= power_iters <= 100000 required"), MIPDHG_ERR_INVALID_ARG;
     if (o->eval_every < 1 || o->eval_every > 4096)
@@ -1581,6 +1581,9 @@ extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, doub
         case MIPDHG_FP32_BF16A:
             return solve_impl<float, uint16_t, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
                                                        r_p, r_d, d_row, d_col, info);
+        case MIPDHG_FP32_A:
+            return solve_impl<double, float, double>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
+                                                     r_d, d_row, d_col, info);
         default:
             return solve_impl<float, float, float>(*lp, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                    r_d, d_row, d_col, info);

@@ -621,6 +621,8 @@ extern "C" int mipdhg_unrolled_forward(const mipdhg_batch* bt, const mipdhg_opti
     if (rc) return rc;
     if (!tape || !x_K) return set_error("tape and x_K are required"), MIPDHG_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    if (opt->precision == MIPDHG_FP32_A)
+        return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     switch (opt->precision) {
         case MIPDHG_FP64:
             return unrolled_impl<double, double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, false, replay,
@@ -646,6 +648,8 @@ extern "C" int mipdhg_unrolled_backward(const mipdhg_batch* bt, const mipdhg_opt
     if (!tape || !grad_xK || !grad_c || !grad_b)
         return set_error("tape, grad_xK, grad_c and grad_b are required"), MIPDHG_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    if (opt->precision == MIPDHG_FP32_A)
+        return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     switch (opt->precision) {
         case MIPDHG_FP64:
             return unrolled_impl<double, double, double>(*bt, *opt, K, ckpt_every, tape, tape_bytes, s, true, 1,

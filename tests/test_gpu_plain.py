@@ -133,6 +133,31 @@ def test_sorted_layout_bitwise_equal_to_row_major(prec, kw):
     assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
 
 
+def test_fp32_values_fp64_iterates_reach_tight_tolerance():
+    # float32 A values with float64 iterates: re-measured in float64 on the
+    # host, the Section 2 tests hold at 1e-6, and the objective obeys the
+    # planted-optimum bound
+    lp = lpgen.cfg2_sub(7, scale=50)
+    dlp = P.DeviceLP.from_lp(lp)
+    eps = 1e-6
+    sol = P.solve(dlp, eps, "fp32a", max_iter=200_000)
+    assert sol.status == 0
+    x, y = _np(sol.x), _np(sol.y)
+    z = np.maximum(lp.c - lp.AT @ y, 0.0)
+    rp = lp.b - lp.A @ x
+    rd = lp.c - lp.AT @ y - z
+    p, d = lp.c @ x, lp.b @ y
+    assert np.linalg.norm(rp) <= eps * (1 + np.linalg.norm(lp.b))
+    assert np.linalg.norm(rd) <= eps * (1 + np.linalg.norm(lp.c))
+    assert abs(p - d) <= eps * (1 + abs(p) + abs(d))
+    bound = np.linalg.norm(lp.y_star) * np.linalg.norm(rp) + np.linalg.norm(lp.x_star) * np.linalg.norm(rd) + abs(p - d)
+    assert abs(p - lp.p_star) <= bound * (1 + 1e-9) + 1e-12
+    # the mode is for single LPs
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(P.DeviceBatch.from_lps([lpgen.tiny(6, 15, 3, 0)]), 1e-4, "fp32a")
+    assert e.value.code == -6
+
+
 def test_back_to_back_kernel_timing_leaves_the_solve_unchanged():
     lp = lpgen.cfg2_sub(6, scale=100)
     dlp = P.DeviceLP.from_lp(lp)
