@@ -65,7 +65,9 @@ def parse():
     ap.add_argument("--no-ratios", action="store_true", help="skip the tolerance-ratio leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--profile", action="store_true",
-                    help="only a short capped solve (256 iterations) of --profile-workload (for hardware counters)")
+                    help="only a short capped solve (256 iterations) of --workload (for hardware counters)")
+    ap.add_argument("--shape", default="",
+                    help="SpMV shape instead of the autotuner's, e.g. spmv_kind=0,tile_nnz=4096,tile_rows=512,short_row=-1")
     ap.add_argument("--workload", default="power_law", choices=["power_law", "block_angular"],
                     help="LP of the main line (the block-angular leg is skipped when it is the main one)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -118,36 +120,46 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def traffic_record(workload_key: str, kernel: str):
+def traffic_record(workload_key: str, kernel: str, shape: dict):
     """Measured HBM bytes per launch of `kernel` on `workload_key`, from the
     committed counter summary (profiles/traffic_<workload_key>.json), or None
-    if there is none or the kernel sources changed since it was taken."""
+    if there is none, or the kernel sources or the SpMV shape differ from the
+    ones it was taken with."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_key}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256") != kernel_source_sha() or kernel not in rec.get("kernels", {}):
+    if (rec.get("source_sha256") != kernel_source_sha() or kernel not in rec.get("kernels", {})
+            or rec.get("spmv_shape") != shape):
         return None
     return rec["kernels"][kernel]
 
 
-def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str) -> dict:
+def tuned_shape(P, dlp, precision: str) -> tuple[dict, float]:
+    """The SpMV shape mipdhg_autotune picks for this LP (a one-off per
+    matrix, outside the timed region)."""
+    t0 = time.perf_counter()
+    best = P.autotune(dlp, precision, iters=64)
+    return {k: best[k] for k in ("spmv_kind", "tile_nnz", "tile_rows", "short_row")}, time.perf_counter() - t0
+
+
+def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str, shape: dict) -> dict:
     """Algorithmic bytes per launch of the slower iteration kernel over its
     mean launch time, against the 8 TB/s HBM peak.  The launch time is from
     HIP events on the solver's stream around 256 back-to-back launches of each
     kernel (kernel_timing=2); the mean with events around every launch of a
     solve (kernel_timing=1, which adds the event cost to each launch) is
     reported beside it."""
-    tsol = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=64, kernel_timing=2, validate=0)
+    tsol = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=64, kernel_timing=2, validate=0, **shape)
     ti = tsol.info
-    each = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=iters, kernel_timing=1, validate=0).info
+    each = P.solve(dlp, 0.0, precision, workspace=ws, max_iter=iters, kernel_timing=1, validate=0, **shape).info
     kern = {"primal": (ti["bytes_primal"], ti["ms_primal"]), "dual": (ti["bytes_dual"], ti["ms_dual"])}
     dom = max(kern, key=lambda k: kern[k][1])
     b, ms = kern[dom]
     achieved = b / (ms * 1e-3) / 1e9
     name = f"k_iter_tiled<{dom}>"
-    rec = traffic_record(workload_key, name)
+    rec = traffic_record(workload_key, name, shape)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec["bytes_per_launch"] if rec else None,
             "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": int(ti["n_primal"]),
@@ -167,15 +179,16 @@ def block_angular_leg(P, torch, eps: float, precision: str, timing_iters: int) -
     lp = lpgen.cfg3(0)
     gen_s = time.perf_counter() - t0
     dlp = P.DeviceLP.from_lp(lp, "cuda:0")
-    ws = torch.empty(P.workspace_bytes(dlp, precision), dtype=torch.uint8, device="cuda:0")
-    P.solve(dlp, eps, precision, workspace=ws, max_iter=64)  # warm-up
+    shape, tune_s = tuned_shape(P, dlp, precision)
+    ws = torch.empty(P.workspace_bytes(dlp, precision, **shape), dtype=torch.uint8, device="cuda:0")
+    P.solve(dlp, eps, precision, workspace=ws, max_iter=64, **shape)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sol = P.solve(dlp, eps, precision, workspace=ws, max_iter=30_000)
+    sol = P.solve(dlp, eps, precision, workspace=ws, max_iter=30_000, **shape)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     inf = sol.info
-    roof = kernel_roofline(P, dlp, ws, precision, timing_iters, "block_angular")
+    roof = kernel_roofline(P, dlp, ws, precision, timing_iters, "block_angular", shape)
     out = {"workload": "block-angular LP, 64 blocks 30000x120000 (6 nnz/col) + 2000 link rows x 1200 nnz, "
                        "planted optimum", "m": lp.m, "n": lp.n, "nnz": lp.nnz, "precision": precision,
            "eps_rel": eps, "status": sol.status_name, "iters": int(inf["iters"]), "restarts": int(inf["restarts"]),
@@ -184,13 +197,14 @@ def block_angular_leg(P, torch, eps: float, precision: str, timing_iters: int) -
            "bytes_per_iter": inf["bytes_per_iter"],
            "iter_only_GBs": inf["bytes_per_iter"] * int(inf["iters"]) / (inf["ms_iter"] * 1e-3) / 1e9,
            "rel_obj_err_vs_planted": abs(inf["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star)),
-           "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof}
+           "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof,
+           "spmv_shape": shape, "autotune_s": tune_s}
     del dlp, ws
     torch.cuda.empty_cache()
     return out
 
 
-def ratio_leg(P, torch, dlp2, ws2, precision: str, t_main: float, iters_main: int) -> dict:
+def ratio_leg(P, torch, dlp2, ws2, precision: str, t_main: float, iters_main: int, shape: dict) -> dict:
     """Solve time at a tighter tolerance over solve time at 1e-4: the small
     LP in FP64 at 1e-8; the power-law LP at 1e-6 in the bench precision
     (float32 iterates stall short of 1e-6 on it: capped), with float32 values
@@ -208,16 +222,16 @@ def ratio_leg(P, torch, dlp2, ws2, precision: str, t_main: float, iters_main: in
     timed(d1, 1e-4, "fp64")
     a_t, a = timed(d1, 1e-4, "fp64")
     b_t, b = timed(d1, 1e-8, "fp64", max_iter=1_000_000)
-    c_t, c = timed(dlp2, 1e-6, precision, workspace=ws2, max_iter=20_000)
+    c_t, c = timed(dlp2, 1e-6, precision, workspace=ws2, max_iter=20_000, **shape)
     out = {"small_fp64": {"t_1e-4_s": a_t, "t_1e-8_s": b_t, "ratio": b_t / a_t, "iters_1e-4": int(a.info["iters"]),
                           "iters_1e-8": int(b.info["iters"]), "status_1e-8": b.status_name},
            "power_law": {"precision": precision, "t_1e-4_s": t_main, "t_1e-6_s": c_t, "ratio": c_t / t_main,
                          "iters_1e-4": iters_main, "iters_1e-6": int(c.info["iters"]), "status_1e-6": c.status_name,
                          "rel_rp_1e-6": c.info["rel_rp"], "omega_1e-6": c.info["omega"]}}
     for prec in ("fp32a", "fp64"):
-        timed(dlp2, 1e-4, prec)
-        u_t, u = timed(dlp2, 1e-4, prec)
-        v_t, v = timed(dlp2, 1e-6, prec, max_iter=200_000)
+        timed(dlp2, 1e-4, prec, **shape)
+        u_t, u = timed(dlp2, 1e-4, prec, **shape)
+        v_t, v = timed(dlp2, 1e-6, prec, max_iter=20_000 if prec == "fp32a" else 200_000, **shape)
         out["power_law_" + prec] = {"t_1e-4_s": u_t, "t_1e-6_s": v_t, "ratio": v_t / u_t,
                                     "iters_1e-4": int(u.info["iters"]), "iters_1e-6": int(v.info["iters"]),
                                     "status_1e-6": v.status_name}
@@ -322,13 +336,19 @@ def main() -> int:
     gen_s = time.perf_counter() - t0
     print(f"# generated m={lp.m} n={lp.n} nnz={lp.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     dlp = P.DeviceLP.from_lp(lp, "cuda:0")
-    ws = torch.empty(P.workspace_bytes(dlp, args.precision), dtype=torch.uint8, device="cuda:0")
+    if args.shape:
+        shape = {k: int(v) for k, v in (kv.split("=") for kv in args.shape.split(","))}
+        tune_s = 0.0
+    else:
+        shape, tune_s = tuned_shape(P, dlp, args.precision)
+    print(f"# SpMV shape {shape} (autotune {tune_s:.1f}s)", file=sys.stderr, flush=True)
+    ws = torch.empty(P.workspace_bytes(dlp, args.precision, **shape), dtype=torch.uint8, device="cuda:0")
 
     def step():
-        return P.solve(dlp, args.eps, args.precision, workspace=ws, max_iter=200_000)
+        return P.solve(dlp, args.eps, args.precision, workspace=ws, max_iter=200_000, **shape)
 
     if args.profile:
-        s = P.solve(dlp, 0.0, args.precision, workspace=ws, max_iter=256)
+        s = P.solve(dlp, 0.0, args.precision, workspace=ws, max_iter=256, **shape)
         torch.cuda.synchronize()
         print(json.dumps({"profile_solve_iters": int(s.info["iters"]), "precision": args.precision}))
         return 0
@@ -350,7 +370,7 @@ def main() -> int:
     value = iters / elapsed
 
     # per-kernel timing leg: HIP events around every primal and dual launch
-    roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, args.workload)
+    roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, args.workload, shape)
 
     out = {
         "metric": "PDHG iter/s (plain solve to eps_rel=1e-4)",
@@ -377,12 +397,12 @@ def main() -> int:
                   "rel_gap": last.info["rel_gap"], "max_violation": last.info["max_violation"],
                   "bytes_per_iter": last.info["bytes_per_iter"],
                   "iter_only_rate": int(last.info["iters"]) / (last.info["ms_iter"] * 1e-3),
-                  "plan": {k: last.info[k] for k in ("lanes_a", "lanes_at", "long_a", "long_at")}},
+                  "spmv_shape": shape, "autotune_s": tune_s},
     }
     if not args.no_ratios:
         print("# tolerance ratios", file=sys.stderr, flush=True)
         out["tolerance_ratios"] = ratio_leg(P, torch, dlp, ws, args.precision, elapsed / args.steps,
-                                            int(last.info["iters"]))
+                                            int(last.info["iters"]), shape)
     if not args.no_diff:
         print("# differentiation leg", file=sys.stderr, flush=True)
         out["differentiation"] = diff_leg(P, torch)
