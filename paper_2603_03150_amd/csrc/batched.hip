@@ -99,9 +99,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         // stored in T
         for (int j = tid; j < n; j += kBatchBlock) {
             const int g = c0 + j;
-            Acc s = 0;
-            for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz)
-                s += (Acc)ld_val(a.at_vs, kz) * (Acc)yL[a.at_col[kz] - r0];
+            const Acc s = row_dot4<Acc>(a.at_vs, a.at_col, yL, r0, a.at_rowptr[g], a.at_rowptr[g + 1]);
             const double o = (double)a.x[g];
             double hh = o - tau * ((double)a.ct[g] - (double)s);
             hh = hh < 0.0 ? 0.0 : hh;
@@ -123,9 +121,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         // dual step over the rows of A
         for (int i = tid; i < m; i += kBatchBlock) {
             const int g = r0 + i;
-            Acc s = 0;
-            for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz)
-                s += (Acc)ld_val(a.a_vs, kz) * (Acc)xbL[a.a_col[kz] - c0];
+            const Acc s = row_dot4<Acc>(a.a_vs, a.a_col, xbL, c0, a.a_rowptr[g], a.a_rowptr[g + 1]);
             const double o = (double)yL[i];
             const double hh = o + sig * ((double)a.bt[g] - (double)s);
             const double an = (double)a.y0[g];

@@ -62,6 +62,13 @@ __device__ __forceinline__ float ld_val(const uint16_t* p, int64_t k) {
 __device__ __forceinline__ int32_t ld_idx(const int32_t* p, int64_t k) {
     return __builtin_nontemporal_load(p + k);
 }
+// Cached loads of values re-read every iteration by the same workgroup (a
+// batched instance's matrix stays in L2 between its iterations).
+__device__ __forceinline__ double ld_val_cached(const double* p, int64_t k) { return p[k]; }
+__device__ __forceinline__ float ld_val_cached(const float* p, int64_t k) { return p[k]; }
+__device__ __forceinline__ float ld_val_cached(const uint16_t* p, int64_t k) {
+    return __uint_as_float((uint32_t)p[k] << 16);
+}
 
 // Element i of an array whose base the whole wavefront shares, addressed as
 // that base plus a 32-bit byte offset (the offset must stay below 4 GiB):

@@ -9,6 +9,28 @@
 
 namespace mip {
 
+// Dot product of the sparse row [s, e) with a vector held in LDS (entry
+// col - off): the loads of four nonzeros are issued together, and the terms
+// are added in the row's order.
+template <typename Acc, typename V, typename X>
+__device__ __forceinline__ Acc row_dot4(const V* vals, const int32_t* cols, const X* xl, int off, int s, int e) {
+    Acc acc = 0;
+    int k = s;
+    for (; k + 4 <= e; k += 4) {
+        int c[4];
+        Acc v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = cols[k + q];
+            v[q] = (Acc)ld_val_cached(vals, k + q);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += v[q] * (Acc)xl[c[q] - off];
+    }
+    for (; k < e; ++k) acc += (Acc)ld_val_cached(vals, k) * (Acc)xl[cols[k] - off];
+    return acc;
+}
+
 constexpr int kBatchBlock = 256;
 
 // Fixed-order workgroup sums (NS) and maxima (NM); every thread gets the result.

@@ -86,9 +86,7 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
     const double omw = 1.0 - w, rho = a.rho, opr = 1.0 + a.rho;
     for (int j = tid; j < u.n; j += kBatchBlock) {
         const int g = u.c0 + j;
-        Acc s = 0;
-        for (int kz = a.M.at_rowptr[g]; kz < a.M.at_rowptr[g + 1]; ++kz)
-            s += (Acc)ld_val(a.at_vs, kz) * (Acc)yL[a.M.at_col[kz] - u.r0];
+        const Acc s = row_dot4<Acc>(a.at_vs, a.M.at_col, yL, u.r0, a.M.at_rowptr[g], a.M.at_rowptr[g + 1]);
         const double o = (double)a.x[g];
         const double v = o - tau * ((double)a.ct[g] - (double)s);
         const double hh = v < 0.0 ? 0.0 : v;
@@ -110,9 +108,7 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
     __syncthreads();
     for (int i = tid; i < u.m; i += kBatchBlock) {
         const int g = u.r0 + i;
-        Acc s = 0;
-        for (int kz = a.M.a_rowptr[g]; kz < a.M.a_rowptr[g + 1]; ++kz)
-            s += (Acc)ld_val(a.a_vs, kz) * (Acc)xbL[a.M.a_col[kz] - u.c0];
+        const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, xbL, u.c0, a.M.a_rowptr[g], a.M.a_rowptr[g + 1]);
         const double o = (double)yL[i];
         const double hh = o + sig * ((double)a.bt[g] - (double)s);
         const double an = (double)a.y0[g];
@@ -314,9 +310,8 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
             const uint64_t* mrow = a.masks + (int64_t)it * a.W + a.word_off[i];
             for (int j = tid; j < u.n; j += kBatchBlock) {
                 const int g = u.c0 + j;
-                Acc s = 0;
-                for (int kz = a.M.at_rowptr[g]; kz < a.M.at_rowptr[g + 1]; ++kz)
-                    s += (Acc)ld_val(a.at_vs, kz) * (Acc)lyhL[a.M.at_col[kz] - u.r0];
+                const Acc s =
+                    row_dot4<Acc>(a.at_vs, a.M.at_col, lyhL, u.r0, a.M.at_rowptr[g], a.M.at_rowptr[g + 1]);
                 const double lxbar = -sig * (double)s;
                 const double lx = (double)a.lx[g], lx0 = (double)a.lx0[g];
                 double lxh = (rs ? lx + lx0 : w * opr * lx) + 2.0 * lxbar;
@@ -333,9 +328,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
             // (R2) rows: lam_y -= A~ lam_g
             for (int r = tid; r < u.m; r += kBatchBlock) {
                 const int g = u.r0 + r;
-                Acc s = 0;
-                for (int kz = a.M.a_rowptr[g]; kz < a.M.a_rowptr[g + 1]; ++kz)
-                    s += (Acc)ld_val(a.a_vs, kz) * (Acc)lgL[a.M.a_col[kz] - u.c0];
+                const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, lgL, u.c0, a.M.a_rowptr[g], a.M.a_rowptr[g + 1]);
                 a.ly[g] = (T)((double)a.ly[g] - (double)s);
             }
             __syncthreads();
