@@ -96,15 +96,34 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         const double omw = 1.0 - w;
         double q[4] = {0.0, 0.0, 0.0, 0.0};
         // primal step over the columns (rows of A^T); float64 arithmetic,
-        // stored in T
+        // stored in T.  The next row's bounds and vector entries are loaded
+        // (branch-free, clamped to the last row) while this row is summed.
+        int nb0 = 0, nb1 = 0;
+        T nx = 0, nx0 = 0, nct = 0;
+        if (n > 0) {
+            const int g = c0 + min(tid, n - 1);
+            nb0 = a.at_rowptr[g];
+            nb1 = a.at_rowptr[g + 1];
+            nx = a.x[g];
+            nx0 = a.x0[g];
+            nct = a.ct[g];
+        }
         for (int j = tid; j < n; j += kBatchBlock) {
             const int g = c0 + j;
-            const Acc s = row_dot4<Acc>(a.at_vs, a.at_col, yL, r0, a.at_rowptr[g], a.at_rowptr[g + 1]);
-            const double o = (double)a.x[g];
-            double hh = o - tau * ((double)a.ct[g] - (double)s);
+            const int b0 = nb0, b1 = nb1;
+            const double o = (double)nx, an = (double)nx0, ctg = (double)nct;
+            {
+                const int gn = c0 + min(j + kBatchBlock, n - 1);
+                nb0 = a.at_rowptr[gn];
+                nb1 = a.at_rowptr[gn + 1];
+                nx = a.x[gn];
+                nx0 = a.x0[gn];
+                nct = a.ct[gn];
+            }
+            const Acc s = row_dot4<Acc>(a.at_vs, a.at_col, yL, r0, b0, b1);
+            double hh = o - tau * (ctg - (double)s);
             hh = hh < 0.0 ? 0.0 : hh;
             xbL[j] = (T)(2.0 * hh - o);
-            const double an = (double)a.x0[g];
             a.x[g] = (T)(w * (opr * hh - rho * o) + omw * an);
             if (first || is_eval) {
                 const double d = o - hh;
@@ -118,13 +137,30 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             }
         }
         __syncthreads();
-        // dual step over the rows of A
+        // dual step over the rows of A, with the same prefetch
+        int mb0 = 0, mb1 = 0;
+        T my0 = 0, mbt = 0;
+        if (m > 0) {
+            const int g = r0 + min(tid, m - 1);
+            mb0 = a.a_rowptr[g];
+            mb1 = a.a_rowptr[g + 1];
+            my0 = a.y0[g];
+            mbt = a.bt[g];
+        }
         for (int i = tid; i < m; i += kBatchBlock) {
             const int g = r0 + i;
-            const Acc s = row_dot4<Acc>(a.a_vs, a.a_col, xbL, c0, a.a_rowptr[g], a.a_rowptr[g + 1]);
+            const int b0 = mb0, b1 = mb1;
+            const double an = (double)my0, btg = (double)mbt;
+            {
+                const int gn = r0 + min(i + kBatchBlock, m - 1);
+                mb0 = a.a_rowptr[gn];
+                mb1 = a.a_rowptr[gn + 1];
+                my0 = a.y0[gn];
+                mbt = a.bt[gn];
+            }
+            const Acc s = row_dot4<Acc>(a.a_vs, a.a_col, xbL, c0, b0, b1);
             const double o = (double)yL[i];
-            const double hh = o + sig * ((double)a.bt[g] - (double)s);
-            const double an = (double)a.y0[g];
+            const double hh = o + sig * (btg - (double)s);
             yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
             if (first || is_eval) {
                 const double d = o - hh;
