@@ -84,18 +84,38 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
     const int tid = threadIdx.x;
     const double w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
     const double omw = 1.0 - w, rho = a.rho, opr = 1.0 + a.rho;
+    // the next row's bounds and vector entries are loaded (branch-free,
+    // clamped to the last row) while this row is summed
+    int nb0 = 0, nb1 = 0;
+    T nx = 0, nx0 = 0, nct = 0;
+    if (u.n > 0) {
+        const int g = u.c0 + min(tid, u.n - 1);
+        nb0 = a.M.at_rowptr[g];
+        nb1 = a.M.at_rowptr[g + 1];
+        nx = a.x[g];
+        nx0 = a.x0[g];
+        nct = a.ct[g];
+    }
     for (int j = tid; j < u.n; j += kBatchBlock) {
         const int g = u.c0 + j;
-        const Acc s = row_dot4<Acc>(a.at_vs, a.M.at_col, yL, u.r0, a.M.at_rowptr[g], a.M.at_rowptr[g + 1]);
-        const double o = (double)a.x[g];
-        const double v = o - tau * ((double)a.ct[g] - (double)s);
+        const int b0 = nb0, b1 = nb1;
+        const double o = (double)nx, an = (double)nx0, ctg = (double)nct;
+        {
+            const int gn = u.c0 + min(j + kBatchBlock, u.n - 1);
+            nb0 = a.M.at_rowptr[gn];
+            nb1 = a.M.at_rowptr[gn + 1];
+            nx = a.x[gn];
+            nx0 = a.x0[gn];
+            nct = a.ct[gn];
+        }
+        const Acc s = row_dot4<Acc>(a.at_vs, a.M.at_col, yL, u.r0, b0, b1);
+        const double v = o - tau * (ctg - (double)s);
         const double hh = v < 0.0 ? 0.0 : v;
         if (maskrow) {
             const unsigned long long bits = __ballot(v > 0.0);
             if ((tid & (kWave - 1)) == 0) maskrow[j >> 6] = bits;
         }
         xbL[j] = (T)(2.0 * hh - o);
-        const double an = (double)a.x0[g];
         a.x[g] = (T)(w * (opr * hh - rho * o) + omw * an);
         if (want_q) {
             const double d = o - hh, e = hh - an;
@@ -106,12 +126,29 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
         if (last) a.xK[g] = a.d_col[g] * hh;
     }
     __syncthreads();
+    int mb0 = 0, mb1 = 0;
+    T my0 = 0, mbt = 0;
+    if (u.m > 0) {
+        const int g = u.r0 + min(tid, u.m - 1);
+        mb0 = a.M.a_rowptr[g];
+        mb1 = a.M.a_rowptr[g + 1];
+        my0 = a.y0[g];
+        mbt = a.bt[g];
+    }
     for (int i = tid; i < u.m; i += kBatchBlock) {
         const int g = u.r0 + i;
-        const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, xbL, u.c0, a.M.a_rowptr[g], a.M.a_rowptr[g + 1]);
+        const int b0 = mb0, b1 = mb1;
+        const double an = (double)my0, btg = (double)mbt;
+        {
+            const int gn = u.r0 + min(i + kBatchBlock, u.m - 1);
+            mb0 = a.M.a_rowptr[gn];
+            mb1 = a.M.a_rowptr[gn + 1];
+            my0 = a.y0[gn];
+            mbt = a.bt[gn];
+        }
+        const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, xbL, u.c0, b0, b1);
         const double o = (double)yL[i];
-        const double hh = o + sig * ((double)a.bt[g] - (double)s);
-        const double an = (double)a.y0[g];
+        const double hh = o + sig * (btg - (double)s);
         yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
         if (want_q) {
             const double d = o - hh, e = hh - an;
