@@ -199,6 +199,13 @@ def block_angular_leg(P, torch, eps: float, precision: str, timing_iters: int) -
            "rel_obj_err_vs_planted": abs(inf["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star)),
            "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof,
            "spmv_shape": shape, "autotune_s": tune_s}
+    # the same LP with the scaled values rounded to BF16: the rounding changes
+    # the LP, and the float64 tests report how far that floor is (capped run)
+    bsol = P.solve(dlp, eps, "bf16", max_iter=5_000, **shape)
+    bi = bsol.info
+    out["bf16_values"] = {"status": bsol.status_name, "iters": int(bi["iters"]), "rel_rp": bi["rel_rp"],
+                          "rel_rd": bi["rel_rd"], "rel_gap": bi["rel_gap"], "iter_only_rate":
+                          int(bi["iters"]) / (bi["ms_iter"] * 1e-3), "bytes_per_iter": bi["bytes_per_iter"]}
     del dlp, ws
     torch.cuda.empty_cache()
     return out
@@ -264,6 +271,37 @@ def diff_leg(P, torch) -> dict:
             "backward_s": t2 - t1, "tape_bytes": umap.tape_bytes}
 
 
+def _oracle_solve(args):
+    import oracle
+    from oracle.pdhg import OracleOptions
+    A, AT, b, c, eps = args
+    return oracle.solve(A, AT, b, c, eps, opts=OracleOptions(max_iter=100_000)).iters
+
+
+def batched_cpu_baseline(lps, eps: float) -> dict:
+    """The oracle on the same stratified sample, one process per host core
+    (at most 16), each single-threaded: LPs/s of the host."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, os.cpu_count() or 1))
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        t0 = time.perf_counter()
+        # fresh interpreters (spawn): the workers import only the oracle and
+        # never touch the GPU this process holds
+        with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("spawn")) as ex:
+            list(ex.map(_oracle_solve, [(lp.A, lp.AT, lp.b, lp.c, eps) for lp in lps], timeout=300))
+        dt = time.perf_counter() - t0
+    finally:
+        if env_threads is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_threads
+    return {"value": len(lps) / dt, "unit": "LPs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(lps)} instances spread over the size range, {cores} processes of one thread each"}
+
+
 def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
     """4,096 LPs (m log-uniform on [20, 2000], n = 2.5 m, 4 nonzeros per
     column) in one persistent launch, FP32 iterates with FP64 per-instance
@@ -297,7 +335,9 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t1
     plain_lps = sample / t_plain
+    cpu = batched_cpu_baseline([lps[i] for i in pick], eps)
     return {"metric": "batched LPs/s to eps_rel=1e-4", "value": count / dt, "unit": "LPs/s",
+            "cpu_baseline": cpu,
             "count": count, "solved": solved, "seconds": dt,
             "iters_p50": float(np.percentile(iters, 50)), "iters_p99": float(np.percentile(iters, 99)),
             "plain_fp64_lps_per_s": plain_lps, "plain_sample": int(sample),
