@@ -136,6 +136,22 @@ typedef struct mipdhg_options {
      * lanes of a load fall on few cache lines (costs 6 more workspace bytes
      * per nonzero and copy); 1 = row-major.  Results are bitwise identical. [0] */
     int32_t gather_order;
+    /* 1 = continue the solve whose state the workspace holds (same LP, same
+     * options but eps_rel, max_iter and time_limit_s; checked by a
+     * fingerprint) instead of starting from (0, 0).  max_iter counts all
+     * iterations, those already done included.  A solve stopped at an
+     * evaluation (optimal or at its iteration limit) skipped that evaluation's
+     * restart decision; it is taken again under the new tolerance, so a solve
+     * stopped at a multiple of eval_every and resumed gives bitwise the
+     * result of one uninterrupted solve with the resumed tolerance and limit.
+     * The outputs are written at evaluations: a resumed solve whose first
+     * decision already stops it leaves them as the stopped solve wrote them,
+     * so pass the same output arrays.  A state that does not match (other
+     * sizes, options, b or c norms or step size) is INVALID_ARG, and so is
+     * one that stopped on non-finite values.  Not with x_init, y_init or
+     * tracing; a kernel_timing = 2 solve is not resumable.  Single-LP solve
+     * only (UNSUPPORTED in the batched and unrolled entry points).          [0] */
+    int32_t resume;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */

@@ -42,7 +42,7 @@ class OptionsStruct(C.Structure):
                 ("short_row", _i32), ("lanes_a", _i32), ("lanes_at", _i32),
                 ("long_row", _i32), ("kernel_timing", _i32), ("trace_iters", _i32),
                 ("trace_x", _p), ("trace_y", _p), ("trace_xhat", _p), ("trace_yhat", _p),
-                ("x_init", _p), ("y_init", _p), ("gather_order", _i32)]
+                ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32)]
 
 
 class InfoStruct(C.Structure):

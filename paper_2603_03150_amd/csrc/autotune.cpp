@@ -46,6 +46,7 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
         o.kernel_timing = 1;
         o.max_iter = iters;
         o.trace_iters = 0;
+        o.resume = 0;
         o.validate = first ? opt->validate : 0;
         size_t need = 0;
         if (mipdhg_workspace_size(lp, &o, &need) != 0 || need > workspace_bytes) continue;

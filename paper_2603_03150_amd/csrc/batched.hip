@@ -576,8 +576,9 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
     if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
     if (!workspace || !x || !y || !z || !r_p || !r_d)
         return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
-    if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing)
-        return set_error("tracing, warm starts and kernel timing are single-LP options"), MIPDHG_ERR_UNSUPPORTED;
+    if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing || opt->resume)
+        return set_error("tracing, warm starts, kernel timing and resume are single-LP options"),
+               MIPDHG_ERR_UNSUPPORTED;
     if (opt->precision == MIPDHG_FP32_A)
         return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;

@@ -27,6 +27,10 @@ struct Ctrl {
     // last evaluation (original model)
     double rp2, rd2, pobj, dobj, xz, rp_inf, rd_inf;
     int64_t eval_t;
+    // resume: iterations of the last evaluated block, the problem and layout
+    // the state belongs to, and whether the state is the solve's own
+    int32_t last_nit, resumable;
+    uint64_t fingerprint;
 };
 
 // shared host helpers (plain.hip, validate.hip)

@@ -558,6 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     c.rd_inf = rd_inf;
     c.eval_t = t_end;
     c.last_R = R;
+    c.last_nit = a.nit;
     const double rp = sqrt(rp2), rd = sqrt(rd2), gap = fabs(pobj - dobj);
     int32_t status = ST_RUNNING;
     if (!(isfinite(rp2) && isfinite(rd2) && isfinite(pobj) && isfinite(dobj))) {
@@ -769,6 +770,25 @@ bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& 
 int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
 int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
 int32_t short_row_of(const mipdhg_options& o) { return o.short_row != 0 ? o.short_row : kShortRowDefault; }
+// What a resumed solve must share with the solve whose state it continues:
+// the problem's sizes and every option that shapes the state or its layout.
+uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the fields
+    auto mix = [&](const void* p, size_t nb) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < nb; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    const int64_t sz[3] = {lp.m, lp.n, lp.nnz};
+    mix(sz, sizeof(sz));
+    const int32_t iv[15] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
+                            o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
+                            o.gather_order, o.lanes_a, o.lanes_at, o.long_row};
+    mix(iv, sizeof(iv));
+    const double dv[7] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, 0.0};
+    mix(dv, sizeof(dv));
+    return h;
+}
+
 // The iteration's SpMV kind.  (Every 32-bit offset of the tile kernels is
 // tile-relative, so no matrix or vector size forces another kind.)
 int iter_kind(const mipdhg_options& o, int64_t, int64_t) { return o.spmv_kind; }
@@ -865,6 +885,10 @@ int check_options(const mipdhg_options* o) {
     if (o->gather_order < 0 || o->gather_order > 1) return set_error("gather_order must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (o->kernel_timing < 0 || o->kernel_timing > 2)
         return set_error("kernel_timing must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
+    if (o->resume < 0 || o->resume > 1) return set_error("resume must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->resume && (o->x_init || o->y_init || o->trace_iters))
+        return set_error("resume continues the workspace's state: no warm start or trace with it"),
+               MIPDHG_ERR_INVALID_ARG;
     if (o->tile_nnz != 0 && (o->tile_nnz < 256 || o->tile_nnz > kMaxTileNnz))
         return set_error("tile_nnz must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
     if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
@@ -1105,6 +1129,11 @@ struct Solver {
         ec.ctrl = w.ctrl;
         hipLaunchKernelGGL((k_eval<false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, ec, tat);
         MIP_LAUNCH_CHECK();
+        return launch_decide(nit);
+    }
+    // decision and restart copy for a block of nit iterations whose
+    // evaluation partials are in the workspace
+    int launch_decide(int nit) {
         DecideArgs d;
         d.ctrl = w.ctrl;
         d.pp = w.pp;
@@ -1192,6 +1221,20 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     S.rdo = r_d;
     PlainWs& w = S.w;
     const int64_t m = lp.m, n = lp.n, nnz = lp.nnz;
+    // a resumed solve checks the state's sizes and options before setup
+    // writes to the workspace (the control block is at its start whatever
+    // the layout), so that a refused resume leaves the state as it was
+    const uint64_t fp = state_fingerprint(lp, o);
+    if (o.resume) {
+        Ctrl cur;
+        MIP_HIP(hipMemcpyAsync(&cur, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        if (!cur.resumable || cur.fingerprint != fp)
+            return set_error("resume: the workspace does not hold a resumable state of this LP with these options"),
+                   MIPDHG_ERR_INVALID_ARG;
+        if (cur.status == MIPDHG_NUMERICAL)
+            return set_error("resume: the stopped solve hit non-finite values"), MIPDHG_ERR_INVALID_ARG;
+    }
 
     // --- row pointers to the host: validation and SpMV plans
     std::vector<int32_t> rpa(m + 1), rpat(n + 1);
@@ -1355,7 +1398,29 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const double nbt = sqrt(red[2]), nct = sqrt(red[3]);
     const double omega0 = (nbt > 1e-10 && nct > 1e-10) ? nct / nbt : 1.0;
 
-    // --- control block and initial point
+    // --- control block and initial point (or, when resuming, the
+    // workspace's own state, checked against this problem and layout)
+    if (o.resume) {
+        Ctrl cur;
+        MIP_HIP(hipMemcpyAsync(&cur, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        // the data, by the norms of b and c and the step size that setup has
+        // just recomputed (setup leaves the iterates and the control block)
+        if (cur.b_norm != sqrt(bn2) || cur.c_norm != sqrt(cn2) || cur.eta != eta)
+            return set_error("resume: the workspace holds the state of another LP of these sizes"),
+                   MIPDHG_ERR_INVALID_ARG;
+        // a solve that stopped at an evaluation (optimal or at its iteration
+        // limit) skipped that evaluation's restart decision: take it again
+        // with the new tolerance and limit
+        const bool redo = cur.status != ST_RUNNING;
+        if (redo) cur.t_base -= cur.last_nit;
+        cur.status = ST_RUNNING;
+        cur.eps = eps;
+        cur.max_iter = o.max_iter;
+        MIP_HIP(hipMemcpyAsync(w.ctrl, &cur, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+        if (redo && (rc = S.launch_decide(cur.last_nit))) return rc;
+        MIP_HIP(hipStreamSynchronize(stream));
+    }
     Ctrl c0;
     memset(&c0, 0, sizeof(c0));
     c0.omega = omega0;
@@ -1377,12 +1442,16 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     c0.pw_theta = o.pw_theta;
     c0.max_iter = o.max_iter;
     c0.do_restarts = o.restarts;
-    MIP_HIP(hipMemcpyAsync(w.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, o.x_init,
-                       (const double*)w.d_col, n, (T*)w.x, (T*)w.x0, (T*)w.xhat);
-    hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, o.y_init,
-                       (const double*)w.d_row, m, (T*)w.y, (T*)w.y0, (T*)w.yhat);
-    MIP_LAUNCH_CHECK();
+    c0.resumable = 1;
+    c0.fingerprint = fp;
+    if (!o.resume) {
+        MIP_HIP(hipMemcpyAsync(w.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, o.x_init,
+                           (const double*)w.d_col, n, (T*)w.x, (T*)w.x0, (T*)w.xhat);
+        hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, o.y_init,
+                           (const double*)w.d_row, m, (T*)w.y, (T*)w.y0, (T*)w.yhat);
+        MIP_LAUNCH_CHECK();
+    }
     MIP_HIP(hipStreamSynchronize(stream));
     const auto t1 = clk::now();
 
@@ -1425,6 +1494,13 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     hipEvent_t ev[kDepth];
     for (int i = 0; i < kDepth; ++i) MIP_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     int64_t launched = 0;
+    if (o.resume) {
+        Ctrl cur;
+        MIP_HIP(hipMemcpyAsync(&cur, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        launched = cur.t_base;  // iterations already done
+        if (cur.status != ST_RUNNING) launched = o.max_iter;  // decided at once (e.g. still optimal)
+    }
     int64_t blocks = 0, checked = 0;
     bool done = false, timed_out = false;
     rc = 0;
@@ -1497,6 +1573,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         for (int r = 0; r < R && !rc; ++r) rc = S.launch_dual(1, 0);
         MIP_HIP(hipEventRecord(te[2], stream));
         MIP_HIP(hipMemcpyAsync(&w.ctrl->status, &cf.status, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        const int32_t no = 0;  // the timing runs moved the iterates: not resumable
+        MIP_HIP(hipMemcpyAsync(&w.ctrl->resumable, &no, sizeof(int32_t), hipMemcpyHostToDevice, stream));
         MIP_HIP(hipStreamSynchronize(stream));
         float a = 0.f, b = 0.f;
         MIP_HIP(hipEventElapsedTime(&a, te[0], te[1]));

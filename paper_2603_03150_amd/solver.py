@@ -85,6 +85,7 @@ class Solution:
     d_col: torch.Tensor
     info: dict
     trace: dict = field(default_factory=dict)
+    workspace: torch.Tensor | None = None  # holds the state a resumed solve continues
 
 
 def workspace_bytes(dlp: DeviceLP, precision: str = "fp64", **opts) -> int:
@@ -117,10 +118,17 @@ def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -
 
 def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters: int = 0,
           x_init: torch.Tensor | None = None, y_init: torch.Tensor | None = None,
-          workspace: torch.Tensor | None = None, **opts) -> Solution:
-    """Run mipdhg_solve on dlp.  Options are the fields of mipdhg_options."""
+          workspace: torch.Tensor | None = None, resume: Solution | None = None, **opts) -> Solution:
+    """Run mipdhg_solve on dlp.  Options are the fields of mipdhg_options.
+
+    resume: a Solution of this LP, solved with the same options; the solve
+    continues its state (its workspace and output tensors are reused and
+    written in place), with max_iter counting all iterations."""
     lib = _lib.load()
     o = make_options(precision, **opts)
+    if resume is not None:
+        o.resume = 1
+        workspace = resume.workspace
     d = dlp.device
     f64 = dict(dtype=torch.float64, device=d)
     trace = {}
@@ -138,15 +146,21 @@ def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters
     lps = dlp.struct()
     nb = C.c_size_t(0)
     _lib.check(lib.mipdhg_workspace_size(C.byref(lps), C.byref(o), C.byref(nb)))
+    if resume is not None and (workspace is None or workspace.numel() < nb.value):
+        raise ValueError("resume: the solution's workspace does not fit these options")
     if workspace is None or workspace.numel() < nb.value:
         workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
-    x = torch.empty(dlp.n, **f64)
-    y = torch.empty(dlp.m, **f64)
-    z = torch.empty(dlp.n, **f64)
-    r_p = torch.empty(dlp.m, **f64)
-    r_d = torch.empty(dlp.n, **f64)
-    d_row = torch.empty(dlp.m, **f64)
-    d_col = torch.empty(dlp.n, **f64)
+    if resume is not None:
+        x, y, z, r_p, r_d, d_row, d_col = (resume.x, resume.y, resume.z, resume.r_p, resume.r_d, resume.d_row,
+                                           resume.d_col)
+    else:
+        x = torch.empty(dlp.n, **f64)
+        y = torch.empty(dlp.m, **f64)
+        z = torch.empty(dlp.n, **f64)
+        r_p = torch.empty(dlp.m, **f64)
+        r_d = torch.empty(dlp.n, **f64)
+        d_row = torch.empty(dlp.m, **f64)
+        d_col = torch.empty(dlp.n, **f64)
     info = _lib.InfoStruct()
     stream = torch.cuda.current_stream(d).cuda_stream
     rc = lib.mipdhg_solve(C.byref(lps), C.byref(o), float(eps), workspace.data_ptr(), workspace.numel(),
@@ -154,7 +168,7 @@ def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters
                           d_row.data_ptr(), d_col.data_ptr(), C.byref(info))
     _lib.check(rc)
     return Solution(rc, lib.mipdhg_status_string(rc).decode(), x, y, z, r_p, r_d, d_row, d_col,
-                    info.as_dict(), trace)
+                    info.as_dict(), trace, workspace)
 
 
 class DeviceBatch:

@@ -1,0 +1,103 @@
+"""Checkpoint/resume of the single-LP solve: a solve stopped at an evaluation
+and resumed from its workspace gives bitwise the iterates, iteration count and
+restart count of one uninterrupted solve, and a workspace that holds another
+problem's (or another layout's) state is refused."""
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_03150_amd")
+torch = pytest.importorskip("torch")
+
+
+def _same(a, b):
+    assert a.status == b.status
+    assert a.info["iters"] == b.info["iters"] and a.info["restarts"] == b.info["restarts"]
+    for k in ("x", "y", "z", "r_p", "r_d"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    assert a.info["omega"] == b.info["omega"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("spmv_kind", [0, 2])
+def test_resume_at_iteration_limit_matches_one_solve(prec, spmv_kind):
+    dlp = P.DeviceLP.from_lp(lpgen.cfg2_sub(6, scale=100))
+    kw = dict(spmv_kind=spmv_kind)
+    ref = P.solve(dlp, 1e-12, prec, max_iter=320, **kw)
+    assert ref.status == 1 and ref.info["restarts"] > 0
+    a = P.solve(dlp, 1e-12, prec, max_iter=128, **kw)
+    assert a.status == 1 and a.info["iters"] == 128
+    b = P.solve(dlp, 1e-12, prec, max_iter=192, resume=a, **kw)
+    assert b.info["iters"] == 192
+    c = P.solve(dlp, 1e-12, prec, max_iter=320, resume=b, **kw)
+    _same(ref, c)
+
+
+def test_resume_direct_launches_and_graph_agree():
+    dlp = P.DeviceLP.from_lp(lpgen.cfg1(2))
+    ref = P.solve(dlp, 1e-12, "fp64", max_iter=256, use_graph=1)
+    a = P.solve(dlp, 1e-12, "fp64", max_iter=64, use_graph=0)
+    b = P.solve(dlp, 1e-12, "fp64", max_iter=256, use_graph=1, resume=a)
+    _same(ref, b)
+
+
+def test_resume_after_optimal_with_tighter_tolerance():
+    dlp = P.DeviceLP.from_lp(lpgen.cfg2_sub(6, scale=100))
+    ref = P.solve(dlp, 1e-7, "fp64")
+    loose = P.solve(dlp, 1e-3, "fp64")
+    assert loose.status == 0 and loose.info["iters"] < ref.info["iters"]
+    tight = P.solve(dlp, 1e-7, "fp64", resume=loose)
+    _same(ref, tight)
+
+
+def test_resume_of_an_optimal_state_stops_at_once():
+    dlp = P.DeviceLP.from_lp(lpgen.cfg1(1))
+    a = P.solve(dlp, 1e-6, "fp64")
+    assert a.status == 0
+    x = a.x.clone()
+    it = a.info["iters"]
+    b = P.solve(dlp, 1e-6, "fp64", max_iter=10 * it, resume=a)
+    assert b.status == 0 and b.info["iters"] == it and torch.equal(b.x, x)
+
+
+def test_resume_refuses_another_state():
+    lp = lpgen.cfg1(1)
+    dlp = P.DeviceLP.from_lp(lp)
+    a = P.solve(dlp, 1e-12, "fp64", max_iter=64)
+    # other options that shape the state or its layout
+    for kw in (dict(precision="fp32"), dict(eval_every=32), dict(tile_nnz=512), dict(gather_order=1)):
+        prec = kw.pop("precision", "fp64")
+        with pytest.raises((P.MipdhgError, ValueError)):
+            P.solve(dlp, 1e-12, prec, max_iter=128, resume=a, **kw)
+    # the same sizes but another right-hand side
+    other = P.DeviceLP.from_lp(lp)
+    other.b.mul_(1.5)
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve(other, 1e-12, "fp64", max_iter=128, resume=a)
+    assert e.value.code == -1
+    # a refused resume leaves the state usable
+    ref = P.solve(dlp, 1e-12, "fp64", max_iter=128)
+    b = P.solve(dlp, 1e-12, "fp64", max_iter=128, resume=a)
+    _same(ref, b)
+    # back-to-back kernel timing moves the iterates: not resumable
+    t = P.solve(dlp, 1e-12, "fp64", max_iter=64, kernel_timing=2)
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve(dlp, 1e-12, "fp64", max_iter=128, resume=t)
+    assert e.value.code == -1
+    # a workspace never used by a solve
+    fresh = P.solve(dlp, 1e-12, "fp64", max_iter=64)
+    fresh.workspace.zero_()
+    with pytest.raises(P.MipdhgError):
+        P.solve(dlp, 1e-12, "fp64", max_iter=128, resume=fresh)
+    # no warm start with a resume
+    with pytest.raises(P.MipdhgError):
+        P.solve(dlp, 1e-12, "fp64", max_iter=128, resume=a, x_init=torch.zeros(lp.n))
+
+
+def test_resume_is_a_single_lp_option():
+    batch = P.DeviceBatch.from_lps([lpgen.tiny(6, 15, 3, 0)])
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp32", resume=1)
+    assert e.value.code == -6
