@@ -197,7 +197,7 @@ __device__ __forceinline__ int xcd_virtual_block(int b, int G) {
 __device__ __forceinline__ int own_tile() { return xcd_virtual_block(blockIdx.x, gridDim.x); }
 
 // The tiles of a persistent launch: the descriptors form 8 contiguous runs,
-// one per XCD (workgroup b runs on XCD b mod 8), and the workgroups of an XCD
+// one per XCD (workgroups b and b + 8 run on the same XCD), and the workgroups of an XCD
 // stride over its run.  Covers [0, ntiles) exactly once for any grid that
 // has at least min(8, ntiles) workgroups.
 struct TileRange {

@@ -682,7 +682,7 @@ RowPlan device_plan(const HostPlan& hp, const int32_t* rowptr, const int32_t* lo
 
 // Greedy cut of the rows into tiles of at most tile_nnz nonzeros and tile_rows
 // rows (a row longer than tile_nnz is a tile by itself), then ordered for the
-// hardware: workgroup b runs on XCD b % 8, and xcd_virtual_block() gives each
+// hardware: workgroups b and b + 8 run on the same XCD, and xcd_virtual_block() gives each
 // XCD a contiguous range of descriptor slots.  "Heavy" tiles (holding a row
 // of more than kHeavyRow nonzeros, whose gathers reach far across the vector)
 // are dealt round-robin over the XCDs, first in each XCD's range; the light
