@@ -14,6 +14,18 @@ Draw order per instance (one PCG64 stream per seed key):
   4. a permutation whose first floor(n/2) entries form supp(x*),
   5. x*_S ~ U(0,1), 6. y* ~ N(0,1), 7. z* ~ U(0,1) off the support,
   8. b = A x*, c = A^T y* + z* in float64.
+
+General-form instances (``general_from_matrix``) add variable bounds
+``lo <= x <= hi`` (either side may be infinite) and a sense per row
+(0: ``(Ax)_i = b_i``, 1: ``>=``, 2: ``<=``), with a planted optimum that
+satisfies the KKT conditions of that form.  Draw order after the matrix:
+  1. a kind per column (0 [0,inf), 1 box [l, l+w], 2 free, 3 (-inf, u],
+     4 [l, inf)), 2. its bounds, 3. its status (at lower, at upper or
+  between) and x*_j, 4. lambda*_j with the sign its status allows, 5. a
+  sense per row, 6. which inequality rows are active, 7. y* (zero on
+  inactive rows, signed on active ones), 8. the slack of inactive rows;
+  then b = A x* -/+ slack, c = A^T y* + lambda*.  p* = c^T x* equals the dual
+  value b^T y* + sum_j (l_j lambda_j^+ - u_j lambda_j^-).
 """
 from __future__ import annotations
 
@@ -27,8 +39,11 @@ __all__ = [
     "LP", "rng_for", "planted_from_columns", "uniform_columns", "cfg1", "cfg2",
     "cfg2_sub", "cfg3", "cfg4_sizes", "cfg4_instance", "cfg4_batch",
     "cfg5_instance", "cfg5_batch", "cfg5_fd_instance", "tiny", "simplex_lp",
-    "powerlaw_counts", "Batch", "stack_batch",
+    "powerlaw_counts", "Batch", "stack_batch", "general_from_matrix", "general_tiny",
+    "general_cfg1", "general_cfg2", "general_cfg2_sub", "SENSE_EQ", "SENSE_GE", "SENSE_LE",
 ]
+
+SENSE_EQ, SENSE_GE, SENSE_LE = 0, 1, 2
 
 POWER_ALPHA = 2.1423  # p(k) ~ k^-alpha on [2, 2000] has mean 8.0
 
@@ -45,6 +60,13 @@ class LP:
     z_star: np.ndarray
     name: str = ""
     meta: dict = field(default_factory=dict)
+    lo: np.ndarray | None = None     # general form: lower bounds of x
+    hi: np.ndarray | None = None     # upper bounds of x
+    sense: np.ndarray | None = None  # int8 per row: 0 =, 1 >=, 2 <=
+
+    @property
+    def general(self) -> bool:
+        return self.lo is not None
 
     @property
     def m(self) -> int:
@@ -330,3 +352,105 @@ def stack_batch(lps: list[LP]) -> Batch:
     b = np.concatenate([lp.b for lp in lps])
     c = np.concatenate([lp.c for lp in lps])
     return Batch(A, AT, b, c, row_off, col_off, nnz_off, list(lps))
+
+
+def general_from_matrix(A: sp.csr_matrix, AT: sp.csr_matrix, rng: np.random.Generator,
+                        name: str = "", meta: dict | None = None,
+                        kind_p=(0.3, 0.25, 0.1, 0.15, 0.2), sense_p=(0.5, 0.25, 0.25)) -> LP:
+    """A general-form LP on the given matrix with a planted KKT point (draw
+    order in the module docstring).  z_star holds the planted reduced costs
+    lambda* (signed)."""
+    m, n = A.shape
+    kind = rng.choice(5, size=n, p=list(kind_p))
+    lo = np.zeros(n)
+    hi = np.full(n, np.inf)
+    box = kind == 1
+    lo[box] = rng.uniform(-1.0, 0.0, size=int(box.sum()))
+    hi[box] = lo[box] + rng.uniform(0.5, 2.0, size=int(box.sum()))
+    free = kind == 2
+    lo[free], hi[free] = -np.inf, np.inf
+    up = kind == 3
+    lo[up] = -np.inf
+    hi[up] = rng.uniform(-1.0, 1.0, size=int(up.sum()))
+    low = kind == 4
+    lo[low] = rng.uniform(-1.0, 1.0, size=int(low.sum()))
+    # status: 0 at lower, 1 at upper, 2 between
+    u = rng.uniform(0.0, 1.0, size=n)
+    status = np.where(kind == 0, np.where(u < 0.5, 0, 2),
+                      np.where(kind == 1, np.where(u < 1 / 3, 0, np.where(u < 2 / 3, 1, 2)),
+                               np.where(kind == 2, 2,
+                                        np.where(kind == 3, np.where(u < 0.5, 1, 2),
+                                                 np.where(u < 0.5, 0, 2)))))
+    t = rng.uniform(0.0, 1.0, size=n)
+    g = rng.standard_normal(n)
+    x = np.empty(n)
+    x[status == 0] = lo[status == 0]
+    x[status == 1] = hi[status == 1]
+    mid = status == 2
+    fin = np.isfinite(lo) & np.isfinite(hi)
+    x[mid & fin] = lo[mid & fin] + t[mid & fin] * (hi[mid & fin] - lo[mid & fin])
+    only_lo = mid & np.isfinite(lo) & ~np.isfinite(hi)
+    x[only_lo] = lo[only_lo] + t[only_lo]
+    only_hi = mid & ~np.isfinite(lo) & np.isfinite(hi)
+    x[only_hi] = hi[only_hi] - t[only_hi]
+    fr = mid & ~np.isfinite(lo) & ~np.isfinite(hi)
+    x[fr] = g[fr]
+    lam_mag = rng.uniform(0.0, 1.0, size=n)
+    lam = np.where(status == 0, lam_mag, np.where(status == 1, -lam_mag, 0.0))
+    sense = rng.choice(3, size=m, p=list(sense_p)).astype(np.int8)
+    active = rng.uniform(0.0, 1.0, size=m) < 0.6
+    ymag = rng.uniform(0.0, 1.0, size=m)
+    yn = rng.standard_normal(m)
+    y = np.where(sense == SENSE_EQ, yn,
+                 np.where(active, np.where(sense == SENSE_GE, ymag, -ymag), 0.0))
+    slack = rng.uniform(0.1, 1.0, size=m)
+    b = A @ x
+    ina = (sense != SENSE_EQ) & ~active
+    b[ina & (sense == SENSE_GE)] -= slack[ina & (sense == SENSE_GE)]
+    b[ina & (sense == SENSE_LE)] += slack[ina & (sense == SENSE_LE)]
+    c = AT @ y + lam
+    return LP(A, AT, b, c, x, y, lam, name=name, meta=dict(meta or {}), lo=lo, hi=hi, sense=sense)
+
+
+def _matrix_uniform(m: int, n: int, per_col: int, rng: np.random.Generator):
+    counts = np.full(n, per_col, dtype=np.int64)
+    rows = _distinct_rows(counts, m, rng)
+    vals = rng.standard_normal(rows.size)
+    return _csr_pair_from_columns(m, n, counts, rows, vals)
+
+
+def general_tiny(m: int, n: int, per_col: int, seed: int) -> LP:
+    """Small general-form LPs for exact checks."""
+    rng = rng_for(11, m, n, per_col, seed)
+    A, AT = _matrix_uniform(m, n, min(per_col, m), rng)
+    return general_from_matrix(A, AT, rng, name=f"gtiny_{m}x{n}_s{seed}")
+
+
+def general_cfg1(seed: int = 0) -> LP:
+    """The small workload's matrix (200 x 500, 5 per column) in general form."""
+    rng = rng_for(12, seed)
+    A, AT = _matrix_uniform(200, 500, 5, rng)
+    return general_from_matrix(A, AT, rng, name=f"gcfg1_s{seed}", meta={"cfg": 1, "seed": seed})
+
+
+def _cfg2_matrix(m: int, n: int, rng: np.random.Generator, kmax: int):
+    counts = powerlaw_counts(n, rng, kmax=min(kmax, m))
+    rows = _distinct_rows(counts, m, rng)
+    vals = rng.standard_normal(rows.size)
+    row_factor = rng.uniform(0.1, 10.0, size=m)
+    return _csr_pair_from_columns(m, n, counts, rows, vals * row_factor[rows])
+
+
+def general_cfg2(seed: int = 0) -> LP:
+    """The power-law workload's shape (100,000 x 400,000, ~3.2M nonzeros) in
+    general form."""
+    rng = rng_for(13, seed)
+    A, AT = _cfg2_matrix(100_000, 400_000, rng, 2000)
+    return general_from_matrix(A, AT, rng, name=f"gcfg2_s{seed}", meta={"cfg": 2, "seed": seed})
+
+
+def general_cfg2_sub(seed: int = 0, scale: int = 100) -> LP:
+    rng = rng_for(13, 1000 + scale, seed)
+    A, AT = _cfg2_matrix(100_000 // scale, 400_000 // scale, rng, 2000)
+    return general_from_matrix(A, AT, rng, name=f"gcfg2sub{scale}_s{seed}",
+                               meta={"cfg": 2, "seed": seed, "scale": scale})

@@ -30,6 +30,21 @@ bound, the KKT gap identity, hand-built termination cases, scaling
 invariants, sigma_hat against a dense SVD, and finite differences plus a
 tangent/adjoint dot-product test for the unrolled map.
 
+General form (bounds l <= x <= u and rows of sense =, >= or <=): the paper
+notes that practical models carry inequalities and variable bounds, that they
+map onto the standard form, and that solvers usually treat them implicitly
+(Section 2).  `solve(..., lo=, hi=, sense=)` treats them implicitly: the
+primal step projects onto the box, the dual step projects y onto the sign
+cone of each row (free, y >= 0 for >= rows, y <= 0 for <= rows), and the
+evaluation uses the reduced costs lambda = c - A^T y projected onto the cone
+the bounds allow, the primal residual as the violation of each row's sense,
+and the dual objective b^T y + sum_j (l_j lambda_j^+ - u_j lambda_j^-).
+With l = 0, u = +inf and every row an equality all of these reduce to the
+standard-form quantities above.  Pins: scipy's HiGHS on general LPs, a
+planted general optimum (closed form and fixed point), the equivalent
+standard-form LP built by slack and split variables, and the special case
+above reproducing the standard-form run bit for bit.
+
 parity unpinned: the restart and primal-weight heuristics (which iterations
 restart, the omega sequence, iteration counts to a tolerance) follow a reading
 with no external reference; only GPU-versus-oracle agreement checks them.
@@ -43,6 +58,7 @@ import numpy as np
 import scipy.sparse as sp
 
 STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL"}
+SENSE_EQ, SENSE_GE, SENSE_LE = 0, 1, 2  # (A x)_i = b_i, >= b_i, <= b_i
 
 
 @dataclass
@@ -100,6 +116,18 @@ class Result:
 # ---------------------------------------------------------------------------
 # input validation (the standard form of Section 2)
 # ---------------------------------------------------------------------------
+
+def validate_general(n: int, m: int, lo, hi, sense) -> None:
+    """Bounds: no NaN, l < +inf, u > -inf, l <= u; senses in {0, 1, 2}."""
+    if lo.shape != (n,) or hi.shape != (n,) or sense.shape != (m,):
+        raise ValueError("shape mismatch")
+    if np.any(np.isnan(lo)) or np.any(np.isnan(hi)):
+        raise ValueError("NaN bound")
+    if np.any(lo == np.inf) or np.any(hi == -np.inf) or np.any(lo > hi):
+        raise ValueError("empty bound interval")
+    if np.any((sense < 0) | (sense > 2)):
+        raise ValueError("row sense must be 0, 1 or 2")
+
 
 def validate(A: sp.csr_matrix, AT: sp.csr_matrix, b: np.ndarray, c: np.ndarray) -> None:
     """Shapes, finiteness, and that AT is exactly the transpose of A."""
@@ -212,14 +240,25 @@ def initial_weight(bt: np.ndarray, ct: np.ndarray) -> float:
 # the PDHG operator on the scaled problem
 # ---------------------------------------------------------------------------
 
-def pdhg_operator(At, AtT, bt, ct, tau, sig, x, y):
+def pdhg_operator(At, AtT, bt, ct, tau, sig, x, y, lo_t=None, hi_t=None, sense=None):
     """One PDHG step T(x, y) = (x_hat, y_hat) for the saddle problem
-    min_{x>=0} max_y c^T x - y^T (A x - b): a projected primal gradient step,
-    then a dual ascent step at the extrapolated point 2 x_hat - x."""
+    min_{x in X} max_{y in Y} c^T x - y^T (A x - b): a projected primal
+    gradient step, then a dual ascent step at the extrapolated point
+    2 x_hat - x.  Standard form: X = {x >= 0}, Y = R^m.  General form:
+    X = [lo_t, hi_t] (scaled bounds), Y_i = R, [0, inf) or (-inf, 0] for rows
+    of sense =, >= or <= (the Lagrangian term y_i (b_i - (A x)_i) is bounded
+    above over Y_i exactly when row i holds)."""
     g = ct - AtT @ y
-    x_hat = np.maximum(x - tau * g, 0.0)
+    if lo_t is None:
+        x_hat = np.maximum(x - tau * g, 0.0)
+    else:
+        x_hat = np.minimum(np.maximum(x - tau * g, lo_t), hi_t)
     x_bar = 2.0 * x_hat - x
     y_hat = y + sig * (bt - At @ x_bar)
+    if sense is not None:
+        ge, le = sense == SENSE_GE, sense == SENSE_LE
+        y_hat[ge] = np.maximum(y_hat[ge], 0.0)
+        y_hat[le] = np.minimum(y_hat[le], 0.0)
     return x_hat, y_hat
 
 
@@ -227,19 +266,39 @@ def pdhg_operator(At, AtT, bt, ct, tau, sig, x, y):
 # evaluation on the original model (Section 2 tests; Section 4.3 metric)
 # ---------------------------------------------------------------------------
 
-def evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat) -> Measures:
+def reduced_costs(g: np.ndarray, lo, hi) -> np.ndarray:
+    """lambda = g projected onto the cone the bounds allow: R where both bounds
+    are finite, [0, inf) with only a lower bound, (-inf, 0] with only an upper
+    bound, {0} for a free variable (standard form: z = max(g, 0))."""
+    if lo is None:
+        return np.maximum(g, 0.0)
+    lf, uf = np.isfinite(lo), np.isfinite(hi)
+    return np.where(lf & uf, g, np.where(lf, np.maximum(g, 0.0), np.where(uf, np.minimum(g, 0.0), 0.0)))
+
+
+def evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat, lo=None, hi=None, sense=None) -> Measures:
     x = d_col * x_hat
     y = d_row * y_hat
     Ax = A @ x
     ATy = AT @ y
-    z = np.maximum(c - ATy, 0.0)
+    z = reduced_costs(c - ATy, lo, hi)
     r_p = b - Ax
+    if sense is not None:  # a row's residual is its violation
+        r_p = np.where(sense == SENSE_GE, np.maximum(r_p, 0.0),
+                       np.where(sense == SENSE_LE, np.minimum(r_p, 0.0), r_p))
     r_d = c - ATy - z
     pobj = float(c @ x)
     dobj = float(b @ y)
+    if lo is None:
+        xz = float(x @ z)
+    else:  # bound terms of the dual objective; complementarity with the bounds
+        lf, uf = np.isfinite(lo), np.isfinite(hi)
+        lo0, hi0 = np.where(lf, lo, 0.0), np.where(uf, hi, 0.0)  # lambda is 0 where a bound is infinite
+        zp, zm = np.maximum(z, 0.0), np.maximum(-z, 0.0)
+        dobj += float(np.sum(lo0 * zp) - np.sum(hi0 * zm))
+        xz = float(np.sum(np.where(lf, zp * (x - lo0), 0.0)) + np.sum(np.where(uf, zm * (hi0 - x), 0.0)))
     rp_inf = float(np.abs(r_p).max()) if r_p.size else 0.0
     rd_inf = float(np.abs(r_d).max()) if r_d.size else 0.0
-    xz = float(x @ z)
     return Measures(x, y, z, r_p, r_d, float(np.linalg.norm(r_p)), float(np.linalg.norm(r_d)),
                     pobj, dobj, abs(pobj - dobj), rp_inf, rd_inf, xz,
                     max(rp_inf, rd_inf, xz / (1.0 + abs(pobj))))
@@ -267,7 +326,9 @@ def restart_due(R: float, R0: float, R_prev: float, k: int, t: int, opts: Oracle
 # ---------------------------------------------------------------------------
 
 def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
-          x_init=None, y_init=None, trace_iters: int = 0) -> Result:
+          x_init=None, y_init=None, trace_iters: int = 0, lo=None, hi=None, sense=None) -> Result:
+    """Standard form, or the general form when any of lo, hi, sense is given
+    (missing ones default to 0, +inf and all equalities)."""
     opts = opts or OracleOptions()
     A = sp.csr_matrix(A)
     AT = sp.csr_matrix(AT)
@@ -275,6 +336,12 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     c = np.asarray(c, dtype=np.float64)
     validate(A, AT, b, c)
     m, n = A.shape
+    general = lo is not None or hi is not None or sense is not None
+    if general:
+        lo = np.zeros(n) if lo is None else np.asarray(lo, dtype=np.float64)
+        hi = np.full(n, np.inf) if hi is None else np.asarray(hi, dtype=np.float64)
+        sense = np.zeros(m, dtype=np.int8) if sense is None else np.asarray(sense, dtype=np.int8)
+        validate_general(n, m, lo, hi, sense)
     b_norm = float(np.linalg.norm(b))
     c_norm = float(np.linalg.norm(c))
 
@@ -282,6 +349,8 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     AtT = sp.csr_matrix(At.T)
     bt = d_row * b
     ct = d_col * c
+    lo_t = lo / d_col if general else None
+    hi_t = hi / d_col if general else None
     sigma_hat, hist = power_sigma(At, opts.power_iters)
     eta = step_size(sigma_hat, hist, opts)
     omega0 = initial_weight(bt, ct)
@@ -303,7 +372,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
 
     while True:
         t += 1
-        x_hat, y_hat = pdhg_operator(At, AtT, bt, ct, tau, sig, x, y)
+        x_hat, y_hat = pdhg_operator(At, AtT, bt, ct, tau, sig, x, y, lo_t, hi_t, sense)
         R = math.sqrt(omega * float(np.sum((x - x_hat) ** 2))
                       + float(np.sum((y - y_hat) ** 2)) / omega)
         if k == 0:
@@ -314,7 +383,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
         k += 1
         restarted = False
         if t % E == 0 or t == opts.max_iter:
-            meas = evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat)
+            meas = evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat, lo, hi, sense)
             status = None
             if not all(math.isfinite(v) for v in (meas.rp_norm, meas.rd_norm, meas.pobj, meas.dobj)):
                 status = 3
