@@ -71,7 +71,15 @@ extern "C" {
                                 FP32 at 4 more bytes per vector entry); single-LP
                                 solve only                                           */
 
-/* One LP in the standard form of Section 2.  Device pointers. */
+/* One LP in the standard form of Section 2, or in the general form that
+ * section mentions (bounds on x and inequality rows, handled implicitly: the
+ * primal step projects onto the bounds, the dual step keeps y_i >= 0 on >=
+ * rows and y_i <= 0 on <= rows, and the evaluation measures each row's
+ * violation, the reduced costs the bounds allow and the dual objective with
+ * the bound terms).  Device pointers. */
+#define MIPDHG_SENSE_EQ 0   /* (A x)_i = b_i  */
+#define MIPDHG_SENSE_GE 1   /* (A x)_i >= b_i */
+#define MIPDHG_SENSE_LE 2   /* (A x)_i <= b_i */
 typedef struct mipdhg_lp {
     int32_t m, n;            /* rows and columns of A                      */
     int64_t nnz;             /* nonzeros of A (= of A^T)                   */
@@ -83,6 +91,14 @@ typedef struct mipdhg_lp {
     const double *at_val;    /* [nnz]                                      */
     const double *b;         /* [m] right-hand side                        */
     const double *c;         /* [n] objective                              */
+    /* General form: all three NULL is the standard form.  lo NULL means
+     * x >= 0, hi NULL no upper bounds, sense NULL all equalities.  Bounds
+     * may be infinite (lo = -INFINITY, hi = +INFINITY) but not NaN, with
+     * lo < +inf, hi > -inf, lo <= hi; checked with `validate`
+     * (INVALID_ARG).  Single-LP solve (tile kernels, spmv_kind 0 or 2) only. */
+    const double *lo;        /* [n] lower bounds of x                      */
+    const double *hi;        /* [n] upper bounds of x                      */
+    const int8_t *sense;     /* [m] MIPDHG_SENSE_* of each row             */
 } mipdhg_lp;
 
 /* Options.  Fill with mipdhg_default_options() and change what you need. */
@@ -160,11 +176,13 @@ typedef struct mipdhg_info {
     int32_t restarts;
     int64_t iters;          /* iteration t at which the returned point was evaluated */
     double rp_norm, rd_norm;/* ||r_P||_2, ||r_D||_2 on the original model          */
-    double gap;             /* |c^T x - b^T y|                                      */
-    double pobj, dobj;      /* c^T x, b^T y                                         */
+    double gap;             /* |c^T x - dobj|                                       */
+    double pobj, dobj;      /* c^T x; b^T y (general form: plus the bound terms
+                               sum_j lo_j z_j^+ - hi_j z_j^- over finite bounds)     */
     double rel_rp, rel_rd, rel_gap; /* the three ratios of Section 2 (<= eps: pass) */
     double rp_inf, rd_inf;  /* infinity norms                                       */
-    double xz;              /* x^T z                                                */
+    double xz;              /* x^T z (general form: sum_j z_j^+ (x_j - lo_j) +
+                               z_j^- (hi_j - x_j) over finite bounds)                */
     double max_violation;   /* max(rp_inf, rd_inf, xz / (1 + |c^T x|)), Section 4.3 */
     double b_norm, c_norm;  /* ||b||_2, ||c||_2                                     */
     double sigma_hat;       /* power-iteration estimate of ||D_r A D_c||_2          */
@@ -188,6 +206,11 @@ int mipdhg_workspace_size(const mipdhg_lp *lp, const mipdhg_options *opt, size_t
 
 /* Solve one LP to eps_rel (Section 2 tests).  Outputs (device float64, all
  * required): x[n], y[m], z[n], r_p[m], r_d[n] in the original space.
+ * General form: z = c - A^T y projected onto the cone the bounds allow
+ * (free where both bounds are finite, >= 0 with only lo, <= 0 with only hi,
+ * 0 if x_j is free), r_d = c - A^T y - z, and r_p_i is b_i - (A x)_i for
+ * equality rows and its violating part (max(., 0) on >= rows, min(., 0) on
+ * <= rows) otherwise.
  * d_row[m], d_col[n] (nullable): the scaling, D_r A D_c being the scaled
  * matrix the iterations run on; x~ = x / d_col, y~ = y / d_row, z~ = z * d_col
  * is the solution of the scaled LP that Algorithm 1 (Section 3.1) consumes.

@@ -28,7 +28,7 @@ class LPStruct(C.Structure):
     _fields_ = [("m", _i32), ("n", _i32), ("nnz", _i64),
                 ("a_rowptr", _p), ("a_col", _p), ("a_val", _p),
                 ("at_rowptr", _p), ("at_col", _p), ("at_val", _p),
-                ("b", _p), ("c", _p)]
+                ("b", _p), ("c", _p), ("lo", _p), ("hi", _p), ("sense", _p)]
 
 
 class OptionsStruct(C.Structure):

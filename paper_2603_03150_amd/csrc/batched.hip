@@ -576,6 +576,8 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
     if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
     if (!workspace || !x || !y || !z || !r_p || !r_d)
         return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
+    if (is_general(bt->whole))
+        return set_error("the general form (bounds, inequality rows) is a single-LP option"), MIPDHG_ERR_UNSUPPORTED;
     if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing || opt->resume)
         return set_error("tracing, warm starts, kernel timing and resume are single-LP options"),
                MIPDHG_ERR_UNSUPPORTED;

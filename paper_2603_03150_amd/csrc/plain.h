@@ -45,6 +45,9 @@ int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat
 int32_t tile_nnz_of(const mipdhg_options& o);
 int32_t tile_rows_of(const mipdhg_options& o);
 int32_t short_row_of(const mipdhg_options& o);
+inline bool has_bounds(const mipdhg_lp& lp) { return lp.lo || lp.hi; }  // general form, columns
+inline bool has_sense(const mipdhg_lp& lp) { return lp.sense != nullptr; } // general form, rows
+inline bool is_general(const mipdhg_lp& lp) { return has_bounds(lp) || has_sense(lp); }
 int iter_kind(const mipdhg_options& o, int64_t m, int64_t n);         // effective spmv_kind
 bool sorted_layout(const mipdhg_options& o, int64_t m, int64_t n);  // sorted tile layout of the iteration copies
 TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,

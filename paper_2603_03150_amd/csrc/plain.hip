@@ -277,6 +277,9 @@ struct IterArgs {
     const double* dscale;  // D_c or D_r
     double* partials;  // [G][3]: ||o - h||^2 at the first iteration, same at the evaluation, ||h - anchor||^2
     const Ctrl* ctrl;
+    const T* lo;          // general form, primal: scaled bounds l / D_c, u / D_c
+    const T* hi;
+    const int8_t* sense;  // general form, dual: row senses
     double rho;
     int32_t halpern;
     int32_t it;
@@ -289,9 +292,14 @@ struct IterArgs {
 template <typename T>
 struct IterPre {
     T o, an, rhs;
+    T lo, hi;  // general form, primal
+    int sense; // general form, dual
 };
 
-template <typename T, typename V, bool PRIMAL>
+// GEN: the general form (Section 2 mentions bounds and inequality rows):
+// the primal step projects onto [l, u] instead of x >= 0, the dual step
+// keeps y_i >= 0 on >= rows and y_i <= 0 on <= rows.
+template <typename T, typename V, bool PRIMAL, bool GEN>
 struct IterEpi {
     const IterArgs<T, V>& a;
     double w, omw, rho, opr, st;
@@ -318,6 +326,11 @@ struct IterEpi {
         p.o = ld_at(a.state + r0, i);
         p.an = ld_at(a.anchor + r0, i);
         p.rhs = ld_at(a.rhs + r0, i);
+        if (GEN && PRIMAL) {
+            p.lo = ld_at(a.lo + r0, i);
+            p.hi = ld_at(a.hi + r0, i);
+        }
+        if (GEN && !PRIMAL) p.sense = ld_at(a.sense + r0, i);
         return p;
     }
     // The arithmetic is float64 whatever the storage type T: the stored
@@ -329,10 +342,19 @@ struct IterEpi {
         if (PRIMAL) {
             const double g = (double)p.rhs - (double)s;
             h = o - st * g;
-            h = h < 0.0 ? 0.0 : h;  // projection onto x >= 0 (NaN propagates)
+            if (GEN) {  // projection onto [l, u] (NaN propagates)
+                const double l = (double)p.lo, u = (double)p.hi;
+                h = h < l ? l : (h > u ? u : h);
+            } else {
+                h = h < 0.0 ? 0.0 : h;  // projection onto x >= 0 (NaN propagates)
+            }
             st_at(a.bar + r0, i, (T)(2.0 * h - o));
         } else {
             h = o + st * ((double)p.rhs - (double)s);
+            if (GEN) {  // the sign each row's sense allows
+                if (p.sense == MIPDHG_SENSE_GE) h = h < 0.0 ? 0.0 : h;
+                else if (p.sense == MIPDHG_SENSE_LE) h = h > 0.0 ? 0.0 : h;
+            }
         }
         if (flags & F_HAT) st_at(a.hat + r0, i, (T)h);
         const double an = (double)p.an;
@@ -356,9 +378,9 @@ struct IterEpi {
     }
 };
 
-template <typename T, typename V, bool PRIMAL>
-__device__ __forceinline__ IterEpi<T, V, PRIMAL> make_epi(const IterArgs<T, V>& a, double* q) {
-    IterEpi<T, V, PRIMAL> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
+template <typename T, typename V, bool PRIMAL, bool GEN = false>
+__device__ __forceinline__ IterEpi<T, V, PRIMAL, GEN> make_epi(const IterArgs<T, V>& a, double* q) {
+    IterEpi<T, V, PRIMAL, GEN> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
     return e;
 }
 
@@ -387,13 +409,13 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 
 // LDS-tiled traversal (TilePlan).  The control word is loaded up front and
 // only checked once the products are in LDS.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto epi = make_epi<T, V, PRIMAL, GEN>(a, q);
     // streamed arrays: tile base + 32-bit offset; the gather: a plain 64-bit
     // address, measured 12-18 % faster than the base + offset form on
     // 4096- and 8192-nonzero tiles
@@ -408,13 +430,13 @@ __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePla
 // The same step as a persistent launch: about one workgroup per resident slot,
 // each walking its XCD's run of tiles, so that no time goes to dispatching a
 // workgroup per tile.  The norm partials cover all tiles of a workgroup.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TilePlan tp) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    auto epi = make_epi<T, V, PRIMAL>(a, q);
+    auto epi = make_epi<T, V, PRIMAL, GEN>(a, q);
     auto prod = [&](int b, int j) {
         return ld_val_at(a.val + b, j) * (Acc)a.gather[(int64_t)ld_at_nt(a.col + b, j)];
     };
@@ -433,7 +455,11 @@ __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TileP
 // ---------------------------------------------------------------------------
 // ROWS:  over A's rows, r_p = b - A x; partials: sum r_p^2, sum b.y, -, max |r_p|
 // !ROWS: over A^T's rows, z = max(c - A^T y, 0), r_d = c - A^T y - z;
-//        partials: sum r_d^2, sum c.x, sum x.z, max |r_d|
+//        partials: sum r_d^2, sum c.x, sum x.z, sum of bound terms, max |r_d|
+// GEN (general form): a row's r_p is the violating part of b - A x for its
+// sense; z is c - A^T y projected onto the cone the bounds allow, the
+// complementarity term is z^+ (x - l) + z^- (u - x) and the dual objective
+// gains l z^+ - u z^- (finite bounds only; NULL lo means 0, NULL hi +inf).
 struct EvalArgs {
     RowPlan p;
     const int32_t* col;
@@ -443,16 +469,19 @@ struct EvalArgs {
     const double* own;     // y (ROWS) or x
     double* out1;          // r_p (ROWS) or z
     double* out2;          // r_d (!ROWS)
-    double* partials;      // [G][4]
+    double* partials;      // [G][4] (ROWS) or [G][5]
     const Ctrl* ctrl;
+    const int8_t* sense;   // GEN, ROWS
+    const double* lo;      // GEN, !ROWS (nullable)
+    const double* hi;      // GEN, !ROWS (nullable)
 };
 
-template <bool ROWS>
+template <bool ROWS, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     const bool active = a.ctrl->status == ST_RUNNING;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, tp);
-    double s[3] = {0.0, 0.0, 0.0};
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     double mx[1] = {0.0};
     auto prod = [&](int b, int j) {
         const int64_t k = (int64_t)b + j;
@@ -461,27 +490,48 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     auto epi = [&](int r, double t) {
         const double v = a.vec[r];
         if (ROWS) {
-            const double rp = v - t;
+            double rp = v - t;
+            if (GEN) {
+                const int sn = a.sense[r];
+                if (sn == MIPDHG_SENSE_GE) rp = rp > 0.0 ? rp : 0.0;
+                else if (sn == MIPDHG_SENSE_LE) rp = rp < 0.0 ? rp : 0.0;
+            }
             a.out1[r] = rp;
             s[0] += rp * rp;
             s[1] += v * a.own[r];
             mx[0] = fmax(mx[0], fabs(rp));
         } else {
             const double g = v - t;
-            const double z = g > 0.0 ? g : 0.0;
+            const double x = a.own[r];
+            double z;
+            if (GEN) {
+                const double l = a.lo ? a.lo[r] : 0.0, u = a.hi ? a.hi[r] : INFINITY;
+                const bool lf = isfinite(l), uf = isfinite(u);
+                z = (lf && uf) ? g : lf ? (g > 0.0 ? g : 0.0) : uf ? (g < 0.0 ? g : 0.0) : 0.0;
+                const double zp = z > 0.0 ? z : 0.0, zm = z < 0.0 ? -z : 0.0;
+                s[2] += (lf ? zp * (x - l) : 0.0) + (uf ? zm * (u - x) : 0.0);
+                s[3] += (lf ? l * zp : 0.0) - (uf ? u * zm : 0.0);
+            } else {
+                z = g > 0.0 ? g : 0.0;
+                s[2] += x * z;
+            }
             const double rd = g - z;
             a.out1[r] = z;
             a.out2[r] = rd;
-            const double x = a.own[r];
             s[0] += rd * rd;
             s[1] += v * x;
-            s[2] += x * z;
             mx[0] = fmax(mx[0], fabs(rd));
         }
     };
     auto le = lepi(epi);
     tiled_rows<false>(tp, own_tile(), L, prod, le, active);
-    if (active) block_reduce_store<3, 1>(s, mx, a.partials + 4 * blockIdx.x);
+    if (!active) return;
+    if (ROWS) {
+        double s3[3] = {s[0], s[1], s[2]};
+        block_reduce_store<3, 1>(s3, mx, a.partials + 4 * blockIdx.x);
+    } else {
+        block_reduce_store<4, 1>(s, mx, a.partials + 5 * blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +542,7 @@ struct DecideArgs {
     const double* pp;  // primal partials [gp][3]
     const double* pd;  // dual partials [gd][3]
     const double* per; // eval rows [ger][4]
-    const double* pec; // eval cols [gec][4]
+    const double* pec; // eval cols [gec][5]
     int32_t gp, gd, ger, gec;
     int32_t nit;
 };
@@ -538,10 +588,11 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     const double rp2 = fixed_sum(a.per, a.ger, 4, 0, sh);
     const double dobj = fixed_sum(a.per, a.ger, 4, 1, sh);
     const double rp_inf = fixed_max(a.per, a.ger, 4, 3, sh);
-    const double rd2 = fixed_sum(a.pec, a.gec, 4, 0, sh);
-    const double pobj = fixed_sum(a.pec, a.gec, 4, 1, sh);
-    const double xz = fixed_sum(a.pec, a.gec, 4, 2, sh);
-    const double rd_inf = fixed_max(a.pec, a.gec, 4, 3, sh);
+    const double rd2 = fixed_sum(a.pec, a.gec, 5, 0, sh);
+    const double pobj = fixed_sum(a.pec, a.gec, 5, 1, sh);
+    const double xz = fixed_sum(a.pec, a.gec, 5, 2, sh);
+    const double bterm = fixed_sum(a.pec, a.gec, 5, 3, sh);  // 0 in the standard form
+    const double rd_inf = fixed_max(a.pec, a.gec, 5, 4, sh);
     if (threadIdx.x != 0) return;
 
     const double om = c.omega;
@@ -552,19 +603,19 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     c.rp2 = rp2;
     c.rd2 = rd2;
     c.pobj = pobj;
-    c.dobj = dobj;
+    c.dobj = dobj + bterm;
     c.xz = xz;
     c.rp_inf = rp_inf;
     c.rd_inf = rd_inf;
     c.eval_t = t_end;
     c.last_R = R;
     c.last_nit = a.nit;
-    const double rp = sqrt(rp2), rd = sqrt(rd2), gap = fabs(pobj - dobj);
+    const double rp = sqrt(rp2), rd = sqrt(rd2), gap = fabs(pobj - c.dobj);
     int32_t status = ST_RUNNING;
-    if (!(isfinite(rp2) && isfinite(rd2) && isfinite(pobj) && isfinite(dobj))) {
+    if (!(isfinite(rp2) && isfinite(rd2) && isfinite(pobj) && isfinite(c.dobj))) {
         status = MIPDHG_NUMERICAL;
     } else if (rp <= c.eps * (1.0 + c.b_norm) && rd <= c.eps * (1.0 + c.c_norm) &&
-               gap <= c.eps * (1.0 + fabs(pobj) + fabs(dobj))) {
+               gap <= c.eps * (1.0 + fabs(pobj) + fabs(c.dobj))) {
         status = MIPDHG_OPTIMAL;
     } else if (t_end >= c.max_iter) {
         status = MIPDHG_ITER_LIMIT;
@@ -615,6 +666,15 @@ __global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t
         const T v = yh[i];
         y[i] = v;
         y0[i] = v;
+    }
+}
+
+// general form: scaled bounds l / D_c and u / D_c (NULL lo: 0, NULL hi: +inf)
+template <typename T>
+__global__ void k_scale_bounds(const double* lo, const double* hi, const double* d, int64_t n, T* lo_t, T* hi_t) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        lo_t[j] = (T)(lo ? lo[j] / d[j] : 0.0);
+        hi_t[j] = (T)(hi ? hi[j] / d[j] : (double)INFINITY);
     }
 }
 
@@ -778,7 +838,7 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
         const unsigned char* c = (const unsigned char*)p;
         for (size_t i = 0; i < nb; ++i) h = (h ^ c[i]) * 1099511628211ull;
     };
-    const int64_t sz[3] = {lp.m, lp.n, lp.nnz};
+    const int64_t sz[4] = {lp.m, lp.n, lp.nnz, (has_bounds(lp) ? 1 : 0) | (has_sense(lp) ? 2 : 0)};
     mix(sz, sizeof(sz));
     const int32_t iv[15] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
@@ -822,11 +882,12 @@ struct PlainWs {
     int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
     int32_t *col_a, *col_at;    // sorted layout: column copies in tile order
     uint16_t *slot_a, *slot_at; // sorted layout: row-major position in the tile
+    void *lo_t, *hi_t;          // general form: scaled bounds l / D_c, u / D_c
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
-                     int64_t tnz, int64_t trows, bool sorted) {
+                     int64_t tnz, int64_t trows, bool sorted, bool bounds) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -845,7 +906,7 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.pp = cv.take<double>((size_t)w.gcap * 3);
     w.pd = cv.take<double>((size_t)w.gcap * 3);
     w.per = cv.take<double>((size_t)w.gcap * 4);
-    w.pec = cv.take<double>((size_t)w.gcap * 4);
+    w.pec = cv.take<double>((size_t)w.gcap * 5);
     w.psetup = cv.take<double>((size_t)w.gcap * 4);
     w.a_vs = cv.take<char>(nnz * vs);
     w.at_vs = cv.take<char>(nnz * vs);
@@ -867,6 +928,8 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.col_at = sorted ? cv.take<int32_t>(nnz) : nullptr;
     w.slot_a = sorted ? cv.take<uint16_t>(nnz) : nullptr;
     w.slot_at = sorted ? cv.take<uint16_t>(nnz) : nullptr;
+    w.lo_t = bounds ? cv.take<char>(n * ts) : nullptr;
+    w.hi_t = bounds ? cv.take<char>(n * ts) : nullptr;
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -932,7 +995,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if (rc) return rc;
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
-                   tile_rows_of(*opt), sorted_layout(*opt, lp->m, lp->n)).bytes;
+                   tile_rows_of(*opt), sorted_layout(*opt, lp->m, lp->n), has_bounds(*lp)).bytes;
     return 0;
 }
 
@@ -966,22 +1029,24 @@ struct Solver {
         const size_t need = std::max(tile_lds_bytes(ta, 8), tile_lds_bytes(tat, 8));
         if (need > 65536) {
             const int lim = (int)need;
-            const void* ks[] = {
-                (const void*)k_iter_tiled<T, V, Acc, true, 8, false>, (const void*)k_iter_tiled<T, V, Acc, false, 8, false>,
-                (const void*)k_iter_tiled<T, V, Acc, true, 16, false>, (const void*)k_iter_tiled<T, V, Acc, false, 16, false>,
-                (const void*)k_iter_tiled<T, V, Acc, true, 8, true>, (const void*)k_iter_tiled<T, V, Acc, false, 8, true>,
-                (const void*)k_iter_tiled<T, V, Acc, true, 16, true>, (const void*)k_iter_tiled<T, V, Acc, false, 16, true>,
-                (const void*)k_iter_persist<T, V, Acc, true, 8, false>,
-                (const void*)k_iter_persist<T, V, Acc, false, 8, false>,
-                (const void*)k_iter_persist<T, V, Acc, true, 16, false>,
-                (const void*)k_iter_persist<T, V, Acc, false, 16, false>,
-                (const void*)k_iter_persist<T, V, Acc, true, 8, true>,
-                (const void*)k_iter_persist<T, V, Acc, false, 8, true>,
-                (const void*)k_iter_persist<T, V, Acc, true, 16, true>,
-                (const void*)k_iter_persist<T, V, Acc, false, 16, true>,
-                (const void*)k_eval<true>, (const void*)k_eval<false>, (const void*)k_scale_stat<true>,
-                (const void*)k_scale_stat<false>, (const void*)k_spmv_copy<V, true>,
-                (const void*)k_spmv_copy<V, false>};
+#define MIP_ITER_KERNELS(G)                                                                                  \
+    (const void*)k_iter_tiled<T, V, Acc, true, 8, false, G>, (const void*)k_iter_tiled<T, V, Acc, false, 8, false, G>,  \
+        (const void*)k_iter_tiled<T, V, Acc, true, 16, false, G>,                                                      \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, false, G>, (const void*)k_iter_tiled<T, V, Acc, true, 8, true, G>, \
+        (const void*)k_iter_tiled<T, V, Acc, false, 8, true, G>, (const void*)k_iter_tiled<T, V, Acc, true, 16, true, G>, \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, true, G>, (const void*)k_iter_persist<T, V, Acc, true, 8, false, G>, \
+        (const void*)k_iter_persist<T, V, Acc, false, 8, false, G>,                                                    \
+        (const void*)k_iter_persist<T, V, Acc, true, 16, false, G>,                                                    \
+        (const void*)k_iter_persist<T, V, Acc, false, 16, false, G>,                                                   \
+        (const void*)k_iter_persist<T, V, Acc, true, 8, true, G>, (const void*)k_iter_persist<T, V, Acc, false, 8, true, G>, \
+        (const void*)k_iter_persist<T, V, Acc, true, 16, true, G>,                                                     \
+        (const void*)k_iter_persist<T, V, Acc, false, 16, true, G>
+            const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true),
+                                (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
+                                (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
+                                (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
+                                (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
+#undef MIP_ITER_KERNELS
             for (const void* k : ks)
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
                     return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
@@ -1002,8 +1067,15 @@ struct Solver {
     int grid_dual() const { return persistent() ? gd_persist : tiled() ? ta.ntiles : hpa.grid(); }
     // Resident workgroups of the persistent kernel over all CUs, at least
     // min(8, ntiles) so that every XCD's run of tiles has a workgroup.
+    // the general-form variant of a kernel: bounds for the primal, senses for the dual
+    bool gen_primal() const { return has_bounds(lp); }
+    bool gen_dual() const { return has_sense(lp); }
     template <bool PRIMAL>
     int persist_grid(const TilePlan& tp) {
+        return (PRIMAL ? gen_primal() : gen_dual()) ? persist_grid_g<PRIMAL, true>(tp) : persist_grid_g<PRIMAL, false>(tp);
+    }
+    template <bool PRIMAL, bool G>
+    int persist_grid_g(const TilePlan& tp) {
         int dev = 0, cus = 0, occ = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1011,15 +1083,15 @@ struct Solver {
         const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
         hipError_t e;
         if (tp.tile_nnz > 8 * kBlock)
-            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 16, true>,
-                                                                       kBlock, lds)
+            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 16, true, G>, kBlock, lds)
                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 16, false>, kBlock, lds);
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 16, false, G>, kBlock, lds);
         else
-            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_iter_persist<T, V, Acc, PRIMAL, 8, true>,
-                                                                       kBlock, lds)
+            e = sorted() ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 8, true, G>, kBlock, lds)
                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 8, false>, kBlock, lds);
+                               &occ, k_iter_persist<T, V, Acc, PRIMAL, 8, false, G>, kBlock, lds);
         if (e != hipSuccess || occ < 1) return 0;
         const int64_t g = std::min<int64_t>((int64_t)cus * occ, tp.ntiles);
         return (int)std::max<int64_t>(g, std::min<int64_t>(8, tp.ntiles));
@@ -1047,6 +1119,9 @@ struct Solver {
         a.dscale = primal ? w.d_col : w.d_row;
         a.partials = primal ? w.pp : w.pd;
         a.ctrl = w.ctrl;
+        a.lo = (const T*)w.lo_t;
+        a.hi = (const T*)w.hi_t;
+        a.sense = lp.sense;
         a.rho = o.reflect_rho;
         a.halpern = o.halpern;
         a.it = it;
@@ -1056,11 +1131,17 @@ struct Solver {
     // products in flight per thread, row-major or sorted layout.
     template <bool PRIMAL>
     void launch_tiles(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
+        if (PRIMAL ? gen_primal() : gen_dual()) launch_tiles_g<PRIMAL, true>(a, tp, gpersist);
+        else launch_tiles_g<PRIMAL, false>(a, tp, gpersist);
+    }
+    template <bool PRIMAL, bool G>
+    void launch_tiles_g(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
         const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
         const bool big = tp.tile_nnz > 8 * kBlock;
         const dim3 grid(persistent() ? gpersist : tp.ntiles);
         if (sorted()) tp.slot = PRIMAL ? w.slot_at : w.slot_a;
-#define MIP_TILE_LAUNCH(K, U, SRT) hipLaunchKernelGGL((K<T, V, Acc, PRIMAL, U, SRT>), grid, dim3(kBlock), lds, stream, a, tp)
+#define MIP_TILE_LAUNCH(K, U, SRT) \
+    hipLaunchKernelGGL((K<T, V, Acc, PRIMAL, U, SRT, G>), grid, dim3(kBlock), lds, stream, a, tp)
         if (persistent()) {
             if (big) {
                 if (sorted()) MIP_TILE_LAUNCH(k_iter_persist, 16, true);
@@ -1115,7 +1196,14 @@ struct Solver {
         er.out2 = nullptr;
         er.partials = w.per;
         er.ctrl = w.ctrl;
-        hipLaunchKernelGGL((k_eval<true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, er, ta);
+        er.sense = lp.sense;
+        er.lo = er.hi = nullptr;
+        if (gen_dual())
+            hipLaunchKernelGGL((k_eval<true, true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, er,
+                               ta);
+        else
+            hipLaunchKernelGGL((k_eval<true, false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream,
+                               er, ta);
         MIP_LAUNCH_CHECK();
         EvalArgs ec;
         ec.col = lp.at_col;
@@ -1127,7 +1215,15 @@ struct Solver {
         ec.out2 = rdo;
         ec.partials = w.pec;
         ec.ctrl = w.ctrl;
-        hipLaunchKernelGGL((k_eval<false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, ec, tat);
+        ec.sense = nullptr;
+        ec.lo = lp.lo;
+        ec.hi = lp.hi;
+        if (gen_primal())
+            hipLaunchKernelGGL((k_eval<false, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream,
+                               ec, tat);
+        else
+            hipLaunchKernelGGL((k_eval<false, false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
+                               stream, ec, tat);
         MIP_LAUNCH_CHECK();
         return launch_decide(nit);
     }
@@ -1209,7 +1305,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const auto t0 = clk::now();
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
-                sorted_layout(o, lp.m, lp.n));
+                sorted_layout(o, lp.m, lp.n), has_bounds(lp));
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1338,6 +1434,12 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
                            (T*)w.ct, w.psetup + G);
         hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream,
                            (const double*)(w.psetup + G), gn, 1, w.red + 3);
+        MIP_LAUNCH_CHECK();
+    }
+
+    if (has_bounds(lp)) {
+        hipLaunchKernelGGL((k_scale_bounds<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, lp.lo, lp.hi,
+                           (const double*)w.d_col, n, (T*)w.lo_t, (T*)w.hi_t);
         MIP_LAUNCH_CHECK();
     }
 
@@ -1620,8 +1722,9 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         const double vs = sizeof(V), ts = sizeof(T);
         // per iteration: A and A^T values + indices, row pointers, gathers,
         // streamed vectors (x, x0, c~, x_bar written; y, y0, b~)
-        info->bytes_primal = nnz * (vs + 4.0) + 4.0 * (n + 1) + ts * (double)m + 5.0 * ts * n;
-        info->bytes_dual = nnz * (vs + 4.0) + 4.0 * (m + 1) + ts * (double)n + 4.0 * ts * m;
+        // general form: the primal reads two scaled bounds per column, the dual one sense byte per row
+        info->bytes_primal = nnz * (vs + 4.0) + 4.0 * (n + 1) + ts * (double)m + (has_bounds(lp) ? 7.0 : 5.0) * ts * n;
+        info->bytes_dual = nnz * (vs + 4.0) + 4.0 * (m + 1) + ts * (double)n + 4.0 * ts * m + (has_sense(lp) ? m : 0);
         info->bytes_per_iter = info->bytes_primal + info->bytes_dual;
         info->ms_primal = S.n_p ? S.ms_p / S.n_p : 0.0;
         info->ms_dual = S.n_d ? S.ms_d / S.n_d : 0.0;
@@ -1647,6 +1750,8 @@ extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, doub
     if ((rc = check_options(opt))) return rc;
     if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
     if (!workspace || !x || !y || !z || !r_p || !r_d) return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
+    if (is_general(*lp) && opt->spmv_kind == 1)
+        return set_error("the general form runs on the tile kernels (spmv_kind 0 or 2)"), MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:

@@ -30,6 +30,24 @@ __global__ void k_check_vec(const double* v, int64_t n, int32_t* flags) {
     if (f) atomicOr(flags, f);
 }
 
+// general form: bit3 a bound is NaN, lo = +inf, hi = -inf or lo > hi;
+// bit4 a row sense outside {0, 1, 2}
+__global__ void k_check_bounds(const double* lo, const double* hi, int64_t n, int32_t* flags) {
+    int f = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double l = lo ? lo[j] : 0.0, u = hi ? hi[j] : INFINITY;
+        if (!(l <= u) || l == INFINITY || u == -INFINITY) f |= 8;  // NaN fails l <= u
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_check_sense(const int8_t* sense, int64_t m, int32_t* flags) {
+    int f = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        if (sense[i] < 0 || sense[i] > 2) f |= 16;
+    if (f) atomicOr(flags, f);
+}
+
 __device__ __forceinline__ double hash_unit(uint32_t i, uint32_t seed) {
     uint32_t h = i * 0x9E3779B1u ^ seed;
     h ^= h >> 16;
@@ -99,12 +117,20 @@ int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat
     }
     hipLaunchKernelGGL(k_check_vec, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.b, (int64_t)lp.m, flags);
     hipLaunchKernelGGL(k_check_vec, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.c, (int64_t)lp.n, flags);
+    if (has_bounds(lp))
+        hipLaunchKernelGGL(k_check_bounds, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.lo, lp.hi,
+                           (int64_t)lp.n, flags);
+    if (has_sense(lp))
+        hipLaunchKernelGGL(k_check_sense, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.sense, (int64_t)lp.m,
+                           flags);
     MIP_LAUNCH_CHECK();
     int32_t f = 0;
     MIP_HIP(hipMemcpyAsync(&f, flags, 4, hipMemcpyDeviceToHost, stream));
     MIP_HIP(hipStreamSynchronize(stream));
     if (f & 1) return set_error("column index out of range"), MIPDHG_ERR_BAD_CSR;
     if (f & 6) return set_error("NaN or Inf in A, A^T, b or c"), MIPDHG_ERR_NONFINITE;
+    if (f & 8) return set_error("a bound is NaN, lo = +inf, hi = -inf or lo > hi"), MIPDHG_ERR_INVALID_ARG;
+    if (f & 16) return set_error("a row sense is not 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (nnz == 0) return 0;
     // u^T (A v) against v^T (A^T u), and the scale sum |u||A||v|
     const uint32_t su = 0x1234u, sv = 0xABCDu;

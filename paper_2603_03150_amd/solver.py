@@ -21,10 +21,12 @@ def _dev_tensor(a, dtype, device) -> torch.Tensor:
 
 
 class DeviceLP:
-    """A standard-form LP held in device memory: A and A^T in CSR (int32
-    indices, float64 values), b and c in float64."""
+    """An LP held in device memory: A and A^T in CSR (int32 indices, float64
+    values), b and c in float64; for the general form also the bounds lo, hi
+    (float64, +-inf allowed) and the row senses (int8: 0 =, 1 >=, 2 <=), any
+    of them None for its standard-form default (x >= 0, equality rows)."""
 
-    def __init__(self, A, AT, b, c, device: str | torch.device = "cuda"):
+    def __init__(self, A, AT, b, c, device: str | torch.device = "cuda", lo=None, hi=None, sense=None):
         m, n = A.shape
         if AT.shape != (n, m):
             raise ValueError("AT must be n x m")
@@ -39,16 +41,23 @@ class DeviceLP:
         self.at_val = _dev_tensor(AT.data, torch.float64, d)
         self.b = _dev_tensor(b, torch.float64, d)
         self.c = _dev_tensor(c, torch.float64, d)
+        self.lo = None if lo is None else _dev_tensor(lo, torch.float64, d)
+        self.hi = None if hi is None else _dev_tensor(hi, torch.float64, d)
+        self.sense = None if sense is None else _dev_tensor(sense, torch.int8, d)
 
     @classmethod
     def from_lp(cls, lp, device="cuda") -> "DeviceLP":
-        return cls(lp.A, lp.AT, lp.b, lp.c, device)
+        return cls(lp.A, lp.AT, lp.b, lp.c, device, getattr(lp, "lo", None), getattr(lp, "hi", None),
+                   getattr(lp, "sense", None))
 
     def struct(self) -> _lib.LPStruct:
         s = _lib.LPStruct()
         s.m, s.n, s.nnz = self.m, self.n, self.nnz
         for name in ("a_rowptr", "a_col", "a_val", "at_rowptr", "at_col", "at_val", "b", "c"):
             setattr(s, name, getattr(self, name).data_ptr())
+        for name in ("lo", "hi", "sense"):
+            t = getattr(self, name)
+            setattr(s, name, None if t is None else t.data_ptr())
         return s
 
 
