@@ -20,8 +20,8 @@ Also reported, on the same JSON line:
                     sources match it;
   cpu_baseline      the float64 NumPy/SciPy oracle on the host, single thread,
                     on a bounded sample of the same workload;
-  block_angular, tolerance_ratios, differentiation, batched: the other
-                    workloads (see their docstrings below).
+  block_angular, tolerance_ratios, differentiation, batched, general: the
+                    other workloads (see their docstrings below).
 """
 from __future__ import annotations
 
@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-block-angular", action="store_true", help="skip the block-angular LP leg")
     ap.add_argument("--no-ratios", action="store_true", help="skip the tolerance-ratio leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
+    ap.add_argument("--no-general", action="store_true", help="skip the general-form LP leg")
     ap.add_argument("--profile", action="store_true",
                     help="only a short capped solve (256 iterations) of --workload (for hardware counters)")
     ap.add_argument("--shape", default="",
@@ -207,6 +208,48 @@ def block_angular_leg(P, torch, eps: float, precision: str, timing_iters: int) -
                           "rel_rd": bi["rel_rd"], "rel_gap": bi["rel_gap"], "iter_only_rate":
                           int(bi["iters"]) / (bi["ms_iter"] * 1e-3), "bytes_per_iter": bi["bytes_per_iter"]}
     del dlp, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def general_leg(P, torch, eps: float, precision: str) -> dict:
+    """The general form (bounds l <= x <= u, rows of sense =, >= or <=) on a
+    power-law LP of the main workload's shape (100,000 x 400,000, ~3.2M
+    nonzeros) with a planted KKT point: a solve to eps, the general kernels'
+    roofline, and the same kernels' standard-form variants on the same matrix
+    (what the bounds and senses cost per launch)."""
+    import lpgen
+    t0 = time.perf_counter()
+    lp = lpgen.general_cfg2(0)
+    gen_s = time.perf_counter() - t0
+    dlp = P.DeviceLP.from_lp(lp, "cuda:0")
+    shape, tune_s = tuned_shape(P, dlp, precision)
+    ws = torch.empty(P.workspace_bytes(dlp, precision, **shape), dtype=torch.uint8, device="cuda:0")
+    P.solve(dlp, eps, precision, workspace=ws, max_iter=64, **shape)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol = P.solve(dlp, eps, precision, workspace=ws, max_iter=200_000, **shape)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf = sol.info
+    roof = kernel_roofline(P, dlp, ws, precision, 256, "general", shape)
+    std = P.DeviceLP(lp.A, lp.AT, lp.b, lp.c, "cuda:0")
+    sroof = kernel_roofline(P, std, ws, precision, 256, "general_std", shape)
+    out = {"workload": "power-law LP m=100000 n=400000 in general form (30% x>=0, 25% boxes, 10% free, "
+                       "15% upper-only, 20% shifted lower bounds; rows 50% =, 25% >=, 25% <=), planted KKT point",
+           "m": lp.m, "n": lp.n, "nnz": lp.nnz, "precision": precision, "eps_rel": eps,
+           "status": sol.status_name, "iters": int(inf["iters"]), "restarts": int(inf["restarts"]),
+           "seconds": dt, "iter_per_s": int(inf["iters"]) / dt,
+           "iter_only_rate": int(inf["iters"]) / (inf["ms_iter"] * 1e-3), "ms_setup": inf["ms_setup"],
+           "rel_obj_err_vs_planted": abs(inf["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star)),
+           "rel_rp": inf["rel_rp"], "rel_rd": inf["rel_rd"], "rel_gap": inf["rel_gap"],
+           "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof,
+           "standard_kernels_same_matrix": {"ms_primal": sroof["ms_per_launch"] if sroof["kernel"].endswith("primal>")
+                                            else sroof["other_kernel"]["primal"]["ms"],
+                                            "ms_dual": sroof["ms_per_launch"] if sroof["kernel"].endswith("dual>")
+                                            else sroof["other_kernel"]["dual"]["ms"]},
+           "spmv_shape": shape, "autotune_s": tune_s}
+    del dlp, std, ws
     torch.cuda.empty_cache()
     return out
 
@@ -446,6 +489,9 @@ def main() -> int:
     if not args.no_diff:
         print("# differentiation leg", file=sys.stderr, flush=True)
         out["differentiation"] = diff_leg(P, torch)
+    if not args.no_general:
+        print("# general-form leg", file=sys.stderr, flush=True)
+        out["general"] = general_leg(P, torch, args.eps, args.precision)
     if not args.no_block_angular and args.workload != "block_angular":
         print("# block-angular leg", file=sys.stderr, flush=True)
         del ws

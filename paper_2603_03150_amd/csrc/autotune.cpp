@@ -37,7 +37,9 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     double best = 1e300;
     Cand win{0, 0, 0, 0};
     bool first = true;
+    const bool general = lp->lo || lp->hi || lp->sense;  // runs on the tile kernels only
     for (const Cand& c : candidates()) {
+        if (general && c.kind == 1) continue;
         mipdhg_options o = *opt;
         o.spmv_kind = c.kind;
         o.tile_nnz = c.tile_nnz;
