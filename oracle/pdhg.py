@@ -45,6 +45,20 @@ planted general optimum (closed form and fixed point), the equivalent
 standard-form LP built by slack and split variables, and the special case
 above reproducing the standard-form run bit for bit.
 
+Infeasibility (a reading; the paper does not treat it): at every evaluation
+after the first, the change (d, e) of the evaluated point since the previous
+evaluation is tested as a certificate.  For an infeasible or unbounded LP the
+PDHG iterates drift along the minimal displacement of the operator, whose
+dual part is a Farkas ray and whose primal part a recession direction; for a
+solvable LP the change goes to zero.  e certifies primal infeasibility when
+its value b^T e + sum_j l_j mu_j^+ - u_j mu_j^- is positive and the norm of
+its residual (-A^T e - mu with mu = -A^T e projected onto the bound cones,
+and the part of e outside its rows' sign cones) is at most infeas_tol times
+that value; d certifies dual infeasibility when c^T d < 0 and the part of
+A d outside the rows' recession cones together with the part of d outside
+the bounds' recession cones is at most infeas_tol |c^T d|.  Pinned by
+scipy's HiGHS classifying the same LPs as infeasible or unbounded.
+
 parity unpinned: the restart and primal-weight heuristics (which iterations
 restart, the omega sequence, iteration counts to a tolerance) follow a reading
 with no external reference; only GPU-versus-oracle agreement checks them.
@@ -57,7 +71,8 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL"}
+STATUS = {0: "OPTIMAL", 1: "ITER_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL", 4: "PRIMAL_INFEASIBLE",
+          5: "DUAL_INFEASIBLE"}
 SENSE_EQ, SENSE_GE, SENSE_LE = 0, 1, 2  # (A x)_i = b_i, >= b_i, <= b_i
 
 
@@ -76,6 +91,7 @@ class OracleOptions:
     beta_art: float = 0.36
     pw_theta: float = 0.5
     max_iter: int = 1_000_000
+    infeas_tol: float = 1e-8  # 0 turns the certificate tests off
 
 
 @dataclass
@@ -304,6 +320,45 @@ def evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat, lo=None, hi=None, sense=No
                     max(rp_inf, rd_inf, xz / (1.0 + abs(pobj))))
 
 
+def ray_measures(A, AT, b, c, d, e, lo=None, hi=None, sense=None):
+    """Certificate quantities of a direction pair in the original space:
+    (value of e as a dual ray, its residual norm, c^T d, residual norm of d as
+    a primal ray); see the module docstring."""
+    Ad = A @ d
+    g = -(AT @ e)
+    mu = reduced_costs(g, lo, hi)
+    if sense is None:
+        viol_ad, viol_e = Ad, np.zeros(0)
+    else:
+        ge, le = sense == SENSE_GE, sense == SENSE_LE
+        viol_ad = np.where(ge, np.minimum(Ad, 0.0), np.where(le, np.maximum(Ad, 0.0), Ad))
+        viol_e = np.where(ge, np.minimum(e, 0.0), np.where(le, np.maximum(e, 0.0), 0.0))
+    if lo is None:
+        bterm = 0.0
+        viol_d = np.minimum(d, 0.0)
+    else:
+        lf, uf = np.isfinite(lo), np.isfinite(hi)
+        lo0, hi0 = np.where(lf, lo, 0.0), np.where(uf, hi, 0.0)
+        bterm = float(np.sum(lo0 * np.maximum(mu, 0.0)) - np.sum(hi0 * np.maximum(-mu, 0.0)))
+        viol_d = np.where(lf & uf, d, np.where(lf, np.minimum(d, 0.0), np.where(uf, np.maximum(d, 0.0), 0.0)))
+    q_e = float(b @ e) + bterm
+    r_e = math.sqrt(float(np.sum((g - mu) ** 2)) + float(np.sum(viol_e ** 2)))
+    q_d = float(c @ d)
+    r_d = math.sqrt(float(np.sum(viol_ad ** 2)) + float(np.sum(viol_d ** 2)))
+    return q_e, r_e, q_d, r_d
+
+
+def infeasibility(q_e: float, r_e: float, q_d: float, r_d: float, tol: float):
+    """4 (primal infeasible), 5 (dual infeasible) or None."""
+    if tol <= 0.0:
+        return None
+    if q_e > 0.0 and r_e <= tol * q_e:
+        return 4
+    if q_d < 0.0 and r_d <= tol * -q_d:
+        return 5
+    return None
+
+
 def terminated(meas: Measures, b_norm: float, c_norm: float, eps: float) -> bool:
     """The three relative tests of Section 2, inclusive."""
     return (meas.rp_norm <= eps * (1.0 + b_norm)
@@ -369,6 +424,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     log = []
     trace = {}
     E = max(1, int(opts.eval_every))
+    prev = None  # the previous evaluated point (x, y), original space
 
     while True:
         t += 1
@@ -389,7 +445,10 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                 status = 3
             elif terminated(meas, b_norm, c_norm, eps):
                 status = 0
-            elif t >= opts.max_iter:
+            if status is None and prev is not None:
+                status = infeasibility(*ray_measures(A, AT, b, c, meas.x - prev[0], meas.y - prev[1],
+                                                     lo, hi, sense), opts.infeas_tol)
+            if status is None and t >= opts.max_iter:
                 status = 1
             if status is not None:
                 if t <= trace_iters:
@@ -412,6 +471,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
             else:
                 R_prev = R
             log.append((t, restarted, omega))
+            prev = (meas.x, meas.y)
         x, y = x_new, y_new
         if t <= trace_iters:
             trace[t] = (x.copy(), y.copy(), x_hat, y_hat)

@@ -314,9 +314,14 @@ def test_empty_row_and_validation():
 
 
 def test_iteration_limit_and_infeasible():
-    # x1 + x2 = -1 with x >= 0 is infeasible: no termination, ITER_LIMIT
+    # x1 + x2 = -1 with x >= 0 is infeasible: without the certificate tests
+    # no termination (ITER_LIMIT); with them, primal infeasibility at the
+    # second evaluation
     A = sp.csr_matrix(np.array([[1.0, 1.0]]))
     res = oracle.solve(A, sp.csr_matrix(A.T), np.array([-1.0]), np.array([1.0, 1.0]), 1e-6,
-                       opts=OracleOptions(max_iter=300))
+                       opts=OracleOptions(max_iter=300, infeas_tol=0.0))
     assert res.status == 1 and res.iters == 300
     assert res.meas.rp_norm > 0.5
+    res = oracle.solve(A, sp.csr_matrix(A.T), np.array([-1.0]), np.array([1.0, 1.0]), 1e-6,
+                       opts=OracleOptions(max_iter=300))
+    assert res.status == 4 and res.iters == 128
