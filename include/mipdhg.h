@@ -50,6 +50,11 @@ extern "C" {
 #define MIPDHG_ITER_LIMIT 1      /* max_iter reached                           */
 #define MIPDHG_TIME_LIMIT 2      /* time_limit_s reached                       */
 #define MIPDHG_NUMERICAL 3       /* a NaN/Inf appeared in an evaluation        */
+#define MIPDHG_PRIMAL_INFEASIBLE 4 /* the change of the evaluated y since the
+                                    previous evaluation is a Farkas ray (see
+                                    infeas_tol)                                */
+#define MIPDHG_DUAL_INFEASIBLE 5   /* the change of the evaluated x is a
+                                    recession direction with c^T d < 0        */
 /* errors (< 0) */
 #define MIPDHG_ERR_INVALID_ARG -1   /* null pointer, bad size or option       */
 #define MIPDHG_ERR_BAD_CSR -2       /* row pointers or column indices invalid */
@@ -168,6 +173,20 @@ typedef struct mipdhg_options {
      * tracing; a kernel_timing = 2 solve is not resumable.  Single-LP solve
      * only (UNSUPPORTED in the batched and unrolled entry points).          [0] */
     int32_t resume;
+    /* Infeasibility certificates (the paper does not treat infeasible LPs;
+     * this is the library's own test).  At every evaluation after the first,
+     * with (d, e) the change of the evaluated (x, y) since the previous
+     * evaluation: PRIMAL_INFEASIBLE when v = b^T e + sum_j lo_j mu_j^+ -
+     * hi_j mu_j^- > 0 and || (-A^T e - mu, part of e outside its rows' sign
+     * cones) || <= infeas_tol * v, with mu = -A^T e projected onto the
+     * cones the bounds allow; DUAL_INFEASIBLE when c^T d < 0 and || (part of
+     * A d outside the rows' recession cones, part of d outside the bounds'
+     * recession cones) || <= infeas_tol * |c^T d|.  0 turns the tests off.
+     * With float32 iterates (rounding ~6e-8 relative, growing with the
+     * drifting iterate of an infeasible LP) use about 1e-5: at 1e-8 such a
+     * run may drift until it overflows (NUMERICAL).
+     * Single-LP solve only (the batched and unrolled solves ignore it). [1e-8] */
+    double infeas_tol;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */

@@ -41,6 +41,7 @@ __all__ = [
     "cfg5_instance", "cfg5_batch", "cfg5_fd_instance", "tiny", "simplex_lp",
     "powerlaw_counts", "Batch", "stack_batch", "general_from_matrix", "general_tiny",
     "general_cfg1", "general_cfg2", "general_cfg2_sub", "SENSE_EQ", "SENSE_GE", "SENSE_LE",
+    "farkas_tiny", "unbounded_tiny", "conflicting_rows", "unbounded_column", "box_infeasible",
 ]
 
 SENSE_EQ, SENSE_GE, SENSE_LE = 0, 1, 2
@@ -454,3 +455,53 @@ def general_cfg2_sub(seed: int = 0, scale: int = 100) -> LP:
     A, AT = _cfg2_matrix(100_000 // scale, 400_000 // scale, rng, 2000)
     return general_from_matrix(A, AT, rng, name=f"gcfg2sub{scale}_s{seed}",
                                meta={"cfg": 2, "seed": seed, "scale": scale})
+
+
+# ---------------------------------------------------------------------------
+# LPs without an optimum (no planted point: x_star, y_star, z_star are None)
+# ---------------------------------------------------------------------------
+
+def _lp_from_dense(A: np.ndarray, b, c, name: str, lo=None, hi=None, sense=None) -> LP:
+    Acsr = sp.csr_matrix(np.asarray(A, dtype=np.float64))
+    Acsr.sort_indices()
+    AT = sp.csr_matrix(Acsr.T)
+    AT.sort_indices()
+    for M in (Acsr, AT):
+        M.indices = M.indices.astype(np.int32)
+        M.indptr = M.indptr.astype(np.int32)
+    return LP(Acsr, AT, np.asarray(b, dtype=np.float64), np.asarray(c, dtype=np.float64), None, None, None,
+              name=name, lo=lo, hi=hi, sense=sense)
+
+
+def farkas_tiny() -> LP:
+    """x1 + x2 = -1, x >= 0: infeasible (y = -1 is a Farkas ray)."""
+    return _lp_from_dense([[1.0, 1.0]], [-1.0], [1.0, 1.0], "farkas_tiny")
+
+
+def unbounded_tiny() -> LP:
+    """min -x1 s.t. x1 - x2 = 0, x >= 0: unbounded along (1, 1)."""
+    return _lp_from_dense([[1.0, -1.0]], [0.0], [-1.0, 0.0], "unbounded_tiny")
+
+
+def conflicting_rows(seed: int) -> LP:
+    """A general tiny LP plus two copies of its first row's coefficients, one
+    >= 1 and one <= 0: infeasible."""
+    g = general_tiny(10, 24, 3, 200 + seed)
+    A = sp.vstack([g.A, g.A[0], g.A[0]]).toarray()
+    return _lp_from_dense(A, np.concatenate([g.b, [1.0, 0.0]]), g.c, f"conflict_s{seed}", g.lo, g.hi,
+                          np.concatenate([g.sense, np.array([SENSE_GE, SENSE_LE], dtype=np.int8)]))
+
+
+def unbounded_column(seed: int) -> LP:
+    """A general tiny LP with an extra free column that is in no row and
+    costs 1: unbounded below."""
+    g = general_tiny(10, 24, 3, 300 + seed)
+    A = np.hstack([g.A.toarray(), np.zeros((g.m, 1))])
+    return _lp_from_dense(A, g.b, np.concatenate([g.c, [1.0]]), f"unbounded_s{seed}",
+                          np.concatenate([g.lo, [-np.inf]]), np.concatenate([g.hi, [np.inf]]), g.sense)
+
+
+def box_infeasible() -> LP:
+    """x1 + x2 = 5 with both in [0, 1]: infeasible."""
+    return _lp_from_dense([[1.0, 1.0]], [5.0], [1.0, -1.0], "box_infeasible", np.zeros(2), np.ones(2),
+                          np.zeros(1, dtype=np.int8))

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmipdhg.so")
 
 # status / error codes
-OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL = 0, 1, 2, 3
+OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 0, 1, 2, 3, 4, 5
 ERR_INVALID_ARG, ERR_BAD_CSR, ERR_TRANSPOSE, ERR_HIP = -1, -2, -3, -4
 ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_NONFINITE = -5, -6, -7
 
@@ -42,7 +42,8 @@ class OptionsStruct(C.Structure):
                 ("short_row", _i32), ("lanes_a", _i32), ("lanes_at", _i32),
                 ("long_row", _i32), ("kernel_timing", _i32), ("trace_iters", _i32),
                 ("trace_x", _p), ("trace_y", _p), ("trace_xhat", _p), ("trace_yhat", _p),
-                ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32)]
+                ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32),
+                ("infeas_tol", _f64)]
 
 
 class InfoStruct(C.Structure):

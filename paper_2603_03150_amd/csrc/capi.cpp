@@ -40,6 +40,7 @@ extern "C" void mipdhg_default_options(mipdhg_options* o) {
     o->time_limit_s = 1e4;
     o->validate = 1;
     o->use_graph = 1;
+    o->infeas_tol = 1e-8;
 }
 
 extern "C" const char* mipdhg_status_string(int code) {
@@ -48,6 +49,8 @@ extern "C" const char* mipdhg_status_string(int code) {
         case MIPDHG_ITER_LIMIT: return "ITER_LIMIT";
         case MIPDHG_TIME_LIMIT: return "TIME_LIMIT";
         case MIPDHG_NUMERICAL: return "NUMERICAL";
+        case MIPDHG_PRIMAL_INFEASIBLE: return "PRIMAL_INFEASIBLE";
+        case MIPDHG_DUAL_INFEASIBLE: return "DUAL_INFEASIBLE";
         case MIPDHG_ERR_INVALID_ARG: return "ERR_INVALID_ARG";
         case MIPDHG_ERR_BAD_CSR: return "ERR_BAD_CSR";
         case MIPDHG_ERR_TRANSPOSE: return "ERR_TRANSPOSE";

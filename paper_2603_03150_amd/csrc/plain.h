@@ -31,6 +31,9 @@ struct Ctrl {
     // the state belongs to, and whether the state is the solve's own
     int32_t last_nit, resumable;
     uint64_t fingerprint;
+    // infeasibility certificates: whether a previous evaluated point is kept
+    int32_t have_prev, pad_;
+    double infeas_tol;
 };
 
 // shared host helpers (plain.hip, validate.hip)

@@ -534,6 +534,100 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     }
 }
 
+// Infeasibility certificates: the change (d, e) = (x - x_prev, y - y_prev)
+// of the evaluated point since the previous evaluation, original model.
+// ROWS:  over A's rows, t = (A d)_i; partials: sum (part of t outside the
+//        row's recession cone)^2, sum b.e, sum (part of e_i outside the row's
+//        sign cone)^2
+// !ROWS: over A^T's rows, g = -(A^T e)_j, mu = g projected onto the cone the
+//        bounds allow; partials: sum (g - mu)^2, sum of bound terms of mu,
+//        sum c.d, sum (part of d_j outside the bounds' recession cone)^2
+// GEN: row senses (ROWS) or bounds (!ROWS) as in the evaluation.
+struct RayArgs {
+    const int32_t* col;
+    const double* val;
+    const double* gv;     // the gathered point (x for ROWS, y)
+    const double* gprev;  // its previous evaluation
+    const double* ov;     // this kernel's own point (y for ROWS, x)
+    const double* oprev;
+    const double* vec;    // b (ROWS) or c
+    double* partials;     // [G][3] (ROWS) or [G][4]
+    const Ctrl* ctrl;
+    const int8_t* sense;
+    const double* lo;
+    const double* hi;
+};
+
+template <bool ROWS, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_ray(RayArgs a, TilePlan tp) {
+    const bool active = a.ctrl->status == ST_RUNNING;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, tp);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    auto prod = [&](int b, int j) {
+        const int64_t k = (int64_t)b + j;
+        const int32_t c = ld_idx(a.col, k);
+        return ld_val(a.val, k) * (a.gv[c] - a.gprev[c]);
+    };
+    auto epi = [&](int r, double t) {
+        const double own = a.ov[r] - a.oprev[r];
+        if (ROWS) {
+            double v = t, ve = 0.0;  // = rows: A d = 0, e free
+            if (GEN) {
+                const int sn = a.sense[r];
+                if (sn == MIPDHG_SENSE_GE) {
+                    v = t < 0.0 ? t : 0.0;
+                    ve = own < 0.0 ? own : 0.0;
+                } else if (sn == MIPDHG_SENSE_LE) {
+                    v = t > 0.0 ? t : 0.0;
+                    ve = own > 0.0 ? own : 0.0;
+                }
+            }
+            s[0] += v * v;
+            s[1] += a.vec[r] * own;
+            s[2] += ve * ve;
+        } else {
+            const double g = -t;
+            double mu, vd;
+            if (GEN) {
+                const double l = a.lo ? a.lo[r] : 0.0, u = a.hi ? a.hi[r] : INFINITY;
+                const bool lf = isfinite(l), uf = isfinite(u);
+                mu = (lf && uf) ? g : lf ? (g > 0.0 ? g : 0.0) : uf ? (g < 0.0 ? g : 0.0) : 0.0;
+                vd = (lf && uf) ? own : lf ? (own < 0.0 ? own : 0.0) : uf ? (own > 0.0 ? own : 0.0) : 0.0;
+                const double mp = mu > 0.0 ? mu : 0.0, mm = mu < 0.0 ? -mu : 0.0;
+                s[1] += (lf ? l * mp : 0.0) - (uf ? u * mm : 0.0);
+            } else {
+                mu = g > 0.0 ? g : 0.0;
+                vd = own < 0.0 ? own : 0.0;
+            }
+            s[0] += (g - mu) * (g - mu);
+            s[2] += a.vec[r] * own;
+            s[3] += vd * vd;
+        }
+    };
+    auto le = lepi(epi);
+    tiled_rows<false>(tp, own_tile(), L, prod, le, active);
+    if (!active) return;
+    if (ROWS) {
+        double s3[3] = {s[0], s[1], s[2]};
+        block_reduce_store<3, 0>(s3, mx, a.partials + 3 * blockIdx.x);
+    } else {
+        block_reduce_store<4, 0>(s, mx, a.partials + 4 * blockIdx.x);
+    }
+}
+
+// after a decision that keeps the solve running: the evaluated point becomes
+// the previous one of the next evaluation
+__global__ void k_copy_prev(const Ctrl* c, const double* x, const double* y, double* xp, double* yp, int64_t n,
+                            int64_t m) {
+    if (c->status != ST_RUNNING) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        xp[i] = x[i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        yp[i] = y[i];
+}
+
 // ---------------------------------------------------------------------------
 // decide: tests, restart, primal weight (one workgroup)
 // ---------------------------------------------------------------------------
@@ -543,6 +637,8 @@ struct DecideArgs {
     const double* pd;  // dual partials [gd][3]
     const double* per; // eval rows [ger][4]
     const double* pec; // eval cols [gec][5]
+    const double* prr; // certificate rows [ger][3] (when infeas_tol > 0)
+    const double* prc; // certificate cols [gec][4]
     int32_t gp, gd, ger, gec;
     int32_t nit;
 };
@@ -593,6 +689,21 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     const double xz = fixed_sum(a.pec, a.gec, 5, 2, sh);
     const double bterm = fixed_sum(a.pec, a.gec, 5, 3, sh);  // 0 in the standard form
     const double rd_inf = fixed_max(a.pec, a.gec, 5, 4, sh);
+    double q_e = 0.0, r_e2 = 0.0, q_d = 0.0, r_d2 = 0.0;
+    const bool rays = c.infeas_tol > 0.0 && c.have_prev;  // uniform over the workgroup
+    if (rays) {
+        const double ad2 = fixed_sum(a.prr, a.ger, 3, 0, sh);
+        const double be = fixed_sum(a.prr, a.ger, 3, 1, sh);
+        const double ve2 = fixed_sum(a.prr, a.ger, 3, 2, sh);
+        const double gm2 = fixed_sum(a.prc, a.gec, 4, 0, sh);
+        const double bt = fixed_sum(a.prc, a.gec, 4, 1, sh);
+        const double cd = fixed_sum(a.prc, a.gec, 4, 2, sh);
+        const double vd2 = fixed_sum(a.prc, a.gec, 4, 3, sh);
+        q_e = be + bt;
+        r_e2 = gm2 + ve2;
+        q_d = cd;
+        r_d2 = ad2 + vd2;
+    }
     if (threadIdx.x != 0) return;
 
     const double om = c.omega;
@@ -617,6 +728,10 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     } else if (rp <= c.eps * (1.0 + c.b_norm) && rd <= c.eps * (1.0 + c.c_norm) &&
                gap <= c.eps * (1.0 + fabs(pobj) + fabs(c.dobj))) {
         status = MIPDHG_OPTIMAL;
+    } else if (rays && q_e > 0.0 && sqrt(r_e2) <= c.infeas_tol * q_e) {
+        status = MIPDHG_PRIMAL_INFEASIBLE;
+    } else if (rays && q_d < 0.0 && sqrt(r_d2) <= c.infeas_tol * -q_d) {
+        status = MIPDHG_DUAL_INFEASIBLE;
     } else if (t_end >= c.max_iter) {
         status = MIPDHG_ITER_LIMIT;
     }
@@ -626,6 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
         c.restart_now = 0;
         return;
     }
+    c.have_prev = 1;  // k_copy_prev keeps this evaluation's point
     bool restart = false;
     if (c.do_restarts) {
         restart = (R <= c.beta_suff * c.R0) || (R <= c.beta_nec * c.R0 && R > c.R_prev) ||
@@ -883,6 +999,8 @@ struct PlainWs {
     int32_t *col_a, *col_at;    // sorted layout: column copies in tile order
     uint16_t *slot_a, *slot_at; // sorted layout: row-major position in the tile
     void *lo_t, *hi_t;          // general form: scaled bounds l / D_c, u / D_c
+    double *xprev, *yprev;      // infeasibility certificates: previous evaluated point
+    double *prr, *prc;          // their partial sums [G][3], [G][4]
     size_t bytes;
 };
 
@@ -907,6 +1025,10 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.pd = cv.take<double>((size_t)w.gcap * 3);
     w.per = cv.take<double>((size_t)w.gcap * 4);
     w.pec = cv.take<double>((size_t)w.gcap * 5);
+    w.prr = cv.take<double>((size_t)w.gcap * 3);
+    w.prc = cv.take<double>((size_t)w.gcap * 4);
+    w.xprev = cv.take<double>(n);
+    w.yprev = cv.take<double>(m);
     w.psetup = cv.take<double>((size_t)w.gcap * 4);
     w.a_vs = cv.take<char>(nnz * vs);
     w.at_vs = cv.take<char>(nnz * vs);
@@ -949,6 +1071,8 @@ int check_options(const mipdhg_options* o) {
     if (o->kernel_timing < 0 || o->kernel_timing > 2)
         return set_error("kernel_timing must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->resume < 0 || o->resume > 1) return set_error("resume must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (!(o->infeas_tol >= 0.0) || !std::isfinite(o->infeas_tol))
+        return set_error("infeas_tol must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
     if (o->resume && (o->x_init || o->y_init || o->trace_iters))
         return set_error("resume continues the workspace's state: no warm start or trace with it"),
                MIPDHG_ERR_INVALID_ARG;
@@ -1044,6 +1168,8 @@ struct Solver {
             const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true),
                                 (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
+                                (const void*)k_ray<true, false>, (const void*)k_ray<false, false>,
+                                (const void*)k_ray<true, true>, (const void*)k_ray<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
                                 (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
 #undef MIP_ITER_KERNELS
@@ -1225,6 +1351,23 @@ struct Solver {
             hipLaunchKernelGGL((k_eval<false, false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
                                stream, ec, tat);
         MIP_LAUNCH_CHECK();
+        if (o.infeas_tol > 0.0) {
+            RayArgs rr{lp.a_col, lp.a_val, xo, w.xprev, yo, w.yprev, lp.b, w.prr, w.ctrl, lp.sense, nullptr, nullptr};
+            RayArgs rc{lp.at_col, lp.at_val, yo, w.yprev, xo, w.xprev, lp.c, w.prc, w.ctrl, nullptr, lp.lo, lp.hi};
+            if (gen_dual())
+                hipLaunchKernelGGL((k_ray<true, true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream,
+                                   rr, ta);
+            else
+                hipLaunchKernelGGL((k_ray<true, false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream,
+                                   rr, ta);
+            if (gen_primal())
+                hipLaunchKernelGGL((k_ray<false, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
+                                   stream, rc, tat);
+            else
+                hipLaunchKernelGGL((k_ray<false, false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
+                                   stream, rc, tat);
+            MIP_LAUNCH_CHECK();
+        }
         return launch_decide(nit);
     }
     // decision and restart copy for a block of nit iterations whose
@@ -1236,6 +1379,8 @@ struct Solver {
         d.pd = w.pd;
         d.per = w.per;
         d.pec = w.pec;
+        d.prr = w.prr;
+        d.prc = w.prc;
         d.gp = grid_primal();
         d.gd = grid_dual();
         d.ger = ta.ntiles;
@@ -1248,6 +1393,11 @@ struct Solver {
                            (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, (const T*)w.xhat, (int64_t)lp.n,
                            (T*)w.y, (T*)w.y0, (const T*)w.yhat, (int64_t)lp.m);
         MIP_LAUNCH_CHECK();
+        if (o.infeas_tol > 0.0) {
+            hipLaunchKernelGGL(k_copy_prev, dim3(grid_for(mx)), dim3(kBlock), 0, stream, (const Ctrl*)w.ctrl,
+                               (const double*)xo, (const double*)yo, w.xprev, w.yprev, (int64_t)lp.n, (int64_t)lp.m);
+            MIP_LAUNCH_CHECK();
+        }
         return 0;
     }
     // One block of nit iterations ending in an evaluation.  With trace, the
@@ -1519,6 +1669,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         cur.status = ST_RUNNING;
         cur.eps = eps;
         cur.max_iter = o.max_iter;
+        cur.infeas_tol = o.infeas_tol;
         MIP_HIP(hipMemcpyAsync(w.ctrl, &cur, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
         if (redo && (rc = S.launch_decide(cur.last_nit))) return rc;
         MIP_HIP(hipStreamSynchronize(stream));
@@ -1546,12 +1697,17 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     c0.do_restarts = o.restarts;
     c0.resumable = 1;
     c0.fingerprint = fp;
+    c0.have_prev = 0;
+    c0.infeas_tol = o.infeas_tol;
     if (!o.resume) {
         MIP_HIP(hipMemcpyAsync(w.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, o.x_init,
                            (const double*)w.d_col, n, (T*)w.x, (T*)w.x0, (T*)w.xhat);
         hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, o.y_init,
                            (const double*)w.d_row, m, (T*)w.y, (T*)w.y0, (T*)w.yhat);
+        MIP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.xprev, n, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.yprev, m, 0.0);
         MIP_LAUNCH_CHECK();
     }
     MIP_HIP(hipStreamSynchronize(stream));

@@ -300,10 +300,14 @@ def test_simplex_and_empty_row():
 
 
 def test_infeasible_hits_iteration_limit():
+    # without the certificate tests an infeasible LP runs to the limit; with
+    # them (the default) it is reported at the second evaluation
     A = sp.csr_matrix(np.array([[1.0, 1.0]]))
-    sol = P.solve(P.DeviceLP(A, sp.csr_matrix(A.T), np.array([-1.0]), np.array([1.0, 1.0])), 1e-6, "fp64",
-                  max_iter=300)
+    dlp = P.DeviceLP(A, sp.csr_matrix(A.T), np.array([-1.0]), np.array([1.0, 1.0]))
+    sol = P.solve(dlp, 1e-6, "fp64", max_iter=300, infeas_tol=0.0)
     assert sol.status == 1 and sol.info["rp_norm"] > 0.5
+    sol = P.solve(dlp, 1e-6, "fp64", max_iter=300)
+    assert sol.status == P.PRIMAL_INFEASIBLE and sol.info["iters"] == 128
 
 
 def test_error_codes():

@@ -71,41 +71,15 @@ def test_standard_form_infeasible_and_unbounded():
     assert _solve(A, b, c).status == 5
 
 
-def _conflicting_rows(seed):
-    """A general tiny LP plus two copies of its first row's coefficients,
-    one >= 1 and one <= 0: infeasible."""
-    lp = lpgen.general_tiny(10, 24, 3, 200 + seed)
-    A = sp.vstack([lp.A, lp.A[0], lp.A[0]]).tocsr()
-    b = np.concatenate([lp.b, [1.0, 0.0]])
-    sense = np.concatenate([lp.sense, np.array([1, 2], dtype=np.int8)])
-    return A, b, lp.c, lp.lo, lp.hi, sense
-
-
-def _unbounded_column(seed):
-    """A general tiny LP with an extra free column that appears in no row and
-    costs 1: unbounded below."""
-    lp = lpgen.general_tiny(10, 24, 3, 300 + seed)
-    A = sp.hstack([lp.A, sp.csr_matrix((lp.m, 1))]).tocsr()
-    c = np.concatenate([lp.c, [1.0]])
-    lo = np.concatenate([lp.lo, [-np.inf]])
-    hi = np.concatenate([lp.hi, [np.inf]])
-    return A, lp.b, c, lo, hi, lp.sense
-
-
-def _box_infeasible():
-    # x1 + x2 = 5 with both in [0, 1]
-    return (sp.csr_matrix(np.array([[1.0, 1.0]])), np.array([5.0]), np.array([1.0, -1.0]), np.zeros(2),
-            np.ones(2), np.zeros(1, dtype=np.int8))
-
-
 @pytest.mark.parametrize("make,highs,want", [
-    (lambda: _conflicting_rows(0), 2, 4), (lambda: _conflicting_rows(1), 2, 4),
-    (lambda: _unbounded_column(0), 3, 5), (lambda: _unbounded_column(1), 3, 5),
-    (_box_infeasible, 2, 4)])
-def test_general_form_against_highs(make, highs, want):
-    A, b, c, lo, hi, sense = make()
-    assert _highs_status(A, b, c, lo, hi, sense) == highs
-    res = _solve(A, b, c, lo=lo, hi=hi, sense=sense)
+    (lambda: lpgen.conflicting_rows(0), 2, 4), (lambda: lpgen.conflicting_rows(1), 2, 4),
+    (lambda: lpgen.unbounded_column(0), 3, 5), (lambda: lpgen.unbounded_column(1), 3, 5),
+    (lpgen.box_infeasible, 2, 4), (lpgen.farkas_tiny, 2, 4), (lpgen.unbounded_tiny, 3, 5)])
+def test_lps_without_optimum_against_highs(make, highs, want):
+    lp = make()
+    assert _highs_status(lp.A, lp.b, lp.c, lp.lo, lp.hi, lp.sense) == highs
+    kw = dict(lo=lp.lo, hi=lp.hi, sense=lp.sense) if lp.general else {}
+    res = _solve(lp.A, lp.b, lp.c, **kw)
     assert res.status == want
 
 
