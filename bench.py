@@ -71,6 +71,8 @@ def parse():
                     help="SpMV shape instead of the autotuner's, e.g. spmv_kind=0,tile_nnz=4096,tile_rows=512,short_row=-1")
     ap.add_argument("--workload", default="power_law", choices=["power_law", "block_angular"],
                     help="LP of the main line (the block-angular leg is skipped when it is the main one)")
+    ap.add_argument("--infeas-tol", type=float, default=None,
+                    help="infeasibility-certificate tolerance of the main-line solves (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only a plain device copy of known size (to calibrate hardware byte counters)")
     return ap.parse_args()
@@ -427,8 +429,10 @@ def main() -> int:
     print(f"# SpMV shape {shape} (autotune {tune_s:.1f}s)", file=sys.stderr, flush=True)
     ws = torch.empty(P.workspace_bytes(dlp, args.precision, **shape), dtype=torch.uint8, device="cuda:0")
 
+    extra = {} if args.infeas_tol is None else {"infeas_tol": args.infeas_tol}
+
     def step():
-        return P.solve(dlp, args.eps, args.precision, workspace=ws, max_iter=200_000, **shape)
+        return P.solve(dlp, args.eps, args.precision, workspace=ws, max_iter=200_000, **shape, **extra)
 
     if args.profile:
         s = P.solve(dlp, 0.0, args.precision, workspace=ws, max_iter=256, **shape)

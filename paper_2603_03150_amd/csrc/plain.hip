@@ -453,9 +453,19 @@ __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TileP
 // ---------------------------------------------------------------------------
 // evaluation on the original model (float64), Section 2 and Section 4.3
 // ---------------------------------------------------------------------------
-// ROWS:  over A's rows, r_p = b - A x; partials: sum r_p^2, sum b.y, -, max |r_p|
+// ROWS:  over A's rows, r_p = b - A x; partials: sum r_p^2, sum b.y, then
+//        the certificate sums below, max |r_p|
 // !ROWS: over A^T's rows, z = max(c - A^T y, 0), r_d = c - A^T y - z;
-//        partials: sum r_d^2, sum c.x, sum x.z, sum of bound terms, max |r_d|
+//        partials: sum r_d^2, sum c.x, sum x.z, sum of bound terms, the
+//        certificate sums, max |r_d|
+// Infeasibility certificates (rays): (d, e) = the change of (x, y) since the
+// previous evaluation, whose A x, A^T y, x and y each kernel keeps per row
+// (read, then overwritten by this evaluation's): A d = A x - (A x)_prev,
+// A^T e = A^T y - (A^T y)_prev.  ROWS sums: (part of A d outside the row's
+// recession cone)^2, b.e, (part of e outside the row's sign cone)^2.
+// !ROWS sums, with g = -A^T e and mu = g projected onto the bound cones:
+// (g - mu)^2, bound terms of mu, c.d, (part of d outside the bounds'
+// recession cone)^2.
 // GEN (general form): a row's r_p is the violating part of b - A x for its
 // sense; z is c - A^T y projected onto the cone the bounds allow, the
 // complementarity term is z^+ (x - l) + z^- (u - x) and the dual objective
@@ -469,19 +479,24 @@ struct EvalArgs {
     const double* own;     // y (ROWS) or x
     double* out1;          // r_p (ROWS) or z
     double* out2;          // r_d (!ROWS)
-    double* partials;      // [G][4] (ROWS) or [G][5]
+    double* partials;      // [G][kEvalRowsW] (ROWS) or [G][kEvalColsW]
     const Ctrl* ctrl;
     const int8_t* sense;   // GEN, ROWS
     const double* lo;      // GEN, !ROWS (nullable)
     const double* hi;      // GEN, !ROWS (nullable)
+    double* prod_prev;     // rays: (A x)_prev (ROWS) or (A^T y)_prev, updated in place
+    double* own_prev;      // rays: y_prev (ROWS) or x_prev, updated in place
+    int32_t rays;          // 1: certificate sums
 };
+constexpr int kEvalRowsW = 6;  // 5 sums + max
+constexpr int kEvalColsW = 9;  // 8 sums + max
 
 template <bool ROWS, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     const bool active = a.ctrl->status == ST_RUNNING;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, tp);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mx[1] = {0.0};
     auto prod = [&](int b, int j) {
         const int64_t k = (int64_t)b + j;
@@ -491,10 +506,27 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
         const double v = a.vec[r];
         if (ROWS) {
             double rp = v - t;
+            const int sn = GEN ? a.sense[r] : MIPDHG_SENSE_EQ;
             if (GEN) {
-                const int sn = a.sense[r];
                 if (sn == MIPDHG_SENSE_GE) rp = rp > 0.0 ? rp : 0.0;
                 else if (sn == MIPDHG_SENSE_LE) rp = rp < 0.0 ? rp : 0.0;
+            }
+            if (a.rays) {
+                const double own = a.own[r];
+                const double td = t - a.prod_prev[r], e = own - a.own_prev[r];
+                double vt = td, ve = 0.0;  // = rows: A d = 0, e free
+                if (sn == MIPDHG_SENSE_GE) {
+                    vt = td < 0.0 ? td : 0.0;
+                    ve = e < 0.0 ? e : 0.0;
+                } else if (sn == MIPDHG_SENSE_LE) {
+                    vt = td > 0.0 ? td : 0.0;
+                    ve = e > 0.0 ? e : 0.0;
+                }
+                s[2] += vt * vt;
+                s[3] += v * e;
+                s[4] += ve * ve;
+                a.prod_prev[r] = t;
+                a.own_prev[r] = own;
             }
             a.out1[r] = rp;
             s[0] += rp * rp;
@@ -503,10 +535,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
         } else {
             const double g = v - t;
             const double x = a.own[r];
+            const double l = GEN && a.lo ? a.lo[r] : 0.0, u = GEN && a.hi ? a.hi[r] : INFINITY;
+            const bool lf = isfinite(l), uf = isfinite(u);
             double z;
             if (GEN) {
-                const double l = a.lo ? a.lo[r] : 0.0, u = a.hi ? a.hi[r] : INFINITY;
-                const bool lf = isfinite(l), uf = isfinite(u);
                 z = (lf && uf) ? g : lf ? (g > 0.0 ? g : 0.0) : uf ? (g < 0.0 ? g : 0.0) : 0.0;
                 const double zp = z > 0.0 ? z : 0.0, zm = z < 0.0 ? -z : 0.0;
                 s[2] += (lf ? zp * (x - l) : 0.0) + (uf ? zm * (u - x) : 0.0);
@@ -514,6 +546,24 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
             } else {
                 z = g > 0.0 ? g : 0.0;
                 s[2] += x * z;
+            }
+            if (a.rays) {
+                const double gr = -(t - a.prod_prev[r]), d = x - a.own_prev[r];
+                double mu, vd;
+                if (GEN) {
+                    mu = (lf && uf) ? gr : lf ? (gr > 0.0 ? gr : 0.0) : uf ? (gr < 0.0 ? gr : 0.0) : 0.0;
+                    vd = (lf && uf) ? d : lf ? (d < 0.0 ? d : 0.0) : uf ? (d > 0.0 ? d : 0.0) : 0.0;
+                    const double mp = mu > 0.0 ? mu : 0.0, mm = mu < 0.0 ? -mu : 0.0;
+                    s[5] += (lf ? l * mp : 0.0) - (uf ? u * mm : 0.0);
+                } else {
+                    mu = gr > 0.0 ? gr : 0.0;
+                    vd = d < 0.0 ? d : 0.0;
+                }
+                s[4] += (gr - mu) * (gr - mu);
+                s[6] += v * d;
+                s[7] += vd * vd;
+                a.prod_prev[r] = t;
+                a.own_prev[r] = x;
             }
             const double rd = g - z;
             a.out1[r] = z;
@@ -527,105 +577,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     tiled_rows<false>(tp, own_tile(), L, prod, le, active);
     if (!active) return;
     if (ROWS) {
-        double s3[3] = {s[0], s[1], s[2]};
-        block_reduce_store<3, 1>(s3, mx, a.partials + 4 * blockIdx.x);
+        double s5[5] = {s[0], s[1], s[2], s[3], s[4]};
+        block_reduce_store<5, 1>(s5, mx, a.partials + kEvalRowsW * blockIdx.x);
     } else {
-        block_reduce_store<4, 1>(s, mx, a.partials + 5 * blockIdx.x);
+        block_reduce_store<8, 1>(s, mx, a.partials + kEvalColsW * blockIdx.x);
     }
-}
-
-// Infeasibility certificates: the change (d, e) = (x - x_prev, y - y_prev)
-// of the evaluated point since the previous evaluation, original model.
-// ROWS:  over A's rows, t = (A d)_i; partials: sum (part of t outside the
-//        row's recession cone)^2, sum b.e, sum (part of e_i outside the row's
-//        sign cone)^2
-// !ROWS: over A^T's rows, g = -(A^T e)_j, mu = g projected onto the cone the
-//        bounds allow; partials: sum (g - mu)^2, sum of bound terms of mu,
-//        sum c.d, sum (part of d_j outside the bounds' recession cone)^2
-// GEN: row senses (ROWS) or bounds (!ROWS) as in the evaluation.
-struct RayArgs {
-    const int32_t* col;
-    const double* val;
-    const double* gv;     // the gathered point (x for ROWS, y)
-    const double* gprev;  // its previous evaluation
-    const double* ov;     // this kernel's own point (y for ROWS, x)
-    const double* oprev;
-    const double* vec;    // b (ROWS) or c
-    double* partials;     // [G][3] (ROWS) or [G][4]
-    const Ctrl* ctrl;
-    const int8_t* sense;
-    const double* lo;
-    const double* hi;
-};
-
-template <bool ROWS, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_ray(RayArgs a, TilePlan tp) {
-    const bool active = a.ctrl->status == ST_RUNNING;
-    extern __shared__ __align__(16) unsigned char smem_t[];
-    const auto L = tile_lds<double>(smem_t, tp);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    double mx[1] = {0.0};
-    auto prod = [&](int b, int j) {
-        const int64_t k = (int64_t)b + j;
-        const int32_t c = ld_idx(a.col, k);
-        return ld_val(a.val, k) * (a.gv[c] - a.gprev[c]);
-    };
-    auto epi = [&](int r, double t) {
-        const double own = a.ov[r] - a.oprev[r];
-        if (ROWS) {
-            double v = t, ve = 0.0;  // = rows: A d = 0, e free
-            if (GEN) {
-                const int sn = a.sense[r];
-                if (sn == MIPDHG_SENSE_GE) {
-                    v = t < 0.0 ? t : 0.0;
-                    ve = own < 0.0 ? own : 0.0;
-                } else if (sn == MIPDHG_SENSE_LE) {
-                    v = t > 0.0 ? t : 0.0;
-                    ve = own > 0.0 ? own : 0.0;
-                }
-            }
-            s[0] += v * v;
-            s[1] += a.vec[r] * own;
-            s[2] += ve * ve;
-        } else {
-            const double g = -t;
-            double mu, vd;
-            if (GEN) {
-                const double l = a.lo ? a.lo[r] : 0.0, u = a.hi ? a.hi[r] : INFINITY;
-                const bool lf = isfinite(l), uf = isfinite(u);
-                mu = (lf && uf) ? g : lf ? (g > 0.0 ? g : 0.0) : uf ? (g < 0.0 ? g : 0.0) : 0.0;
-                vd = (lf && uf) ? own : lf ? (own < 0.0 ? own : 0.0) : uf ? (own > 0.0 ? own : 0.0) : 0.0;
-                const double mp = mu > 0.0 ? mu : 0.0, mm = mu < 0.0 ? -mu : 0.0;
-                s[1] += (lf ? l * mp : 0.0) - (uf ? u * mm : 0.0);
-            } else {
-                mu = g > 0.0 ? g : 0.0;
-                vd = own < 0.0 ? own : 0.0;
-            }
-            s[0] += (g - mu) * (g - mu);
-            s[2] += a.vec[r] * own;
-            s[3] += vd * vd;
-        }
-    };
-    auto le = lepi(epi);
-    tiled_rows<false>(tp, own_tile(), L, prod, le, active);
-    if (!active) return;
-    if (ROWS) {
-        double s3[3] = {s[0], s[1], s[2]};
-        block_reduce_store<3, 0>(s3, mx, a.partials + 3 * blockIdx.x);
-    } else {
-        block_reduce_store<4, 0>(s, mx, a.partials + 4 * blockIdx.x);
-    }
-}
-
-// after a decision that keeps the solve running: the evaluated point becomes
-// the previous one of the next evaluation
-__global__ void k_copy_prev(const Ctrl* c, const double* x, const double* y, double* xp, double* yp, int64_t n,
-                            int64_t m) {
-    if (c->status != ST_RUNNING) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        xp[i] = x[i];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        yp[i] = y[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -635,75 +591,64 @@ struct DecideArgs {
     Ctrl* ctrl;
     const double* pp;  // primal partials [gp][3]
     const double* pd;  // dual partials [gd][3]
-    const double* per; // eval rows [ger][4]
-    const double* pec; // eval cols [gec][5]
-    const double* prr; // certificate rows [ger][3] (when infeas_tol > 0)
-    const double* prc; // certificate cols [gec][4]
+    const double* per; // eval rows [ger][kEvalRowsW]
+    const double* pec; // eval cols [gec][kEvalColsW]
     int32_t gp, gd, ger, gec;
     int32_t nit;
 };
 
-__device__ double fixed_sum(const double* p, int G, int W, int q, double* sh) {
-    double s = 0.0;
-    for (int g = threadIdx.x; g < G; g += kBlock) s += p[(int64_t)g * W + q];
-    sh[threadIdx.x] = s;
+// Every column of a [G][W] array of partials reduced in one pass: column q
+// is summed (or, for q >= NS, maximised) over g = tid, tid + kBlock, ... by
+// each thread, then by the same pairwise tree for every column, so the
+// result does not depend on the launch and is the same for each column as a
+// reduction of that column alone.
+template <int W, int NS>
+__device__ void fixed_cols(const double* p, int G, double (&out)[W], double (*sh)[kBlock]) {
+    double v[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const double x = p[(int64_t)g * W + q];
+            v[q] = q < NS ? v[q] + x : fmax(v[q], x);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < W; ++q) sh[q][threadIdx.x] = v[q];
     __syncthreads();
     for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        if (threadIdx.x < st) {
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                sh[q][threadIdx.x] = q < NS ? sh[q][threadIdx.x] + sh[q][threadIdx.x + st]
+                                            : fmax(sh[q][threadIdx.x], sh[q][threadIdx.x + st]);
+        }
         __syncthreads();
     }
-    const double r = sh[0];
+#pragma unroll
+    for (int q = 0; q < W; ++q) out[q] = sh[q][0];
     __syncthreads();
-    return r;
-}
-
-__device__ double fixed_max(const double* p, int G, int W, int q, double* sh) {
-    double s = 0.0;
-    for (int g = threadIdx.x; g < G; g += kBlock) s = fmax(s, p[(int64_t)g * W + q]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     Ctrl& c = *a.ctrl;
     if (c.status != ST_RUNNING) return;
-    __shared__ double sh[kBlock];
-    const double px_first = fixed_sum(a.pp, a.gp, 3, 0, sh);
-    const double px_eval = fixed_sum(a.pp, a.gp, 3, 1, sh);
-    const double px_anchor = fixed_sum(a.pp, a.gp, 3, 2, sh);
-    const double py_first = fixed_sum(a.pd, a.gd, 3, 0, sh);
-    const double py_eval = fixed_sum(a.pd, a.gd, 3, 1, sh);
-    const double py_anchor = fixed_sum(a.pd, a.gd, 3, 2, sh);
-    const double rp2 = fixed_sum(a.per, a.ger, 4, 0, sh);
-    const double dobj = fixed_sum(a.per, a.ger, 4, 1, sh);
-    const double rp_inf = fixed_max(a.per, a.ger, 4, 3, sh);
-    const double rd2 = fixed_sum(a.pec, a.gec, 5, 0, sh);
-    const double pobj = fixed_sum(a.pec, a.gec, 5, 1, sh);
-    const double xz = fixed_sum(a.pec, a.gec, 5, 2, sh);
-    const double bterm = fixed_sum(a.pec, a.gec, 5, 3, sh);  // 0 in the standard form
-    const double rd_inf = fixed_max(a.pec, a.gec, 5, 4, sh);
-    double q_e = 0.0, r_e2 = 0.0, q_d = 0.0, r_d2 = 0.0;
-    const bool rays = c.infeas_tol > 0.0 && c.have_prev;  // uniform over the workgroup
-    if (rays) {
-        const double ad2 = fixed_sum(a.prr, a.ger, 3, 0, sh);
-        const double be = fixed_sum(a.prr, a.ger, 3, 1, sh);
-        const double ve2 = fixed_sum(a.prr, a.ger, 3, 2, sh);
-        const double gm2 = fixed_sum(a.prc, a.gec, 4, 0, sh);
-        const double bt = fixed_sum(a.prc, a.gec, 4, 1, sh);
-        const double cd = fixed_sum(a.prc, a.gec, 4, 2, sh);
-        const double vd2 = fixed_sum(a.prc, a.gec, 4, 3, sh);
-        q_e = be + bt;
-        r_e2 = gm2 + ve2;
-        q_d = cd;
-        r_d2 = ad2 + vd2;
-    }
+    __shared__ double sh[kEvalColsW][kBlock];
+    double vp[3], vd[3], vr[kEvalRowsW], vc[kEvalColsW];
+    fixed_cols<3, 3>(a.pp, a.gp, vp, sh);
+    fixed_cols<3, 3>(a.pd, a.gd, vd, sh);
+    fixed_cols<kEvalRowsW, kEvalRowsW - 1>(a.per, a.ger, vr, sh);
+    fixed_cols<kEvalColsW, kEvalColsW - 1>(a.pec, a.gec, vc, sh);
+    const double px_first = vp[0], px_eval = vp[1], px_anchor = vp[2];
+    const double py_first = vd[0], py_eval = vd[1], py_anchor = vd[2];
+    const double rp2 = vr[0], dobj = vr[1], rp_inf = vr[kEvalRowsW - 1];
+    const double rd2 = vc[0], pobj = vc[1], xz = vc[2], bterm = vc[3];  // bterm: 0 in the standard form
+    const double rd_inf = vc[kEvalColsW - 1];
+    // certificate quantities (see k_eval)
+    const bool rays = c.infeas_tol > 0.0 && c.have_prev;
+    const double q_e = vr[3] + vc[5], r_e2 = vc[4] + vr[4];
+    const double q_d = vc[6], r_d2 = vr[2] + vc[7];
     if (threadIdx.x != 0) return;
 
     const double om = c.omega;
@@ -741,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
         c.restart_now = 0;
         return;
     }
-    c.have_prev = 1;  // k_copy_prev keeps this evaluation's point
+    c.have_prev = 1;  // the evaluation kernels have kept this evaluation's point
     bool restart = false;
     if (c.do_restarts) {
         restart = (R <= c.beta_suff * c.R0) || (R <= c.beta_nec * c.R0 && R > c.R_prev) ||
@@ -1000,7 +945,7 @@ struct PlainWs {
     uint16_t *slot_a, *slot_at; // sorted layout: row-major position in the tile
     void *lo_t, *hi_t;          // general form: scaled bounds l / D_c, u / D_c
     double *xprev, *yprev;      // infeasibility certificates: previous evaluated point
-    double *prr, *prc;          // their partial sums [G][3], [G][4]
+    double *axprev, *atyprev;   // and its A x, A^T y
     size_t bytes;
 };
 
@@ -1023,12 +968,12 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.red = cv.take<double>(16);
     w.pp = cv.take<double>((size_t)w.gcap * 3);
     w.pd = cv.take<double>((size_t)w.gcap * 3);
-    w.per = cv.take<double>((size_t)w.gcap * 4);
-    w.pec = cv.take<double>((size_t)w.gcap * 5);
-    w.prr = cv.take<double>((size_t)w.gcap * 3);
-    w.prc = cv.take<double>((size_t)w.gcap * 4);
+    w.per = cv.take<double>((size_t)w.gcap * kEvalRowsW);
+    w.pec = cv.take<double>((size_t)w.gcap * kEvalColsW);
     w.xprev = cv.take<double>(n);
     w.yprev = cv.take<double>(m);
+    w.axprev = cv.take<double>(m);
+    w.atyprev = cv.take<double>(n);
     w.psetup = cv.take<double>((size_t)w.gcap * 4);
     w.a_vs = cv.take<char>(nnz * vs);
     w.at_vs = cv.take<char>(nnz * vs);
@@ -1168,8 +1113,6 @@ struct Solver {
             const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true),
                                 (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
-                                (const void*)k_ray<true, false>, (const void*)k_ray<false, false>,
-                                (const void*)k_ray<true, true>, (const void*)k_ray<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
                                 (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
 #undef MIP_ITER_KERNELS
@@ -1324,6 +1267,9 @@ struct Solver {
         er.ctrl = w.ctrl;
         er.sense = lp.sense;
         er.lo = er.hi = nullptr;
+        er.prod_prev = w.axprev;
+        er.own_prev = w.yprev;
+        er.rays = o.infeas_tol > 0.0;
         if (gen_dual())
             hipLaunchKernelGGL((k_eval<true, true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, er,
                                ta);
@@ -1344,6 +1290,9 @@ struct Solver {
         ec.sense = nullptr;
         ec.lo = lp.lo;
         ec.hi = lp.hi;
+        ec.prod_prev = w.atyprev;
+        ec.own_prev = w.xprev;
+        ec.rays = o.infeas_tol > 0.0;
         if (gen_primal())
             hipLaunchKernelGGL((k_eval<false, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream,
                                ec, tat);
@@ -1351,23 +1300,6 @@ struct Solver {
             hipLaunchKernelGGL((k_eval<false, false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
                                stream, ec, tat);
         MIP_LAUNCH_CHECK();
-        if (o.infeas_tol > 0.0) {
-            RayArgs rr{lp.a_col, lp.a_val, xo, w.xprev, yo, w.yprev, lp.b, w.prr, w.ctrl, lp.sense, nullptr, nullptr};
-            RayArgs rc{lp.at_col, lp.at_val, yo, w.yprev, xo, w.xprev, lp.c, w.prc, w.ctrl, nullptr, lp.lo, lp.hi};
-            if (gen_dual())
-                hipLaunchKernelGGL((k_ray<true, true>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream,
-                                   rr, ta);
-            else
-                hipLaunchKernelGGL((k_ray<true, false>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream,
-                                   rr, ta);
-            if (gen_primal())
-                hipLaunchKernelGGL((k_ray<false, true>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
-                                   stream, rc, tat);
-            else
-                hipLaunchKernelGGL((k_ray<false, false>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8),
-                                   stream, rc, tat);
-            MIP_LAUNCH_CHECK();
-        }
         return launch_decide(nit);
     }
     // decision and restart copy for a block of nit iterations whose
@@ -1379,8 +1311,6 @@ struct Solver {
         d.pd = w.pd;
         d.per = w.per;
         d.pec = w.pec;
-        d.prr = w.prr;
-        d.prc = w.prc;
         d.gp = grid_primal();
         d.gd = grid_dual();
         d.ger = ta.ntiles;
@@ -1393,11 +1323,6 @@ struct Solver {
                            (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, (const T*)w.xhat, (int64_t)lp.n,
                            (T*)w.y, (T*)w.y0, (const T*)w.yhat, (int64_t)lp.m);
         MIP_LAUNCH_CHECK();
-        if (o.infeas_tol > 0.0) {
-            hipLaunchKernelGGL(k_copy_prev, dim3(grid_for(mx)), dim3(kBlock), 0, stream, (const Ctrl*)w.ctrl,
-                               (const double*)xo, (const double*)yo, w.xprev, w.yprev, (int64_t)lp.n, (int64_t)lp.m);
-            MIP_LAUNCH_CHECK();
-        }
         return 0;
     }
     // One block of nit iterations ending in an evaluation.  With trace, the
@@ -1708,6 +1633,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         MIP_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.xprev, n, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.yprev, m, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.atyprev, n, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.axprev, m, 0.0);
         MIP_LAUNCH_CHECK();
     }
     MIP_HIP(hipStreamSynchronize(stream));
