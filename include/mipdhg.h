@@ -187,6 +187,12 @@ typedef struct mipdhg_options {
      * run may drift until it overflows (NUMERICAL).
      * Single-LP solve only (the batched and unrolled solves ignore it). [1e-8] */
     double infeas_tol;
+    /* Primal weight as a PID controller on e = log(omega) - log(dy/dx) at
+     * each update: omega <- exp(log(omega) - (pw_theta e + pw_ki I +
+     * pw_kd (e - e_prev))), I the sum of the errors so far (this one
+     * included), e_prev the previous update's error (0 at the first).  Both
+     * 0: the smoothing rule of pw_theta alone.                      [0, 0] */
+    double pw_ki, pw_kd;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */

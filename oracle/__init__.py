@@ -17,4 +17,5 @@ from .pdhg import (  # noqa: F401
     initial_weight, pdhg_operator, evaluate, terminated, restart_due, solve,
     unrolled_forward, unrolled_grad, unrolled_tangent, Schedule, STATUS,
     SENSE_EQ, SENSE_GE, SENSE_LE, validate_general, reduced_costs, ray_measures, infeasibility,
+    primal_weight_update,
 )

@@ -59,6 +59,13 @@ A d outside the rows' recession cones together with the part of d outside
 the bounds' recession cones is at most infeas_tol |c^T d|.  Pinned by
 scipy's HiGHS classifying the same LPs as infeasible or unbounded.
 
+Primal weight as a PID controller (a variant, off by default): at an
+update, with the error e = log(omega) - log(dy/dx), omega becomes
+exp(log(omega) - (theta e + ki I + kd (e - e_prev))), I the sum of the errors
+of all updates so far including e, e_prev the previous update's error (0 at
+the first).  ki = kd = 0 is the smoothing rule above, which is then computed
+in its own form.
+
 parity unpinned: the restart and primal-weight heuristics (which iterations
 restart, the omega sequence, iteration counts to a tolerance) follow a reading
 with no external reference; only GPU-versus-oracle agreement checks them.
@@ -92,6 +99,8 @@ class OracleOptions:
     pw_theta: float = 0.5
     max_iter: int = 1_000_000
     infeas_tol: float = 1e-8  # 0 turns the certificate tests off
+    pw_ki: float = 0.0        # primal weight as a PID controller: integral gain
+    pw_kd: float = 0.0        # and derivative gain (pw_theta is the proportional one)
 
 
 @dataclass
@@ -366,6 +375,21 @@ def terminated(meas: Measures, b_norm: float, c_norm: float, eps: float) -> bool
             and meas.gap <= eps * (1.0 + abs(meas.pobj) + abs(meas.dobj)))
 
 
+def primal_weight_update(omega: float, dx: float, dy: float, pid: list, opts: OracleOptions) -> float:
+    """The primal weight after a restart whose distances to the epoch's anchor
+    are dx, dy (both > 1e-10); pid = [integral, previous error, count] is
+    updated in place."""
+    th = opts.pw_theta
+    if opts.pw_ki == 0.0 and opts.pw_kd == 0.0:
+        return math.exp(th * math.log(dy / dx) + (1.0 - th) * math.log(omega))
+    e = math.log(omega) - math.log(dy / dx)
+    pid[0] += e
+    de = e - pid[1] if pid[2] > 0 else 0.0
+    pid[1] = e
+    pid[2] += 1
+    return math.exp(math.log(omega) - (th * e + opts.pw_ki * pid[0] + opts.pw_kd * de))
+
+
 def restart_due(R: float, R0: float, R_prev: float, k: int, t: int, opts: OracleOptions) -> bool:
     """Sufficient decay, necessary decay without progress, or an epoch that
     has grown past a fixed share of all iterations (k counts this iteration)."""
@@ -425,6 +449,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     trace = {}
     E = max(1, int(opts.eval_every))
     prev = None  # the previous evaluated point (x, y), original space
+    pid = [0.0, 0.0, 0]  # primal-weight controller state
 
     while True:
         t += 1
@@ -459,8 +484,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                 dx = float(np.linalg.norm(x_hat - x0))
                 dy = float(np.linalg.norm(y_hat - y0))
                 if dx > 1e-10 and dy > 1e-10:
-                    th = opts.pw_theta
-                    omega = math.exp(th * math.log(dy / dx) + (1.0 - th) * math.log(omega))
+                    omega = primal_weight_update(omega, dx, dy, pid, opts)
                     tau, sig = eta / omega, eta * omega
                 x_new, y_new = x_hat.copy(), y_hat.copy()
                 x0, y0 = x_hat.copy(), y_hat.copy()

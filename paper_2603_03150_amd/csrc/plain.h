@@ -32,8 +32,10 @@ struct Ctrl {
     int32_t last_nit, resumable;
     uint64_t fingerprint;
     // infeasibility certificates: whether a previous evaluated point is kept
-    int32_t have_prev, pad_;
+    int32_t have_prev, pw_count;
     double infeas_tol;
+    // primal weight as a PID controller: gains, integral, previous error
+    double pw_ki, pw_kd, pw_int, pw_err;
 };
 
 // shared host helpers (plain.hip, validate.hip)

@@ -696,7 +696,16 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
         const double dx = sqrt(px_anchor), dy = sqrt(py_anchor);
         if (dx > 1e-10 && dy > 1e-10) {
             const double th = c.pw_theta;
-            c.omega = exp(th * log(dy / dx) + (1.0 - th) * log(c.omega));
+            if (c.pw_ki == 0.0 && c.pw_kd == 0.0) {
+                c.omega = exp(th * log(dy / dx) + (1.0 - th) * log(c.omega));
+            } else {
+                const double e = log(c.omega) - log(dy / dx);
+                c.pw_int += e;
+                const double de = c.pw_count > 0 ? e - c.pw_err : 0.0;
+                c.pw_err = e;
+                c.pw_count += 1;
+                c.omega = exp(log(c.omega) - (th * e + c.pw_ki * c.pw_int + c.pw_kd * de));
+            }
             c.tau = c.eta / c.omega;
             c.sigma = c.eta * c.omega;
         }
@@ -905,7 +914,8 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
                             o.gather_order, o.lanes_a, o.lanes_at, o.long_row};
     mix(iv, sizeof(iv));
-    const double dv[7] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, 0.0};
+    const double dv[8] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
+                          o.pw_kd};
     mix(dv, sizeof(dv));
     return h;
 }
@@ -1011,6 +1021,8 @@ int check_options(const mipdhg_options* o) {
         return set_error("step_safety > 0 and reflect_rho in [0,1] required"), MIPDHG_ERR_INVALID_ARG;
     if (o->max_iter < 1) return set_error("max_iter must be >= 1"), MIPDHG_ERR_INVALID_ARG;
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
+    if (!std::isfinite(o->pw_ki) || !std::isfinite(o->pw_kd))
+        return set_error("pw_ki and pw_kd must be finite"), MIPDHG_ERR_INVALID_ARG;
     if (o->spmv_kind < 0 || o->spmv_kind > 2) return set_error("spmv_kind must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
     if (o->gather_order < 0 || o->gather_order > 1) return set_error("gather_order must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (o->kernel_timing < 0 || o->kernel_timing > 2)
@@ -1618,6 +1630,11 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     c0.beta_nec = o.beta_nec;
     c0.beta_art = o.beta_art;
     c0.pw_theta = o.pw_theta;
+    c0.pw_ki = o.pw_ki;
+    c0.pw_kd = o.pw_kd;
+    c0.pw_int = 0.0;
+    c0.pw_err = 0.0;
+    c0.pw_count = 0;
     c0.max_iter = o.max_iter;
     c0.do_restarts = o.restarts;
     c0.resumable = 1;

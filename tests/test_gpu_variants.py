@@ -1,0 +1,55 @@
+"""GPU parity of the method variants against the oracle: the PID primal
+weight (per-iterate FP64 parity across restarts, full-solve iteration and
+restart counts), and its refusal by the batched and unrolled solves."""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from oracle.pdhg import OracleOptions
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_03150_amd")
+torch = pytest.importorskip("torch")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b)) / max(1.0, float(np.linalg.norm(b)))
+
+
+@pytest.mark.parametrize("ki,kd", [(0.1, 0.3), (0.02, 0.0)])
+def test_pid_trace_parity(ki, kd):
+    lp = lpgen.cfg2_sub(0, 100)
+    T = 320
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-12, "fp64", trace_iters=T, max_iter=T, eval_every=16, pw_ki=ki,
+                  pw_kd=kd)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, opts=OracleOptions(max_iter=T, eval_every=16, pw_ki=ki,
+                                                                           pw_kd=kd), trace_iters=T)
+    assert ref.restarts >= 3 and sol.info["restarts"] == ref.restarts
+    assert abs(sol.info["omega"] - ref.omega) <= 1e-9 * ref.omega
+    for t in range(1, T + 1):
+        xs, ys, xh, yh = ref.trace[t]
+        for key, r in (("x", xs), ("y", ys), ("xhat", xh), ("yhat", yh)):
+            assert _rel(_np(sol.trace[key][t - 1]), r) <= 1e-9, (t, key)
+
+
+def test_pid_full_solve_matches_oracle():
+    lp = lpgen.cfg1(0)
+    kw = dict(pw_ki=0.1, pw_kd=0.2)
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-8, "fp64", **kw)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-8, opts=OracleOptions(**kw))
+    assert sol.status == ref.status == 0
+    assert sol.info["iters"] == ref.iters and sol.info["restarts"] == ref.restarts
+    assert _rel(_np(sol.x), ref.meas.x) <= 1e-8
+
+
+def test_pid_is_a_single_lp_option():
+    batch = P.DeviceBatch.from_lps([lpgen.tiny(6, 15, 3, 0)])
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp32", pw_ki=0.1)
+    assert e.value.code == -6
