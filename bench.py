@@ -126,15 +126,19 @@ def kernel_source_sha() -> str:
 def traffic_record(workload_key: str, kernel: str, shape: dict):
     """Measured HBM bytes per launch of `kernel` on `workload_key`, from the
     committed counter summary (profiles/traffic_<workload_key>.json), or None
-    if there is none, or the kernel sources or the SpMV shape differ from the
-    ones it was taken with."""
+    if there is none, or the kernel sources or the kernel's side of the SpMV
+    shape differ from the ones it was taken with."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_key}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    # the kernel's own side of the shape: A's tiles for the dual, A^T's for the primal
+    side = ("spmv_kind", "tile_nnz_at", "tile_rows_at", "short_row_at") if kernel.endswith("<primal>") else \
+        ("spmv_kind", "tile_nnz", "tile_rows", "short_row")
+    stored = rec.get("spmv_shape", {})
     if (rec.get("source_sha256") != kernel_source_sha() or kernel not in rec.get("kernels", {})
-            or rec.get("spmv_shape") != shape):
+            or any(stored.get(k) != shape.get(k) for k in side)):
         return None
     return rec["kernels"][kernel]
 
@@ -144,7 +148,8 @@ def tuned_shape(P, dlp, precision: str) -> tuple[dict, float]:
     matrix, outside the timed region)."""
     t0 = time.perf_counter()
     best = P.autotune(dlp, precision, iters=64)
-    return {k: best[k] for k in ("spmv_kind", "tile_nnz", "tile_rows", "short_row")}, time.perf_counter() - t0
+    keys = ("spmv_kind", "tile_nnz", "tile_rows", "short_row", "tile_nnz_at", "tile_rows_at", "short_row_at")
+    return {k: best[k] for k in keys}, time.perf_counter() - t0
 
 
 def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str, shape: dict) -> dict:

@@ -193,6 +193,10 @@ typedef struct mipdhg_options {
      * included), e_prev the previous update's error (0 at the first).  Both
      * 0: the smoothing rule of pw_theta alone.                      [0, 0] */
     double pw_ki, pw_kd;
+    /* LDS tiles of A^T (the primal SpMV and the column-side evaluation) when
+     * they should differ from A's: 0 = the value of tile_nnz, tile_rows,
+     * short_row.  mipdhg_autotune picks both sides.              [0, 0, 0] */
+    int32_t tile_nnz_at, tile_rows_at, short_row_at;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */
@@ -336,11 +340,16 @@ int mipdhg_center_reclamp(int32_t n, double alpha_min, void *stream, double *x_i
 size_t mipdhg_sizeof(int which);
 
 /* Times every candidate shape of the two iteration SpMVs on this LP (lane
- * groups; LDS tiles of 512..4096 nonzeros, 256 or 512 rows, short-row limit
- * 32 or 128) for `iters` iterations each, with per-kernel hipEvents, and
- * writes the fastest into opt (spmv_kind, tile_nnz, tile_rows, short_row).
- * best_ms (host, nullable) receives its mean primal + dual time per
- * iteration.  Arguments as for mipdhg_solve, whose output buffers are used as
+ * groups; LDS tiles of 1024..8192 nonzeros, 256 or 512 rows, chunked or
+ * short-row-32 sums, one workgroup per tile or persistent) for `iters`
+ * iterations each, with per-kernel hipEvents.  For each spmv_kind it takes
+ * the fastest shape of the dual kernel (A's tiles) and of the primal kernel
+ * (A^T's tiles) separately, and writes the kind with the smallest sum into
+ * opt (spmv_kind, tile_nnz, tile_rows, short_row for A, the *_at fields for
+ * A^T).  A side keeps the default shape (2,048 nonzeros, 512 rows, chunked
+ * sums) unless another is more than 3 % faster, so that the choice does not
+ * flip with timing noise.  best_ms (host, nullable) receives that primal +
+ * dual time per iteration.  Arguments as for mipdhg_solve, whose output buffers are used as
  * scratch; the workspace must be large enough for the smallest tiles, i.e. at
  * least mipdhg_workspace_size() of opt with tile_nnz = 512, tile_rows = 256.
  * Candidates that do not fit are skipped. */

@@ -50,6 +50,9 @@ int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat
 int32_t tile_nnz_of(const mipdhg_options& o);
 int32_t tile_rows_of(const mipdhg_options& o);
 int32_t short_row_of(const mipdhg_options& o);
+int32_t tile_nnz_at_of(const mipdhg_options& o);   // A^T's tiles (default: A's)
+int32_t tile_rows_at_of(const mipdhg_options& o);
+int32_t short_row_at_of(const mipdhg_options& o);
 inline bool has_bounds(const mipdhg_lp& lp) { return lp.lo || lp.hi; }  // general form, columns
 inline bool has_sense(const mipdhg_lp& lp) { return lp.sense != nullptr; } // general form, rows
 inline bool is_general(const mipdhg_lp& lp) { return has_bounds(lp) || has_sense(lp); }

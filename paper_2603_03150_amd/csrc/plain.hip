@@ -900,6 +900,9 @@ bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& 
 int32_t tile_nnz_of(const mipdhg_options& o) { return o.tile_nnz > 0 ? o.tile_nnz : kTileNnzDefault; }
 int32_t tile_rows_of(const mipdhg_options& o) { return o.tile_rows > 0 ? o.tile_rows : kTileRowsDefault; }
 int32_t short_row_of(const mipdhg_options& o) { return o.short_row != 0 ? o.short_row : kShortRowDefault; }
+int32_t tile_nnz_at_of(const mipdhg_options& o) { return o.tile_nnz_at > 0 ? o.tile_nnz_at : tile_nnz_of(o); }
+int32_t tile_rows_at_of(const mipdhg_options& o) { return o.tile_rows_at > 0 ? o.tile_rows_at : tile_rows_of(o); }
+int32_t short_row_at_of(const mipdhg_options& o) { return o.short_row_at != 0 ? o.short_row_at : short_row_of(o); }
 // What a resumed solve must share with the solve whose state it continues:
 // the problem's sizes and every option that shapes the state or its layout.
 uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
@@ -910,9 +913,10 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
     };
     const int64_t sz[4] = {lp.m, lp.n, lp.nnz, (has_bounds(lp) ? 1 : 0) | (has_sense(lp) ? 2 : 0)};
     mix(sz, sizeof(sz));
-    const int32_t iv[15] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
+    const int32_t iv[18] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
-                            o.gather_order, o.lanes_a, o.lanes_at, o.long_row};
+                            o.gather_order, o.lanes_a, o.lanes_at, o.long_row, tile_nnz_at_of(o),
+                            tile_rows_at_of(o), short_row_at_of(o)};
     mix(iv, sizeof(iv));
     const double dv[8] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
                           o.pw_kd};
@@ -960,12 +964,13 @@ struct PlainWs {
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
-                     int64_t tnz, int64_t trows, bool sorted, bool bounds) {
+                     int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
     const size_t ts = (prec == MIPDHG_FP64 || prec == MIPDHG_FP32_A) ? 8 : 4;
-    w.gcap = std::max<int64_t>(kMaxRowBlocks, std::max(max_tiles(m, nnz, tnz, trows), max_tiles(n, nnz, tnz, trows)));
+    w.gcap = std::max<int64_t>(kMaxRowBlocks,
+                               std::max(max_tiles(m, nnz, tnz, trows), max_tiles(n, nnz, tnz_t, trows_t)));
     w.ctrl = cv.take<Ctrl>(1);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
@@ -999,7 +1004,7 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.long_a = cv.take<int32_t>(m);
     w.long_at = cv.take<int32_t>(n);
     w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, tnz, trows));
-    w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, tnz, trows));
+    w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, tnz_t, trows_t));
     w.flags = cv.take<int32_t>(64);
     w.col_a = sorted ? cv.take<int32_t>(nnz) : nullptr;
     w.col_at = sorted ? cv.take<int32_t>(nnz) : nullptr;
@@ -1038,6 +1043,11 @@ int check_options(const mipdhg_options* o) {
     if (o->tile_rows < 0 || o->tile_rows > kMaxTileRows)
         return set_error("tile_rows must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
     if (o->short_row < -1) return set_error("short_row must be >= -1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->tile_nnz_at != 0 && (o->tile_nnz_at < 256 || o->tile_nnz_at > kMaxTileNnz))
+        return set_error("tile_nnz_at must be 0 or in [256, %d]", kMaxTileNnz), MIPDHG_ERR_INVALID_ARG;
+    if (o->tile_rows_at < 0 || o->tile_rows_at > kMaxTileRows)
+        return set_error("tile_rows_at must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
+    if (o->short_row_at < -1) return set_error("short_row_at must be >= -1"), MIPDHG_ERR_INVALID_ARG;
     for (int L : {o->lanes_a, o->lanes_at})
         if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
             return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
@@ -1076,7 +1086,8 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if (rc) return rc;
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
-                   tile_rows_of(*opt), sorted_layout(*opt, lp->m, lp->n), has_bounds(*lp)).bytes;
+                   tile_rows_of(*opt), tile_nnz_at_of(*opt), tile_rows_at_of(*opt), sorted_layout(*opt, lp->m, lp->n),
+                   has_bounds(*lp)).bytes;
     return 0;
 }
 
@@ -1392,7 +1403,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const auto t0 = clk::now();
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
-                sorted_layout(o, lp.m, lp.n), has_bounds(lp));
+                tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp));
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1440,14 +1451,15 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const int ga = S.hpa.grid(), gat = S.hpat.grid();
     {
         const int32_t tnz = tile_nnz_of(o), trows = tile_rows_of(o), srow = short_row_of(o);
+        const int32_t tnz_t = tile_nnz_at_of(o), trows_t = tile_rows_at_of(o), srow_t = short_row_at_of(o);
         const std::vector<int32_t> ta = make_tile_desc(rpa, lp.m, tnz, trows),
-                                   tat = make_tile_desc(rpat, lp.n, tnz, trows);
-        if (!tile_desc_ok(ta, rpa, lp.m, tnz, trows) || !tile_desc_ok(tat, rpat, lp.n, tnz, trows))
+                                   tat = make_tile_desc(rpat, lp.n, tnz_t, trows_t);
+        if (!tile_desc_ok(ta, rpa, lp.m, tnz, trows) || !tile_desc_ok(tat, rpat, lp.n, tnz_t, trows_t))
             return set_error("internal: tile plan does not cover the rows"), MIPDHG_ERR_UNSUPPORTED;
         MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
         S.ta = make_tile_plan(lp.a_rowptr, w.tiles_a, (int32_t)(ta.size() / 4), lp.m, tnz, trows, srow);
-        S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n, tnz, trows, srow);
+        S.tat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n, tnz_t, trows_t, srow_t);
         if ((rc = S.allow_tile_lds())) return rc;
         if ((rc = S.plan_persistent())) return rc;
         MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope

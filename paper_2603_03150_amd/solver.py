@@ -122,6 +122,7 @@ def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -
                              torch.cuda.current_stream(d).cuda_stream, *[b.data_ptr() for b in bufs], C.byref(best))
     _lib.check(rc)
     return {"spmv_kind": o.spmv_kind, "tile_nnz": o.tile_nnz, "tile_rows": o.tile_rows, "short_row": o.short_row,
+            "tile_nnz_at": o.tile_nnz_at, "tile_rows_at": o.tile_rows_at, "short_row_at": o.short_row_at,
             "ms_per_iter": best.value}
 
 

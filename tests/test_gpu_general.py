@@ -179,7 +179,7 @@ def test_autotune_on_a_general_lp_picks_a_tile_shape():
     dlp = P.DeviceLP.from_lp(lp)
     best = P.autotune(dlp, "fp32", iters=32)
     assert best["spmv_kind"] in (0, 2) and best["ms_per_iter"] > 0
-    shape = {k: best[k] for k in ("spmv_kind", "tile_nnz", "tile_rows", "short_row")}
+    shape = {k: v for k, v in best.items() if k != "ms_per_iter"}
     a = P.solve(dlp, 1e-4, "fp32", **shape)
     b = P.solve(dlp, 1e-4, "fp32")
     assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]

@@ -361,11 +361,30 @@ def test_autotune_picks_a_valid_shape_with_identical_results():
     dlp = P.DeviceLP.from_lp(lp)
     best = P.autotune(dlp, "fp64", iters=64)
     assert best["ms_per_iter"] > 0
-    shape = {k: best[k] for k in ("spmv_kind", "tile_nnz", "tile_rows", "short_row")}
+    shape = {k: v for k, v in best.items() if k != "ms_per_iter"}
     a = P.solve(dlp, 1e-6, "fp64", **shape)
     b = P.solve(dlp, 1e-6, "fp64")
     assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]
     assert _rel(_np(a.x), _np(b.x)) <= 1e-9
+
+
+@pytest.mark.parametrize("spmv_kind", [0, 2])
+def test_trace_parity_different_tiles_for_a_and_at(spmv_kind):
+    # A's tiles (dual, row-side evaluation) and A^T's (primal, column side) of different shapes
+    lp = lpgen.cfg2_sub(2, scale=100)
+    dlp = P.DeviceLP.from_lp(lp)
+    T = 100
+    sol = P.solve(dlp, 1e-12, "fp64", trace_iters=T, max_iter=T, spmv_kind=spmv_kind, tile_nnz=8192,
+                  tile_rows=512, short_row=32, tile_nnz_at=512, tile_rows_at=64, short_row_at=-1)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, opts=_oracle_opts(max_iter=T), trace_iters=T)
+    for t in range(1, T + 1):
+        xs, ys, xh, yh = ref.trace[t]
+        for key, r in (("x", xs), ("y", ys), ("xhat", xh), ("yhat", yh)):
+            assert _rel(_np(sol.trace[key][t - 1]), r) <= 1e-10, (t, key)
+    full = P.solve(dlp, 1e-8, "fp64", spmv_kind=spmv_kind, tile_nnz=8192, tile_rows=512, short_row=32,
+                   tile_nnz_at=512, tile_rows_at=64, short_row_at=-1)
+    refs = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-8)
+    assert full.status == refs.status == 0 and full.info["iters"] == refs.iters
 
 
 @pytest.mark.parametrize("spmv_kind", [0, 2])
