@@ -6,7 +6,9 @@ iterate after iteration 1 (exported by the trace) is fed to the oracle's step
 (its own float64 scaling of the caller's matrix, the step sizes the GPU
 reports), and a random sample of the entries of iteration 2 — x_hat and the
 Halpern state on sampled columns, y_hat on sampled rows — is compared.
-FP64 to 1e-10, float32 iterates (float32 matrix values) to 1e-5.
+FP64 to 1e-10, float32 iterates (float32 matrix values) to 1e-5.  The
+general-form LP of the benchmark is checked the same way with its bound and
+sign projections.
 """
 import numpy as np
 import pytest
@@ -20,8 +22,11 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2603_03150_amd")
 torch = pytest.importorskip("torch")
 
-SHAPES = {"power_law": dict(spmv_kind=0, tile_nnz=2048, tile_rows=256, short_row=-1),
-          "block_angular": dict(spmv_kind=0, tile_nnz=4096, tile_rows=512, short_row=32)}
+# the shapes the autotuner picks for these LPs (A's tiles, then A^T's)
+SHAPES = {"power_law": dict(spmv_kind=0, tile_nnz=2048, tile_rows=512, short_row=-1, tile_nnz_at=2048,
+                            tile_rows_at=256, short_row_at=32),
+          "block_angular": dict(spmv_kind=0, tile_nnz=8192, tile_rows=512, short_row=32, tile_nnz_at=4096,
+                                tile_rows_at=512, short_row_at=32)}
 
 
 def _np(t):
@@ -46,7 +51,19 @@ def _one_step_check(lp, prec, shape, tol, samples=3000, seed=0):
     rng = np.random.default_rng(seed)
     # x_hat and the state on sampled columns (k = 1: Halpern weight 2/3, anchor 0)
     J = rng.choice(lp.n, size=min(samples, lp.n), replace=False)
-    xh = np.maximum(x1[J] - tau * (ct[J] - AtT[J] @ y1), 0.0)
+    lo_t = np.zeros(lp.n) if lp.lo is None else lp.lo / d_col
+    hi_t = np.full(lp.n, np.inf) if lp.hi is None else lp.hi / d_col
+
+    def proj_x(v, idx):
+        return np.minimum(np.maximum(v, lo_t[idx]), hi_t[idx])
+
+    def proj_y(v, idx):
+        if lp.sense is None:
+            return v
+        s_ = lp.sense[idx]
+        return np.where(s_ == 1, np.maximum(v, 0.0), np.where(s_ == 2, np.minimum(v, 0.0), v))
+
+    xh = proj_x(x1[J] - tau * (ct[J] - AtT[J] @ y1), J)
     assert _rel(tr["xhat"][1][J], xh) <= tol
     w = 2.0 / 3.0
     assert _rel(tr["x"][1][J], w * (2.0 * xh - x1[J])) <= tol
@@ -54,10 +71,10 @@ def _one_step_check(lp, prec, shape, tol, samples=3000, seed=0):
     I = rng.choice(lp.m, size=min(samples, lp.m), replace=False)
     rows = At[I]
     cols = np.unique(rows.indices)
-    xh_c = np.maximum(x1[cols] - tau * (ct[cols] - AtT[cols] @ y1), 0.0)
+    xh_c = proj_x(x1[cols] - tau * (ct[cols] - AtT[cols] @ y1), cols)
     xbar = np.zeros(lp.n)
     xbar[cols] = 2.0 * xh_c - x1[cols]
-    yh = y1[I] + sig * (bt[I] - rows @ xbar)
+    yh = proj_y(y1[I] + sig * (bt[I] - rows @ xbar), I)
     assert _rel(tr["yhat"][1][I], yh) <= tol
 
 
@@ -69,3 +86,9 @@ def test_one_step_parity_full_power_law(prec, tol):
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_one_step_parity_full_block_angular(prec, tol):
     _one_step_check(lpgen.cfg3(0), prec, SHAPES["block_angular"], tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_one_step_parity_full_general_power_law(prec, tol):
+    # the general-form leg of the benchmark: bounds and row senses on the power-law shape
+    _one_step_check(lpgen.general_cfg2(0), prec, SHAPES["power_law"], tol)
