@@ -341,7 +341,9 @@ size_t mipdhg_sizeof(int which);
 
 /* Times every candidate shape of the two iteration SpMVs on this LP (lane
  * groups; LDS tiles of 1024..8192 nonzeros, 256 or 512 rows, chunked or
- * short-row-32 sums, one workgroup per tile or persistent) for `iters`
+ * short-row-32 sums, one workgroup per tile or persistent; and tiles sized
+ * so that their count is 4..8 per compute unit, from the row pointers) for
+ * `iters`
  * iterations each, with per-kernel hipEvents.  For each spmv_kind it takes
  * the fastest shape of the dual kernel (A's tiles) and of the primal kernel
  * (A^T's tiles) separately, and writes the kind with the smallest sum into

@@ -10,12 +10,14 @@
 
 namespace mip {
 void set_error(const char* fmt, ...);
+int64_t tile_count(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz, int32_t tile_rows);
 }
 
 namespace {
 
+// A candidate: the shape of A's tiles (dual) and of A^T's (primal).
 struct Cand {
-    int32_t kind, tile_nnz, tile_rows, short_row;
+    int32_t kind, tile_nnz, tile_rows, short_row, tile_nnz_at, tile_rows_at, short_row_at;
 };
 
 // the library's default tile shape, and how much faster (ratio) another
@@ -25,12 +27,47 @@ constexpr double kMargin = 1.03;
 
 std::vector<Cand> candidates() {
     std::vector<Cand> c;
-    c.push_back({1, 0, 0, 0});  // lane groups with the planner's lane counts
+    c.push_back({1, 0, 0, 0, 0, 0, 0});  // lane groups with the planner's lane counts
     for (int kind : {0, 2})
         for (int tn : {1024, 2048, 4096, 8192})
             for (int tr : {256, 512})
-                for (int sr : {-1, 32}) c.push_back({kind, tn, tr, sr});
+                for (int sr : {-1, 32}) c.push_back({kind, tn, tr, sr, tn, tr, sr});
     return c;
+}
+
+// The smallest tile size up to 2,048 nonzeros (8 products per thread) whose
+// greedy cut gives at most `target` tiles of at most 512 rows (so the count
+// is as close to the target as the cut allows), or 0 if none does.
+int32_t balanced_nnz(const std::vector<int32_t>& rp, int32_t nrows, int64_t target) {
+    int32_t lo = 256, hi = 2048;
+    if (mip::tile_count(rp, nrows, hi, 512) > target) return 0;
+    while (lo < hi) {  // the count does not grow with the tile size
+        const int32_t mid = (lo + hi) / 2;
+        if (mip::tile_count(rp, nrows, mid, 512) <= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Tiles sized so that their count is a whole number k of workgroups per CU
+// (k = 4..8): every CU then gets the same number of tiles of one wave.
+void balanced_candidates(const mipdhg_lp* lp, hipStream_t s, std::vector<Cand>& out) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return;
+    std::vector<int32_t> ra(lp->m + 1), rat(lp->n + 1);
+    if (hipMemcpyAsync(ra.data(), lp->a_rowptr, ra.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(rat.data(), lp->at_rowptr, rat.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return;
+    if (ra[0] != 0 || rat[0] != 0 || ra[lp->m] != lp->nnz || rat[lp->n] != lp->nnz) return;  // the solve reports it
+    for (int k = 4; k <= 8; ++k) {
+        const int32_t ta = balanced_nnz(ra, lp->m, (int64_t)k * cus);
+        const int32_t tat = balanced_nnz(rat, lp->n, (int64_t)k * cus);
+        if (ta > 0 && tat > 0)
+            for (int sr : {-1, 32}) out.push_back({0, ta, 512, sr, tat, 512, sr});
+    }
 }
 
 }  // namespace
@@ -42,19 +79,23 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     // per spmv_kind: the fastest dual (A's tiles) and primal (A^T's tiles) shapes
     struct Best {
         double ms = 1e300;
-        Cand c{0, 0, 0, 0};
+        Cand c{0, 0, 0, 0, 0, 0, 0};
     };
     Best dual[3], primal[3], dual_def[3], primal_def[3];
     bool first = true;
     const bool general = lp->lo || lp->hi || lp->sense;  // runs on the tile kernels only
-    for (const Cand& c : candidates()) {
+    std::vector<Cand> cands = candidates();
+    balanced_candidates(lp, (hipStream_t)stream, cands);
+    for (const Cand& c : cands) {
         if (general && c.kind == 1) continue;
         mipdhg_options o = *opt;
         o.spmv_kind = c.kind;
         o.tile_nnz = c.tile_nnz;
         o.tile_rows = c.tile_rows;
         o.short_row = c.short_row;
-        o.tile_nnz_at = o.tile_rows_at = o.short_row_at = 0;  // the same shape on both sides
+        o.tile_nnz_at = c.tile_nnz_at;
+        o.tile_rows_at = c.tile_rows_at;
+        o.short_row_at = c.short_row_at;
         o.kernel_timing = 1;
         o.max_iter = iters;
         o.trace_iters = 0;
@@ -72,7 +113,8 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
         first = false;
         if (info.ms_dual > 0.0 && info.ms_dual < dual[c.kind].ms) dual[c.kind] = Best{info.ms_dual, c};
         if (info.ms_primal > 0.0 && info.ms_primal < primal[c.kind].ms) primal[c.kind] = Best{info.ms_primal, c};
-        if (c.tile_nnz == kDefNnz && c.tile_rows == kDefRows && c.short_row == kDefShort) {
+        if (c.tile_nnz == kDefNnz && c.tile_rows == kDefRows && c.short_row == kDefShort &&
+            c.tile_nnz_at == kDefNnz) {
             dual_def[c.kind] = Best{info.ms_dual, c};
             primal_def[c.kind] = Best{info.ms_primal, c};
         }
@@ -98,9 +140,9 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     opt->tile_nnz = dual[kind].c.tile_nnz;
     opt->tile_rows = dual[kind].c.tile_rows;
     opt->short_row = dual[kind].c.short_row;
-    opt->tile_nnz_at = primal[kind].c.tile_nnz;
-    opt->tile_rows_at = primal[kind].c.tile_rows;
-    opt->short_row_at = primal[kind].c.short_row;
+    opt->tile_nnz_at = primal[kind].c.tile_nnz_at;
+    opt->tile_rows_at = primal[kind].c.tile_rows_at;
+    opt->short_row_at = primal[kind].c.short_row_at;
     if (best_ms) *best_ms = best;
     return 0;
 }

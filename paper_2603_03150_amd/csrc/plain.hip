@@ -876,6 +876,11 @@ std::vector<int32_t> make_tile_desc(const std::vector<int32_t>& rowptr, int32_t 
     return desc;
 }
 
+// Tiles of the greedy cut (for the autotuner's CU-balanced candidates).
+int64_t tile_count(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz, int32_t tile_rows) {
+    return (int64_t)(make_tile_desc(rowptr, nrows, tile_nnz, tile_rows).size() / 4);
+}
+
 // The descriptors must cover every row exactly once with matching nonzero
 // ranges and respect the tile limits; checked on the host before any launch.
 bool tile_desc_ok(const std::vector<int32_t>& desc, const std::vector<int32_t>& rowptr, int32_t nrows,
