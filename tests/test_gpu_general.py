@@ -182,4 +182,7 @@ def test_autotune_on_a_general_lp_picks_a_tile_shape():
     shape = {k: v for k, v in best.items() if k != "ms_per_iter"}
     a = P.solve(dlp, 1e-4, "fp32", **shape)
     b = P.solve(dlp, 1e-4, "fp32")
-    assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]
+    # float32 row sums round differently with other tiles: the stopping
+    # evaluation may move by a block
+    assert a.status == b.status == 0 and abs(a.info["iters"] - b.info["iters"]) <= 128
+    assert abs(a.info["pobj"] - b.info["pobj"]) <= 1e-3 * (1 + abs(b.info["pobj"]))

@@ -101,3 +101,28 @@ def test_resume_is_a_single_lp_option():
     with pytest.raises(P.MipdhgError) as e:
         P.solve_batched(batch, 1e-4, "fp32", resume=1)
     assert e.value.code == -6
+
+
+def test_time_limit_stops_at_a_block_and_resumes_bitwise():
+    # a limit that has passed once the first block is queued: the solve stops
+    # after that block (TIME_LIMIT), and resuming it is one uninterrupted solve
+    dlp = P.DeviceLP.from_lp(lpgen.cfg2_sub(6, scale=100))
+    ref = P.solve(dlp, 1e-7, "fp64")
+    a = P.solve(dlp, 1e-7, "fp64", time_limit_s=1e-9)
+    assert a.status == P.TIME_LIMIT and a.info["iters"] == 64
+    b = P.solve(dlp, 1e-7, "fp64", resume=a)
+    _same(ref, b)
+
+
+def test_resume_general_form():
+    lp = lpgen.general_cfg1(1)
+    dlp = P.DeviceLP.from_lp(lp)
+    ref = P.solve(dlp, 1e-12, "fp64", max_iter=256)
+    a = P.solve(dlp, 1e-12, "fp64", max_iter=128)
+    b = P.solve(dlp, 1e-12, "fp64", max_iter=256, resume=a)
+    _same(ref, b)
+    # the same matrix and data as a standard-form LP is another state
+    std = P.DeviceLP(lp.A, lp.AT, lp.b, lp.c)
+    c = P.solve(dlp, 1e-12, "fp64", max_iter=64)
+    with pytest.raises(P.MipdhgError):
+        P.solve(std, 1e-12, "fp64", max_iter=128, resume=c)
