@@ -1116,7 +1116,8 @@ struct Solver {
 
     Solver(const mipdhg_lp& l, const mipdhg_options& op, hipStream_t s) : lp(l), o(op), stream(s) {}
     ~Solver() {
-        for (auto e : tev) (void)hipEventDestroy(e);
+        for (auto e : tev)
+            if (e) (void)hipEventDestroy(e);
     }
     bool tiled() const { return iter_kind(o, lp.m, lp.n) != 1; }
     bool persistent() const { return iter_kind(o, lp.m, lp.n) == 2; }
@@ -1683,35 +1684,40 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         S.tev.resize(3 * (size_t)E);
         for (auto& e : S.tev) MIP_HIP(hipEventCreate(&e));
     }
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t g = nullptr;
-    hipStream_t cap = nullptr;
-    if (graph && o.max_iter >= E) {
-        MIP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        S.stream = cap;
-        MIP_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        rc = S.enqueue_block(E, 1, false);
-        hipGraph_t gtmp = nullptr;
-        hipError_t ce = hipStreamEndCapture(cap, &gtmp);
-        S.stream = stream;
-        if (rc) {
-            if (gtmp) (void)hipGraphDestroy(gtmp);
-            (void)hipStreamDestroy(cap);
-            return rc;
-        }
-        if (ce != hipSuccess) {
-            (void)hipStreamDestroy(cap);
-            MIP_HIP(ce);
-        }
-        g = gtmp;
-        MIP_HIP(hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0));
-    }
-    // pinned ring of status words, one per block in flight
+    // host objects of the loop, released on every return path (after the
+    // stream has been synchronised on the normal one)
     constexpr int kDepth = 3;
-    Ctrl* ring = nullptr;
-    MIP_HIP(hipHostMalloc((void**)&ring, sizeof(Ctrl) * kDepth, hipHostMallocDefault));
-    hipEvent_t ev[kDepth];
-    for (int i = 0; i < kDepth; ++i) MIP_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    struct LoopRes {
+        hipGraphExec_t gexec = nullptr;
+        hipGraph_t g = nullptr;
+        hipStream_t cap = nullptr;
+        Ctrl* ring = nullptr;  // pinned ring of status words, one per block in flight
+        hipEvent_t ev[kDepth] = {};
+        ~LoopRes() {
+            for (auto e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (ring) (void)hipHostFree(ring);
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            if (g) (void)hipGraphDestroy(g);
+            if (cap) (void)hipStreamDestroy(cap);
+        }
+    } res;
+    if (graph && o.max_iter >= E) {
+        MIP_HIP(hipStreamCreateWithFlags(&res.cap, hipStreamNonBlocking));
+        S.stream = res.cap;
+        MIP_HIP(hipStreamBeginCapture(res.cap, hipStreamCaptureModeThreadLocal));
+        rc = S.enqueue_block(E, 1, false);
+        hipError_t ce = hipStreamEndCapture(res.cap, &res.g);
+        S.stream = stream;
+        if (rc) return rc;
+        MIP_HIP(ce);
+        MIP_HIP(hipGraphInstantiate(&res.gexec, res.g, nullptr, nullptr, 0));
+    }
+    MIP_HIP(hipHostMalloc((void**)&res.ring, sizeof(Ctrl) * kDepth, hipHostMallocDefault));
+    for (int i = 0; i < kDepth; ++i) MIP_HIP(hipEventCreateWithFlags(&res.ev[i], hipEventDisableTiming));
+    Ctrl* const ring = res.ring;
+    hipEvent_t* const ev = res.ev;
+    const hipGraphExec_t gexec = res.gexec;
     int64_t launched = 0;
     if (o.resume) {
         Ctrl cur;
@@ -1766,11 +1772,6 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     }
     hipError_t se = hipStreamSynchronize(stream);
     const auto t2 = clk::now();
-    for (int i = 0; i < kDepth; ++i) (void)hipEventDestroy(ev[i]);
-    (void)hipHostFree(ring);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (g) (void)hipGraphDestroy(g);
-    if (cap) (void)hipStreamDestroy(cap);
     if (rc) return rc;
     MIP_HIP(se);
 
@@ -1781,8 +1782,9 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         // control word is set to running for the runs (a finished solve makes
         // the kernels skip their row sums) and restored afterwards
         constexpr int R = 256;
-        hipEvent_t te[3];
-        for (auto& e : te) MIP_HIP(hipEventCreate(&e));
+        S.tev.assign(3, nullptr);  // the solver releases its events
+        for (auto& e : S.tev) MIP_HIP(hipEventCreate(&e));
+        hipEvent_t* const te = S.tev.data();
         const int32_t running = ST_RUNNING;
         MIP_HIP(hipMemcpyAsync(&w.ctrl->status, &running, sizeof(int32_t), hipMemcpyHostToDevice, stream));
         S.stream = stream;
@@ -1798,7 +1800,6 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         float a = 0.f, b = 0.f;
         MIP_HIP(hipEventElapsedTime(&a, te[0], te[1]));
         MIP_HIP(hipEventElapsedTime(&b, te[1], te[2]));
-        for (auto e : te) (void)hipEventDestroy(e);
         if (rc) return rc;
         S.ms_p = a;
         S.ms_d = b;
