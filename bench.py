@@ -79,9 +79,10 @@ def parse():
 
 
 def cpu_baseline(lp, gpu_iters: int, eps: float) -> dict:
-    """The oracle as it stands, one thread, on a bounded sample: two runs
-    capped at 64 and 192 iterations give its setup time and per-iteration
-    time; the rate is quoted for a solve of the GPU's iteration count."""
+    """The oracle as it stands, one thread, on a bounded sample (about 10 s of
+    CPU work on the power-law LP): two runs capped at 128 and 768 iterations
+    give its setup time and per-iteration time; the rate is quoted for a
+    solve of the GPU's iteration count."""
     import oracle
     from oracle.pdhg import OracleOptions
     try:
@@ -93,18 +94,18 @@ def cpu_baseline(lp, gpu_iters: int, eps: float) -> dict:
     if ctx:
         ctx.__enter__()
     try:
-        for n in (64, 192):
+        for n in (128, 768):
             t0 = time.perf_counter()
             oracle.solve(lp.A, lp.AT, lp.b, lp.c, eps, opts=OracleOptions(max_iter=n))
             times[n] = time.perf_counter() - t0
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    per_iter = (times[192] - times[64]) / 128.0
-    setup = max(0.0, times[64] - 64 * per_iter)
+    per_iter = (times[768] - times[128]) / 640.0
+    setup = max(0.0, times[128] - 128 * per_iter)
     value = gpu_iters / (setup + gpu_iters * per_iter)
     return {"value": value, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle capped at 64 and 192 iterations on the same LP: setup {setup:.2f} s, "
+            "sample": (f"oracle capped at 128 and 768 iterations on the same LP: setup {setup:.2f} s, "
                        f"{per_iter * 1e3:.1f} ms/iteration, rate quoted for a {gpu_iters}-iteration solve")}
 
 
