@@ -10,11 +10,18 @@
  * The tests and every reported figure are computed in float64 on the original
  * (unscaled) model, as Sections 2.1 and 4.3 ask, whatever the precision of the
  * iterations.  z is max(c - A^T y, 0), the z >= 0 that minimises ||r_D||.
+ * The general form Section 2 mentions (bounds lo <= x <= hi, rows of sense
+ * =, >= or <=) is accepted through the optional fields of mipdhg_lp and
+ * handled implicitly; the quantities above then take their general-form
+ * meaning (see mipdhg_lp and mipdhg_solve).  Infeasible and unbounded LPs are
+ * reported through certificate tests (see infeas_tol).
  *
  * The PDHG itself (Section 4.1 only says it follows cuPDLP+) is: diagonal
  * scaling (Ruiz infinity-norm passes plus one Pock-Chambolle pass), a constant
  * step from a power-iteration estimate of ||A||_2, a primal weight re-balanced
- * at restarts, reflected Halpern iterations, and fixed-point-residual restarts.
+ * at restarts (smoothed, or by a PID controller), reflected Halpern
+ * iterations, and fixed-point-residual restarts.  A stopped solve can be
+ * resumed from its workspace (option resume).
  *
  * Conventions for every entry point
  *  - All array arguments are DEVICE pointers (hipMalloc'd or torch tensors on
@@ -28,8 +35,9 @@
  *    m rows; the caller also passes A^T as CSR with n rows (the same matrix,
  *    transposed).  Column indices need not be sorted; duplicates are not
  *    allowed.
- *  - Return value >= 0 is a solver status (MIPDHG_OPTIMAL ... NUMERICAL); the
- *    outputs then hold the last evaluated point and info is filled.  A
+ *  - Return value >= 0 is a solver status (MIPDHG_OPTIMAL ...
+ *    DUAL_INFEASIBLE); the outputs then hold the last evaluated point and
+ *    info is filled.  A
  *    negative value is an error: no output is written, and
  *    mipdhg_last_error() returns a message (thread-local).
  *  - Re-entrant for distinct workspaces; two calls that share a workspace must
