@@ -258,6 +258,24 @@ int mipdhg_solve(const mipdhg_lp *lp, const mipdhg_options *opt, double eps_rel,
                  double *x, double *y, double *z, double *r_p, double *r_d,
                  double *d_row, double *d_col, mipdhg_info *info);
 
+/* Checkpoint of a solve (for the callers that want to keep a stopped solve
+ * beyond its workspace, e.g. on disk): the part of the workspace that
+ * options.resume continues from -- control block, iterates, anchors,
+ * projected points, the previous evaluated point and the last evaluation's
+ * partial sums -- for the LP sizes and options given (the same as the
+ * solve's).  mipdhg_state_size gives its bytes; export copies it from a
+ * workspace to `dst`, import from `src` into a workspace of at least
+ * mipdhg_workspace_size() bytes; `dst`/`src` may be host or device memory.
+ * After an import, mipdhg_solve with resume = 1 on the same LP and options
+ * continues the exported solve as if it had never stopped (its outputs are
+ * written at the next evaluation).  Both are synchronous on `stream`.
+ * Errors: INVALID_ARG (NULL, buffer too small), WORKSPACE (too small), HIP. */
+int mipdhg_state_size(const mipdhg_lp *lp, const mipdhg_options *opt, size_t *bytes);
+int mipdhg_state_export(const mipdhg_lp *lp, const mipdhg_options *opt, const void *workspace,
+                        size_t workspace_bytes, void *dst, size_t dst_bytes, void *stream);
+int mipdhg_state_import(const mipdhg_lp *lp, const mipdhg_options *opt, void *workspace, size_t workspace_bytes,
+                        const void *src, size_t src_bytes, void *stream);
+
 /* Many independent LPs, stacked as the diagonal blocks of one block-diagonal
  * LP: instance i owns rows [row_off[i], row_off[i+1]), columns
  * [col_off[i], col_off[i+1]) and nonzeros [nnz_off[i], nnz_off[i+1]) of both

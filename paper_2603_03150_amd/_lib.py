@@ -88,6 +88,11 @@ SIGNATURES = {
     "mipdhg_center_reclamp": (C.c_int, [_i32, _f64, _p, _p, _p]),
     "mipdhg_autotune": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _i32, _p, C.c_size_t, _p,
                                   _p, _p, _p, _p, _p, C.POINTER(_f64)]),
+    "mipdhg_state_size": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), C.POINTER(C.c_size_t)]),
+    "mipdhg_state_export": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _p, C.c_size_t, _p, C.c_size_t,
+                                      _p]),
+    "mipdhg_state_import": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _p, C.c_size_t, _p, C.c_size_t,
+                                      _p]),
     "mipdhg_sizeof": (C.c_size_t, [C.c_int]),
     "mipdhg_status_string": (C.c_char_p, [C.c_int]),
     "mipdhg_last_error": (C.c_char_p, []),

@@ -1858,6 +1858,73 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
 
 }  // namespace mip
 
+namespace mip {
+
+// The parts of the workspace a resumed solve continues from, as (offset,
+// bytes) pairs in the workspace layout of these LP sizes and options.
+static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp, const mipdhg_options& o) {
+    char* const base = reinterpret_cast<char*>(uintptr_t(4096));  // layout only, never dereferenced
+    const PlainWs w = carve(base, 0, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
+                            tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp));
+    const size_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
+    const size_t m = (size_t)lp.m, n = (size_t)lp.n, G = (size_t)w.gcap;
+    auto at = [&](const void* p, size_t bytes) { return std::make_pair((size_t)((const char*)p - base), bytes); };
+    return {at(w.ctrl, sizeof(Ctrl)),       at(w.pp, G * 3 * 8),          at(w.pd, G * 3 * 8),
+            at(w.per, G * kEvalRowsW * 8),  at(w.pec, G * kEvalColsW * 8), at(w.xprev, n * 8),
+            at(w.yprev, m * 8),             at(w.axprev, m * 8),          at(w.atyprev, n * 8),
+            at(w.x, n * ts),                at(w.x0, n * ts),             at(w.xhat, n * ts),
+            at(w.y, m * ts),                at(w.y0, m * ts),             at(w.yhat, m * ts)};
+}
+
+static int state_copy(const mipdhg_lp* lp, const mipdhg_options* opt, char* ws, size_t ws_bytes, char* buf,
+                      size_t buf_bytes, bool out, hipStream_t stream) {
+    clear_error();
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (!opt || !ws || !buf) return set_error("NULL argument"), MIPDHG_ERR_INVALID_ARG;
+    if ((rc = check_options(opt))) return rc;
+    size_t need = 0;
+    if ((rc = mipdhg_workspace_size(lp, opt, &need))) return rc;
+    if (ws_bytes < need) return set_error("workspace too small: %zu bytes, %zu needed", ws_bytes, need), MIPDHG_ERR_WORKSPACE;
+    const auto regions = state_regions(*lp, *opt);
+    size_t total = 0;
+    for (const auto& r : regions) total += r.second;
+    if (buf_bytes < total)
+        return set_error("state buffer too small: %zu bytes, %zu needed", buf_bytes, total), MIPDHG_ERR_INVALID_ARG;
+    size_t pos = 0;
+    for (const auto& r : regions) {
+        if (out) MIP_HIP(hipMemcpyAsync(buf + pos, ws + r.first, r.second, hipMemcpyDefault, stream));
+        else MIP_HIP(hipMemcpyAsync(ws + r.first, buf + pos, r.second, hipMemcpyDefault, stream));
+        pos += r.second;
+    }
+    MIP_HIP(hipStreamSynchronize(stream));
+    return 0;
+}
+
+}  // namespace mip
+
+extern "C" int mipdhg_state_size(const mipdhg_lp* lp, const mipdhg_options* opt, size_t* bytes) {
+    clear_error();
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (!opt || !bytes) return set_error("NULL argument"), MIPDHG_ERR_INVALID_ARG;
+    if ((rc = check_options(opt))) return rc;
+    size_t total = 0;
+    for (const auto& r : state_regions(*lp, *opt)) total += r.second;
+    *bytes = total;
+    return 0;
+}
+
+extern "C" int mipdhg_state_export(const mipdhg_lp* lp, const mipdhg_options* opt, const void* workspace,
+                                   size_t workspace_bytes, void* dst, size_t dst_bytes, void* stream) {
+    return state_copy(lp, opt, (char*)workspace, workspace_bytes, (char*)dst, dst_bytes, true, (hipStream_t)stream);
+}
+
+extern "C" int mipdhg_state_import(const mipdhg_lp* lp, const mipdhg_options* opt, void* workspace,
+                                   size_t workspace_bytes, const void* src, size_t src_bytes, void* stream) {
+    return state_copy(lp, opt, (char*)workspace, workspace_bytes, (char*)src, src_bytes, false, (hipStream_t)stream);
+}
+
 extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, double eps_rel, void* workspace,
                             size_t workspace_bytes, void* stream, double* x, double* y, double* z, double* r_p,
                             double* r_d, double* d_row, double* d_col, mipdhg_info* info) {

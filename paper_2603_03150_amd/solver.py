@@ -128,17 +128,20 @@ def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -
 
 def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters: int = 0,
           x_init: torch.Tensor | None = None, y_init: torch.Tensor | None = None,
-          workspace: torch.Tensor | None = None, resume: Solution | None = None, **opts) -> Solution:
+          workspace: torch.Tensor | None = None, resume: "Solution | torch.Tensor | None" = None,
+          **opts) -> Solution:
     """Run mipdhg_solve on dlp.  Options are the fields of mipdhg_options.
 
-    resume: a Solution of this LP, solved with the same options; the solve
-    continues its state (its workspace and output tensors are reused and
-    written in place), with max_iter counting all iterations."""
+    resume: a Solution of this LP, solved with the same options, whose state
+    the solve continues (its workspace and output tensors are reused and
+    written in place), or a workspace holding an imported state
+    (import_state); max_iter counts all iterations."""
     lib = _lib.load()
     o = make_options(precision, **opts)
+    resumed_ws = isinstance(resume, torch.Tensor)
     if resume is not None:
         o.resume = 1
-        workspace = resume.workspace
+        workspace = resume if resumed_ws else resume.workspace
     d = dlp.device
     f64 = dict(dtype=torch.float64, device=d)
     trace = {}
@@ -160,7 +163,7 @@ def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters
         raise ValueError("resume: the solution's workspace does not fit these options")
     if workspace is None or workspace.numel() < nb.value:
         workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
-    if resume is not None:
+    if resume is not None and not resumed_ws:
         x, y, z, r_p, r_d, d_row, d_col = (resume.x, resume.y, resume.z, resume.r_p, resume.r_d, resume.d_row,
                                            resume.d_col)
     else:
@@ -179,6 +182,39 @@ def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters
     _lib.check(rc)
     return Solution(rc, lib.mipdhg_status_string(rc).decode(), x, y, z, r_p, r_d, d_row, d_col,
                     info.as_dict(), trace, workspace)
+
+
+def state_bytes(dlp: DeviceLP, precision: str = "fp64", **opts) -> int:
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_state_size(C.byref(dlp.struct()), C.byref(o), C.byref(nb)))
+    return int(nb.value)
+
+
+def export_state(dlp: DeviceLP, sol: Solution, precision: str = "fp64", **opts) -> torch.Tensor:
+    """The resumable state of a solve (mipdhg_state_export) as a host uint8
+    tensor; opts as for that solve."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    out = torch.empty(state_bytes(dlp, precision, **opts), dtype=torch.uint8)
+    _lib.check(lib.mipdhg_state_export(C.byref(dlp.struct()), C.byref(o), sol.workspace.data_ptr(),
+                                       sol.workspace.numel(), out.data_ptr(), out.numel(),
+                                       torch.cuda.current_stream(dlp.device).cuda_stream))
+    return out
+
+
+def import_state(dlp: DeviceLP, state: torch.Tensor, precision: str = "fp64", **opts) -> torch.Tensor:
+    """A new workspace holding `state` (mipdhg_state_import), to pass as
+    solve(..., resume=workspace) with the same options."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    state = state.contiguous()
+    ws = torch.empty(workspace_bytes(dlp, precision, **opts), dtype=torch.uint8, device=dlp.device)
+    _lib.check(lib.mipdhg_state_import(C.byref(dlp.struct()), C.byref(o), ws.data_ptr(), ws.numel(),
+                                       state.data_ptr(), state.numel(),
+                                       torch.cuda.current_stream(dlp.device).cuda_stream))
+    return ws
 
 
 class DeviceBatch:

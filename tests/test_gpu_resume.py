@@ -126,3 +126,19 @@ def test_resume_general_form():
     c = P.solve(dlp, 1e-12, "fp64", max_iter=64)
     with pytest.raises(P.MipdhgError):
         P.solve(std, 1e-12, "fp64", max_iter=128, resume=c)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exported_state_resumes_in_a_new_workspace(prec):
+    dlp = P.DeviceLP.from_lp(lpgen.cfg2_sub(6, scale=100))
+    ref = P.solve(dlp, 1e-12, prec, max_iter=320)
+    a = P.solve(dlp, 1e-12, prec, max_iter=128)
+    state = P.export_state(dlp, a, prec)
+    assert state.device.type == "cpu" and state.numel() == P.state_bytes(dlp, prec)
+    a.workspace.zero_()  # the original workspace is gone
+    ws = P.import_state(dlp, state, prec)
+    b = P.solve(dlp, 1e-12, prec, max_iter=320, resume=ws)
+    _same(ref, b)
+    # a state of other options does not import into this layout's checks
+    with pytest.raises(P.MipdhgError):
+        P.import_state(dlp, state[:-8], prec)
