@@ -66,6 +66,13 @@ of all updates so far including e, e_prev the previous update's error (0 at
 the first).  ki = kd = 0 is the smoothing rule above, which is then computed
 in its own form.
 
+Restart to the average (a variant, off by default, meant for halpern = 0):
+the projected points of the current epoch are averaged with equal weights,
+avg <- avg + (z_hat - avg) / j after the epoch's j-th iteration; a restart
+then moves the state and the anchor to that average instead of the last
+projected point, and the primal-weight update measures the distances of the
+average to the old anchor.  The restart tests themselves are unchanged.
+
 parity unpinned: the restart and primal-weight heuristics (which iterations
 restart, the omega sequence, iteration counts to a tolerance) follow a reading
 with no external reference; only GPU-versus-oracle agreement checks them.
@@ -101,6 +108,7 @@ class OracleOptions:
     infeas_tol: float = 1e-8  # 0 turns the certificate tests off
     pw_ki: float = 0.0        # primal weight as a PID controller: integral gain
     pw_kd: float = 0.0        # and derivative gain (pw_theta is the proportional one)
+    restart_avg: bool = False  # restart to the epoch's average of the projected points
 
 
 @dataclass
@@ -450,6 +458,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     E = max(1, int(opts.eval_every))
     prev = None  # the previous evaluated point (x, y), original space
     pid = [0.0, 0.0, 0]  # primal-weight controller state
+    x_avg, y_avg = np.zeros(n), np.zeros(m)  # epoch averages (restart_avg)
 
     while True:
         t += 1
@@ -461,6 +470,10 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
         w = (k + 1.0) / (k + 2.0) if opts.halpern else 1.0
         x_new = w * ((1.0 + rho) * x_hat - rho * x) + (1.0 - w) * x0
         y_new = w * ((1.0 + rho) * y_hat - rho * y) + (1.0 - w) * y0
+        if opts.restart_avg:
+            inv = 1.0 / (k + 1.0)
+            x_avg = x_avg + (x_hat - x_avg) * inv
+            y_avg = y_avg + (y_hat - y_avg) * inv
         k += 1
         restarted = False
         if t % E == 0 or t == opts.max_iter:
@@ -481,13 +494,14 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                 return Result(status, t, restarts, meas, d_row, d_col, sigma_hat, eta,
                               omega0, omega, log, trace)
             if opts.restarts and restart_due(R, R0, R_prev, k, t, opts):
-                dx = float(np.linalg.norm(x_hat - x0))
-                dy = float(np.linalg.norm(y_hat - y0))
+                px, py = (x_avg, y_avg) if opts.restart_avg else (x_hat, y_hat)
+                dx = float(np.linalg.norm(px - x0))
+                dy = float(np.linalg.norm(py - y0))
                 if dx > 1e-10 and dy > 1e-10:
                     omega = primal_weight_update(omega, dx, dy, pid, opts)
                     tau, sig = eta / omega, eta * omega
-                x_new, y_new = x_hat.copy(), y_hat.copy()
-                x0, y0 = x_hat.copy(), y_hat.copy()
+                x_new, y_new = px.copy(), py.copy()
+                x0, y0 = px.copy(), py.copy()
                 k = 0
                 R_prev = math.inf
                 restarts += 1
