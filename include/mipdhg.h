@@ -205,6 +205,13 @@ typedef struct mipdhg_options {
      * they should differ from A's: 0 = the value of tile_nnz, tile_rows,
      * short_row.  mipdhg_autotune picks both sides.              [0, 0, 0] */
     int32_t tile_nnz_at, tile_rows_at, short_row_at;
+    /* 1 = restart to the epoch's average: the projected points of the
+     * current epoch are averaged (equal weights) and a restart moves the
+     * state and the anchor to that average instead of the last projected
+     * point; the primal-weight update measures the average's distances.  The
+     * restart tests and the evaluated point are unchanged.  Meant with
+     * halpern = 0; single-LP solve with spmv_kind 0 only.               [0] */
+    int32_t restart_avg;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */

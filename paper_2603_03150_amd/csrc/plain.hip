@@ -280,6 +280,7 @@ struct IterArgs {
     const T* lo;          // general form, primal: scaled bounds l / D_c, u / D_c
     const T* hi;
     const int8_t* sense;  // general form, dual: row senses
+    T* avg;               // restart to average: the epoch's mean of x^ or y^
     double rho;
     int32_t halpern;
     int32_t it;
@@ -294,18 +295,23 @@ struct IterPre {
     T o, an, rhs;
     T lo, hi;  // general form, primal
     int sense; // general form, dual
+    T av;      // restart to average
 };
 
 // GEN: the general form (Section 2 mentions bounds and inequality rows):
 // the primal step projects onto [l, u] instead of x >= 0, the dual step
 // keeps y_i >= 0 on >= rows and y_i <= 0 on <= rows.
-template <typename T, typename V, bool PRIMAL, bool GEN>
+// AVG: restart to average: the epoch's running mean of the projected points
+// is updated (avg += (h - avg) / j after the epoch's j-th iteration) and its
+// distance to the anchor replaces that of h in the evaluation partials.
+template <typename T, typename V, bool PRIMAL, bool GEN, bool AVG = false>
 struct IterEpi {
     const IterArgs<T, V>& a;
     double w, omw, rho, opr, st;
     int flags;
     double* q;
     bool run;
+    double inv_j = 1.0;
     typedef IterPre<T> Pre;
     // The run flag, the Halpern weight and the step come from the device
     // control block; they are read here, once the tile's independent loads
@@ -318,6 +324,7 @@ struct IterEpi {
         w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
         omw = 1.0 - w;
         st = PRIMAL ? c->tau : c->sigma;
+        if (AVG) inv_j = 1.0 / (double)(k + 1);
     }
     // branch-free, so that the loads of all rows of a thread are in flight
     // together (the scaling factor is fetched by apply() on evaluations only)
@@ -331,6 +338,7 @@ struct IterEpi {
             p.hi = ld_at(a.hi + r0, i);
         }
         if (GEN && !PRIMAL) p.sense = ld_at(a.sense + r0, i);
+        if (AVG) p.av = ld_at(a.avg + r0, i);
         return p;
     }
     // The arithmetic is float64 whatever the storage type T: the stored
@@ -359,6 +367,12 @@ struct IterEpi {
         if (flags & F_HAT) st_at(a.hat + r0, i, (T)h);
         const double an = (double)p.an;
         st_at(a.state + r0, i, (T)(w * (opr * h - rho * o) + omw * an));
+        double rp = h;  // the restart point's entry
+        if (AVG) {
+            const double av = (double)p.av;
+            rp = av + (h - av) * inv_j;
+            st_at(a.avg + r0, i, (T)rp);
+        }
         if (flags & (F_FIRST | F_EVAL)) {
             double d = o - h;
             d *= d;
@@ -366,7 +380,7 @@ struct IterEpi {
             if (flags & F_EVAL) q[1] += d;
         }
         if (flags & F_EVAL) {
-            const double d = h - an;
+            const double d = rp - an;
             q[2] += d * d;
             st_at(a.out64 + r0, i, ld_at(a.dscale + r0, i) * h);
         }
@@ -378,9 +392,9 @@ struct IterEpi {
     }
 };
 
-template <typename T, typename V, bool PRIMAL, bool GEN = false>
-__device__ __forceinline__ IterEpi<T, V, PRIMAL, GEN> make_epi(const IterArgs<T, V>& a, double* q) {
-    IterEpi<T, V, PRIMAL, GEN> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
+template <typename T, typename V, bool PRIMAL, bool GEN = false, bool AVG = false>
+__device__ __forceinline__ IterEpi<T, V, PRIMAL, GEN, AVG> make_epi(const IterArgs<T, V>& a, double* q) {
+    IterEpi<T, V, PRIMAL, GEN, AVG> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
     return e;
 }
 
@@ -409,13 +423,13 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 
 // LDS-tiled traversal (TilePlan).  The control word is loaded up front and
 // only checked once the products are in LDS.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN, bool AVG = false>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
     double mx[1] = {0.0};
-    auto epi = make_epi<T, V, PRIMAL, GEN>(a, q);
+    auto epi = make_epi<T, V, PRIMAL, GEN, AVG>(a, q);
     // streamed arrays: tile base + 32-bit offset; the gather: a plain 64-bit
     // address, measured 12-18 % faster than the base + offset form on
     // 4096- and 8192-nonzero tiles
@@ -918,10 +932,10 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
     };
     const int64_t sz[4] = {lp.m, lp.n, lp.nnz, (has_bounds(lp) ? 1 : 0) | (has_sense(lp) ? 2 : 0)};
     mix(sz, sizeof(sz));
-    const int32_t iv[18] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
+    const int32_t iv[19] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
                             o.gather_order, o.lanes_a, o.lanes_at, o.long_row, tile_nnz_at_of(o),
-                            tile_rows_at_of(o), short_row_at_of(o)};
+                            tile_rows_at_of(o), short_row_at_of(o), o.restart_avg};
     mix(iv, sizeof(iv));
     const double dv[8] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
                           o.pw_kd};
@@ -965,11 +979,13 @@ struct PlainWs {
     void *lo_t, *hi_t;          // general form: scaled bounds l / D_c, u / D_c
     double *xprev, *yprev;      // infeasibility certificates: previous evaluated point
     double *axprev, *atyprev;   // and its A x, A^T y
+    void *x_avg, *y_avg;        // restart to average: the epoch's means
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
-                     int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds) {
+                     int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds,
+                     bool avg) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -1017,6 +1033,8 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.slot_at = sorted ? cv.take<uint16_t>(nnz) : nullptr;
     w.lo_t = bounds ? cv.take<char>(n * ts) : nullptr;
     w.hi_t = bounds ? cv.take<char>(n * ts) : nullptr;
+    w.x_avg = avg ? cv.take<char>(n * ts) : nullptr;
+    w.y_avg = avg ? cv.take<char>(m * ts) : nullptr;
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -1053,6 +1071,7 @@ int check_options(const mipdhg_options* o) {
     if (o->tile_rows_at < 0 || o->tile_rows_at > kMaxTileRows)
         return set_error("tile_rows_at must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
     if (o->short_row_at < -1) return set_error("short_row_at must be >= -1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->restart_avg < 0 || o->restart_avg > 1) return set_error("restart_avg must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     for (int L : {o->lanes_a, o->lanes_at})
         if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
             return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
@@ -1092,7 +1111,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
                    tile_rows_of(*opt), tile_nnz_at_of(*opt), tile_rows_at_of(*opt), sorted_layout(*opt, lp->m, lp->n),
-                   has_bounds(*lp)).bytes;
+                   has_bounds(*lp), opt->restart_avg != 0).bytes;
     return 0;
 }
 
@@ -1139,12 +1158,23 @@ struct Solver {
         (const void*)k_iter_persist<T, V, Acc, true, 8, true, G>, (const void*)k_iter_persist<T, V, Acc, false, 8, true, G>, \
         (const void*)k_iter_persist<T, V, Acc, true, 16, true, G>,                                                     \
         (const void*)k_iter_persist<T, V, Acc, false, 16, true, G>
-            const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true),
+#define MIP_AVG_KERNELS(G)                                                                                   \
+    (const void*)k_iter_tiled<T, V, Acc, true, 8, false, G, true>,                                            \
+        (const void*)k_iter_tiled<T, V, Acc, false, 8, false, G, true>,                                       \
+        (const void*)k_iter_tiled<T, V, Acc, true, 16, false, G, true>,                                       \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, false, G, true>,                                      \
+        (const void*)k_iter_tiled<T, V, Acc, true, 8, true, G, true>,                                         \
+        (const void*)k_iter_tiled<T, V, Acc, false, 8, true, G, true>,                                        \
+        (const void*)k_iter_tiled<T, V, Acc, true, 16, true, G, true>,                                        \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, true, G, true>
+            const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true), MIP_AVG_KERNELS(false),
+                                MIP_AVG_KERNELS(true),
                                 (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
                                 (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
 #undef MIP_ITER_KERNELS
+#undef MIP_AVG_KERNELS
             for (const void* k : ks)
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
                     return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
@@ -1220,6 +1250,7 @@ struct Solver {
         a.lo = (const T*)w.lo_t;
         a.hi = (const T*)w.hi_t;
         a.sense = lp.sense;
+        a.avg = (T*)(primal ? w.x_avg : w.y_avg);
         a.rho = o.reflect_rho;
         a.halpern = o.halpern;
         a.it = it;
@@ -1229,10 +1260,16 @@ struct Solver {
     // products in flight per thread, row-major or sorted layout.
     template <bool PRIMAL>
     void launch_tiles(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
-        if (PRIMAL ? gen_primal() : gen_dual()) launch_tiles_g<PRIMAL, true>(a, tp, gpersist);
-        else launch_tiles_g<PRIMAL, false>(a, tp, gpersist);
+        const bool g = PRIMAL ? gen_primal() : gen_dual();
+        if (o.restart_avg) {  // one workgroup per tile only (checked with the options)
+            if (g) launch_tiles_g<PRIMAL, true, true>(a, tp, gpersist);
+            else launch_tiles_g<PRIMAL, false, true>(a, tp, gpersist);
+        } else {
+            if (g) launch_tiles_g<PRIMAL, true, false>(a, tp, gpersist);
+            else launch_tiles_g<PRIMAL, false, false>(a, tp, gpersist);
+        }
     }
-    template <bool PRIMAL, bool G>
+    template <bool PRIMAL, bool G, bool AVG>
     void launch_tiles_g(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
         const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
         const bool big = tp.tile_nnz > 8 * kBlock;
@@ -1240,7 +1277,17 @@ struct Solver {
         if (sorted()) tp.slot = PRIMAL ? w.slot_at : w.slot_a;
 #define MIP_TILE_LAUNCH(K, U, SRT) \
     hipLaunchKernelGGL((K<T, V, Acc, PRIMAL, U, SRT, G>), grid, dim3(kBlock), lds, stream, a, tp)
-        if (persistent()) {
+#define MIP_AVG_LAUNCH(U, SRT) \
+    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, PRIMAL, U, SRT, G, true>), grid, dim3(kBlock), lds, stream, a, tp)
+        if constexpr (AVG) {
+            if (big) {
+                if (sorted()) MIP_AVG_LAUNCH(16, true);
+                else MIP_AVG_LAUNCH(16, false);
+            } else {
+                if (sorted()) MIP_AVG_LAUNCH(8, true);
+                else MIP_AVG_LAUNCH(8, false);
+            }
+        } else if (persistent()) {
             if (big) {
                 if (sorted()) MIP_TILE_LAUNCH(k_iter_persist, 16, true);
                 else MIP_TILE_LAUNCH(k_iter_persist, 16, false);
@@ -1258,6 +1305,7 @@ struct Solver {
             }
         }
 #undef MIP_TILE_LAUNCH
+#undef MIP_AVG_LAUNCH
     }
     int launch_primal(int it, int flags) {
         IterArgs<T, V> a;
@@ -1348,9 +1396,12 @@ struct Solver {
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, stream, d);
         MIP_LAUNCH_CHECK();
         const int64_t mx = std::max<int64_t>(lp.m, lp.n);
+        // the restart point: the evaluation's projected point, or the epoch average
+        const T* rx = (const T*)(o.restart_avg ? w.x_avg : w.xhat);
+        const T* ry = (const T*)(o.restart_avg ? w.y_avg : w.yhat);
         hipLaunchKernelGGL((k_apply_restart<T>), dim3(grid_for(mx)), dim3(kBlock), 0, stream,
-                           (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, (const T*)w.xhat, (int64_t)lp.n,
-                           (T*)w.y, (T*)w.y0, (const T*)w.yhat, (int64_t)lp.m);
+                           (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, rx, (int64_t)lp.n, (T*)w.y, (T*)w.y0, ry,
+                           (int64_t)lp.m);
         MIP_LAUNCH_CHECK();
         return 0;
     }
@@ -1409,7 +1460,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     const auto t0 = clk::now();
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
-                tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp));
+                tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
+                o.restart_avg != 0);
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1865,15 +1917,22 @@ namespace mip {
 static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp, const mipdhg_options& o) {
     char* const base = reinterpret_cast<char*>(uintptr_t(4096));  // layout only, never dereferenced
     const PlainWs w = carve(base, 0, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
-                            tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp));
+                            tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
+                            o.restart_avg != 0);
     const size_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
     const size_t m = (size_t)lp.m, n = (size_t)lp.n, G = (size_t)w.gcap;
     auto at = [&](const void* p, size_t bytes) { return std::make_pair((size_t)((const char*)p - base), bytes); };
-    return {at(w.ctrl, sizeof(Ctrl)),       at(w.pp, G * 3 * 8),          at(w.pd, G * 3 * 8),
-            at(w.per, G * kEvalRowsW * 8),  at(w.pec, G * kEvalColsW * 8), at(w.xprev, n * 8),
-            at(w.yprev, m * 8),             at(w.axprev, m * 8),          at(w.atyprev, n * 8),
-            at(w.x, n * ts),                at(w.x0, n * ts),             at(w.xhat, n * ts),
-            at(w.y, m * ts),                at(w.y0, m * ts),             at(w.yhat, m * ts)};
+    std::vector<std::pair<size_t, size_t>> r = {
+        at(w.ctrl, sizeof(Ctrl)),      at(w.pp, G * 3 * 8),          at(w.pd, G * 3 * 8),
+        at(w.per, G * kEvalRowsW * 8), at(w.pec, G * kEvalColsW * 8), at(w.xprev, n * 8),
+        at(w.yprev, m * 8),            at(w.axprev, m * 8),          at(w.atyprev, n * 8),
+        at(w.x, n * ts),               at(w.x0, n * ts),             at(w.xhat, n * ts),
+        at(w.y, m * ts),               at(w.y0, m * ts),             at(w.yhat, m * ts)};
+    if (o.restart_avg) {
+        r.push_back(at(w.x_avg, n * ts));
+        r.push_back(at(w.y_avg, m * ts));
+    }
+    return r;
 }
 
 static int state_copy(const mipdhg_lp* lp, const mipdhg_options* opt, char* ws, size_t ws_bytes, char* buf,
@@ -1937,6 +1996,9 @@ extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, doub
     if (!workspace || !x || !y || !z || !r_p || !r_d) return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
     if (is_general(*lp) && opt->spmv_kind == 1)
         return set_error("the general form runs on the tile kernels (spmv_kind 0 or 2)"), MIPDHG_ERR_UNSUPPORTED;
+    if (opt->restart_avg && opt->spmv_kind != 0)
+        return set_error("restart to average runs on the one-workgroup-per-tile kernels (spmv_kind 0)"),
+               MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:

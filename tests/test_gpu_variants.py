@@ -53,3 +53,43 @@ def test_pid_is_a_single_lp_option():
     with pytest.raises(P.MipdhgError) as e:
         P.solve_batched(batch, 1e-4, "fp32", pw_ki=0.1)
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(gather_order=1), dict(tile_nnz=4096, tile_nnz_at=512, tile_rows_at=64)])
+def test_restart_to_average_trace_parity(kw):
+    lp = lpgen.cfg2_sub(1, 100)
+    T = 320
+    opts = dict(halpern=0, restart_avg=1, eval_every=16)
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-12, "fp64", trace_iters=T, max_iter=T, **opts, **kw)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, trace_iters=T,
+                       opts=OracleOptions(max_iter=T, eval_every=16, halpern=False, restart_avg=True))
+    assert ref.restarts >= 3 and sol.info["restarts"] == ref.restarts
+    for t in range(1, T + 1):
+        xs, ys, xh, yh = ref.trace[t]
+        for key, r in (("x", xs), ("y", ys), ("xhat", xh), ("yhat", yh)):
+            assert _rel(_np(sol.trace[key][t - 1]), r) <= 1e-9, (t, key)
+
+
+@pytest.mark.parametrize("halpern", [0, 1])
+def test_restart_to_average_full_solve(halpern):
+    lp = lpgen.cfg1(2)
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-7, "fp64", halpern=halpern, restart_avg=1)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-7, opts=OracleOptions(halpern=bool(halpern), restart_avg=True))
+    assert sol.status == ref.status == 0
+    assert sol.info["iters"] == ref.iters and sol.info["restarts"] == ref.restarts
+    # float32 iterates reach the tolerance too
+    s32 = P.solve(P.DeviceLP.from_lp(lp), 1e-4, "fp32", halpern=halpern, restart_avg=1)
+    assert s32.status == 0
+
+
+def test_restart_to_average_limits():
+    lp = lpgen.cfg1(0)
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve(P.DeviceLP.from_lp(lp), 1e-4, "fp64", restart_avg=1, spmv_kind=2)
+    assert e.value.code == -6
+    batch = P.DeviceBatch.from_lps([lpgen.tiny(6, 15, 3, 0)])
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp32", restart_avg=1)
+    assert e.value.code == -6
+    best = P.autotune(P.DeviceLP.from_lp(lp), "fp64", iters=16, restart_avg=1)
+    assert best["spmv_kind"] == 0
