@@ -375,9 +375,9 @@ size_t mipdhg_sizeof(int which);
 /* Times every candidate shape of the two iteration SpMVs on this LP (lane
  * groups; LDS tiles of 1024..8192 nonzeros, 256 or 512 rows, chunked or
  * short-row-32 sums, one workgroup per tile or persistent; and tiles sized
- * so that their count is 4..8 per compute unit, from the row pointers) for
- * `iters`
- * iterations each, with per-kernel hipEvents.  For each spmv_kind it takes
+ * so that their count is 4..8 per compute unit, from the row pointers): each
+ * runs `iters` iterations, then 256 back-to-back launches of each kernel
+ * timed with hipEvents (kernel_timing = 2).  For each spmv_kind it takes
  * the fastest shape of the dual kernel (A's tiles) and of the primal kernel
  * (A^T's tiles) separately, and writes the kind with the smallest sum into
  * opt (spmv_kind, tile_nnz, tile_rows, short_row for A, the *_at fields for

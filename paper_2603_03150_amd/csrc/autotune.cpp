@@ -97,7 +97,7 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
         o.tile_nnz_at = c.tile_nnz_at;
         o.tile_rows_at = c.tile_rows_at;
         o.short_row_at = c.short_row_at;
-        o.kernel_timing = 1;
+        o.kernel_timing = 2;  // 256 back-to-back launches of each kernel, timed by events around them
         o.max_iter = iters;
         o.trace_iters = 0;
         o.resume = 0;
