@@ -68,7 +68,8 @@ in its own form.
 
 Restart to the average (a variant, off by default, meant for halpern = 0):
 the projected points of the current epoch are averaged with equal weights,
-avg <- avg + (z_hat - avg) / j after the epoch's j-th iteration; a restart
+avg = z_hat after the epoch's first iteration and avg <- avg + (z_hat - avg) / j
+after its j-th; a restart
 then moves the state and the anchor to that average instead of the last
 projected point, and the primal-weight update measures the distances of the
 average to the old anchor.  The restart tests themselves are unchanged.
@@ -470,10 +471,13 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
         w = (k + 1.0) / (k + 2.0) if opts.halpern else 1.0
         x_new = w * ((1.0 + rho) * x_hat - rho * x) + (1.0 - w) * x0
         y_new = w * ((1.0 + rho) * y_hat - rho * y) + (1.0 - w) * y0
-        if opts.restart_avg:
-            inv = 1.0 / (k + 1.0)
-            x_avg = x_avg + (x_hat - x_avg) * inv
-            y_avg = y_avg + (y_hat - y_avg) * inv
+        if opts.restart_avg:  # the mean of the epoch's points; the first is its own mean
+            if k == 0:
+                x_avg, y_avg = x_hat.copy(), y_hat.copy()
+            else:
+                inv = 1.0 / (k + 1.0)
+                x_avg = x_avg + (x_hat - x_avg) * inv
+                y_avg = y_avg + (y_hat - y_avg) * inv
         k += 1
         restarted = False
         if t % E == 0 or t == opts.max_iter:

@@ -302,8 +302,9 @@ struct IterPre {
 // the primal step projects onto [l, u] instead of x >= 0, the dual step
 // keeps y_i >= 0 on >= rows and y_i <= 0 on <= rows.
 // AVG: restart to average: the epoch's running mean of the projected points
-// is updated (avg += (h - avg) / j after the epoch's j-th iteration) and its
-// distance to the anchor replaces that of h in the evaluation partials.
+// is updated (avg = h after the epoch's first iteration, avg += (h - avg) / j
+// after its j-th) and its distance to the anchor replaces that of h in the
+// evaluation partials.
 template <typename T, typename V, bool PRIMAL, bool GEN, bool AVG = false>
 struct IterEpi {
     const IterArgs<T, V>& a;
@@ -324,7 +325,7 @@ struct IterEpi {
         w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
         omw = 1.0 - w;
         st = PRIMAL ? c->tau : c->sigma;
-        if (AVG) inv_j = 1.0 / (double)(k + 1);
+        if (AVG) inv_j = k == 0 ? 0.0 : 1.0 / (double)(k + 1);  // 0: the epoch's first point
     }
     // branch-free, so that the loads of all rows of a thread are in flight
     // together (the scaling factor is fetched by apply() on evaluations only)
@@ -368,9 +369,11 @@ struct IterEpi {
         const double an = (double)p.an;
         st_at(a.state + r0, i, (T)(w * (opr * h - rho * o) + omw * an));
         double rp = h;  // the restart point's entry
-        if (AVG) {
-            const double av = (double)p.av;
-            rp = av + (h - av) * inv_j;
+        if (AVG) {  // the epoch's mean; its first point is taken as it is (the buffer is not read)
+            if (inv_j != 0.0) {
+                const double av = (double)p.av;
+                rp = av + (h - av) * inv_j;
+            }
             st_at(a.avg + r0, i, (T)rp);
         }
         if (flags & (F_FIRST | F_EVAL)) {

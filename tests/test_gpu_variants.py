@@ -93,3 +93,18 @@ def test_restart_to_average_limits():
     assert e.value.code == -6
     best = P.autotune(P.DeviceLP.from_lp(lp), "fp64", iters=16, restart_avg=1)
     assert best["spmv_kind"] == 0
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(halpern=0, restart_avg=1), dict(restart_avg=1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_workspace_contents_do_not_matter(kw, prec):
+    # a workspace full of NaN bit patterns gives bitwise the solve of a zeroed one:
+    # nothing is read before the solve writes it (the epoch average included)
+    dlp = P.DeviceLP.from_lp(lpgen.cfg2_sub(0, 100))
+    nb = P.workspace_bytes(dlp, prec, **kw)
+    zero = torch.zeros(nb, dtype=torch.uint8, device=dlp.device)
+    junk = torch.full((nb,), 0xFF, dtype=torch.uint8, device=dlp.device)
+    a = P.solve(dlp, 1e-6, prec, workspace=zero, max_iter=2000, **kw)
+    b = P.solve(dlp, 1e-6, prec, workspace=junk, max_iter=2000, **kw)
+    assert a.status == b.status and a.status != 3
+    assert a.info["iters"] == b.info["iters"] and torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
