@@ -401,7 +401,7 @@ def main() -> int:
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(this build is single-GPU; sharding is described, not built)", file=sys.stderr)
+              "(the solver runs on a single GPU; how it would shard is described, not built)", file=sys.stderr)
         return 2
     import torch
 
