@@ -142,3 +142,16 @@ def test_exported_state_resumes_in_a_new_workspace(prec):
     # a state of other options does not import into this layout's checks
     with pytest.raises(P.MipdhgError):
         P.import_state(dlp, state[:-8], prec)
+
+
+@pytest.mark.parametrize("kw", [dict(halpern=0, restart_avg=1), dict(pw_ki=0.1, pw_kd=0.2)])
+def test_variant_states_export_and_resume(kw):
+    # the epoch averages and the PID state travel with the exported state
+    lp = lpgen.general_cfg1(2)
+    dlp = P.DeviceLP.from_lp(lp)
+    ref = P.solve(dlp, 1e-12, "fp64", max_iter=384, eval_every=32, **kw)
+    assert ref.info["restarts"] >= 2
+    a = P.solve(dlp, 1e-12, "fp64", max_iter=160, eval_every=32, **kw)
+    ws = P.import_state(dlp, P.export_state(dlp, a, "fp64", eval_every=32, **kw), "fp64", eval_every=32, **kw)
+    b = P.solve(dlp, 1e-12, "fp64", max_iter=384, eval_every=32, resume=ws, **kw)
+    _same(ref, b)
