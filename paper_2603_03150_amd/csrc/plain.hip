@@ -1509,7 +1509,6 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
                                hipMemcpyHostToDevice, stream));
     S.pa = device_plan(S.hpa, lp.a_rowptr, w.long_a, lp.m);
     S.pat = device_plan(S.hpat, lp.at_rowptr, w.long_at, lp.n);
-    const int ga = S.hpa.grid(), gat = S.hpat.grid();
     {
         const int32_t tnz = tile_nnz_of(o), trows = tile_rows_of(o), srow = short_row_of(o);
         const int32_t tnz_t = tile_nnz_at_of(o), trows_t = tile_rows_at_of(o), srow_t = short_row_at_of(o);
