@@ -1,44 +1,49 @@
 """Centered start point of Algorithm 1 (Section 3.1).  TEST INFRASTRUCTURE ONLY.
 
-Input: a PDHG solution (x, y, z) of the scaled LP and the parameters mu_min,
-delta_max, alpha_min (Section 3.1 reports 1e-6, 1e-4, 1e-6 as the best
-settings).  mu_target is the larger of the average complementarity x^T z / n
-of the given point and mu_min.  Every pair (x_j, z_j) is first lifted to at
-least alpha_min; then the smaller of the two is moved toward
-mu_target / (the other), by at most delta_max, and afterwards the other one
-toward mu_target / (the new smaller one), again by at most delta_max.  y is
-passed through.  When the interior-point solver cannot take a step,
-alpha_min grows tenfold and both vectors are lifted to it again.
+What the map computes, from a PDHG solution (x, y, z) of the scaled LP and
+the parameters mu_min, delta_max, alpha_min (Section 3.1 reports 1e-6, 1e-4,
+1e-6 as the best settings):
+
+  * mu_target = max(x^T z / n, mu_min), the average complementarity of the
+    given point, floored;
+  * each pair (x_j, z_j) is raised to at least alpha_min;
+  * the member of the pair that is strictly smaller (z when the two are
+    equal) is pulled toward mu_target divided by the other member; then the
+    other member is pulled toward mu_target divided by the new value of the
+    first.  Each pull ends where the target is, or delta_max away from the
+    value it started from, whichever is nearer;
+  * y is passed through unchanged.
+
+Afterwards, while the interior-point solver cannot take a step, alpha_min
+grows tenfold and both vectors are raised to it again (`reclamp`).
 
 Pins (tests/test_oracle_centering.py): hand-computed cases, and invariants
 that follow from the definition (moves bounded by delta_max, positivity,
-exact centering when the bounds do not bind).
+exact centring when the bounds do not bind).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
+def _pull(v: np.ndarray, target: np.ndarray, delta: float) -> np.ndarray:
+    """v moved to target, but by at most delta."""
+    return np.minimum(np.maximum(target, v - delta), v + delta)
+
+
 def center(x, z, mu_min: float = 1e-6, delta_max: float = 1e-4, alpha_min: float = 1e-6):
-    """Returns (x', z', mu_target), element by element as Algorithm 1 states."""
+    """Returns (x', z', mu_target) of Algorithm 1's centring map."""
     x = np.asarray(x, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
-    n = x.size
-    mu_t = max(float(x @ z) / n, mu_min)
-    xp = np.empty(n)
-    zp = np.empty(n)
-    for j in range(n):
-        a = max(x[j], alpha_min)
-        b = max(z[j], alpha_min)
-        if a < b:
-            a = min(max(mu_t / b, a - delta_max), a + delta_max)
-            b = min(max(mu_t / a, b - delta_max), b + delta_max)
-        else:
-            b = min(max(mu_t / a, b - delta_max), b + delta_max)
-            a = min(max(mu_t / b, a - delta_max), a + delta_max)
-        xp[j] = a
-        zp[j] = b
-    return xp, zp, mu_t
+    mu_t = max(float(x @ z) / x.size, mu_min)
+    xl = np.maximum(x, alpha_min)
+    zl = np.maximum(z, alpha_min)
+    x_moves_first = xl < zl
+    first = np.where(x_moves_first, xl, zl)
+    second = np.where(x_moves_first, zl, xl)
+    first = _pull(first, mu_t / second, delta_max)
+    second = _pull(second, mu_t / first, delta_max)
+    return np.where(x_moves_first, first, second), np.where(x_moves_first, second, first), mu_t
 
 
 def reclamp(xp, zp, alpha_min: float):

@@ -11,7 +11,8 @@
 namespace mip {
 
 // Optionally scales an original-space (x, z) to the scaled LP
-// (x~ = x / d_col, z~ = z * d_col) into xs/zs; partial sums of x~_j z~_j.
+// (x~ = x / d_col, z~ = z * d_col), kept in xs/zs unless they are NULL;
+// partial sums of x~_j z~_j.
 __global__ __launch_bounds__(kBlock) void k_center_dot(const double* x, const double* z, const double* d_col,
                                                        int64_t n, double* xs, double* zs, double* partials) {
     double s[1] = {0.0};
@@ -22,8 +23,10 @@ __global__ __launch_bounds__(kBlock) void k_center_dot(const double* x, const do
             xv = xv / d_col[j];
             zv = zv * d_col[j];
         }
-        xs[j] = xv;
-        zs[j] = zv;
+        if (xs) {
+            xs[j] = xv;
+            zs[j] = zv;
+        }
         s[0] += xv * zv;
     }
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
@@ -44,28 +47,31 @@ __global__ __launch_bounds__(kBlock) void k_center_mu(const double* partials, in
     if (threadIdx.x == 0) *mu = fmax(sh[0] / (double)n, mu_min);
 }
 
-__device__ __forceinline__ double clamp_move(double target, double from, double delta) {
-    return fmin(fmax(target, from - delta), from + delta);
+// v moved to target, but by at most delta
+__device__ __forceinline__ double pull(double v, double target, double delta) {
+    return fmin(fmax(target, v - delta), v + delta);
 }
 
-// the per-pair map: lift to alpha_min, move the smaller toward mu/other,
-// then the other toward mu/(new smaller), each by at most delta_max
+// The centring map of one pair, both members raised to alpha first: the
+// strictly smaller member (z on a tie) is pulled toward mu / (the other),
+// then the other toward mu / (the first's new value), each by at most delta.
+__device__ __forceinline__ void center_pair(double xv, double zv, double mu, double delta, double alpha,
+                                            double& xo, double& zo) {
+    const double xl = fmax(xv, alpha), zl = fmax(zv, alpha);
+    const bool x_first = xl < zl;
+    double first = x_first ? xl : zl, second = x_first ? zl : xl;
+    first = pull(first, mu / second, delta);
+    second = pull(second, mu / first, delta);
+    xo = x_first ? first : second;
+    zo = x_first ? second : first;
+}
+
+// the map over all pairs of an already scaled (xs, zs)
 __global__ void k_center_map(const double* xs, const double* zs, int64_t n, const double* mu_p, double delta,
                              double alpha, double* xo, double* zo) {
     const double mu = *mu_p;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        double a = fmax(xs[j], alpha);
-        double b = fmax(zs[j], alpha);
-        if (a < b) {
-            a = clamp_move(mu / b, a, delta);
-            b = clamp_move(mu / a, b, delta);
-        } else {
-            b = clamp_move(mu / a, b, delta);
-            a = clamp_move(mu / b, a, delta);
-        }
-        xo[j] = a;
-        zo[j] = b;
-    }
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        center_pair(xs[j], zs[j], mu, delta, alpha, xo[j], zo[j]);
 }
 
 __global__ void k_reclamp(double* x, double* z, int64_t n, double alpha) {
@@ -123,3 +129,4 @@ extern "C" int mipdhg_center_reclamp(int32_t n, double alpha_min, void* stream, 
     MIP_HIP(hipStreamSynchronize(s));
     return 0;
 }
+
