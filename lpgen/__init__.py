@@ -319,6 +319,29 @@ def simplex_lp(c: np.ndarray) -> LP:
     return LP(A, AT, np.array([1.0]), c.astype(np.float64), x, y, z, name="simplex")
 
 
+def slow_power_lp(seed: int = 0) -> LP:
+    """A 3 x 201 LP on which 100 power iterations of the scaled matrix have not
+    settled: [1] beside a 2 x 200 all-ones block with six entries negated.
+    After scaling the lone entry is a singular value 1 whose singular vector
+    holds weight 1/sqrt(201) of the uniform start, and the block's largest
+    singular value is about 0.985.  Planted optimum as elsewhere."""
+    B2 = np.ones((2, 200))
+    for k in range(6):
+        B2[k % 2, (7 * k) % 200] = -1.0
+    A = sp.csr_matrix(sp.block_diag([np.ones((1, 1)), B2]))
+    A.sort_indices()
+    rng = rng_for(10, seed)
+    m, n = A.shape
+    x = np.zeros(n)
+    supp = rng.permutation(n)[: n // 2]
+    x[supp] = rng.uniform(0.0, 1.0, supp.size)
+    y = rng.normal(size=m)
+    z = np.where(x > 0, 0.0, rng.uniform(0.0, 1.0, n))
+    AT = sp.csr_matrix(A.T)
+    AT.sort_indices()
+    return LP(A, AT, A @ x, AT @ y + z, x, y, z, name=f"slow_power_s{seed}")
+
+
 @dataclass
 class Batch:
     """Block-diagonal stacking of independent LPs (global column indices)."""

@@ -26,9 +26,13 @@ Pins (tests/test_oracle_*.py): planted optimum (closed form), brute-force
 vertex enumeration, scipy's HiGHS on the same LP, the m = 1 simplex LP, the
 fixed point of the PDHG operator at the planted optimum, firm
 nonexpansiveness of that operator in its metric, the Halpern O(1/k) residual
-bound, the KKT gap identity, hand-built termination cases, scaling
-invariants, sigma_hat against a dense SVD, and finite differences plus a
-tangent/adjoint dot-product test for the unrolled map.
+bound, a dense ten-line Chambolle-Pock loop (reflection 0, Halpern and
+restarts off), the KKT gap identity, hand-built termination cases, scaling
+invariants, sigma_hat against a dense SVD, hand-built cases at and just past
+every bound of the restart rule, the step rule and the initial primal weight
+(with a matrix whose power iteration has not settled after 100 iterations),
+a restart schedule derived by hand in integer arithmetic, and finite
+differences plus a tangent/adjoint dot-product test for the unrolled map.
 
 General form (bounds l <= x <= u and rows of sense =, >= or <=): the paper
 notes that practical models carry inequalities and variable bounds, that they
@@ -74,9 +78,11 @@ then moves the state and the anchor to that average instead of the last
 projected point, and the primal-weight update measures the distances of the
 average to the old anchor.  The restart tests themselves are unchanged.
 
-parity unpinned: the restart and primal-weight heuristics (which iterations
-restart, the omega sequence, iteration counts to a tolerance) follow a reading
-with no external reference; only GPU-versus-oracle agreement checks them.
+The restart rule, the primal-weight update and the step rule are pinned as
+definitions (hand-built cases above).  What no pin can fix is whether these
+constants are those of the solver the paper used: the iteration counts to a
+tolerance that follow from them are this reading's, compared GPU against
+oracle only.
 """
 from __future__ import annotations
 
@@ -145,6 +151,7 @@ class Result:
     omega: float
     log: list = field(default_factory=list)  # (t, restarted, omega after)
     trace: dict = field(default_factory=dict)  # t -> (x, y, x_hat, y_hat), scaled
+    evals: list = field(default_factory=list)  # (t, k, R, R0, R_prev) seen by each restart decision
 
 
 # ---------------------------------------------------------------------------
@@ -455,6 +462,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     R_prev = math.inf
     restarts = 0
     log = []
+    evals = []
     trace = {}
     E = max(1, int(opts.eval_every))
     prev = None  # the previous evaluated point (x, y), original space
@@ -496,7 +504,8 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                 if t <= trace_iters:
                     trace[t] = (x_new, y_new, x_hat, y_hat)
                 return Result(status, t, restarts, meas, d_row, d_col, sigma_hat, eta,
-                              omega0, omega, log, trace)
+                              omega0, omega, log, trace, evals)
+            evals.append((t, k, R, R0, R_prev))
             if opts.restarts and restart_due(R, R0, R_prev, k, t, opts):
                 px, py = (x_avg, y_avg) if opts.restart_avg else (x_hat, y_hat)
                 dx = float(np.linalg.norm(px - x0))

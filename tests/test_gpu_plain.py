@@ -190,6 +190,17 @@ def test_trace_parity_eval_every_one():
     _trace_parity(lpgen.tiny(6, 15, 3, 2), T=40, eval_every=1)
 
 
+def test_unsettled_power_iteration_takes_the_safe_step():
+    """A matrix whose power iteration is still turning after 100 iterations:
+    the GPU takes eta = safety, as the oracle does, and follows its iterates."""
+    lp = lpgen.slow_power_lp(0)
+    _trace_parity(lp, T=100)
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-9, "fp64")
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-9)
+    assert ref.eta == 0.95 and sol.info["eta"] == 0.95
+    assert sol.status == ref.status == 0 and sol.info["iters"] == ref.iters
+
+
 @pytest.mark.parametrize("eps", [1e-4, 1e-8])
 def test_solve_cfg1_fp64_matches_oracle(eps):
     lp = lpgen.cfg1(0)
