@@ -342,6 +342,30 @@ def slow_power_lp(seed: int = 0) -> LP:
     return LP(A, AT, A @ x, AT @ y + z, x, y, z, name=f"slow_power_s{seed}")
 
 
+def off_block_pair() -> "Batch":
+    """Two stacked instances (m = 25) whose A, and its exact transpose, carry
+    one entry of instance 0 in instance 1's columns and one of instance 1 in
+    instance 0's: row pointers, nonzero offsets and A^T = A^T all hold, only
+    the block-diagonal structure is broken (an invalid batch for validation
+    tests)."""
+    lps = [cfg4_instance(500 + i, 25) for i in range(2)]
+    good = stack_batch(lps)
+    ro, co = good.row_off, good.col_off
+    A = good.A.tocoo()
+    r, c, v = A.row.copy(), A.col.copy(), A.data.copy()
+    k0 = int(np.flatnonzero(r < ro[1])[0])
+    k1 = int(np.flatnonzero(r >= ro[1])[0])
+    used0 = set(c[r == r[k0]].tolist())
+    used1 = set(c[r == r[k1]].tolist())
+    c[k0] = next(j for j in range(co[1], co[2]) if j not in used0)
+    c[k1] = next(j for j in range(co[0], co[1]) if j not in used1)
+    Ab = sp.csr_matrix((v, (r, c)), shape=A.shape)
+    Ab.sort_indices()
+    ATb = sp.csr_matrix(Ab.T)
+    ATb.sort_indices()
+    return Batch(Ab, ATb, good.b, good.c, good.row_off, good.col_off, good.nnz_off, lps)
+
+
 @dataclass
 class Batch:
     """Block-diagonal stacking of independent LPs (global column indices)."""

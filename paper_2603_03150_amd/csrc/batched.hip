@@ -312,6 +312,42 @@ __global__ void k_check_blockdiag(const int32_t* rowptr, const int32_t* col, con
     }
 }
 
+int validate_blockdiag(const mipdhg_batch& bt, const std::vector<int32_t>& rpa, const std::vector<int32_t>& rpat,
+                       int32_t* tiles_a, int32_t* tiles_at, const int32_t* row_off_dev, const int32_t* col_off_dev,
+                       int32_t* flags, double* partials, double* red, hipStream_t stream) {
+    const mipdhg_lp& lp = bt.whole;
+    const std::vector<int32_t> ta = make_tile_desc(rpa, lp.m, kTileNnzDefault, kTileRowsDefault),
+                               tat = make_tile_desc(rpat, lp.n, kTileNnzDefault, kTileRowsDefault);
+    if (!tile_desc_ok(ta, rpa, lp.m, kTileNnzDefault, kTileRowsDefault) ||
+        !tile_desc_ok(tat, rpat, lp.n, kTileNnzDefault, kTileRowsDefault))
+        return set_error("internal: tile plan does not cover the rows"), MIPDHG_ERR_UNSUPPORTED;
+    MIP_HIP(hipMemcpyAsync(tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
+    const TilePlan pa = make_tile_plan(lp.a_rowptr, tiles_a, (int32_t)(ta.size() / 4), lp.m, kTileNnzDefault,
+                                       kTileRowsDefault, kShortRowDefault);
+    const TilePlan pat = make_tile_plan(lp.at_rowptr, tiles_at, (int32_t)(tat.size() / 4), lp.n, kTileNnzDefault,
+                                        kTileRowsDefault, kShortRowDefault);
+    int rc;
+    if ((rc = allow_validate_lds((int)std::max(tile_lds_bytes(pa, 8), tile_lds_bytes(pat, 8))))) return rc;
+    if ((rc = validate_device(lp, pa, pat, flags, partials, red, stream))) return rc;
+    MIP_HIP(hipMemsetAsync(flags, 0, 4, stream));
+    hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.a_rowptr, lp.a_col,
+                       row_off_dev, col_off_dev, bt.count, lp.m, flags);
+    hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.at_rowptr, lp.at_col,
+                       col_off_dev, row_off_dev, bt.count, lp.n, flags);
+    MIP_LAUNCH_CHECK();
+    int32_t f = 0;
+    MIP_HIP(hipMemcpyAsync(&f, flags, 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    if (f & 8) return set_error("an entry lies outside its instance's diagonal block"), MIPDHG_ERR_BAD_CSR;
+    return 0;
+}
+
+int64_t blockdiag_tile_slots(int64_t m, int64_t n, int64_t nnz) {
+    return std::max(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault),
+                    max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault));
+}
+
 struct BatchWs {
     int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
@@ -416,31 +452,10 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     MIP_HIP(hipMemcpyAsync(w.order, order.data(), B * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
-    if (o.validate) {
-        const std::vector<int32_t> ta = make_tile_desc(rpa, lp.m, kTileNnzDefault, kTileRowsDefault),
-                                   tat = make_tile_desc(rpat, lp.n, kTileNnzDefault, kTileRowsDefault);
-        if (!tile_desc_ok(ta, rpa, lp.m, kTileNnzDefault, kTileRowsDefault) ||
-            !tile_desc_ok(tat, rpat, lp.n, kTileNnzDefault, kTileRowsDefault))
-            return set_error("internal: tile plan does not cover the rows"), MIPDHG_ERR_UNSUPPORTED;
-        MIP_HIP(hipMemcpyAsync(w.tiles_a, ta.data(), ta.size() * 4, hipMemcpyHostToDevice, stream));
-        MIP_HIP(hipMemcpyAsync(w.tiles_at, tat.data(), tat.size() * 4, hipMemcpyHostToDevice, stream));
-        const TilePlan pa = make_tile_plan(lp.a_rowptr, w.tiles_a, (int32_t)(ta.size() / 4), lp.m, kTileNnzDefault,
-                                           kTileRowsDefault, kShortRowDefault);
-        const TilePlan pat = make_tile_plan(lp.at_rowptr, w.tiles_at, (int32_t)(tat.size() / 4), lp.n,
-                                            kTileNnzDefault, kTileRowsDefault, kShortRowDefault);
-        if ((rc = allow_validate_lds((int)std::max(tile_lds_bytes(pa, 8), tile_lds_bytes(pat, 8))))) return rc;
-        if ((rc = validate_device(lp, pa, pat, w.flags, w.partials, w.red, stream))) return rc;
-        MIP_HIP(hipMemsetAsync(w.flags, 0, 4, stream));
-        hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.m)), dim3(kBlock), 0, stream, lp.a_rowptr, lp.a_col,
-                           (const int32_t*)w.row_off, (const int32_t*)w.col_off, B, lp.m, w.flags);
-        hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(lp.n)), dim3(kBlock), 0, stream, lp.at_rowptr,
-                           lp.at_col, (const int32_t*)w.col_off, (const int32_t*)w.row_off, B, lp.n, w.flags);
-        MIP_LAUNCH_CHECK();
-        int32_t f = 0;
-        MIP_HIP(hipMemcpyAsync(&f, w.flags, 4, hipMemcpyDeviceToHost, stream));
-        MIP_HIP(hipStreamSynchronize(stream));
-        if (f & 8) return set_error("an entry lies outside its instance's diagonal block"), MIPDHG_ERR_BAD_CSR;
-    }
+    if (o.validate &&
+        (rc = validate_blockdiag(bt, rpa, rpat, w.tiles_a, w.tiles_at, w.row_off, w.col_off, w.flags, w.partials,
+                                 w.red, stream)))
+        return rc;
     BArgs<T, V> a;
     a.B = B;
     a.lds_m = max_m;

@@ -47,6 +47,17 @@ int check_rowptr(const std::vector<int32_t>& rp, int32_t nrows, int64_t nnz, con
 int validate_device(const mipdhg_lp& lp, const TilePlan& ta, const TilePlan& tat, int32_t* flags,
                     double* partials, double* red, hipStream_t stream);
 
+// Batched and unrolled solves: validate_device() on the whole block-diagonal
+// pair, then every entry of an instance's rows (of A and of A^T) checked to lie
+// in that instance's columns (rows).  rpa, rpat: the row pointers on the host;
+// tiles_a, tiles_at: 4 * blockdiag_tile_slots() ints each; row_off_dev,
+// col_off_dev: the instance offsets on the device; flags: 4 ints; partials:
+// blockdiag_tile_slots() + 16 doubles; red: 4 doubles.
+int validate_blockdiag(const mipdhg_batch& bt, const std::vector<int32_t>& rpa, const std::vector<int32_t>& rpat,
+                       int32_t* tiles_a, int32_t* tiles_at, const int32_t* row_off_dev, const int32_t* col_off_dev,
+                       int32_t* flags, double* partials, double* red, hipStream_t stream);
+int64_t blockdiag_tile_slots(int64_t m, int64_t n, int64_t nnz);
+
 int32_t tile_nnz_of(const mipdhg_options& o);
 int32_t tile_rows_of(const mipdhg_options& o);
 int32_t short_row_of(const mipdhg_options& o);

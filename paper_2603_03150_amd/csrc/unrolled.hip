@@ -423,6 +423,8 @@ struct TapeLayout {
     double *tbuf, *sbuf;
     void *lx, *lx0, *ly, *ly0;
     double *lct, *lbt;
+    int32_t *vtiles_a, *vtiles_at, *vflags;  // input validation (forward)
+    double *vpartials, *vred;
     int32_t W, nseg, nep;
     size_t bytes;
 };
@@ -477,6 +479,12 @@ static TapeLayout carve_tape(void* base, size_t cap, const mipdhg_batch& bt, int
     t.ly0 = cv.take<char>(m * ts);
     t.lct = cv.take<double>(n);
     t.lbt = cv.take<double>(m);
+    const int64_t vs_slots = blockdiag_tile_slots(m, n, nnz);
+    t.vtiles_a = cv.take<int32_t>(4 * vs_slots);
+    t.vtiles_at = cv.take<int32_t>(4 * vs_slots);
+    t.vflags = cv.take<int32_t>(64);
+    t.vpartials = cv.take<double>((size_t)vs_slots + 16);
+    t.vred = cv.take<double>(16);
     t.bytes = (cv.off + 255) & ~size_t(255);
     return t;
 }
@@ -538,6 +546,11 @@ static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K,
         MIP_HIP(hipMemcpyAsync(t.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(t.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
         MIP_HIP(hipMemcpyAsync(t.word_off, wo.data(), (B + 1) * 4, hipMemcpyHostToDevice, stream));
+        // column ranges, finiteness, A^T against A, and the block-diagonal
+        // structure, before any kernel indexes with the columns
+        if (o.validate && (rc = validate_blockdiag(bt, rpa, rpat, t.vtiles_a, t.vtiles_at, t.row_off, t.col_off,
+                                                   t.vflags, t.vpartials, t.vred, stream)))
+            return rc;
         if (!replay)
             hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for((int64_t)K * B)), dim3(kBlock), 0, stream,
                                (uint8_t*)t.restart, (int64_t)K * B);

@@ -127,3 +127,13 @@ def test_batched_rejects_off_block_entry():
     with pytest.raises(P.MipdhgError) as e:
         P.solve_batched(batch, 1e-4, "fp64")
     assert e.value.code in (-2, -3)
+
+
+def test_batched_rejects_consistent_off_block_pair():
+    """Off-block entries with A^T the exact transpose: only the block check
+    can see them."""
+    ob = lpgen.off_block_pair()
+    batch = P.DeviceBatch(ob.A, ob.AT, ob.b, ob.c, ob.row_off, ob.col_off, ob.nnz_off, device="cuda")
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp64")
+    assert e.value.code == -2 and "outside" in str(e.value)

@@ -150,3 +150,26 @@ def test_fp32_gradient_error_vs_fp64_oracle():
         assert np.all(np.isfinite(_seg(batch, gc, i)))
         assert ex <= 1e-2, (i, ex)
     print("fp32 unrolled relative errors (x_K, dL/dc):", errs)
+
+
+def _swapped_off_block_batch():
+    ob = lpgen.off_block_pair()
+    return P.DeviceBatch(ob.A, ob.AT, ob.b, ob.c, ob.row_off, ob.col_off, ob.nnz_off, device="cuda")
+
+
+def test_forward_rejects_off_block_entry_before_any_kernel():
+    batch = _swapped_off_block_batch()
+    umap = P.UnrolledMap(batch, K=20, ckpt_every=10, precision="fp64")
+    with pytest.raises(P.MipdhgError) as e:
+        umap.forward_raw(batch.lp.c, batch.lp.b)
+    assert e.value.code == -2 and "outside" in str(e.value)
+
+
+def test_forward_rejects_column_out_of_range():
+    lps, _ = _fd_set(2)
+    batch = P.DeviceBatch.from_lps(lps)
+    batch.lp.a_col[0] = batch.lp.n + 3
+    umap = P.UnrolledMap(batch, K=20, ckpt_every=10, precision="fp32")
+    with pytest.raises(P.MipdhgError) as e:
+        umap.forward_raw(batch.lp.c, batch.lp.b)
+    assert e.value.code == -2 and "range" in str(e.value)

@@ -1,5 +1,6 @@
 """The synthetic workloads have the stated shapes and a planted KKT point."""
 import numpy as np
+import scipy.sparse as sp
 
 import lpgen
 
@@ -62,3 +63,14 @@ def test_stack_batch():
     assert bt.A.shape == (94, sum(lp.n for lp in lps)) and list(bt.row_off) == [0, 20, 53, 94]
     x = np.concatenate([lp.x_star for lp in lps])
     assert np.abs(bt.A @ x - bt.b).max() < 1e-12
+
+
+def test_off_block_pair_breaks_only_the_block_structure():
+    ob = lpgen.off_block_pair()
+    assert abs(sp.csr_matrix(ob.A.T) - ob.AT).max() == 0.0
+    assert np.array_equal(ob.A.indptr[ob.row_off], ob.nnz_off)
+    assert np.array_equal(ob.AT.indptr[ob.col_off], ob.nnz_off)
+    A = ob.A.tocoo()
+    inst_r = np.searchsorted(ob.row_off, A.row, side="right") - 1
+    inst_c = np.searchsorted(ob.col_off, A.col, side="right") - 1
+    assert int(np.sum(inst_r != inst_c)) == 2
