@@ -362,6 +362,23 @@ int mipdhg_center_start(int32_t n, const double *x, const double *z, const doubl
                         double delta_max, double alpha_min, void *workspace, size_t workspace_bytes,
                         void *stream, double *x_out, double *z_out, double *mu_target);
 
+/* mipdhg_center_start without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as
+ * mipdhg_center_start; its scratch (partial sums, target, scaled copies) is a
+ * fixed device array of the library, 33.6 MB, held by every GPU the library
+ * runs on until the process ends.  n may be at most
+ * mipdhg_center_noalloc_max_n() (2,097,152 pairs); larger n returns
+ * MIPDHG_ERR_INVALID_ARG before any device work.  The call allocates nothing.
+ * Calls on one GPU share its scratch array: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller; sequential calls are independent (nothing in the scratch is read
+ * before it is written). */
+int32_t mipdhg_center_noalloc_max_n(void);
+int mipdhg_center_start_noalloc(int32_t n, const double *x, const double *z, const double *d_col, double mu_min,
+                                double delta_max, double alpha_min, void *stream, double *x_out, double *z_out,
+                                double *mu_target);
+
 /* The re-clamp of Algorithm 1's recovery loop (run after the caller has
  * raised alpha_min tenfold because the interior-point step was too small):
  * x_j <- max(x_j, alpha_min), z_j <- max(z_j, alpha_min), in place. */

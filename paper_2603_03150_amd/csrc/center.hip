@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "plain.h"
@@ -85,25 +86,68 @@ __global__ void k_reclamp(double* x, double* z, int64_t n, double alpha) {
 
 using namespace mip;
 
-extern "C" size_t mipdhg_center_workspace_size(int32_t n) {
-    const int G = grid_for(n, 1024);
+namespace {
+
+// Bytes the centring needs for n pairs: the partial sums of x~ z~ (one per
+// workgroup, at most 1,024), the target mu, and the scaled copies x~, z~.
+constexpr size_t center_bytes(int64_t n) {
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    const int64_t G = g < 1 ? 1 : (g > 1024 ? 1024 : g);
     return ((size_t)G * 8 + 255) / 256 * 256 + 256 + 2 * (((size_t)n * 8 + 255) / 256 * 256);
 }
 
-extern "C" int mipdhg_center_start(int32_t n, const double* x, const double* z, const double* d_col, double mu_min,
-                                   double delta_max, double alpha_min, void* workspace, size_t workspace_bytes,
-                                   void* stream, double* x_out, double* z_out, double* mu_target) {
-    clear_error();
-    if (n < 1 || !x || !z || !x_out || !z_out || !workspace)
-        return set_error("n >= 1 and non-NULL x, z, x_out, z_out, workspace are required"), MIPDHG_ERR_INVALID_ARG;
+// The allocation-free entry point keeps its scratch in this array: every
+// GPU the library runs on holds its own copy (33.6 MB) until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int32_t kNoAllocMaxN = 1 << 21;
+constexpr size_t kNoAllocBytes = center_bytes(kNoAllocMaxN);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch array, looked up once
+// per device (with that device current) and kept.
+int scratch_of_current_device(void** out) {
+    int dev = -1;
+    MIP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error("device ordinal %d out of range", dev), MIPDHG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error("hipGetSymbolAddress of the centring scratch failed: %s", hipGetErrorString(e)),
+                   MIPDHG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+int check_center_args(int32_t n, const double* x, const double* z, double mu_min, double delta_max,
+                      double alpha_min, const double* x_out, const double* z_out) {
+    if (n < 1 || !x || !z || !x_out || !z_out)
+        return set_error("n >= 1 and non-NULL x, z, x_out, z_out are required"), MIPDHG_ERR_INVALID_ARG;
     if (!(mu_min > 0.0) || !(delta_max >= 0.0) || !(alpha_min >= 0.0) || !std::isfinite(mu_min) ||
         !std::isfinite(delta_max) || !std::isfinite(alpha_min))
         return set_error("need mu_min > 0, delta_max >= 0, alpha_min >= 0, all finite"), MIPDHG_ERR_INVALID_ARG;
-    if (workspace_bytes < mipdhg_center_workspace_size(n))
-        return set_error("workspace too small"), MIPDHG_ERR_WORKSPACE;
-    if (((uintptr_t)workspace & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    Carver cv(workspace, workspace_bytes);
+    return 0;
+}
+
+// The three launches of the centring on a buffer of center_bytes(n) bytes.
+int center_run(int32_t n, const double* x, const double* z, const double* d_col, double mu_min, double delta_max,
+               double alpha_min, void* buf, size_t bytes, hipStream_t s, double* x_out, double* z_out,
+               double* mu_target) {
+    Carver cv(buf, bytes);
     const int G = grid_for(n, 1024);
     double* partials = cv.take<double>(G);
     double* mu = cv.take<double>(32);
@@ -117,6 +161,42 @@ extern "C" int mipdhg_center_start(int32_t n, const double* x, const double* z, 
     if (mu_target) MIP_HIP(hipMemcpyAsync(mu_target, mu, 8, hipMemcpyDeviceToHost, s));
     MIP_HIP(hipStreamSynchronize(s));
     return 0;
+}
+
+}  // namespace
+
+extern "C" size_t mipdhg_center_workspace_size(int32_t n) { return center_bytes(n); }
+
+extern "C" int mipdhg_center_start(int32_t n, const double* x, const double* z, const double* d_col, double mu_min,
+                                   double delta_max, double alpha_min, void* workspace, size_t workspace_bytes,
+                                   void* stream, double* x_out, double* z_out, double* mu_target) {
+    clear_error();
+    int rc = check_center_args(n, x, z, mu_min, delta_max, alpha_min, x_out, z_out);
+    if (rc) return rc;
+    if (!workspace) return set_error("workspace is NULL"), MIPDHG_ERR_INVALID_ARG;
+    if (workspace_bytes < mipdhg_center_workspace_size(n))
+        return set_error("workspace too small"), MIPDHG_ERR_WORKSPACE;
+    if (((uintptr_t)workspace & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
+    return center_run(n, x, z, d_col, mu_min, delta_max, alpha_min, workspace, workspace_bytes, (hipStream_t)stream,
+                      x_out, z_out, mu_target);
+}
+
+extern "C" int32_t mipdhg_center_noalloc_max_n(void) { return kNoAllocMaxN; }
+
+extern "C" int mipdhg_center_start_noalloc(int32_t n, const double* x, const double* z, const double* d_col,
+                                           double mu_min, double delta_max, double alpha_min, void* stream,
+                                           double* x_out, double* z_out, double* mu_target) {
+    clear_error();
+    int rc = check_center_args(n, x, z, mu_min, delta_max, alpha_min, x_out, z_out);
+    if (rc) return rc;
+    if (n > kNoAllocMaxN)
+        return set_error("n = %d is more than the %d pairs the allocation-free scratch holds; "
+                         "use mipdhg_center_start with a workspace", n, kNoAllocMaxN),
+               MIPDHG_ERR_INVALID_ARG;
+    void* buf = nullptr;
+    if ((rc = scratch_of_current_device(&buf))) return rc;
+    return center_run(n, x, z, d_col, mu_min, delta_max, alpha_min, buf, kNoAllocBytes, (hipStream_t)stream, x_out,
+                      z_out, mu_target);
 }
 
 extern "C" int mipdhg_center_reclamp(int32_t n, double alpha_min, void* stream, double* x_io, double* z_io) {
