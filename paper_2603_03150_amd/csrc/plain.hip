@@ -199,7 +199,8 @@ inline size_t sort_lds_bytes(const TilePlan& p) {
     return 8 * pw + 4 * (size_t)(p.tile_rows + 1);
 }
 
-// t[i] = d[i] * v[i] rounded to T; partial sums of squares in float64
+// t[i] = d[i] * v[i] rounded to T (unless out is NULL); partial sums of
+// squares in float64
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const double* d, int64_t n,
                                                       T* out, double* partials) {
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const dou
     double mx[1] = {0.0};
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         double t = d[i] * v[i];
-        out[i] = (T)t;
+        if (out) out[i] = (T)t;
         s[0] += t * t;
     }
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
@@ -262,17 +263,25 @@ __global__ __launch_bounds__(kBlock) void k_normalize(const double* u, double* v
 // ---------------------------------------------------------------------------
 // iteration kernels
 // ---------------------------------------------------------------------------
+// Iterates are held relative to the epoch's anchor (x0, y0): the state is
+// u = x - x0, v = y - y0, the extrapolation x_bar - x0, and the right-hand
+// sides are the anchor's residuals r_c = c~ - A~^T y0, r_b = b~ - A~ x0,
+// formed in float64 with the caller's matrix at every restart.  So
+// g = c~ - A~^T y = r_c - A~^T v and b~ - A~ x_bar = r_b - A~ (x_bar - x0):
+// the stored matrix and vectors only ever carry the epoch's movement, and
+// in reduced precision their rounding errors are relative to it (not to the
+// iterate).  The projected points x^, y^ are stored absolute.
 template <typename T, typename V>
 struct IterArgs {
     RowPlan p;
     const int32_t* col;
     const V* val;
-    const T* gather;   // y (primal) or x_bar (dual)
-    T* state;          // x or y
-    T* bar;            // x_bar (primal only)
-    T* hat;            // x^ or y^
+    const T* gather;   // v (primal) or x_bar - x0 (dual)
+    T* state;          // u or v
+    T* bar;            // x_bar - x0 (primal only)
+    T* hat;            // x^ or y^ (absolute)
     const T* anchor;   // Halpern anchor x0 or y0
-    const T* rhs;      // c~ or b~
+    const T* rhs;      // r_c or r_b
     double* out64;     // x or y of the original model, written at evaluations
     const double* dscale;  // D_c or D_r
     double* partials;  // [G][3]: ||o - h||^2 at the first iteration, same at the evaluation, ||h - anchor||^2
@@ -332,7 +341,9 @@ struct IterEpi {
     __device__ __forceinline__ Pre load(int r0, int i) const {
         Pre p;
         p.o = ld_at(a.state + r0, i);
-        p.an = ld_at(a.anchor + r0, i);
+        // the dual needs its anchor only to project (general form), to
+        // average, or to form y^ at stored iterations
+        p.an = (PRIMAL || GEN || AVG || (flags & F_HAT)) ? ld_at(a.anchor + r0, i) : (T)0;
         p.rhs = ld_at(a.rhs + r0, i);
         if (GEN && PRIMAL) {
             p.lo = ld_at(a.lo + r0, i);
@@ -343,48 +354,52 @@ struct IterEpi {
         return p;
     }
     // The arithmetic is float64 whatever the storage type T: the stored
-    // iterates are rounded once, at the store.
+    // iterates are rounded once, at the store.  dh is the projected point
+    // relative to the anchor (x^ - x0 or y^ - y0).
     template <typename Acc>
     __device__ __forceinline__ void apply(int r0, int i, const Pre& p, Acc s) const {
-        const double o = (double)p.o;
-        double h;
+        const double o = (double)p.o;    // u or v
+        const double an = (double)p.an;  // x0 or y0 (0 where the dual did not load it)
+        double dh;
         if (PRIMAL) {
-            const double g = (double)p.rhs - (double)s;
-            h = o - st * g;
-            if (GEN) {  // projection onto [l, u] (NaN propagates)
-                const double l = (double)p.lo, u = (double)p.hi;
-                h = h < l ? l : (h > u ? u : h);
+            const double g = (double)p.rhs - (double)s;  // c~ - A~^T y
+            dh = o - st * g;
+            if (GEN) {  // projection of x0 + dh onto [l, u] (NaN propagates)
+                const double l = (double)p.lo - an, u = (double)p.hi - an;
+                dh = dh < l ? l : (dh > u ? u : dh);
             } else {
-                h = h < 0.0 ? 0.0 : h;  // projection onto x >= 0 (NaN propagates)
+                dh = dh < -an ? -an : dh;  // projection onto x >= 0 (NaN propagates)
             }
-            st_at(a.bar + r0, i, (T)(2.0 * h - o));
+            st_at(a.bar + r0, i, (T)(2.0 * dh - o));
         } else {
-            h = o + st * ((double)p.rhs - (double)s);
-            if (GEN) {  // the sign each row's sense allows
-                if (p.sense == MIPDHG_SENSE_GE) h = h < 0.0 ? 0.0 : h;
-                else if (p.sense == MIPDHG_SENSE_LE) h = h > 0.0 ? 0.0 : h;
+            dh = o + st * ((double)p.rhs - (double)s);  // v + sigma (b~ - A~ x_bar)
+            if (GEN) {  // the sign each row's sense allows y0 + dh
+                if (p.sense == MIPDHG_SENSE_GE) dh = dh < -an ? -an : dh;
+                else if (p.sense == MIPDHG_SENSE_LE) dh = dh > -an ? -an : dh;
             }
         }
+        const double h = an + dh;  // x^ or y^
         if (flags & F_HAT) st_at(a.hat + r0, i, (T)h);
-        const double an = (double)p.an;
-        st_at(a.state + r0, i, (T)(w * (opr * h - rho * o) + omw * an));
-        double rp = h;  // the restart point's entry
+        // Halpern/reflection step; the anchor is 0 in these coordinates
+        st_at(a.state + r0, i, (T)(w * (opr * dh - rho * o)));
+        double rd = dh;  // the restart point's distance to the anchor
         if (AVG) {  // the epoch's mean; its first point is taken as it is (the buffer is not read)
+            double rp = h;
             if (inv_j != 0.0) {
                 const double av = (double)p.av;
                 rp = av + (h - av) * inv_j;
             }
             st_at(a.avg + r0, i, (T)rp);
+            rd = rp - an;
         }
         if (flags & (F_FIRST | F_EVAL)) {
-            double d = o - h;
+            double d = o - dh;
             d *= d;
             if (flags & F_FIRST) q[0] += d;
             if (flags & F_EVAL) q[1] += d;
         }
         if (flags & F_EVAL) {
-            const double d = rp - an;
-            q[2] += d * d;
+            q[2] += rd * rd;
             st_at(a.out64 + r0, i, ld_at(a.dscale + r0, i) * h);
         }
     }
@@ -737,23 +752,44 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     }
 }
 
-// on a restart: state and anchor <- projected point
+// on a restart: anchor <- restart point, state (relative to it) <- 0
 template <typename T>
 __global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t n, T* y, T* y0,
                                 const T* yh, int64_t m) {
     if (!c->restart_now) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const T v = xh[i];
-        x[i] = v;
-        x0[i] = v;
+        x0[i] = xh[i];
+        x[i] = (T)0;
     }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const T v = yh[i];
-        y[i] = v;
-        y0[i] = v;
+        y0[i] = yh[i];
+        y[i] = (T)0;
     }
+}
+
+// The anchor's residuals in float64 on the caller's matrix, rounded once to
+// T: over A's rows r_b = D_r (b - A D_c x0), over A^T's rows
+// r_c = D_c (c - A^T D_r y0) (d_self, d_other: the row and column factors of
+// the matrix walked; anchor: the anchor of the other side).  Runs at setup
+// (force) and after a restart.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_anchor_resid(TilePlan tp, const int32_t* col, const double* val,
+                                                         const double* d_self, const double* d_other,
+                                                         const double* vec, const T* anchor, T* out,
+                                                         const Ctrl* ctrl, int force) {
+    if (!force && !ctrl->restart_now) return;
+    extern __shared__ __align__(16) unsigned char smem_t[];
+    const auto L = tile_lds<double>(smem_t, tp);
+    auto prod = [&](int b, int j) {
+        const int64_t k = (int64_t)b + j;
+        const int32_t cc = ld_idx(col, k);
+        return ld_val(val, k) * (d_other[cc] * (double)anchor[cc]);
+    };
+    auto epi = [&](int r, double t) { out[r] = (T)(d_self[r] * (vec[r] - t)); };
+    auto le = lepi(epi);
+    tiled_rows<false>(tp, own_tile(), L, prod, le);
 }
 
 // general form: scaled bounds l / D_c and u / D_c (NULL lo: 0, NULL hi: +inf)
@@ -765,23 +801,24 @@ __global__ void k_scale_bounds(const double* lo, const double* hi, const double*
     }
 }
 
-// initial point: state = anchor = init / d (or 0)
+// initial point: anchor = projected point = init / d (or 0), state 0
 template <typename T>
 __global__ void k_init_state(const double* init, const double* d, int64_t n, T* s, T* s0, T* hat) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const T v = init ? (T)(init[i] / d[i]) : (T)0;
-        s[i] = v;
+        s[i] = (T)0;
         s0[i] = v;
         hat[i] = v;
     }
 }
 
+// dst = src (+ base): the absolute iterate from the anchor and the state
 template <typename T>
-__global__ void k_export(const T* src, double* dst, int64_t n) {
+__global__ void k_export(const T* src, const T* base, double* dst, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = (double)src[i];
+        dst[i] = base ? (double)base[i] + (double)src[i] : (double)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -975,6 +1012,9 @@ struct PlainWs {
     double *pp, *pd, *per, *pec, *psetup;
     int64_t gcap;  // partial slots per kernel
     void *a_vs, *at_vs;
+    // iterates relative to the anchors (u = x - x0 in x, v = y - y0 in y,
+    // x_bar - x0 in xbar), anchors, absolute projected points, and the
+    // anchor residuals r_c (in ct) and r_b (in bt)
     void *x, *xbar, *x0, *xhat, *ct, *y, *y0, *yhat, *bt;
     int32_t *long_a, *long_at, *tiles_a, *tiles_at, *flags;
     int32_t *col_a, *col_at;    // sorted layout: column copies in tile order
@@ -1175,6 +1215,7 @@ struct Solver {
                                 (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
+                                (const void*)k_anchor_resid<T>,
                                 (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
 #undef MIP_ITER_KERNELS
 #undef MIP_AVG_KERNELS
@@ -1406,6 +1447,17 @@ struct Solver {
                            (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, rx, (int64_t)lp.n, (T*)w.y, (T*)w.y0, ry,
                            (int64_t)lp.m);
         MIP_LAUNCH_CHECK();
+        return launch_anchor_resid(0);
+    }
+    // r_b, r_c of the current anchor (force: whatever the restart flag says)
+    int launch_anchor_resid(int force) {
+        hipLaunchKernelGGL((k_anchor_resid<T>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, ta,
+                           lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, lp.b,
+                           (const T*)w.x0, (T*)w.bt, (const Ctrl*)w.ctrl, force);
+        hipLaunchKernelGGL((k_anchor_resid<T>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, tat,
+                           lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.c,
+                           (const T*)w.y0, (T*)w.ct, (const Ctrl*)w.ctrl, force);
+        MIP_LAUNCH_CHECK();
         return 0;
     }
     // One block of nit iterations ending in an evaluation.  With trace, the
@@ -1426,16 +1478,16 @@ struct Solver {
                 const int64_t off_n = (t - 1) * (int64_t)lp.n, off_m = (t - 1) * (int64_t)lp.m;
                 if (o.trace_x)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
-                                       (const T*)w.x, o.trace_x + off_n, (int64_t)lp.n);
+                                       (const T*)w.x, (const T*)w.x0, o.trace_x + off_n, (int64_t)lp.n);
                 if (o.trace_y)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
-                                       (const T*)w.y, o.trace_y + off_m, (int64_t)lp.m);
+                                       (const T*)w.y, (const T*)w.y0, o.trace_y + off_m, (int64_t)lp.m);
                 if (o.trace_xhat)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
-                                       (const T*)w.xhat, o.trace_xhat + off_n, (int64_t)lp.n);
+                                       (const T*)w.xhat, (const T*)nullptr, o.trace_xhat + off_n, (int64_t)lp.n);
                 if (o.trace_yhat)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
-                                       (const T*)w.yhat, o.trace_yhat + off_m, (int64_t)lp.m);
+                                       (const T*)w.yhat, (const T*)nullptr, o.trace_yhat + off_m, (int64_t)lp.m);
                 MIP_LAUNCH_CHECK();
             }
         }
@@ -1586,11 +1638,11 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     {
         const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
         hipLaunchKernelGGL((k_scale_vec<T>), dim3(gm), dim3(kBlock), 0, stream, lp.b, (const double*)w.d_row, m,
-                           (T*)w.bt, w.psetup);
+                           (T*)nullptr, w.psetup);
         hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gm, 1,
                            w.red + 2);
         hipLaunchKernelGGL((k_scale_vec<T>), dim3(gn), dim3(kBlock), 0, stream, lp.c, (const double*)w.d_col, n,
-                           (T*)w.ct, w.psetup + G);
+                           (T*)nullptr, w.psetup + G);
         hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream,
                            (const double*)(w.psetup + G), gn, 1, w.red + 3);
         MIP_LAUNCH_CHECK();
@@ -1720,6 +1772,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, o.y_init,
                            (const double*)w.d_row, m, (T*)w.y, (T*)w.y0, (T*)w.yhat);
         MIP_LAUNCH_CHECK();
+        if ((rc = S.launch_anchor_resid(1))) return rc;
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.xprev, n, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.yprev, m, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.atyprev, n, 0.0);
@@ -1893,10 +1946,13 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         info->ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
         const double vs = sizeof(V), ts = sizeof(T);
         // per iteration: A and A^T values + indices, row pointers, gathers,
-        // streamed vectors (x, x0, c~, x_bar written; y, y0, b~)
-        // general form: the primal reads two scaled bounds per column, the dual one sense byte per row
+        // streamed vectors (primal: u, x0, r_c read, u, x_bar - x0 written;
+        // dual: v, r_b read, v written)
+        // general form: the primal reads two scaled bounds per column, the
+        // dual its anchor and one sense byte per row
         info->bytes_primal = nnz * (vs + 4.0) + 4.0 * (n + 1) + ts * (double)m + (has_bounds(lp) ? 7.0 : 5.0) * ts * n;
-        info->bytes_dual = nnz * (vs + 4.0) + 4.0 * (m + 1) + ts * (double)n + 4.0 * ts * m + (has_sense(lp) ? m : 0);
+        info->bytes_dual = nnz * (vs + 4.0) + 4.0 * (m + 1) + ts * (double)n + 3.0 * ts * m +
+                           (has_sense(lp) ? (ts + 1.0) * m : 0.0);
         info->bytes_per_iter = info->bytes_primal + info->bytes_dual;
         info->ms_primal = S.n_p ? S.ms_p / S.n_p : 0.0;
         info->ms_dual = S.n_d ? S.ms_d / S.n_d : 0.0;
@@ -1929,7 +1985,8 @@ static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp,
         at(w.per, G * kEvalRowsW * 8), at(w.pec, G * kEvalColsW * 8), at(w.xprev, n * 8),
         at(w.yprev, m * 8),            at(w.axprev, m * 8),          at(w.atyprev, n * 8),
         at(w.x, n * ts),               at(w.x0, n * ts),             at(w.xhat, n * ts),
-        at(w.y, m * ts),               at(w.y0, m * ts),             at(w.yhat, m * ts)};
+        at(w.y, m * ts),               at(w.y0, m * ts),             at(w.yhat, m * ts),
+        at(w.ct, n * ts),              at(w.bt, m * ts)};
     if (o.restart_avg) {
         r.push_back(at(w.x_avg, n * ts));
         r.push_back(at(w.y_avg, m * ts));
