@@ -300,8 +300,9 @@ typedef struct mipdhg_batch {
 /* Bytes of device workspace mipdhg_solve_batched needs. */
 int mipdhg_batch_workspace_size(const mipdhg_batch *batch, const mipdhg_options *opt, size_t *bytes);
 
-/* Solve every instance of the batch to eps_rel (the Section 2 tests, each
- * instance on its own norms), in one persistent kernel launch: one workgroup
+/* Solve every instance i of the batch to its own eps_rel[i] (eps_rel: HOST
+ * array of `count` tolerances, each finite and >= 0; the Section 2 tests,
+ * each instance on its own norms), in one persistent kernel launch: one workgroup
  * per instance at a time, instances taken largest first from a queue, each
  * with its own scaling, step, primal weight, restarts and termination.
  * Outputs are the stacked per-instance vectors (device float64, same layout as
@@ -311,7 +312,7 @@ int mipdhg_batch_workspace_size(const mipdhg_batch *batch, const mipdhg_options 
  * An instance needs (m_i + n_i) * sizeof(iterate) bytes of LDS, at most
  * 150 KiB; larger instances return MIPDHG_ERR_UNSUPPORTED.  Tracing, warm
  * starts and kernel timing are not available here. */
-int mipdhg_solve_batched(const mipdhg_batch *batch, const mipdhg_options *opt, double eps_rel,
+int mipdhg_solve_batched(const mipdhg_batch *batch, const mipdhg_options *opt, const double *eps_rel,
                          void *workspace, size_t workspace_bytes, void *stream,
                          double *x, double *y, double *z, double *r_p, double *r_d,
                          mipdhg_info *info);

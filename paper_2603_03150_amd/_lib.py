@@ -74,7 +74,7 @@ SIGNATURES = {
                                _p, _p, _p, _p, _p, _p, _p, C.POINTER(InfoStruct)]),
     "mipdhg_batch_workspace_size": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct),
                                               C.POINTER(C.c_size_t)]),
-    "mipdhg_solve_batched": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _f64, _p, C.c_size_t,
+    "mipdhg_solve_batched": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _p, _p, C.c_size_t,
                                        _p, _p, _p, _p, _p, _p, _p]),
     "mipdhg_unrolled_tape_size": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32,
                                             C.POINTER(C.c_size_t)]),

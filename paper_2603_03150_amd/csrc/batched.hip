@@ -50,7 +50,8 @@ struct BArgs {
     double *xo, *yo, *zo, *rpo, *rdo;
     BInst* info;
     int32_t* counter;
-    double eps, step_safety, rho, beta_suff, beta_nec, beta_art, theta;
+    const double* eps;  // per-instance eps_rel
+    double step_safety, rho, beta_suff, beta_nec, beta_art, theta;
     int64_t max_iter;
     int32_t ruiz, pc, power_iters, eval_every, halpern, restarts;
 };
@@ -68,6 +69,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     const double b_norm = su.b_norm, c_norm = su.c_norm, sigma_hat = su.sigma_hat, eta = su.eta,
                  omega0 = su.omega0;
     double omega = omega0, tau = eta / omega, sig = eta * omega;
+    const double eps = a.eps[inst];
 
     // initial point (0, 0)
     for (int j = tid; j < n; j += kBatchBlock) {
@@ -215,8 +217,8 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         const double rp = sqrt(ev[0]), rd = sqrt(ev[2]), pobj = ev[3], dobj = ev[1];
         const double gap = fabs(pobj - dobj);
         if (!(isfinite(ev[0]) && isfinite(ev[2]) && isfinite(pobj) && isfinite(dobj))) status = MIPDHG_NUMERICAL;
-        else if (rp <= a.eps * (1.0 + b_norm) && rd <= a.eps * (1.0 + c_norm) &&
-                 gap <= a.eps * (1.0 + fabs(pobj) + fabs(dobj)))
+        else if (rp <= eps * (1.0 + b_norm) && rd <= eps * (1.0 + c_norm) &&
+                 gap <= eps * (1.0 + fabs(pobj) + fabs(dobj)))
             status = MIPDHG_OPTIMAL;
         else if (t >= a.max_iter) status = MIPDHG_ITER_LIMIT;
         if (status >= 0) break;
@@ -351,7 +353,7 @@ int64_t blockdiag_tile_slots(int64_t m, int64_t n, int64_t nnz) {
 struct BatchWs {
     int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
-    double *d_row, *d_col, *pv, *pu, *pav, *partials, *red;
+    double *d_row, *d_col, *pv, *pu, *pav, *partials, *red, *eps;
     void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
     size_t bytes;
 };
@@ -369,6 +371,7 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault));
     w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault));
     w.info = cv.take<BInst>(B);
+    w.eps = cv.take<double>(B);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
     w.pv = cv.take<double>(n);
@@ -412,7 +415,7 @@ static int lds_bytes_for(int max_m, int max_n, size_t ts) {
 }
 
 template <typename T, typename V, typename Acc>
-static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double eps, void* ws, size_t ws_bytes,
+static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const double* eps, void* ws, size_t ws_bytes,
                         hipStream_t stream, double* x, double* y, double* z, double* r_p, double* r_d,
                         mipdhg_info* info) {
     using clk = std::chrono::steady_clock;
@@ -451,6 +454,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     });
     MIP_HIP(hipMemcpyAsync(w.order, order.data(), B * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(w.eps, eps, (size_t)B * 8, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     if (o.validate &&
         (rc = validate_blockdiag(bt, rpa, rpat, w.tiles_a, w.tiles_at, w.row_off, w.col_off, w.flags, w.partials,
@@ -492,7 +496,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, double 
     a.rdo = r_d;
     a.info = w.info;
     a.counter = w.counter;
-    a.eps = eps;
+    a.eps = w.eps;
     a.step_safety = o.step_safety;
     a.rho = o.reflect_rho;
     a.beta_suff = o.beta_suff;
@@ -580,7 +584,7 @@ extern "C" int mipdhg_batch_workspace_size(const mipdhg_batch* bt, const mipdhg_
     return 0;
 }
 
-extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options* opt, double eps_rel,
+extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options* opt, const double* eps_rel,
                                     void* workspace, size_t workspace_bytes, void* stream, double* x, double* y,
                                     double* z, double* r_p, double* r_d, mipdhg_info* info) {
     clear_error();
@@ -588,7 +592,10 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
     if (rc) return rc;
     if (!opt) return set_error("options are NULL"), MIPDHG_ERR_INVALID_ARG;
     if ((rc = check_options(opt))) return rc;
-    if (!(eps_rel >= 0.0) || !std::isfinite(eps_rel)) return set_error("eps_rel must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
+    if (!eps_rel) return set_error("eps_rel (one per instance) is NULL"), MIPDHG_ERR_INVALID_ARG;
+    for (int i = 0; i < bt->count; ++i)
+        if (!(eps_rel[i] >= 0.0) || !std::isfinite(eps_rel[i]))
+            return set_error("eps_rel[%d] must be finite and >= 0", i), MIPDHG_ERR_INVALID_ARG;
     if (!workspace || !x || !y || !z || !r_p || !r_d)
         return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
     if (is_general(bt->whole))

@@ -276,9 +276,10 @@ class BatchSolution:
                 "r_d": self.r_d[c0:c1], "info": self.infos[i]}
 
 
-def solve_batched(batch: DeviceBatch, eps: float = 1e-4, precision: str = "fp32",
+def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
                   workspace: torch.Tensor | None = None, **opts) -> BatchSolution:
-    """Run mipdhg_solve_batched on every instance of the batch."""
+    """Run mipdhg_solve_batched on every instance of the batch; eps is one
+    tolerance for all instances or a sequence of one per instance."""
     lib = _lib.load()
     o = make_options(precision, **opts)
     st = batch.struct()
@@ -293,7 +294,8 @@ def solve_batched(batch: DeviceBatch, eps: float = 1e-4, precision: str = "fp32"
     r_p, r_d = torch.empty(m, **f64), torch.empty(n, **f64)
     infos = (_lib.InfoStruct * batch.count)()
     stream = torch.cuda.current_stream(d).cuda_stream
-    rc = lib.mipdhg_solve_batched(C.byref(st), C.byref(o), float(eps), workspace.data_ptr(), workspace.numel(),
+    eps_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (batch.count,)))
+    rc = lib.mipdhg_solve_batched(C.byref(st), C.byref(o), eps_arr.ctypes.data, workspace.data_ptr(), workspace.numel(),
                                   stream, x.data_ptr(), y.data_ptr(), z.data_ptr(), r_p.data_ptr(),
                                   r_d.data_ptr(), infos)
     _lib.check(rc)

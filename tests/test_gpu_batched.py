@@ -137,3 +137,29 @@ def test_batched_rejects_consistent_off_block_pair():
     with pytest.raises(P.MipdhgError) as e:
         P.solve_batched(batch, 1e-4, "fp64")
     assert e.value.code == -2 and "outside" in str(e.value)
+
+
+def test_batched_per_instance_tolerances():
+    """Each instance stops by its own eps_rel (Section 2 tests): the same LP
+    twice at 1e-3 and 1e-7 takes the iterations the single-LP solve takes at
+    each tolerance, and each returned point passes its own tests."""
+    lp = lpgen.cfg1(2)
+    eps = [1e-3, 1e-7]
+    b = P.solve_batched(P.DeviceBatch.from_lps([lp, lp]), eps, "fp64")
+    nb, nc = np.linalg.norm(lp.b), np.linalg.norm(lp.c)
+    its = []
+    for i, e in enumerate(eps):
+        p = P.solve(P.DeviceLP.from_lp(lp), e, "fp64")
+        assert b.infos[i]["status"] == 0 and b.infos[i]["iters"] == p.info["iters"], (i, e)
+        its.append(b.infos[i]["iters"])
+        x = _np(b.x)[lp.n * i:lp.n * (i + 1)]
+        y = _np(b.y)[lp.m * i:lp.m * (i + 1)]
+        rp = lp.b - lp.A @ x
+        rd = lp.c - lp.AT @ y - np.maximum(lp.c - lp.AT @ y, 0.0)
+        pv, dv = lp.c @ x, lp.b @ y
+        assert np.linalg.norm(rp) <= e * (1 + nb) and np.linalg.norm(rd) <= e * (1 + nc)
+        assert abs(pv - dv) <= e * (1 + abs(pv) + abs(dv))
+    assert its[0] < its[1]
+    # a tolerance per instance is required, each finite and >= 0
+    with pytest.raises(P.MipdhgError):
+        P.solve_batched(P.DeviceBatch.from_lps([lp, lp]), [1e-4, float("nan")], "fp64")
