@@ -87,6 +87,25 @@ def test_batched_fp64_iteration_limit_and_options():
         assert _rel(_np(got["x"]), ref.meas.x) <= 1e-10
 
 
+@pytest.mark.parametrize("T", [1, 64, 100, 257])
+def test_batched_fp64_iterates_match_oracle_at_default_options(T):
+    """Per-iterate parity with the default options (Halpern, reflection 1,
+    restarts): cut at iteration T by the iteration limit, every instance's
+    evaluated point equals the oracle's after T iterations, on sizes up to
+    m = 2,000 (LDS-resident instances of every size the batch holds)."""
+    sizes = [20, 150, 700, 2000]
+    lps = [lpgen.cfg4_instance(600 + i, m) for i, m in enumerate(sizes)]
+    batch = P.DeviceBatch.from_lps(lps)
+    sol = P.solve_batched(batch, 1e-14, "fp64", max_iter=T)
+    for i, lp in enumerate(lps):
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-14, opts=OracleOptions(max_iter=T))
+        got = sol.split(batch, i)
+        assert got["info"]["status"] == ref.status == 1 and got["info"]["iters"] == T
+        assert got["info"]["restarts"] == ref.restarts, i
+        assert _rel(_np(got["x"]), ref.meas.x) <= 1e-10, (i, T)
+        assert _rel(_np(got["y"]), ref.meas.y) <= 1e-10, (i, T)
+
+
 def test_batched_fp32_reaches_tolerance():
     lps = [lpgen.cfg4_instance(200 + i, m) for i, m in enumerate(_sizes(64, 20, 2000, seed=1))]
     batch = P.DeviceBatch.from_lps(lps)

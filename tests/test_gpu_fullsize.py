@@ -1,4 +1,5 @@
-"""Parity at the full sizes, in the launch configuration bench.py times.
+"""Parity at the full sizes, in the launch configuration bench.py times (the tile shapes
+mipdhg_autotune picks for each LP and precision).
 
 The oracle cannot iterate the full LPs in a test's time, but it can recompute
 any single entry of one PDHG step from the previous iterate: the GPU's own
@@ -6,7 +7,9 @@ iterate after iteration 1 (exported by the trace) is fed to the oracle's step
 (its own float64 scaling of the caller's matrix, the step sizes the GPU
 reports), and a random sample of the entries of iteration 2 — x_hat and the
 Halpern state on sampled columns, y_hat on sampled rows — is compared.
-FP64 to 1e-10, float32 iterates (float32 matrix values) to 1e-5.  The
+FP64 to 1e-10, float32 iterates (float32 matrix values) to 1e-5, BF16
+matrix values (the oracle's step on its scaled matrix rounded to BF16) to
+1e-5.  The
 general-form LP of the benchmark is checked the same way with its bound and
 sign projections.
 """
@@ -22,11 +25,31 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2603_03150_amd")
 torch = pytest.importorskip("torch")
 
-# the shapes the autotuner picks for these LPs (A's tiles, then A^T's)
-SHAPES = {"power_law": dict(spmv_kind=0, tile_nnz=2048, tile_rows=512, short_row=-1, tile_nnz_at=2048,
-                            tile_rows_at=256, short_row_at=32),
-          "block_angular": dict(spmv_kind=0, tile_nnz=8192, tile_rows=512, short_row=32, tile_nnz_at=4096,
-                                tile_rows_at=512, short_row_at=32)}
+_LPS = {}
+_SHAPES = {}
+_KEYS = ("spmv_kind", "tile_nnz", "tile_rows", "short_row", "tile_nnz_at", "tile_rows_at", "short_row_at")
+
+
+def _lp(name):
+    if name not in _LPS:
+        _LPS[name] = {"power_law": lpgen.cfg2, "block_angular": lpgen.cfg3, "general": lpgen.general_cfg2}[name](0)
+    return _LPS[name]
+
+
+def _tuned(name, prec):
+    """The shape mipdhg_autotune picks for this LP and precision: the launch
+    configuration bench.py times (its CU-balanced tile sizes included)."""
+    if (name, prec) not in _SHAPES:
+        best = P.autotune(P.DeviceLP.from_lp(_lp(name)), prec, iters=64)
+        _SHAPES[(name, prec)] = {k: best[k] for k in _KEYS}
+    return _SHAPES[(name, prec)]
+
+
+def _bf16(v):
+    """Round to bfloat16 (nearest even) through float32, as the library does."""
+    u = np.asarray(v, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def _np(t):
@@ -43,6 +66,9 @@ def _one_step_check(lp, prec, shape, tol, samples=3000, seed=0):
     tr = {k: _np(v) for k, v in sol.trace.items()}
     d_row, d_col, At = scale(lp.A)
     assert _rel(_np(sol.d_row), d_row) <= 1e-12 and _rel(_np(sol.d_col), d_col) <= 1e-12
+    if prec == "bf16":  # the matrix the iteration applies: scaled values rounded to BF16
+        At = At.copy()
+        At.data = _bf16(At.data)
     bt, ct = d_row * lp.b, d_col * lp.c
     info = sol.info
     tau, sig = info["eta"] / info["omega0"], info["eta"] * info["omega0"]
@@ -78,17 +104,17 @@ def _one_step_check(lp, prec, shape, tol, samples=3000, seed=0):
     assert _rel(tr["yhat"][1][I], yh) <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16", 1e-5)])
 def test_one_step_parity_full_power_law(prec, tol):
-    _one_step_check(lpgen.cfg2(0), prec, SHAPES["power_law"], tol)
+    _one_step_check(_lp("power_law"), prec, _tuned("power_law", prec), tol)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16", 1e-5)])
 def test_one_step_parity_full_block_angular(prec, tol):
-    _one_step_check(lpgen.cfg3(0), prec, SHAPES["block_angular"], tol)
+    _one_step_check(_lp("block_angular"), prec, _tuned("block_angular", prec), tol)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_one_step_parity_full_general_power_law(prec, tol):
     # the general-form leg of the benchmark: bounds and row senses on the power-law shape
-    _one_step_check(lpgen.general_cfg2(0), prec, SHAPES["power_law"], tol)
+    _one_step_check(_lp("general"), prec, _tuned("general", prec), tol)

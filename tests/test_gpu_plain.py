@@ -250,7 +250,7 @@ def _oracle_objective(lp, key, eps):
     return _REF[(key, eps)]
 
 
-@pytest.mark.parametrize("prec,eps", [("fp32", 1e-4), ("bf16", 1e-4), ("fp32a", 1e-4),
+@pytest.mark.parametrize("prec,eps", [("fp32", 1e-4), ("bf16", 1e-4), ("fp32a", 1e-4), ("fp32acc32", 1e-4),
                                       ("fp32", 1e-6), ("bf16", 1e-6), ("fp32a", 1e-6), ("fp32", 1e-7)])
 def test_solve_reduced_precision_remeasured(prec, eps):
     """Reduced precision reaches the tolerance as re-measured in float64 on

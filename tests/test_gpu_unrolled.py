@@ -56,7 +56,7 @@ def test_fp64_forward_and_gradient_match_oracle(K, ckpt):
 
 
 def test_fp64_finite_differences_with_replay():
-    lps, ws = _fd_set(4)
+    lps, ws = _fd_set(16)
     batch = P.DeviceBatch.from_lps(lps)
     K, h = 300, 1e-6
     umap = P.UnrolledMap(batch, K=K, ckpt_every=100, precision="fp64")
@@ -95,7 +95,7 @@ def test_fp64_finite_differences_with_replay():
                 g = gc[batch.col_off[i] + j] if which == "c" else gb[batch.row_off[i] + j]
                 assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)) + 1e-8, (i, which, j, fd, g)
                 checked += 1
-    assert checked >= 16
+    assert checked >= 64
 
 
 def test_gradient_independent_of_checkpoint_interval():
