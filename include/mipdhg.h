@@ -239,6 +239,8 @@ typedef struct mipdhg_info {
     double ms_primal, ms_dual;       /* with kernel_timing: mean duration per launch  */
     int64_t n_primal, n_dual;        /* with kernel_timing: launches timed            */
     int32_t lanes_a, lanes_at, long_a, long_at; /* SpMV plan used                   */
+    double ms_graph;        /* part of ms_iter spent capturing and instantiating the
+                               iteration block's hipGraph                            */
 } mipdhg_info;
 
 /* Fill `opt` with the defaults shown in brackets above. */

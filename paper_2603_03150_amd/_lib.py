@@ -56,7 +56,8 @@ class InfoStruct(C.Structure):
                 ("omega", _f64), ("ms_setup", _f64), ("ms_iter", _f64), ("ms_total", _f64),
                 ("bytes_per_iter", _f64), ("bytes_primal", _f64), ("bytes_dual", _f64),
                 ("ms_primal", _f64), ("ms_dual", _f64), ("n_primal", _i64), ("n_dual", _i64),
-                ("lanes_a", _i32), ("lanes_at", _i32), ("long_a", _i32), ("long_at", _i32)]
+                ("lanes_a", _i32), ("lanes_at", _i32), ("long_a", _i32), ("long_at", _i32),
+                ("ms_graph", _f64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

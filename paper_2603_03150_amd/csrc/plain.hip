@@ -443,6 +443,8 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 // only checked once the products are in LDS.
 template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN, bool AVG = false>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
+    // blocks queued behind the one that ended the solve stream nothing
+    if (a.ctrl->status != ST_RUNNING) return;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
@@ -464,6 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePla
 // workgroup per tile.  The norm partials cover all tiles of a workgroup.
 template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TilePlan tp) {
+    if (a.ctrl->status != ST_RUNNING) return;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
     double q[3] = {0.0, 0.0, 0.0};
@@ -526,6 +529,7 @@ constexpr int kEvalColsW = 9;  // 8 sums + max
 template <bool ROWS, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a, TilePlan tp) {
     const bool active = a.ctrl->status == ST_RUNNING;
+    if (!active) return;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, tp);
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1809,7 +1813,9 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
             if (cap) (void)hipStreamDestroy(cap);
         }
     } res;
+    double ms_graph = 0.0;
     if (graph && o.max_iter >= E) {
+        const auto tg = clk::now();
         MIP_HIP(hipStreamCreateWithFlags(&res.cap, hipStreamNonBlocking));
         S.stream = res.cap;
         MIP_HIP(hipStreamBeginCapture(res.cap, hipStreamCaptureModeThreadLocal));
@@ -1819,6 +1825,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         if (rc) return rc;
         MIP_HIP(ce);
         MIP_HIP(hipGraphInstantiate(&res.gexec, res.g, nullptr, nullptr, 0));
+        ms_graph = std::chrono::duration<double, std::milli>(clk::now() - tg).count();
     }
     MIP_HIP(hipHostMalloc((void**)&res.ring, sizeof(Ctrl) * kDepth, hipHostMallocDefault));
     for (int i = 0; i < kDepth; ++i) MIP_HIP(hipEventCreateWithFlags(&res.ev[i], hipEventDisableTiming));
@@ -1962,6 +1969,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         info->lanes_at = S.hpat.lanes;
         info->long_a = (int32_t)S.hpa.long_rows.size();
         info->long_at = (int32_t)S.hpat.long_rows.size();
+        info->ms_graph = ms_graph;
     }
     return status;
 }
