@@ -412,6 +412,20 @@ int mipdhg_autotune(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, voi
                     size_t workspace_bytes, void *stream, double *x, double *y, double *z, double *r_p,
                     double *r_d, double *best_ms);
 
+/* mipdhg_autotune with its choice cached by matrix signature: the device
+ * (architecture and compute units), the precision and the options that change
+ * the candidates, m, n, nnz, and the sparsity structure (hashes of the row
+ * pointers and column indices of A and A^T; the values do not enter).  A
+ * signature seen before in this process, or found in the text file cache_path
+ * (nullable; one line per signature, the last line of a signature wins),
+ * fills opt without timing anything (*hit = 1); otherwise the tuner runs, and
+ * its choice is kept for the process and appended to cache_path (*hit = 0).
+ * Arguments otherwise as for mipdhg_autotune (the first 8 bytes of the
+ * workspace are used for the hash). */
+int mipdhg_autotune_cached(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, const char *cache_path,
+                           void *workspace, size_t workspace_bytes, void *stream, double *x, double *y, double *z,
+                           double *r_p, double *r_d, double *best_ms, int32_t *hit);
+
 /* Text for a status or error code. */
 const char *mipdhg_status_string(int code);
 

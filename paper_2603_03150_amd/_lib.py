@@ -91,6 +91,8 @@ SIGNATURES = {
     "mipdhg_center_start_noalloc": (C.c_int, [_i32, _p, _p, _p, _f64, _f64, _f64, _p, _p, _p, C.POINTER(_f64)]),
     "mipdhg_autotune": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _i32, _p, C.c_size_t, _p,
                                   _p, _p, _p, _p, _p, C.POINTER(_f64)]),
+    "mipdhg_autotune_cached": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _i32, C.c_char_p, _p,
+                                         C.c_size_t, _p, _p, _p, _p, _p, _p, C.POINTER(_f64), C.POINTER(_i32)]),
     "mipdhg_state_size": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), C.POINTER(C.c_size_t)]),
     "mipdhg_state_export": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _p, C.c_size_t, _p, C.c_size_t,
                                       _p]),

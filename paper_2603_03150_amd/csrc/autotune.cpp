@@ -3,7 +3,11 @@
 // events) and returns the fastest in the options.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "mipdhg.h"
@@ -11,6 +15,7 @@
 namespace mip {
 void set_error(const char* fmt, ...);
 int64_t tile_count(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t tile_nnz, int32_t tile_rows);
+int column_hash(const int32_t* col, int64_t nnz, uint64_t* scratch, hipStream_t stream, uint64_t* out);
 }
 
 namespace {
@@ -145,5 +150,135 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     opt->tile_rows_at = primal[kind].c.tile_rows_at;
     opt->short_row_at = primal[kind].c.short_row_at;
     if (best_ms) *best_ms = best;
+    return 0;
+}
+
+namespace {
+
+// The shape fields the tuner chooses, and their text form in the cache file.
+struct Shape {
+    int32_t v[7];
+    double ms;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Shape> g_tuned;  // this process's choices by signature
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// What the choice depends on: the device (architecture, compute units), the
+// options that change the kernels or the candidates, the sizes, and the
+// sparsity structure (row pointers of A and A^T, column indices of both).
+int signature(const mipdhg_lp* lp, const mipdhg_options* opt, void* ws, hipStream_t s, std::string* out) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return mip::set_error("could not query the device"), MIPDHG_ERR_HIP;
+    std::vector<int32_t> ra(lp->m + 1), rat(lp->n + 1);
+    if (hipMemcpyAsync(ra.data(), lp->a_rowptr, ra.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(rat.data(), lp->at_rowptr, rat.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return mip::set_error("could not read the row pointers"), MIPDHG_ERR_HIP;
+    uint64_t ca = 0, cat = 0;
+    int rc;
+    if ((rc = mip::column_hash(lp->a_col, lp->nnz, (uint64_t*)ws, s, &ca))) return rc;
+    if ((rc = mip::column_hash(lp->at_col, lp->nnz, (uint64_t*)ws, s, &cat))) return rc;
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s:%d:p%d:g%d%d%d:a%d:m%d:n%d:z%lld:%016llx:%016llx:%016llx:%016llx", prop.gcnArchName,
+             prop.multiProcessorCount, opt->precision, lp->lo != nullptr, lp->hi != nullptr, lp->sense != nullptr,
+             opt->restart_avg, lp->m, lp->n, (long long)lp->nnz,
+             (unsigned long long)fnv1a(ra.data(), ra.size() * 4), (unsigned long long)fnv1a(rat.data(), rat.size() * 4),
+             (unsigned long long)ca, (unsigned long long)cat);
+    for (char* c = buf; *c; ++c)
+        if (*c == ' ') *c = '_';
+    *out = buf;
+    return 0;
+}
+
+void apply_shape(const Shape& sh, mipdhg_options* opt) {
+    opt->spmv_kind = sh.v[0];
+    opt->tile_nnz = sh.v[1];
+    opt->tile_rows = sh.v[2];
+    opt->short_row = sh.v[3];
+    opt->tile_nnz_at = sh.v[4];
+    opt->tile_rows_at = sh.v[5];
+    opt->short_row_at = sh.v[6];
+}
+
+bool find_in_file(const char* path, const std::string& key, Shape* sh) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {  // the last entry of a signature wins
+        char k[600];
+        Shape t;
+        if (sscanf(line, "%599s %d %d %d %d %d %d %d %lf", k, &t.v[0], &t.v[1], &t.v[2], &t.v[3], &t.v[4], &t.v[5],
+                   &t.v[6], &t.ms) == 9 &&
+            key == k) {
+            *sh = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" int mipdhg_autotune_cached(const mipdhg_lp* lp, mipdhg_options* opt, int32_t iters, const char* cache_path,
+                                      void* workspace, size_t workspace_bytes, void* stream, double* x, double* y,
+                                      double* z, double* r_p, double* r_d, double* best_ms, int32_t* hit) {
+    if (!lp || !opt || iters < 1 || !workspace || workspace_bytes < 8)
+        return mip::set_error("lp, opt, a workspace and iters >= 1 are required"), MIPDHG_ERR_INVALID_ARG;
+    if (lp->m < 1 || lp->n < 1 || lp->nnz < 0 || !lp->a_rowptr || !lp->at_rowptr || !lp->a_col || !lp->at_col)
+        return mip::set_error("the LP's sizes and structure arrays are required"), MIPDHG_ERR_INVALID_ARG;
+    if (hit) *hit = 0;
+    std::string key;
+    int rc = signature(lp, opt, workspace, (hipStream_t)stream, &key);
+    if (rc) return rc;
+    Shape sh;
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            sh = it->second;
+            found = true;
+        } else if (cache_path && find_in_file(cache_path, key, &sh)) {
+            g_tuned[key] = sh;
+            found = true;
+        }
+    }
+    if (found) {
+        apply_shape(sh, opt);
+        if (best_ms) *best_ms = sh.ms;
+        if (hit) *hit = 1;
+        return 0;
+    }
+    double ms = 0.0;
+    rc = mipdhg_autotune(lp, opt, iters, workspace, workspace_bytes, stream, x, y, z, r_p, r_d, &ms);
+    if (rc) return rc;
+    sh = Shape{{opt->spmv_kind, opt->tile_nnz, opt->tile_rows, opt->short_row, opt->tile_nnz_at, opt->tile_rows_at,
+                opt->short_row_at},
+               ms};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[key] = sh;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", key.c_str(), sh.v[0], sh.v[1], sh.v[2], sh.v[3], sh.v[4],
+                    sh.v[5], sh.v[6], sh.ms);
+            fclose(f);
+        }
+    }
+    if (best_ms) *best_ms = ms;
     return 0;
 }

@@ -72,6 +72,9 @@ bool sorted_layout(const mipdhg_options& o, int64_t m, int64_t n);  // sorted ti
 TilePlan make_tile_plan(const int32_t* rowptr, const int32_t* desc, int32_t ntiles, int32_t nrows, int32_t tnz,
                         int32_t trows, int32_t srow);
 int allow_validate_lds(int bytes);
+// Order-independent hash of a device column index array (the matrix
+// structure the autotuner's choice depends on); scratch: 8 device bytes.
+int column_hash(const int32_t* col, int64_t nnz, uint64_t* scratch, hipStream_t stream, uint64_t* out);
 
 inline int grid_for(int64_t n, int cap = 2048) {
     int64_t g = (n + kBlock - 1) / kBlock;

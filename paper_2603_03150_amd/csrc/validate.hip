@@ -94,6 +94,37 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partials,
     if (threadIdx.x == 0) *out = sh[0];
 }
 
+// Order-independent 64-bit hash of a column index array: the wrapping sum
+// over k of a mix of (k, col[k]) (integer adds commute, so the result does
+// not depend on the launch).
+__device__ __forceinline__ uint64_t mix64(uint64_t v) {
+    v ^= v >> 33;
+    v *= 0xff51afd7ed558ccdull;
+    v ^= v >> 33;
+    v *= 0xc4ceb9fe1a85ec53ull;
+    v ^= v >> 33;
+    return v;
+}
+
+__global__ void k_hash_cols(const int32_t* col, int64_t nnz, unsigned long long* out) {
+    uint64_t h = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+        h += mix64(((uint64_t)k << 32) ^ (uint32_t)col[k]);
+    for (int o = kWave / 2; o > 0; o >>= 1) h += __shfl_xor(h, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, (unsigned long long)h);
+}
+
+int column_hash(const int32_t* col, int64_t nnz, uint64_t* scratch, hipStream_t stream, uint64_t* out) {
+    MIP_HIP(hipMemsetAsync(scratch, 0, 8, stream));
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_hash_cols, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, col, nnz,
+                           (unsigned long long*)scratch);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipMemcpyAsync(out, scratch, 8, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    return 0;
+}
+
 int allow_validate_lds(int bytes) {
     if (bytes <= 65536) return 0;
     if (hipFuncSetAttribute((const void*)k_transpose_dot<false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=

@@ -105,9 +105,11 @@ def workspace_bytes(dlp: DeviceLP, precision: str = "fp64", **opts) -> int:
     return int(nb.value)
 
 
-def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -> dict:
-    """Pick the fastest SpMV shape for this LP (mipdhg_autotune); returns the
-    option fields to pass to solve()."""
+def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, cache: str | None = None, **opts) -> dict:
+    """Pick the fastest SpMV shape for this LP (mipdhg_autotune_cached: a
+    matrix structure seen before in this process, or listed in the file
+    `cache`, is not timed again); returns the option fields to pass to
+    solve(), plus 'cache_hit'."""
     lib = _lib.load()
     o = make_options(precision, **opts)
     small = make_options(precision, **dict(opts, tile_nnz=512, tile_rows=256))
@@ -118,12 +120,15 @@ def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, **opts) -
     f64 = dict(dtype=torch.float64, device=d)
     bufs = [torch.empty(k, **f64) for k in (dlp.n, dlp.m, dlp.n, dlp.m, dlp.n)]
     best = C.c_double(0.0)
-    rc = lib.mipdhg_autotune(C.byref(dlp.struct()), C.byref(o), int(iters), ws.data_ptr(), ws.numel(),
-                             torch.cuda.current_stream(d).cuda_stream, *[b.data_ptr() for b in bufs], C.byref(best))
+    hit = C.c_int32(0)
+    rc = lib.mipdhg_autotune_cached(C.byref(dlp.struct()), C.byref(o), int(iters),
+                                    None if cache is None else str(cache).encode(), ws.data_ptr(), ws.numel(),
+                                    torch.cuda.current_stream(d).cuda_stream, *[b.data_ptr() for b in bufs],
+                                    C.byref(best), C.byref(hit))
     _lib.check(rc)
     return {"spmv_kind": o.spmv_kind, "tile_nnz": o.tile_nnz, "tile_rows": o.tile_rows, "short_row": o.short_row,
             "tile_nnz_at": o.tile_nnz_at, "tile_rows_at": o.tile_rows_at, "short_row_at": o.short_row_at,
-            "ms_per_iter": best.value}
+            "ms_per_iter": best.value, "cache_hit": bool(hit.value)}
 
 
 def solve(dlp: DeviceLP, eps: float = 1e-4, precision: str = "fp64", trace_iters: int = 0,

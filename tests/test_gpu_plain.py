@@ -391,11 +391,36 @@ def test_autotune_picks_a_valid_shape_with_identical_results():
     dlp = P.DeviceLP.from_lp(lp)
     best = P.autotune(dlp, "fp64", iters=64)
     assert best["ms_per_iter"] > 0
-    shape = {k: v for k, v in best.items() if k != "ms_per_iter"}
+    shape = {k: v for k, v in best.items() if k not in ("ms_per_iter", "cache_hit")}
     a = P.solve(dlp, 1e-6, "fp64", **shape)
     b = P.solve(dlp, 1e-6, "fp64")
     assert a.status == b.status == 0 and a.info["iters"] == b.info["iters"]
     assert _rel(_np(a.x), _np(b.x)) <= 1e-9
+
+
+def test_autotune_cache_by_matrix_signature(tmp_path):
+    """A matrix structure tuned before is not timed again: in this process,
+    and through the cache file; other values on the same structure hit, another
+    structure or precision misses."""
+    path = str(tmp_path / "tune.txt")
+    keys = ("spmv_kind", "tile_nnz", "tile_rows", "short_row", "tile_nnz_at", "tile_rows_at", "short_row_at")
+    lp = lpgen.cfg2_sub(4, scale=100)
+    first = P.autotune(P.DeviceLP.from_lp(lp), "fp32", iters=32, cache=path)
+    assert not first["cache_hit"]
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:8] == [str(first[k]) for k in keys]
+    # same structure, other values: a hit with the same shape
+    A2 = lp.A.copy()
+    A2.data = A2.data * 3.0
+    AT2 = sp.csr_matrix(A2.T)
+    AT2.sort_indices()
+    again = P.autotune(P.DeviceLP(A2, AT2, 2.0 * lp.b, lp.c, "cuda"), "fp32", iters=32, cache=path)
+    assert again["cache_hit"] and all(again[k] == first[k] for k in keys)
+    # another precision, another structure: misses, each appended to the file
+    assert not P.autotune(P.DeviceLP.from_lp(lp), "fp64", iters=32, cache=path)["cache_hit"]
+    other = lpgen.cfg2_sub(5, scale=100)
+    assert not P.autotune(P.DeviceLP.from_lp(other), "fp32", iters=32, cache=path)["cache_hit"]
+    assert len(open(path).read().splitlines()) == 3
 
 
 @pytest.mark.parametrize("spmv_kind", [0, 2])
