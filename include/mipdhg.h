@@ -136,7 +136,13 @@ typedef struct mipdhg_options {
     int32_t spmv_kind;      /* iteration SpMVs: 0 = nnz-balanced LDS tiles, one
                                workgroup per tile; 1 = lane groups per row
                                (lanes_a/lanes_at); 2 = the same LDS tiles walked
-                               by a persistent grid of resident workgroups   [0] */
+                               by a persistent grid of resident workgroups;
+                               3 = the dual step on a panel layout of A (row
+                               groups of narrow column span, each panel of the
+                               gathered vector staged in LDS, row sums per
+                               panel added in panel order), the primal step on
+                               A^T's LDS tiles as with 0; UNSUPPORTED when A
+                               does not fit the layout's limits            [0] */
     int32_t tile_nnz;       /* LDS tiles: nonzeros per tile, 256..8192 (0 = 2048) */
     int32_t tile_rows;      /* LDS tiles: rows per tile, 1..512 (0 = 512)           */
     int32_t short_row;      /* LDS tile row sums: 0 or -1 = every thread reduces an equal chunk of
@@ -212,6 +218,11 @@ typedef struct mipdhg_options {
      * restart tests and the evaluated point are unchanged.  Meant with
      * halpern = 0; single-LP solve with spmv_kind 0 only.               [0] */
     int32_t restart_avg;
+    /* spmv_kind 3: entries of the gathered vector one panel stages in LDS, a
+     * power of two from 64 up to 128 KB worth (0 = 128 KB worth: 32,768 in
+     * float32, 16,384 in float64); smaller panels exist to test the layout on
+     * small matrices.                                                     [0] */
+    int32_t panel_width;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */
@@ -394,8 +405,10 @@ size_t mipdhg_sizeof(int which);
 
 /* Times every candidate shape of the two iteration SpMVs on this LP (lane
  * groups; LDS tiles of 1024..8192 nonzeros, 256 or 512 rows, chunked or
- * short-row-32 sums, one workgroup per tile or persistent; and tiles sized
- * so that their count is 4..8 per compute unit, from the row pointers): each
+ * short-row-32 sums, one workgroup per tile or persistent; tiles sized
+ * so that their count is 4..8 per compute unit, from the row pointers; the
+ * dual step on A's panel layout, spmv_kind 3, whose primal step is kind 0's
+ * and takes kind 0's fastest primal shape): each
  * runs `iters` iterations, then 256 back-to-back launches of each kernel
  * timed with hipEvents (kernel_timing = 2).  For each spmv_kind it takes
  * the fastest shape of the dual kernel (A's tiles) and of the primal kernel
@@ -405,9 +418,10 @@ size_t mipdhg_sizeof(int which);
  * sums) unless another is more than 3 % faster, so that the choice does not
  * flip with timing noise.  best_ms (host, nullable) receives that primal +
  * dual time per iteration.  Arguments as for mipdhg_solve, whose output buffers are used as
- * scratch; the workspace must be large enough for the smallest tiles, i.e. at
- * least mipdhg_workspace_size() of opt with tile_nnz = 512, tile_rows = 256.
- * Candidates that do not fit are skipped. */
+ * scratch; candidates whose workspace does not fit are skipped, so a
+ * workspace that runs all of them holds the larger of
+ * mipdhg_workspace_size() of opt with tile_nnz = 512, tile_rows = 256 (the
+ * smallest tiles) and with spmv_kind = 3 (the panel layout). */
 int mipdhg_autotune(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, void *workspace,
                     size_t workspace_bytes, void *stream, double *x, double *y, double *z, double *r_p,
                     double *r_d, double *best_ms);

@@ -44,7 +44,8 @@ class OptionsStruct(C.Structure):
                 ("trace_x", _p), ("trace_y", _p), ("trace_xhat", _p), ("trace_yhat", _p),
                 ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32),
                 ("infeas_tol", _f64), ("pw_ki", _f64), ("pw_kd", _f64),
-                ("tile_nnz_at", _i32), ("tile_rows_at", _i32), ("short_row_at", _i32), ("restart_avg", _i32)]
+                ("tile_nnz_at", _i32), ("tile_rows_at", _i32), ("short_row_at", _i32), ("restart_avg", _i32),
+                ("panel_width", _i32)]
 
 
 class InfoStruct(C.Structure):

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmipdhg.so")
 
-SOURCES = ["capi.cpp", "validate.hip", "plain.hip", "batched.hip", "unrolled.hip", "center.hip", "autotune.cpp"]
+SOURCES = ["capi.cpp", "validate.hip", "plain.hip", "panel.hip", "batched.hip", "unrolled.hip", "center.hip",
+           "autotune.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

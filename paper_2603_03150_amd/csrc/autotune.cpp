@@ -37,6 +37,9 @@ std::vector<Cand> candidates() {
         for (int tn : {1024, 2048, 4096, 8192})
             for (int tr : {256, 512})
                 for (int sr : {-1, 32}) c.push_back({kind, tn, tr, sr, tn, tr, sr});
+    // the dual on A's panel layout, which has no tile shape; its primal step
+    // is kind 0's, so kind 0's fastest primal shape goes with it
+    c.push_back({3, kDefNnz, kDefRows, kDefShort, kDefNnz, kDefRows, kDefShort});
     return c;
 }
 
@@ -86,7 +89,8 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
         double ms = 1e300;
         Cand c{0, 0, 0, 0, 0, 0, 0};
     };
-    Best dual[3], primal[3], dual_def[3], primal_def[3];
+    constexpr int kKinds = 4;
+    Best dual[kKinds], primal[kKinds], dual_def[kKinds], primal_def[kKinds];
     bool first = true;
     const bool general = lp->lo || lp->hi || lp->sense;  // runs on the tile kernels only
     std::vector<Cand> cands = candidates();
@@ -127,13 +131,14 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     }
     // keep the default shape unless a candidate beats it by more than the
     // timing noise, so that the choice is stable from run to run
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         if (dual_def[k].ms < 1e300 && dual[k].ms * kMargin >= dual_def[k].ms) dual[k] = dual_def[k];
         if (primal_def[k].ms < 1e300 && primal[k].ms * kMargin >= primal_def[k].ms) primal[k] = primal_def[k];
     }
+    if (primal[3].ms < 1e300 && primal[0].ms < 1e300) primal[3] = primal[0];
     int kind = -1;
     double best = 1e300;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         if (dual[k].ms >= 1e300 || primal[k].ms >= 1e300) continue;
         const double t = dual[k].ms + primal[k].ms;
         if (t < best) {

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "common.h"
+#include "panel.h"
 #include "plain.h"
 
 namespace mip {
@@ -480,6 +481,186 @@ __global__ __launch_bounds__(kBlock) void k_iter_persist(IterArgs<T, V> a, TileP
         tiled_rows<false, Acc, U, SORTED>(tp, t, L, prod, epi);
         if (!epi.running()) return;
         __syncthreads();  // the next tile reuses the LDS
+    }
+    if (a.flags & (F_FIRST | F_EVAL))
+        block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+}
+
+// ---------------------------------------------------------------------------
+// dual step on the panel layout (panel.h)
+// ---------------------------------------------------------------------------
+typedef float pf4 __attribute__((ext_vector_type(4)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
+typedef unsigned pu4 __attribute__((ext_vector_type(4)));
+
+// eight consecutive values (the first a multiple of 8 elements from an
+// aligned base) widened to float64, streamed past the caches
+__device__ __forceinline__ void load8(const float* p, double (&v)[8]) {
+    const pf4 a = __builtin_nontemporal_load((const pf4*)p), b = __builtin_nontemporal_load((const pf4*)(p + 4));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void load8(const double* p, double (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const pd2 a = __builtin_nontemporal_load((const pd2*)(p + 2 * q));
+        v[2 * q] = a.x;
+        v[2 * q + 1] = a.y;
+    }
+}
+__device__ __forceinline__ void load8(const uint16_t* p, double (&v)[8]) {
+    const pu4 a = __builtin_nontemporal_load((const pu4*)p);
+    const unsigned w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[2 * q] = (double)__uint_as_float(w[q] << 16);
+        v[2 * q + 1] = (double)__uint_as_float(w[q] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ void load8u16(const uint16_t* p, int (&v)[8]) {
+    const pu4 a = __builtin_nontemporal_load((const pu4*)p);
+    const unsigned w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[2 * q] = (int)(w[q] & 0xffffu);
+        v[2 * q + 1] = (int)(w[q] >> 16);
+    }
+}
+
+template <typename T, typename V>
+struct PanelArgs {
+    int32_t width;     // panel width, a power of two <= panel_width<T>()
+    const PanelGroup* groups;
+    const PanelUnit* units;
+    const PanelChunk* chunks;
+    const V* val;
+    const uint16_t* col;
+    const uint16_t* rid;
+    const T* gather;   // x_bar - x0
+    T* partial;
+    int64_t ncols;
+    const Ctrl* ctrl;
+};
+
+// One workgroup per unit: the panel's slice of the gathered vector is staged
+// in LDS, then every wave takes chunks of up to 512 nonzeros, 8 per lane
+// (vector loads), and sums each row's products in float64 in the row order
+// of the matrix: a lane adds its own run of elements, a segmented scan over
+// the lanes adds the runs of rows that cross lanes, and the lane holding a
+// row's last element writes the row's sum to its partial.
+template <typename T, typename V>
+__global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    __shared__ T xs[panel_width<T>()];
+    const int W = a.width;
+    const PanelUnit un = a.units[blockIdx.x];
+    const PanelGroup g = a.groups[un.group];
+    const int64_t c0 = (int64_t)g.lo + (int64_t)un.panel * W;
+    for (int i = threadIdx.x; i < W; i += kPanelBlock) {
+        const int64_t c = c0 + i;
+        xs[i] = c < a.ncols ? a.gather[c] : (T)0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t pbase = g.seg_base + (int64_t)un.panel * (g.r1 - g.r0) - g.r0;
+    for (int c = un.c0 + wave; c < un.c1; c += kPanelBlock / kWave) {
+        const PanelChunk ch = a.chunks[c];
+        const int64_t e0 = (int64_t)ch.start + lane * 8;
+        const int n = ch.count - lane * 8;  // this lane's elements (may be <= 0 or > 8)
+        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int cc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, rr[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        if (n > 0) {  // lanes past the chunk's end load nothing
+            load8(a.val + e0, v);
+            load8u16(a.col + e0, cc);
+            load8u16(a.rid + e0, rr);
+        }
+        double s[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double pr = j < n ? v[j] * (double)xs[cc[j] & (W - 1)] : 0.0;
+            s[j] = (j > 0 && rr[j] == rr[j - 1]) ? s[j - 1] + pr : pr;
+        }
+        // the run ending at element 7 starts in this lane unless element 0
+        // continues the previous lane's last row and no row starts after it
+        const int prev_r7 = __shfl_up(rr[7], 1, kWave);
+        const bool cont0 = lane > 0 && rr[0] == prev_r7;
+        bool starts = !cont0;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) starts = starts || rr[j] != rr[j - 1];
+        // inclusive segmented scan of the runs over the lanes (earlier on the left)
+        double inc = s[7];
+        int f = starts ? 1 : 0;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const double t2 = __shfl_up(inc, d, kWave);
+            const int f2 = __shfl_up(f, d, kWave);
+            if (lane >= d) {
+                if (!f) inc = t2 + inc;
+                f |= f2;
+            }
+        }
+        double carry = __shfl_up(inc, 1, kWave);
+        if (!cont0) carry = 0.0;
+        const int next_r0 = __shfl_down(rr[0], 1, kWave);
+        const int next_n = __shfl_down(n, 1, kWave);
+        bool head = true;  // element j still in the row of element 0
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j >= n) break;
+            head = head && rr[j] == rr[0];
+            const bool last = (j == 7) ? (lane == kWave - 1 || next_n <= 0 || next_r0 != rr[7])
+                                       : (j + 1 >= n || rr[j + 1] != rr[j]);
+            if (last) a.partial[pbase + ch.row0 + rr[j]] = (T)(s[j] + (head ? carry : 0.0));
+        }
+    }
+}
+
+struct PanelRows {
+    const PanelGroup* groups;
+    const int32_t* row_group;
+    const int32_t* wide_rows;  // rows of groups with more than kPanelRowsSerial panels
+    int32_t nrows, nwide;
+};
+
+// Each row's partial sums added in a fixed order, then the dual epilogue.
+// The first workgroups take one row per thread, adding a row's panels in
+// panel order; rows of groups with more than kPanelRowsSerial panels
+// (linking rows) are left to the last workgroups, where a wave takes one such
+// row: lane l adds panels l, l + 64, ..., then a fixed butterfly tree adds
+// the lanes and lane 0 finishes the row.
+constexpr int kPanelRowsSerial = kPanelWideRow;
+
+template <typename T, typename V, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_panel_rows(IterArgs<T, V> a, PanelRows pr, const T* partial) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    double q[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    auto epi = make_epi<T, V, false, GEN>(a, q);
+    epi.ready();
+    const int nb = (pr.nrows + kBlock - 1) / kBlock;
+    if ((int)blockIdx.x < nb) {
+        const int r = blockIdx.x * kBlock + threadIdx.x;
+        if (r < pr.nrows) {
+            const PanelGroup g = pr.groups[pr.row_group[r]];
+            if (g.np <= kPanelRowsSerial) {
+                const int64_t R = g.r1 - g.r0;
+                double sum = 0.0;
+                for (int p = 0; p < g.np; ++p) sum += (double)partial[g.seg_base + p * R + (r - g.r0)];
+                epi.apply(r, 0, epi.load(r, 0), sum);
+            }
+        }
+    } else {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int w = ((int)blockIdx.x - nb) * (kBlock / kWave) + (int)(threadIdx.x / kWave);
+        if (w < pr.nwide) {
+            const int r = pr.wide_rows[w];
+            const PanelGroup g = pr.groups[pr.row_group[r]];
+            const int64_t R = g.r1 - g.r0, off = g.seg_base + (r - g.r0);
+            double v = 0.0;
+            for (int p = lane; p < g.np; p += kWave) v += (double)partial[off + p * R];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+            if (lane == 0) epi.apply(r, 0, epi.load(r, 0), v);
+        }
     }
     if (a.flags & (F_FIRST | F_EVAL))
         block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
@@ -976,10 +1157,10 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
     };
     const int64_t sz[4] = {lp.m, lp.n, lp.nnz, (has_bounds(lp) ? 1 : 0) | (has_sense(lp) ? 2 : 0)};
     mix(sz, sizeof(sz));
-    const int32_t iv[19] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
+    const int32_t iv[20] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
                             o.gather_order, o.lanes_a, o.lanes_at, o.long_row, tile_nnz_at_of(o),
-                            tile_rows_at_of(o), short_row_at_of(o), o.restart_avg};
+                            tile_rows_at_of(o), short_row_at_of(o), o.restart_avg, o.panel_width};
     mix(iv, sizeof(iv));
     const double dv[8] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
                           o.pw_kd};
@@ -1027,12 +1208,13 @@ struct PlainWs {
     double *xprev, *yprev;      // infeasibility certificates: previous evaluated point
     double *axprev, *atyprev;   // and its A x, A^T y
     void *x_avg, *y_avg;        // restart to average: the epoch's means
+    PanelLayout pl;             // spmv_kind 3: A's panel layout (dual step)
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
                      int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds,
-                     bool avg) {
+                     bool avg, bool panel) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -1082,6 +1264,22 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.hi_t = bounds ? cv.take<char>(n * ts) : nullptr;
     w.x_avg = avg ? cv.take<char>(n * ts) : nullptr;
     w.y_avg = avg ? cv.take<char>(m * ts) : nullptr;
+    memset(&w.pl, 0, sizeof(w.pl));
+    if (panel) {
+        const int64_t sc = panel_seg_cap(m, nnz), cc = panel_chunk_cap(nnz), ec = panel_elem_cap(nnz);
+        w.pl.groups = cv.take<PanelGroup>(kPanelMaxUnits);
+        w.pl.units = cv.take<PanelUnit>(kPanelMaxUnits);
+        w.pl.chunks = cv.take<PanelChunk>(cc);
+        w.pl.row_group = cv.take<int32_t>(m);
+        w.pl.wide_rows = cv.take<int32_t>(m);
+        w.pl.counts = cv.take<int32_t>(sc);
+        w.pl.seg_off = cv.take<int32_t>(sc);
+        w.pl.seg_rid = cv.take<uint16_t>(sc);
+        w.pl.val = cv.take<char>(ec * vs);
+        w.pl.col = cv.take<uint16_t>(ec);
+        w.pl.rid = cv.take<uint16_t>(ec);
+        w.pl.partial = cv.take<char>(sc * ts);
+    }
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -1098,7 +1296,12 @@ int check_options(const mipdhg_options* o) {
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
     if (!std::isfinite(o->pw_ki) || !std::isfinite(o->pw_kd))
         return set_error("pw_ki and pw_kd must be finite"), MIPDHG_ERR_INVALID_ARG;
-    if (o->spmv_kind < 0 || o->spmv_kind > 2) return set_error("spmv_kind must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
+    if (o->spmv_kind < 0 || o->spmv_kind > 3) return set_error("spmv_kind must be 0, 1, 2 or 3"), MIPDHG_ERR_INVALID_ARG;
+    if (o->panel_width != 0) {
+        const int maxw = kPanelBytes / ((o->precision == MIPDHG_FP64 || o->precision == MIPDHG_FP32_A) ? 8 : 4);
+        if (o->panel_width < 64 || o->panel_width > maxw || (o->panel_width & (o->panel_width - 1)))
+            return set_error("panel_width must be 0 or a power of two in [64, %d]", maxw), MIPDHG_ERR_INVALID_ARG;
+    }
     if (o->gather_order < 0 || o->gather_order > 1) return set_error("gather_order must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (o->kernel_timing < 0 || o->kernel_timing > 2)
         return set_error("kernel_timing must be 0, 1 or 2"), MIPDHG_ERR_INVALID_ARG;
@@ -1158,7 +1361,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
                    tile_rows_of(*opt), tile_nnz_at_of(*opt), tile_rows_at_of(*opt), sorted_layout(*opt, lp->m, lp->n),
-                   has_bounds(*lp), opt->restart_avg != 0).bytes;
+                   has_bounds(*lp), opt->restart_avg != 0, opt->spmv_kind == 3).bytes;
     return 0;
 }
 
@@ -1239,8 +1442,15 @@ struct Solver {
         return 0;
     }
     bool sorted() const { return sorted_layout(o, lp.m, lp.n); }
+    // spmv_kind 3: the dual step on A's panel layout, the primal on A^T's tiles
+    bool panel() const { return o.spmv_kind == 3; }
+    int panel_w() const { return o.panel_width > 0 ? o.panel_width : panel_width<T>(); }
     int grid_primal() const { return persistent() ? gp_persist : tiled() ? tat.ntiles : hpat.grid(); }
-    int grid_dual() const { return persistent() ? gd_persist : tiled() ? ta.ntiles : hpa.grid(); }
+    int grid_dual() const {
+        if (panel())
+            return (int)((lp.m + kBlock - 1) / kBlock + (w.pl.nwide + kBlock / kWave - 1) / (kBlock / kWave));
+        return persistent() ? gd_persist : tiled() ? ta.ntiles : hpa.grid();
+    }
     // Resident workgroups of the persistent kernel over all CUs, at least
     // min(8, ntiles) so that every XCD's run of tiles has a workgroup.
     // the general-form variant of a kernel: bounds for the primal, senses for the dual
@@ -1370,7 +1580,29 @@ struct Solver {
     int launch_dual(int it, int flags) {
         IterArgs<T, V> a;
         fill_iter(a, false, it, flags);
-        if (tiled()) {
+        if (panel()) {
+            PanelArgs<T, V> pa;
+            pa.width = panel_w();
+            pa.groups = w.pl.groups;
+            pa.units = w.pl.units;
+            pa.chunks = w.pl.chunks;
+            pa.val = (const V*)w.pl.val;
+            pa.col = w.pl.col;
+            pa.rid = w.pl.rid;
+            pa.gather = (const T*)w.xbar;
+            pa.partial = (T*)w.pl.partial;
+            pa.ncols = lp.n;
+            pa.ctrl = w.ctrl;
+            if (w.pl.nunits > 0)
+                hipLaunchKernelGGL((k_panel_spmv<T, V>), dim3(w.pl.nunits), dim3(kPanelBlock), 0, stream, pa);
+            const PanelRows pr{w.pl.groups, w.pl.row_group, w.pl.wide_rows, lp.m, w.pl.nwide};
+            if (gen_dual())
+                hipLaunchKernelGGL((k_panel_rows<T, V, true>), dim3(grid_dual()), dim3(kBlock), 0, stream, a, pr,
+                                   (const T*)w.pl.partial);
+            else
+                hipLaunchKernelGGL((k_panel_rows<T, V, false>), dim3(grid_dual()), dim3(kBlock), 0, stream, a, pr,
+                                   (const T*)w.pl.partial);
+        } else if (tiled()) {
             launch_tiles<false>(a, ta, gd_persist);
         } else {
             MIP_DISPATCH_L(pa.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, false>), dim3(hpa.grid()), dim3(kBlock),
@@ -1520,7 +1752,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                 tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                o.restart_avg != 0);
+                o.restart_avg != 0, o.spmv_kind == 3);
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1638,6 +1870,11 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         hipLaunchKernelGGL((k_scale_values<V>), dim3(grid_for(n * kWave, 4096)), dim3(kBlock), 0, stream,
                            lp.at_rowptr, lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.n,
                            (V*)w.at_vs);
+    }
+    if (S.panel()) {  // A's panel layout for the dual step (same scaled values as the copies)
+        rc = panel_build<V>(rpa, lp.m, lp.n, nnz, lp.a_rowptr, lp.a_col, lp.a_val, (const double*)w.d_row,
+                            (const double*)w.d_col, S.panel_w(), sizeof(T), w.pl, stream);
+        if (rc) return rc;
     }
     {
         const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
@@ -1984,7 +2221,7 @@ static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp,
     char* const base = reinterpret_cast<char*>(uintptr_t(4096));  // layout only, never dereferenced
     const PlainWs w = carve(base, 0, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                             tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                            o.restart_avg != 0);
+                            o.restart_avg != 0, o.spmv_kind == 3);
     const size_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
     const size_t m = (size_t)lp.m, n = (size_t)lp.n, G = (size_t)w.gcap;
     auto at = [&](const void* p, size_t bytes) { return std::make_pair((size_t)((const char*)p - base), bytes); };

@@ -112,11 +112,11 @@ def autotune(dlp: DeviceLP, precision: str = "fp32", iters: int = 128, cache: st
     solve(), plus 'cache_hit'."""
     lib = _lib.load()
     o = make_options(precision, **opts)
-    small = make_options(precision, **dict(opts, tile_nnz=512, tile_rows=256))
-    nb = C.c_size_t(0)
-    _lib.check(lib.mipdhg_workspace_size(C.byref(dlp.struct()), C.byref(small), C.byref(nb)))
+    need = 0
+    for extra in (dict(tile_nnz=512, tile_rows=256), dict(spmv_kind=3)):  # smallest tiles; the panel layout
+        need = max(need, workspace_bytes(dlp, precision, **dict(opts, **extra)))
     d = dlp.device
-    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    ws = torch.empty(need, dtype=torch.uint8, device=d)
     f64 = dict(dtype=torch.float64, device=d)
     bufs = [torch.empty(k, **f64) for k in (dlp.n, dlp.m, dlp.n, dlp.m, dlp.n)]
     best = C.c_double(0.0)
