@@ -165,8 +165,8 @@ int panel_build(const std::vector<int32_t>& rp, int32_t nrows, int32_t ncols, in
         PanelGroup g;
         g.r0 = cur.r0;
         g.r1 = r_end;
-        g.lo = cur.hi >= cur.lo ? cur.lo : 0;
-        g.np = cur.hi >= cur.lo ? (int32_t)((cur.hi - cur.lo) / width + 1) : 0;
+        g.lo = cur.hi >= cur.lo ? cur.lo & ~7 : 0;  // a multiple of 8: aligned vector loads of a panel
+        g.np = cur.hi >= cur.lo ? (int32_t)((cur.hi - g.lo) / width + 1) : 0;
         g.seg_base = 0;
         groups.push_back(g);
     };
@@ -183,11 +183,11 @@ int panel_build(const std::vector<int32_t>& rp, int32_t nrows, int32_t ncols, in
             row_group[r] = (int32_t)groups.size();
             continue;
         }
-        const int kind = (int64_t)hi - lo + 1 > span_max ? 1 : 0;
+        const int kind = (int64_t)hi - (lo & ~7) + 1 > span_max ? 1 : 0;  // spans from the aligned start
         bool join = !rows_full && (cur.kind < 0 || cur.kind == kind);
         if (join && cur.kind >= 0) {
             const int64_t nlo = std::min(cur.lo, lo), nhi = std::max(cur.hi, hi);
-            if (kind == 0) join = nhi - nlo + 1 <= span_max && cur.nnz + len <= kNarrowNnz;
+            if (kind == 0) join = nhi - (nlo & ~7) + 1 <= span_max && cur.nnz + len <= kNarrowNnz;
             else join = cur.nnz + len <= kWideNnz;
         }
         if (!join) {

@@ -493,39 +493,6 @@ typedef float pf4 __attribute__((ext_vector_type(4)));
 typedef double pd2 __attribute__((ext_vector_type(2)));
 typedef unsigned pu4 __attribute__((ext_vector_type(4)));
 
-// eight consecutive values (the first a multiple of 8 elements from an
-// aligned base) widened to float64, streamed past the caches
-__device__ __forceinline__ void load8(const float* p, double (&v)[8]) {
-    const pf4 a = __builtin_nontemporal_load((const pf4*)p), b = __builtin_nontemporal_load((const pf4*)(p + 4));
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-__device__ __forceinline__ void load8(const double* p, double (&v)[8]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const pd2 a = __builtin_nontemporal_load((const pd2*)(p + 2 * q));
-        v[2 * q] = a.x;
-        v[2 * q + 1] = a.y;
-    }
-}
-__device__ __forceinline__ void load8(const uint16_t* p, double (&v)[8]) {
-    const pu4 a = __builtin_nontemporal_load((const pu4*)p);
-    const unsigned w[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v[2 * q] = (double)__uint_as_float(w[q] << 16);
-        v[2 * q + 1] = (double)__uint_as_float(w[q] & 0xffff0000u);
-    }
-}
-__device__ __forceinline__ void load8u16(const uint16_t* p, int (&v)[8]) {
-    const pu4 a = __builtin_nontemporal_load((const pu4*)p);
-    const unsigned w[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v[2 * q] = (int)(w[q] & 0xffffu);
-        v[2 * q + 1] = (int)(w[q] >> 16);
-    }
-}
-
 template <typename T, typename V>
 struct PanelArgs {
     int32_t width;     // panel width, a power of two <= panel_width<T>()
@@ -541,12 +508,58 @@ struct PanelArgs {
     const Ctrl* ctrl;
 };
 
+// A chunk's raw loads for one lane: 8 values, 8 columns, 8 row indices.
+template <typename V>
+struct PanelRaw;
+template <>
+struct PanelRaw<float> {
+    pf4 v0, v1;
+    pu4 col, rid;
+    __device__ __forceinline__ void load(const float* v, const uint16_t* c, const uint16_t* r) {
+        v0 = __builtin_nontemporal_load((const pf4*)v);
+        v1 = __builtin_nontemporal_load((const pf4*)(v + 4));
+        col = __builtin_nontemporal_load((const pu4*)c);
+        rid = __builtin_nontemporal_load((const pu4*)r);
+    }
+    __device__ __forceinline__ double val(int j) const { return j < 4 ? v0[j] : v1[j - 4]; }
+};
+template <>
+struct PanelRaw<double> {
+    pd2 v[4];
+    pu4 col, rid;
+    __device__ __forceinline__ void load(const double* p, const uint16_t* c, const uint16_t* r) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load((const pd2*)(p + 2 * q));
+        col = __builtin_nontemporal_load((const pu4*)c);
+        rid = __builtin_nontemporal_load((const pu4*)r);
+    }
+    __device__ __forceinline__ double val(int j) const { return v[j >> 1][j & 1]; }
+};
+template <>
+struct PanelRaw<uint16_t> {  // BF16 values, widened exactly
+    pu4 v, col, rid;
+    __device__ __forceinline__ void load(const uint16_t* p, const uint16_t* c, const uint16_t* r) {
+        v = __builtin_nontemporal_load((const pu4*)p);
+        col = __builtin_nontemporal_load((const pu4*)c);
+        rid = __builtin_nontemporal_load((const pu4*)r);
+    }
+    __device__ __forceinline__ double val(int j) const {
+        const unsigned w = v[j >> 1];
+        return (double)__uint_as_float((j & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
+__device__ __forceinline__ int u16_at(const pu4& w, int j) {
+    return (int)((j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xffffu));
+}
+
 // One workgroup per unit: the panel's slice of the gathered vector is staged
-// in LDS, then every wave takes chunks of up to 512 nonzeros, 8 per lane
-// (vector loads), and sums each row's products in float64 in the row order
-// of the matrix: a lane adds its own run of elements, a segmented scan over
-// the lanes adds the runs of rows that cross lanes, and the lane holding a
-// row's last element writes the row's sum to its partial.
+// in LDS (every load of a thread issued before its LDS writes), then every
+// wave takes chunks of up to 512 nonzeros, 8 per lane (vector loads, the next
+// chunk's issued before the current one is summed), and sums each row's
+// products in float64 in the row order of the matrix: a lane adds its own run
+// of elements, a segmented scan over the lanes adds the runs of rows that
+// cross lanes, and the lane holding a row's last element writes the row's sum
+// to its partial.
 template <typename T, typename V>
 __global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
     if (a.ctrl->status != ST_RUNNING) return;
@@ -554,29 +567,63 @@ __global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
     const int W = a.width;
     const PanelUnit un = a.units[blockIdx.x];
     const PanelGroup g = a.groups[un.group];
-    const int64_t c0 = (int64_t)g.lo + (int64_t)un.panel * W;
-    for (int i = threadIdx.x; i < W; i += kPanelBlock) {
-        const int64_t c = c0 + i;
-        xs[i] = c < a.ncols ? a.gather[c] : (T)0;
+    const int64_t c0 = (int64_t)g.lo + (int64_t)un.panel * W;  // a multiple of 8
+    {
+        constexpr int kVec = 16 / (int)sizeof(T);
+        typedef T VT __attribute__((ext_vector_type(kVec)));
+        constexpr int kPer = panel_width<T>() / (kPanelBlock * kVec);
+        VT buf[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
+            if (i < W) {
+                const int64_t c = c0 + i;
+                if (c + kVec <= a.ncols) {
+                    buf[k] = *(const VT*)(a.gather + c);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kVec; ++e) buf[k][e] = c + e < a.ncols ? a.gather[c + e] : (T)0;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
+            if (i < W) *(VT*)&xs[i] = buf[k];
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t pbase = g.seg_base + (int64_t)un.panel * (g.r1 - g.r0) - g.r0;
-    for (int c = un.c0 + wave; c < un.c1; c += kPanelBlock / kWave) {
-        const PanelChunk ch = a.chunks[c];
-        const int64_t e0 = (int64_t)ch.start + lane * 8;
-        const int n = ch.count - lane * 8;  // this lane's elements (may be <= 0 or > 8)
-        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int cc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, rr[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-        if (n > 0) {  // lanes past the chunk's end load nothing
-            load8(a.val + e0, v);
-            load8u16(a.col + e0, cc);
-            load8u16(a.rid + e0, rr);
+    constexpr int kStride = kPanelBlock / kWave;
+    int c = un.c0 + wave;
+    PanelChunk ch{0, 0, 0, 0};
+    PanelRaw<V> raw;
+    if (c < un.c1) {
+        ch = a.chunks[c];
+        if (ch.count > lane * 8) {
+            const int64_t e0 = (int64_t)ch.start + lane * 8;
+            raw.load(a.val + e0, a.col + e0, a.rid + e0);
         }
+    }
+    for (; c < un.c1; c += kStride) {
+        const PanelChunk cur = ch;
+        const PanelRaw<V> rc = raw;
+        if (c + kStride < un.c1) {  // the next chunk's loads go out first
+            ch = a.chunks[c + kStride];
+            if (ch.count > lane * 8) {
+                const int64_t e0 = (int64_t)ch.start + lane * 8;
+                raw.load(a.val + e0, a.col + e0, a.rid + e0);
+            }
+        }
+        const int n = cur.count - lane * 8;  // this lane's elements (may be <= 0 or > 8)
+        int rr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rr[j] = n > 0 ? u16_at(rc.rid, j) : -1;
         double s[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const double pr = j < n ? v[j] * (double)xs[cc[j] & (W - 1)] : 0.0;
+            const double pr = j < n ? rc.val(j) * (double)xs[u16_at(rc.col, j) & (W - 1)] : 0.0;
             s[j] = (j > 0 && rr[j] == rr[j - 1]) ? s[j - 1] + pr : pr;
         }
         // the run ending at element 7 starts in this lane unless element 0
@@ -609,7 +656,7 @@ __global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
             head = head && rr[j] == rr[0];
             const bool last = (j == 7) ? (lane == kWave - 1 || next_n <= 0 || next_r0 != rr[7])
                                        : (j + 1 >= n || rr[j + 1] != rr[j]);
-            if (last) a.partial[pbase + ch.row0 + rr[j]] = (T)(s[j] + (head ? carry : 0.0));
+            if (last) a.partial[pbase + cur.row0 + rr[j]] = (T)(s[j] + (head ? carry : 0.0));
         }
     }
 }
