@@ -78,7 +78,11 @@ def parse():
     ap.add_argument("--infeas-tol", type=float, default=None,
                     help="infeasibility-certificate tolerance of the main-line solves (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only a plain device copy of known size (to calibrate hardware byte counters)")
+                    help="only a plain device copy and a streaming read of known sizes (to calibrate hardware "
+                         "byte counters)")
+    ap.add_argument("--counter-summary", default="",
+                    help="no GPU: write profiles/traffic_<workload>.json and the profile summary of --workload "
+                         "from the rocprofv3 outputs under this folder (see counter_summary)")
     return ap.parse_args()
 
 
@@ -147,7 +151,31 @@ def cpu_baseline_block_angular(gpu_iters: int, eps: float, seed: int) -> dict:
 
 
 KERNEL_SOURCES = ("paper_2603_03150_amd/csrc/common.h", "paper_2603_03150_amd/csrc/plain.h",
-                  "paper_2603_03150_amd/csrc/plain.hip")
+                  "paper_2603_03150_amd/csrc/plain.hip", "paper_2603_03150_amd/csrc/panel.h",
+                  "paper_2603_03150_amd/csrc/panel.hip")
+PANEL_DUAL = "k_panel_spmv+k_panel_rows<dual>"
+
+
+def kernel_names(shape: dict) -> dict:
+    """Names of the kernels of one primal and one dual step for an SpMV
+    shape; the panel layout's dual step is two kernels."""
+    kind = int(shape.get("spmv_kind", 0))
+    base = {0: "k_iter_tiled", 1: "k_iter", 2: "k_iter_persist", 3: "k_iter_tiled"}[kind]
+    return {"primal": f"{base}<primal>", "dual": PANEL_DUAL if kind == 3 else f"{base}<dual>"}
+
+
+def short_kernel(symbol: str):
+    """The name kernel_names() uses for a kernel symbol of a profile (the
+    panel kernels under their own names), or None for other kernels."""
+    import re
+    m = re.search(r"mip::(k_iter_tiled|k_iter_persist|k_iter|k_panel_spmv|k_panel_rows)<([^()]*)>", symbol)
+    if not m:
+        return None
+    name, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if name.startswith("k_panel"):
+        return name
+    primal = targs[4 if name == "k_iter" else 3] == "true"
+    return f"{name}<{'primal' if primal else 'dual'}>"
 
 
 def kernel_source_sha() -> str:
@@ -171,14 +199,36 @@ def traffic_record(workload_key: str, kernel: str, shape: dict):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    # the kernel's own side of the shape: A's tiles for the dual, A^T's for the primal
-    side = ("spmv_kind", "tile_nnz_at", "tile_rows_at", "short_row_at") if kernel.endswith("<primal>") else \
-        ("spmv_kind", "tile_nnz", "tile_rows", "short_row")
+    # the kernel's own side of the shape: A's tiles (or panels) for the dual, A^T's tiles for the primal
+    if kernel.endswith("<primal>"):
+        side = ("spmv_kind", "tile_nnz_at", "tile_rows_at", "short_row_at")
+    elif kernel == PANEL_DUAL:
+        side = ("spmv_kind", "panel_width")
+    else:
+        side = ("spmv_kind", "tile_nnz", "tile_rows", "short_row")
     stored = rec.get("spmv_shape", {})
     if (rec.get("source_sha256") != kernel_source_sha() or kernel not in rec.get("kernels", {})
-            or any(stored.get(k) != shape.get(k) for k in side)):
+            or any(stored.get(k, 0) != shape.get(k, 0) for k in side)):
         return None
     return rec["kernels"][kernel]
+
+
+def read_ceiling(P, torch, nbytes: int = 2 << 30, reps: int = 20) -> dict:
+    """The device's streaming-read rate: mipdhg_read_probe over a buffer of
+    nbytes, timed by HIP events on the current stream (the stream it runs
+    on), mean over reps launches after one untimed launch."""
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    P.read_probe(buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.read_probe(buf)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
 def tuned_shape(P, dlp, precision: str) -> tuple[dict, float]:
@@ -204,14 +254,17 @@ def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str, s
     dom = max(kern, key=lambda k: kern[k][1])
     b, ms = kern[dom]
     achieved = b / (ms * 1e-3) / 1e9
-    name = f"k_iter_tiled<{dom}>"
+    names = kernel_names(shape)
+    name = names[dom]
     rec = traffic_record(workload_key, name, shape)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec["bytes_per_launch"] if rec else None,
             "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": int(ti["n_primal"]),
             "ms_per_launch_events_each": each["ms_" + dom],
             "traffic_source": f"profiles/traffic_{workload_key}.json" if rec else None,
-            "other_kernel": {k: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9}
+            "other_kernel": {names[k]: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9,
+                                        "traffic": (traffic_record(workload_key, names[k], shape) or {}).get(
+                                            "bytes_per_launch")}
                              for k, v in kern.items() if k != dom}}
 
 
@@ -537,8 +590,139 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
                         "FP32 iterates, FP64 per-instance tests"}
 
 
+def _counter_rows(folder: str) -> dict:
+    """Per kernel symbol of a rocprofv3 --pmc csv output: {counter: mean per
+    dispatch} (rows of one dispatch and counter are added first)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {folder}")
+    per = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                key = (row["Kernel_Name"], row["Counter_Name"], row.get("Dispatch_Id", ""))
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (kern, ctr, _), v in per.items():
+        d = out.setdefault(kern, {}).setdefault(ctr, [])
+        d.append(v)
+    return {k: {c: (sum(v) / len(v), len(v)) for c, v in cs.items()} for k, cs in out.items()}
+
+
+def counter_summary(folder: str, workload: str, precision: str, shape_text: str) -> int:
+    """Write profiles/traffic_<workload>.json from the rocprofv3 outputs of
+    the commands listed in it (run from the repository root, outputs under
+    `folder`): FETCH_SIZE and WRITE_SIZE of the iteration kernels (bench.py
+    --profile), each scaled by what the same counter reads for reads and
+    writes of known size (bench.py --calibrate-copy: FETCH_SIZE from the
+    streaming-read probe, WRITE_SIZE from the device copy), and the per-kernel
+    statistics of the bench command (kernel trace) beside them in
+    profiles/iteration_kernels_<workload>_<precision>.md."""
+    import csv
+    shape = {k: int(v) for k, v in (kv.split("=") for kv in shape_text.split(","))} if shape_text else {}
+    prof = f"python3 bench.py --profile --workload {workload} --precision {precision} --shape {shape_text}"
+    cmds = {
+        "fetch": f"timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE -d {folder}/pmc_{workload}_FETCH_SIZE -o run "
+                 f"--output-format csv -- {prof}",
+        "write": f"timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE -d {folder}/pmc_{workload}_WRITE_SIZE -o run "
+                 f"--output-format csv -- {prof}",
+        "cfetch": f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d {folder}/pmc_copy_FETCH_SIZE -o run "
+                  "--output-format csv -- python3 bench.py --calibrate-copy",
+        "cwrite": f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d {folder}/pmc_copy_WRITE_SIZE -o run "
+                  "--output-format csv -- python3 bench.py --calibrate-copy",
+        "trace": f"rocprofv3 --kernel-trace --stats -d {folder}/profb_{workload} -o run --output-format csv -- "
+                 f"python3 bench.py --workload {workload} --precision {precision} --shape {shape_text} --steps 2 "
+                 "--warmup 1 --no-batched --no-ratios --no-diff --no-cpu-baseline --no-other --no-general",
+    }
+    fetch = _counter_rows(f"{folder}/pmc_{workload}_FETCH_SIZE")
+    write = _counter_rows(f"{folder}/pmc_{workload}_WRITE_SIZE")
+    cf = _counter_rows(f"{folder}/pmc_copy_FETCH_SIZE")
+    cw = _counter_rows(f"{folder}/pmc_copy_WRITE_SIZE")
+    gib = float(1 << 30)
+    probe_f = [v["FETCH_SIZE"][0] for k, v in cf.items() if "k_read_probe" in k]
+    copy_w = [v["WRITE_SIZE"][0] for k, v in cw.items() if "copyBuffer" in k]
+    if not probe_f or not copy_w:
+        raise RuntimeError("calibration kernels not found in the copy profiles")
+    ff, wf = gib / (probe_f[0] * 1024.0), gib / (copy_w[0] * 1024.0)
+    kernels = {}
+    for sym, cs in fetch.items():
+        short = short_kernel(sym)
+        if short is None or "FETCH_SIZE" not in cs or sym not in write:
+            continue
+        fk, nd = cs["FETCH_SIZE"]
+        wk = write[sym]["WRITE_SIZE"][0]
+        kernels[short] = {"kernel_symbol": sym.split("(")[0], "dispatches": nd, "fetch_kib": fk, "write_kib": wk,
+                          "bytes_per_launch": fk * 1024.0 * ff + wk * 1024.0 * wf}
+    if "k_panel_spmv" in kernels and "k_panel_rows" in kernels:
+        kernels[PANEL_DUAL] = {"parts": ["k_panel_spmv", "k_panel_rows"],
+                               "bytes_per_launch": kernels["k_panel_spmv"]["bytes_per_launch"]
+                               + kernels["k_panel_rows"]["bytes_per_launch"]}
+    rec = {"workload": workload, "precision": precision, "spmv_shape": shape, "source_sha256": kernel_source_sha(),
+           "kernel_sources": list(KERNEL_SOURCES), "fetch_factor": ff, "write_factor": wf,
+           "calibration": (f"FETCH_SIZE {probe_f[0]:.1f} KiB per 1 GiB streaming read (k_read_probe), WRITE_SIZE "
+                           f"{copy_w[0]:.1f} KiB per 1 GiB device copy (__amd_rocclr_copyBuffer), bench.py "
+                           "--calibrate-copy"),
+           "commands": [cmds["fetch"], cmds["write"], cmds["cfetch"], cmds["cwrite"]], "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    # the kernel statistics of the bench command, and its bench line if it was kept
+    stats = []
+    import glob
+    for f in glob.glob(os.path.join(folder, f"profb_{workload}", "**", "*kernel_stats.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            stats += list(csv.DictReader(fh))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# Iteration kernels, {workload} LP, {precision}, SpMV shape {shape_text}", "",
+             "Kernel statistics (rocprofv3 --kernel-trace --stats) of the single-workload bench command:", "",
+             "```", cmds["trace"] + f" > {folder}/bench_{workload}.json", "```", "",
+             "| kernel | calls | avg us | min us | max us | total ms |", "|---|---|---|---|---|---|"]
+    for r in stats[:12]:
+        lines.append(f"| `{r['Name'].split('(')[0]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
+    bj = os.path.join(folder, f"bench_{workload}.json")
+    if os.path.exists(bj):
+        with open(bj) as fh:
+            line = [ln for ln in fh if ln.startswith("{")]
+        if line:
+            roof = json.loads(line[-1])["roofline"]
+            lines += ["", "The same run's bench line (HIP events on the solver's stream around 256 back-to-back "
+                      "launches of each kernel):", "",
+                      f"* {roof['kernel']}: {roof['ms_per_launch'] * 1e3:.2f} us per launch, "
+                      f"{roof['bytes_per_launch'] / 1e6:.1f} MB algorithmic -> {roof['achieved']:.0f} GB/s, "
+                      f"frac {roof['frac']:.3f} of 8 TB/s"]
+            for k, v in roof.get("other_kernel", {}).items():
+                lines.append(f"* {k}: {v['ms'] * 1e3:.2f} us per launch, {v['bytes'] / 1e6:.1f} MB -> "
+                             f"{v['GBs']:.0f} GB/s")
+            if "read_probe" in roof:
+                rp = roof["read_probe"]
+                lines.append(f"* streaming-read probe (mipdhg_read_probe, {rp['bytes'] / 2**30:.0f} GiB): "
+                             f"{rp['GBs']:.0f} GB/s")
+    lines += ["", "## HBM-side traffic (rocprofv3 --pmc, one counter per run)", "", "```"]
+    lines += [cmds[k] for k in ("fetch", "write", "cfetch", "cwrite")]
+    lines += ["```", "", rec["calibration"] + f": factors {ff:.3f} (FETCH_SIZE) and {wf:.3f} (WRITE_SIZE).", "",
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated MB per launch |",
+              "|---|---|---|---|---|"]
+    for k, v in kernels.items():
+        if "parts" in v:
+            lines.append(f"| {k} (sum) | | | | {v['bytes_per_launch'] / 1e6:.1f} |")
+        else:
+            lines.append(f"| `{v['kernel_symbol']}` ({k}) | {v['dispatches']} | {v['fetch_kib']:.1f} | "
+                         f"{v['write_kib']:.1f} | {v['bytes_per_launch'] / 1e6:.1f} |")
+    lines += ["", f"Kernel sources sha256 {rec['source_sha256']} ({', '.join(KERNEL_SOURCES)}); bench.py reports "
+              f"`traffic` from profiles/traffic_{workload}.json only while they match."]
+    with open(os.path.join(ROOT, "profiles", f"iteration_kernels_{workload}_{precision}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({k: v["bytes_per_launch"] for k, v in kernels.items()}))
+    return 0
+
+
 def main() -> int:
     args = parse()
+    if args.counter_summary:
+        return counter_summary(args.counter_summary, args.workload, args.precision, args.shape)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the solver runs on a single GPU; how it would shard is described, not built)", file=sys.stderr)
@@ -553,14 +737,18 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     if args.calibrate_copy:
-        # 1 GiB read + 1 GiB written per copy, four copies
+        # 1 GiB read + 1 GiB written per copy, four copies; then four 1 GiB
+        # streaming reads with the SpMV kernels' loads (mipdhg_read_probe)
         a = torch.empty(256 * 2**20, dtype=torch.float32, device="cuda:0")
         a.fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(4):
             b.copy_(a)
+        for _ in range(4):
+            P.read_probe(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 4}))
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 4,
+                          "read_probe_bytes": a.numel() * 4, "read_probes": 4}))
         return 0
     t0 = time.perf_counter()
     lp = lpgen.cfg3(args.seed) if args.workload == "block_angular" else lpgen.cfg2(args.seed)
@@ -605,6 +793,9 @@ def main() -> int:
 
     # per-kernel timing leg: HIP events around every primal and dual launch
     roofline = kernel_roofline(P, dlp, ws, args.precision, args.timing_iters, args.workload, shape)
+    rc = read_ceiling(P, torch)
+    roofline["read_probe"] = rc
+    roofline["frac_of_read_probe"] = roofline["achieved"] / rc["GBs"]
 
     out = {
         "metric": "PDHG iter/s (plain solve to eps_rel=1e-4)",

@@ -440,6 +440,17 @@ int mipdhg_autotune_cached(const mipdhg_lp *lp, mipdhg_options *opt, int32_t ite
                            void *workspace, size_t workspace_bytes, void *stream, double *x, double *y, double *z,
                            double *r_p, double *r_d, double *best_ms, int32_t *hit);
 
+/* Not an operation of the method: a plain streaming read of `bytes` bytes of
+ * device memory at buf (16-byte aligned, a positive multiple of 16), with the
+ * non-temporal 16-byte vector loads the SpMV kernels stream their matrices
+ * with, by `blocks` workgroups of 256 threads on `stream`.  It writes one
+ * 32-bit word per wave (blocks * 4 words) to the device array out, the XOR of
+ * the words the wave read.  Timed, it gives the read rate a kernel reaches on
+ * the device, the ceiling the iteration kernels are measured against; under
+ * a hardware counter it gives the counter's reading for a known number of
+ * bytes read.  Asynchronous; INVALID_ARG on a bad argument. */
+int mipdhg_read_probe(const void *buf, size_t bytes, int32_t blocks, void *stream, uint32_t *out);
+
 /* Text for a status or error code. */
 const char *mipdhg_status_string(int code);
 

@@ -89,6 +89,7 @@ SIGNATURES = {
                                       C.POINTER(_f64)]),
     "mipdhg_center_reclamp": (C.c_int, [_i32, _f64, _p, _p, _p]),
     "mipdhg_center_noalloc_max_n": (_i32, []),
+    "mipdhg_read_probe": (C.c_int, [_p, C.c_size_t, _i32, _p, _p]),
     "mipdhg_center_start_noalloc": (C.c_int, [_i32, _p, _p, _p, _f64, _f64, _f64, _p, _p, _p, C.POINTER(_f64)]),
     "mipdhg_autotune": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _i32, _p, C.c_size_t, _p,
                                   _p, _p, _p, _p, _p, C.POINTER(_f64)]),

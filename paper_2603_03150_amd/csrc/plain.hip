@@ -1006,18 +1006,25 @@ __global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t
 // r_c = D_c (c - A^T D_r y0) (d_self, d_other: the row and column factors of
 // the matrix walked; anchor: the anchor of the other side).  Runs at setup
 // (force) and after a restart.
+// d_other * anchor in float64 (the factor k_anchor_resid gathers per
+// nonzero), under the same gate
+template <typename T>
+__global__ void k_anchor_scale(const double* d, const T* anchor, int64_t n, double* out, const Ctrl* ctrl, int force) {
+    if (!force && !ctrl->restart_now) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = d[i] * (double)anchor[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_anchor_resid(TilePlan tp, const int32_t* col, const double* val,
-                                                         const double* d_self, const double* d_other,
-                                                         const double* vec, const T* anchor, T* out,
-                                                         const Ctrl* ctrl, int force) {
+                                                         const double* d_self, const double* scaled_anchor,
+                                                         const double* vec, T* out, const Ctrl* ctrl, int force) {
     if (!force && !ctrl->restart_now) return;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, tp);
     auto prod = [&](int b, int j) {
         const int64_t k = (int64_t)b + j;
-        const int32_t cc = ld_idx(col, k);
-        return ld_val(val, k) * (d_other[cc] * (double)anchor[cc]);
+        return ld_val(val, k) * scaled_anchor[ld_idx(col, k)];
     };
     auto epi = [&](int r, double t) { out[r] = (T)(d_self[r] * (vec[r] - t)); };
     auto le = lepi(epi);
@@ -1733,13 +1740,19 @@ struct Solver {
         return launch_anchor_resid(0);
     }
     // r_b, r_c of the current anchor (force: whatever the restart flag says)
+    // (the power iteration's vectors, free after setup, hold D_c x0 and D_r y0)
     int launch_anchor_resid(int force) {
+        const Ctrl* c = (const Ctrl*)w.ctrl;
+        hipLaunchKernelGGL((k_anchor_scale<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
+                           (const double*)w.d_col, (const T*)w.x0, (int64_t)lp.n, w.pu, c, force);
+        hipLaunchKernelGGL((k_anchor_scale<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
+                           (const double*)w.d_row, (const T*)w.y0, (int64_t)lp.m, w.pav, c, force);
         hipLaunchKernelGGL((k_anchor_resid<T>), dim3(ta.ntiles), dim3(kBlock), tile_lds_bytes(ta, 8), stream, ta,
-                           lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, lp.b,
-                           (const T*)w.x0, (T*)w.bt, (const Ctrl*)w.ctrl, force);
+                           lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.pu, lp.b, (T*)w.bt, c,
+                           force);
         hipLaunchKernelGGL((k_anchor_resid<T>), dim3(tat.ntiles), dim3(kBlock), tile_lds_bytes(tat, 8), stream, tat,
-                           lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.c,
-                           (const T*)w.y0, (T*)w.ct, (const Ctrl*)w.ctrl, force);
+                           lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.pav, lp.c, (T*)w.ct, c,
+                           force);
         MIP_LAUNCH_CHECK();
         return 0;
     }

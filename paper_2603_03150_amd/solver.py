@@ -343,3 +343,16 @@ def center_reclamp(xp: torch.Tensor, zp: torch.Tensor, alpha_min: float) -> None
     _lib.check(lib.mipdhg_center_reclamp(int(xp.numel()), float(alpha_min),
                                          torch.cuda.current_stream(xp.device).cuda_stream,
                                          xp.data_ptr(), zp.data_ptr()))
+
+
+def read_probe(buf: torch.Tensor, blocks: int = 2048) -> torch.Tensor:
+    """Stream-read all of buf (a contiguous device tensor whose size is a
+    multiple of 16 bytes) on the current stream (mipdhg_read_probe); returns
+    the per-wave XOR words, asynchronously."""
+    lib = _lib.load()
+    if not buf.is_contiguous():
+        raise ValueError("read_probe needs a contiguous tensor")
+    out = torch.empty(blocks * 4, dtype=torch.int32, device=buf.device)
+    _lib.check(lib.mipdhg_read_probe(buf.data_ptr(), buf.numel() * buf.element_size(), int(blocks),
+                                     torch.cuda.current_stream(buf.device).cuda_stream, out.data_ptr()))
+    return out
