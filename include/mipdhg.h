@@ -408,7 +408,9 @@ size_t mipdhg_sizeof(int which);
  * short-row-32 sums, one workgroup per tile or persistent; tiles sized
  * so that their count is 4..8 per compute unit, from the row pointers; the
  * dual step on A's panel layout, spmv_kind 3, whose primal step is kind 0's
- * and takes kind 0's fastest primal shape): each
+ * and takes kind 0's fastest primal shape, and whose A tiles, which the
+ * power iteration and the evaluations still use, take kind 0's fastest dual
+ * shape): each
  * runs `iters` iterations, then 256 back-to-back launches of each kernel
  * timed with hipEvents (kernel_timing = 2).  For each spmv_kind it takes
  * the fastest shape of the dual kernel (A's tiles) and of the primal kernel

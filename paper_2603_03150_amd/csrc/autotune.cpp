@@ -148,9 +148,12 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     }
     if (kind < 0) return mip::set_error("no candidate shape could be timed"), MIPDHG_ERR_UNSUPPORTED;
     opt->spmv_kind = kind;
-    opt->tile_nnz = dual[kind].c.tile_nnz;
-    opt->tile_rows = dual[kind].c.tile_rows;
-    opt->short_row = dual[kind].c.short_row;
+    // kind 3 still runs the power iteration and the evaluations on A's tiles:
+    // the shape of kind 0's fastest dual
+    const Cand& ac = (kind == 3 && dual[0].ms < 1e300) ? dual[0].c : dual[kind].c;
+    opt->tile_nnz = ac.tile_nnz;
+    opt->tile_rows = ac.tile_rows;
+    opt->short_row = ac.short_row;
     opt->tile_nnz_at = primal[kind].c.tile_nnz_at;
     opt->tile_rows_at = primal[kind].c.tile_rows_at;
     opt->short_row_at = primal[kind].c.short_row_at;

@@ -57,7 +57,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rows(const double* partials, 
     __shared__ double sh[kBlock];
     for (int q = 0; q < W; ++q) {
         double s = 0.0;
-        for (int g = threadIdx.x; g < G; g += kBlock) s += partials[(int64_t)g * W + q];
+        int g = threadIdx.x;
+        for (; g + 7 * kBlock < G; g += 8 * kBlock) {  // 8 loads in flight, added in the same order
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = partials[(int64_t)(g + u * kBlock) * W + q];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; g < G; g += kBlock) s += partials[(int64_t)g * W + q];
         sh[threadIdx.x] = s;
         __syncthreads();
         for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -871,7 +879,21 @@ __device__ void fixed_cols(const double* p, int G, double (&out)[W], double (*sh
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
-    for (int g = threadIdx.x; g < G; g += kBlock) {
+    // a thread's entries g, g + kBlock, ... in that order; U of them loaded at once
+    constexpr int U = W > 4 ? 4 : 8;
+    int g = threadIdx.x;
+    for (; g + (U - 1) * kBlock < G; g += U * kBlock) {
+        double x[U][W];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < W; ++q) x[u][q] = p[(int64_t)(g + u * kBlock) * W + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < W; ++q) v[q] = q < NS ? v[q] + x[u][q] : fmax(v[q], x[u][q]);
+    }
+    for (; g < G; g += kBlock) {
 #pragma unroll
         for (int q = 0; q < W; ++q) {
             const double x = p[(int64_t)g * W + q];
@@ -2094,7 +2116,10 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     }
     // host objects of the loop, released on every return path (after the
     // stream has been synchronised on the normal one)
-    constexpr int kDepth = 3;
+    // blocks in flight: one running and one queued behind it, so that the GPU
+    // never waits for the host, and one block (returning at once) runs past
+    // the one that ends the solve
+    constexpr int kDepth = 2;
     struct LoopRes {
         hipGraphExec_t gexec = nullptr;
         hipGraph_t g = nullptr;

@@ -178,8 +178,9 @@ def test_autotune_on_a_general_lp_picks_a_tile_shape():
     lp = lpgen.general_cfg2_sub(0, 100)
     dlp = P.DeviceLP.from_lp(lp)
     best = P.autotune(dlp, "fp32", iters=32)
-    assert best["spmv_kind"] in (0, 2) and best["ms_per_iter"] > 0
-    shape = {k: v for k, v in best.items() if k != "ms_per_iter"}
+    # lane groups (kind 1) do not run the general form; tiles, persistent tiles, panels do
+    assert best["spmv_kind"] in (0, 2, 3) and best["ms_per_iter"] > 0
+    shape = {k: v for k, v in best.items() if k not in ("ms_per_iter", "cache_hit")}
     a = P.solve(dlp, 1e-4, "fp32", **shape)
     b = P.solve(dlp, 1e-4, "fp32")
     # float32 row sums round differently with other tiles: the stopping

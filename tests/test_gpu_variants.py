@@ -95,7 +95,7 @@ def test_restart_to_average_limits():
     assert best["spmv_kind"] == 0
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(halpern=0, restart_avg=1), dict(restart_avg=1)])
+@pytest.mark.parametrize("kw", [dict(), dict(halpern=0, restart_avg=1), dict(restart_avg=1), dict(spmv_kind=3)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_workspace_contents_do_not_matter(kw, prec):
     # a workspace full of NaN bit patterns gives bitwise the solve of a zeroed one:
