@@ -78,6 +78,28 @@ then moves the state and the anchor to that average instead of the last
 projected point, and the primal-weight update measures the distances of the
 average to the old anchor.  The restart tests themselves are unchanged.
 
+Adaptive step with rejection (a variant, off by default: step_rule = 1,
+the per-iteration step rule of PDLP, which the cuPDLP family descends from;
+Section 4.1 names that family).  It needs plain PDHG (halpern off, reflection
+0, restarts to the last point), so that an iterate is the projected point
+T(z) of the previous one.  The step starts at 1 / max_ij |A~_ij| (no power
+iteration).  Every iteration is an attempt: with the current eta it forms
+z' = T(z) (tau = eta / omega, sigma = eta omega) and the largest step the
+move admits, eta_bar = (omega ||x' - x||^2 + ||y' - y||^2 / omega) /
+(2 |(y' - y)^T A~ (x' - x)|) (infinite when the product is 0).  The attempt
+is accepted when eta <= eta_bar (z <- z'), rejected otherwise (z stays);
+either way the next attempt uses eta <- min((1 - (t + 1)^-0.3) eta_bar,
+(1 + (t + 1)^-0.6) eta), t the attempt's 1-based number.  Readings: t counts
+every attempt, rejected ones included, and so do the iteration limit, the
+evaluation schedule and the restart rule's k and t; the fixed-point residual
+R of an evaluation is that of its attempt, z - T(z) with the attempt's step,
+while the evaluated and restart point is the current z (after the accept or
+reject).  Pinned by hand-built accept, reject and boundary cases of the rule,
+the bound |dy^T A~ dx| <= ||A~||_2 ||dz||^2_omega / 2 (a step of at most
+1 / ||A~||_2 is never rejected, whatever the move), planted optima reached
+with rejections on the way, and rejected attempts leaving the iterate
+unchanged.
+
 The restart rule, the primal-weight update and the step rule are pinned as
 definitions (hand-built cases above).  What no pin can fix is whether these
 constants are those of the solver the paper used: the iteration counts to a
@@ -116,6 +138,7 @@ class OracleOptions:
     pw_ki: float = 0.0        # primal weight as a PID controller: integral gain
     pw_kd: float = 0.0        # and derivative gain (pw_theta is the proportional one)
     restart_avg: bool = False  # restart to the epoch's average of the projected points
+    step_rule: int = 0         # 0: eta = safety / sigma_hat; 1: adaptive with rejection (plain PDHG only)
 
 
 @dataclass
@@ -152,6 +175,7 @@ class Result:
     log: list = field(default_factory=list)  # (t, restarted, omega after)
     trace: dict = field(default_factory=dict)  # t -> (x, y, x_hat, y_hat), scaled
     evals: list = field(default_factory=list)  # (t, k, R, R0, R_prev) seen by each restart decision
+    rejected: int = 0  # step_rule 1: attempts whose step was rejected
 
 
 # ---------------------------------------------------------------------------
@@ -267,6 +291,22 @@ def step_size(sigma_hat: float, hist: list, opts: OracleOptions) -> float:
         if abs(hist[-1] - hist[-11]) > 1e-3 * hist[-1]:
             return opts.step_safety
     return opts.step_safety / sigma_hat
+
+
+def adaptive_initial_step(At) -> float:
+    """step_rule 1: the first step, 1 / (largest |entry| of the scaled matrix)."""
+    big = float(np.max(np.abs(At.data))) if At.nnz else 0.0
+    return 1.0 / big if big > 0.0 else 1.0
+
+
+def adaptive_step(dx2: float, dy2: float, cross: float, eta: float, omega: float, t: int):
+    """step_rule 1 on one attempt of step eta, whose move has squared norms
+    dx2 = ||x' - x||^2, dy2 = ||y' - y||^2 and cross = (y' - y)^T A~ (x' - x):
+    returns (accepted, next step, eta_bar)."""
+    mag = abs(cross)
+    eta_bar = (omega * dx2 + dy2 / omega) / (2.0 * mag) if mag > 0.0 else math.inf
+    nxt = min((1.0 - (t + 1.0) ** -0.3) * eta_bar, (1.0 + (t + 1.0) ** -0.6) * eta)
+    return eta <= eta_bar, nxt, eta_bar
 
 
 def initial_weight(bt: np.ndarray, ct: np.ndarray) -> float:
@@ -446,8 +486,15 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     ct = d_col * c
     lo_t = lo / d_col if general else None
     hi_t = hi / d_col if general else None
-    sigma_hat, hist = power_sigma(At, opts.power_iters)
-    eta = step_size(sigma_hat, hist, opts)
+    adaptive = opts.step_rule == 1
+    if adaptive:
+        if opts.halpern or opts.reflect_rho != 0.0 or opts.restart_avg:
+            raise ValueError("step_rule 1 needs halpern off, reflect_rho 0 and restarts to the last point")
+        sigma_hat, eta = 0.0, adaptive_initial_step(At)
+    else:
+        sigma_hat, hist = power_sigma(At, opts.power_iters)
+        eta = step_size(sigma_hat, hist, opts)
+    rejected = 0
     omega0 = initial_weight(bt, ct)
     omega = omega0
     tau, sig = eta / omega, eta * omega
@@ -476,9 +523,18 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                       + float(np.sum((y - y_hat) ** 2)) / omega)
         if k == 0:
             R0 = R
-        w = (k + 1.0) / (k + 2.0) if opts.halpern else 1.0
-        x_new = w * ((1.0 + rho) * x_hat - rho * x) + (1.0 - w) * x0
-        y_new = w * ((1.0 + rho) * y_hat - rho * y) + (1.0 - w) * y0
+        if adaptive:  # accept T(z) or keep z; either way the step changes
+            dx, dy = x_hat - x, y_hat - y
+            ok, eta, _ = adaptive_step(float(dx @ dx), float(dy @ dy), float(dy @ (At @ dx)), eta, omega, t)
+            tau, sig = eta / omega, eta * omega
+            x_new, y_new = (x_hat, y_hat) if ok else (x.copy(), y.copy())
+            rejected += 0 if ok else 1
+            x_ev, y_ev = x_new, y_new
+        else:
+            w = (k + 1.0) / (k + 2.0) if opts.halpern else 1.0
+            x_new = w * ((1.0 + rho) * x_hat - rho * x) + (1.0 - w) * x0
+            y_new = w * ((1.0 + rho) * y_hat - rho * y) + (1.0 - w) * y0
+            x_ev, y_ev = x_hat, y_hat
         if opts.restart_avg:  # the mean of the epoch's points; the first is its own mean
             if k == 0:
                 x_avg, y_avg = x_hat.copy(), y_hat.copy()
@@ -489,7 +545,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
         k += 1
         restarted = False
         if t % E == 0 or t == opts.max_iter:
-            meas = evaluate(A, AT, b, c, d_row, d_col, x_hat, y_hat, lo, hi, sense)
+            meas = evaluate(A, AT, b, c, d_row, d_col, x_ev, y_ev, lo, hi, sense)
             status = None
             if not all(math.isfinite(v) for v in (meas.rp_norm, meas.rd_norm, meas.pobj, meas.dobj)):
                 status = 3
@@ -502,12 +558,12 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
                 status = 1
             if status is not None:
                 if t <= trace_iters:
-                    trace[t] = (x_new, y_new, x_hat, y_hat)
+                    trace[t] = (x_new, y_new, x_ev, y_ev)
                 return Result(status, t, restarts, meas, d_row, d_col, sigma_hat, eta,
-                              omega0, omega, log, trace, evals)
+                              omega0, omega, log, trace, evals, rejected)
             evals.append((t, k, R, R0, R_prev))
             if opts.restarts and restart_due(R, R0, R_prev, k, t, opts):
-                px, py = (x_avg, y_avg) if opts.restart_avg else (x_hat, y_hat)
+                px, py = (x_avg, y_avg) if opts.restart_avg else (x_ev, y_ev)
                 dx = float(np.linalg.norm(px - x0))
                 dy = float(np.linalg.norm(py - y0))
                 if dx > 1e-10 and dy > 1e-10:
@@ -525,7 +581,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
             prev = (meas.x, meas.y)
         x, y = x_new, y_new
         if t <= trace_iters:
-            trace[t] = (x.copy(), y.copy(), x_hat, y_hat)
+            trace[t] = (x.copy(), y.copy(), x_ev, y_ev)
 
 
 # ---------------------------------------------------------------------------
