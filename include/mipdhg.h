@@ -223,6 +223,22 @@ typedef struct mipdhg_options {
      * float32, 16,384 in float64); smaller panels exist to test the layout on
      * small matrices.                                                     [0] */
     int32_t panel_width;
+    /* Step rule: 0 = eta = step_safety / sigma_hat from the power iteration,
+     * held fixed; 1 = the adaptive step with rejection of PDLP, the solver
+     * family Section 4.1 builds on: the step starts at 1 / max |A~_ij|, every
+     * iteration is an attempt z' = T(z) with the current eta, accepted when
+     * eta <= eta_bar = (omega ||x' - x||^2 + ||y' - y||^2 / omega) /
+     * (2 |(y' - y)^T A~ (x' - x)|) and rejected (z unchanged) otherwise, and
+     * the next attempt uses min((1 - (t + 1)^-0.3) eta_bar,
+     * (1 + (t + 1)^-0.6) eta), t the attempt's 1-based number.  Attempts
+     * count as iterations (limit, evaluations, restart rule); an evaluation
+     * measures the current iterate and takes the fixed-point residual of its
+     * attempt.  Needs plain PDHG (halpern 0, reflect_rho 0, restart_avg 0;
+     * INVALID_ARG otherwise) and spmv_kind 0 (UNSUPPORTED otherwise); single-LP
+     * solve only.                                                          [0] */
+    int32_t step_rule;
+    /* step_rule 1: the first step, > 0 (0 = 1 / max |A~_ij|)              [0] */
+    double step0;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */
@@ -240,8 +256,10 @@ typedef struct mipdhg_info {
                                z_j^- (hi_j - x_j) over finite bounds)                */
     double max_violation;   /* max(rp_inf, rd_inf, xz / (1 + |c^T x|)), Section 4.3 */
     double b_norm, c_norm;  /* ||b||_2, ||c||_2                                     */
-    double sigma_hat;       /* power-iteration estimate of ||D_r A D_c||_2          */
-    double eta;             /* step, tau * sigma = eta^2                            */
+    double sigma_hat;       /* power-iteration estimate of ||D_r A D_c||_2 (0 with
+                               step_rule 1, which runs no power iteration)           */
+    double eta;             /* step, tau * sigma = eta^2 (step_rule 1: the step the
+                               next attempt would take)                              */
     double omega0, omega;   /* initial and final primal weight                      */
     double ms_setup, ms_iter, ms_total; /* wall time: validation+scaling+step, loop, all */
     double bytes_per_iter;  /* algorithmic bytes of one iteration: A and A^T values and
@@ -252,6 +270,7 @@ typedef struct mipdhg_info {
     int32_t lanes_a, lanes_at, long_a, long_at; /* SpMV plan used                   */
     double ms_graph;        /* part of ms_iter spent capturing and instantiating the
                                iteration block's hipGraph                            */
+    int64_t rejected;       /* step_rule 1: attempts whose step was rejected        */
 } mipdhg_info;
 
 /* Fill `opt` with the defaults shown in brackets above. */

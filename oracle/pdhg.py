@@ -83,7 +83,7 @@ the per-iteration step rule of PDLP, which the cuPDLP family descends from;
 Section 4.1 names that family).  It needs plain PDHG (halpern off, reflection
 0, restarts to the last point), so that an iterate is the projected point
 T(z) of the previous one.  The step starts at 1 / max_ij |A~_ij| (no power
-iteration).  Every iteration is an attempt: with the current eta it forms
+iteration; or a first step the caller gives).  Every iteration is an attempt: with the current eta it forms
 z' = T(z) (tau = eta / omega, sigma = eta omega) and the largest step the
 move admits, eta_bar = (omega ||x' - x||^2 + ||y' - y||^2 / omega) /
 (2 |(y' - y)^T A~ (x' - x)|) (infinite when the product is 0).  The attempt
@@ -139,6 +139,7 @@ class OracleOptions:
     pw_kd: float = 0.0        # and derivative gain (pw_theta is the proportional one)
     restart_avg: bool = False  # restart to the epoch's average of the projected points
     step_rule: int = 0         # 0: eta = safety / sigma_hat; 1: adaptive with rejection (plain PDHG only)
+    step0: float = 0.0         # step_rule 1: the first step (0: 1 / max |A~_ij|)
 
 
 @dataclass
@@ -490,7 +491,7 @@ def solve(A, AT, b, c, eps: float, opts: OracleOptions | None = None,
     if adaptive:
         if opts.halpern or opts.reflect_rho != 0.0 or opts.restart_avg:
             raise ValueError("step_rule 1 needs halpern off, reflect_rho 0 and restarts to the last point")
-        sigma_hat, eta = 0.0, adaptive_initial_step(At)
+        sigma_hat, eta = 0.0, (opts.step0 if opts.step0 > 0.0 else adaptive_initial_step(At))
     else:
         sigma_hat, hist = power_sigma(At, opts.power_iters)
         eta = step_size(sigma_hat, hist, opts)

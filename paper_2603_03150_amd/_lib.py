@@ -45,7 +45,7 @@ class OptionsStruct(C.Structure):
                 ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32),
                 ("infeas_tol", _f64), ("pw_ki", _f64), ("pw_kd", _f64),
                 ("tile_nnz_at", _i32), ("tile_rows_at", _i32), ("short_row_at", _i32), ("restart_avg", _i32),
-                ("panel_width", _i32)]
+                ("panel_width", _i32), ("step_rule", _i32), ("step0", _f64)]
 
 
 class InfoStruct(C.Structure):
@@ -58,7 +58,7 @@ class InfoStruct(C.Structure):
                 ("bytes_per_iter", _f64), ("bytes_primal", _f64), ("bytes_dual", _f64),
                 ("ms_primal", _f64), ("ms_dual", _f64), ("n_primal", _i64), ("n_dual", _i64),
                 ("lanes_a", _i32), ("lanes_at", _i32), ("long_a", _i32), ("long_at", _i32),
-                ("ms_graph", _f64)]
+                ("ms_graph", _f64), ("rejected", _i64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

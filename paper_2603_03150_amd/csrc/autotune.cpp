@@ -97,7 +97,7 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     balanced_candidates(lp, (hipStream_t)stream, cands);
     for (const Cand& c : cands) {
         if (general && c.kind == 1) continue;
-        if (opt->restart_avg && c.kind != 0) continue;  // one workgroup per tile only
+        if ((opt->restart_avg || opt->step_rule == 1) && c.kind != 0) continue;  // one workgroup per tile only
         mipdhg_options o = *opt;
         o.spmv_kind = c.kind;
         o.tile_nnz = c.tile_nnz;

@@ -600,8 +600,8 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
         return set_error("workspace and all five outputs are required"), MIPDHG_ERR_INVALID_ARG;
     if (is_general(bt->whole))
         return set_error("the general form (bounds, inequality rows) is a single-LP option"), MIPDHG_ERR_UNSUPPORTED;
-    if (opt->pw_ki != 0.0 || opt->pw_kd != 0.0 || opt->restart_avg)
-        return set_error("the PID primal weight and restart to average are single-LP options"),
+    if (opt->pw_ki != 0.0 || opt->pw_kd != 0.0 || opt->restart_avg || opt->step_rule)
+        return set_error("the PID primal weight, restart to average and the adaptive step are single-LP options"),
                MIPDHG_ERR_UNSUPPORTED;
     if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing || opt->resume)
         return set_error("tracing, warm starts, kernel timing and resume are single-LP options"),

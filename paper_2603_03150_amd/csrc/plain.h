@@ -36,6 +36,11 @@ struct Ctrl {
     double infeas_tol;
     // primal weight as a PID controller: gains, integral, previous error
     double pw_ki, pw_kd, pw_int, pw_err;
+    // the step setup computed (what a resumed solve must recompute), and the
+    // adaptive step rule's last decision and rejection count
+    double eta0;
+    int32_t accepted, step_rule;
+    int64_t rejected;
 };
 
 // shared host helpers (plain.hip, validate.hip)

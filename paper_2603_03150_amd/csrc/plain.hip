@@ -42,6 +42,12 @@ __global__ void k_fill(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
+template <typename T>
+__global__ void k_fill_t(T* p, int64_t n, T v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // partial sums of squares of a float64 vector, one slot per workgroup
 __global__ __launch_bounds__(kBlock) void k_sumsq(const double* v, int64_t n, double* partials) {
     double s[1] = {0.0};
@@ -105,6 +111,21 @@ __global__ void k_scale_update(double* d, const double* stat, int64_t n) {
         double s = stat[i];
         if (s > 0.0) d[i] = d[i] * (1.0 / sqrt(s));
     }
+}
+
+// part[b] = max of this block's grid-stride share of v (0 for none)
+__global__ __launch_bounds__(kBlock) void k_max_part(const double* v, int64_t n, double* part) {
+    __shared__ double sh[kBlock];
+    double mx = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        mx = fmax(mx, v[i]);
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 // out[k] = d_self[r] * val[k] * d_other[col[k]] rounded to V, for every row r
@@ -299,6 +320,11 @@ struct IterArgs {
     const T* hi;
     const int8_t* sense;  // general form, dual: row senses
     T* avg;               // restart to average: the epoch's mean of x^ or y^
+    T* state_out;         // where the new u or v goes (the state itself, or with the
+                          // adaptive step the other buffer of the pair)
+    const T* ax_in;       // adaptive step, dual: A~ (x - x0) of the current iterate
+    T* ax_out;            // and of the attempt's x^ (A~ (x - x0) + A~ (x^ - x))
+    double* apart;        // adaptive step: per-block sums of the attempt's move
     double rho;
     int32_t halpern;
     int32_t it;
@@ -314,6 +340,7 @@ struct IterPre {
     T lo, hi;  // general form, primal
     int sense; // general form, dual
     T av;      // restart to average
+    T ax;      // adaptive step, dual: A~ (x - x0)
 };
 
 // GEN: the general form (Section 2 mentions bounds and inequality rows):
@@ -323,7 +350,14 @@ struct IterPre {
 // is updated (avg = h after the epoch's first iteration, avg += (h - avg) / j
 // after its j-th) and its distance to the anchor replaces that of h in the
 // evaluation partials.
-template <typename T, typename V, bool PRIMAL, bool GEN, bool AVG = false>
+// ADAPT: the adaptive step (plain PDHG, no Halpern, no reflection): the
+// primal hands the dual the move x^ - x instead of x_bar - x0, so that the
+// dual's row sum is A~ (x^ - x) itself (no cancellation in the step rule's
+// cross term); the dual forms A~ (x_bar - x0) = A~ (x - x0) + 2 A~ (x^ - x)
+// from the kept product of the current iterate, keeps A~ (x^ - x0) for the
+// next attempt, and both add the move's terms ||x^ - x||^2 (q[3]),
+// ||y^ - y||^2 (q[3]) and (y^ - y)^T A~ (x^ - x) (q[4]).
+template <typename T, typename V, bool PRIMAL, bool GEN, bool AVG = false, bool ADAPT = false>
 struct IterEpi {
     const IterArgs<T, V>& a;
     double w, omw, rho, opr, st;
@@ -360,6 +394,7 @@ struct IterEpi {
         }
         if (GEN && !PRIMAL) p.sense = ld_at(a.sense + r0, i);
         if (AVG) p.av = ld_at(a.avg + r0, i);
+        if (ADAPT && !PRIMAL) p.ax = ld_at(a.ax_in + r0, i);
         return p;
     }
     // The arithmetic is float64 whatever the storage type T: the stored
@@ -379,18 +414,30 @@ struct IterEpi {
             } else {
                 dh = dh < -an ? -an : dh;  // projection onto x >= 0 (NaN propagates)
             }
-            st_at(a.bar + r0, i, (T)(2.0 * dh - o));
+            st_at(a.bar + r0, i, (T)(ADAPT ? dh - o : 2.0 * dh - o));
+            if (ADAPT) q[3] += (dh - o) * (dh - o);
         } else {
-            dh = o + st * ((double)p.rhs - (double)s);  // v + sigma (b~ - A~ x_bar)
+            double sb = (double)s;
+            if (ADAPT) {  // s = A~ (x^ - x): extrapolate from the kept A~ (x - x0)
+                const double ax = (double)p.ax;
+                sb = ax + 2.0 * (double)s;
+                st_at(a.ax_out + r0, i, (T)(ax + (double)s));
+            }
+            dh = o + st * ((double)p.rhs - sb);  // v + sigma (b~ - A~ x_bar)
             if (GEN) {  // the sign each row's sense allows y0 + dh
                 if (p.sense == MIPDHG_SENSE_GE) dh = dh < -an ? -an : dh;
                 else if (p.sense == MIPDHG_SENSE_LE) dh = dh > -an ? -an : dh;
+            }
+            if (ADAPT) {
+                const double dy = dh - o;
+                q[3] += dy * dy;
+                q[4] += dy * (double)s;
             }
         }
         const double h = an + dh;  // x^ or y^
         if (flags & F_HAT) st_at(a.hat + r0, i, (T)h);
         // Halpern/reflection step; the anchor is 0 in these coordinates
-        st_at(a.state + r0, i, (T)(w * (opr * dh - rho * o)));
+        st_at(a.state_out + r0, i, (T)(w * (opr * dh - rho * o)));
         double rd = dh;  // the restart point's distance to the anchor
         if (AVG) {  // the epoch's mean; its first point is taken as it is (the buffer is not read)
             double rp = h;
@@ -419,9 +466,9 @@ struct IterEpi {
     }
 };
 
-template <typename T, typename V, bool PRIMAL, bool GEN = false, bool AVG = false>
-__device__ __forceinline__ IterEpi<T, V, PRIMAL, GEN, AVG> make_epi(const IterArgs<T, V>& a, double* q) {
-    IterEpi<T, V, PRIMAL, GEN, AVG> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
+template <typename T, typename V, bool PRIMAL, bool GEN = false, bool AVG = false, bool ADAPT = false>
+__device__ __forceinline__ IterEpi<T, V, PRIMAL, GEN, AVG, ADAPT> make_epi(const IterArgs<T, V>& a, double* q) {
+    IterEpi<T, V, PRIMAL, GEN, AVG, ADAPT> e{a, 1.0, 0.0, a.rho, 1.0 + a.rho, 0.0, a.flags, q, false};
     return e;
 }
 
@@ -450,15 +497,16 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs<T, V> a) {
 
 // LDS-tiled traversal (TilePlan).  The control word is loaded up front and
 // only checked once the products are in LDS.
-template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN, bool AVG = false>
+template <typename T, typename V, typename Acc, bool PRIMAL, int U, bool SORTED, bool GEN, bool AVG = false,
+          bool ADAPT = false>
 __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePlan tp) {
     // blocks queued behind the one that ended the solve stream nothing
     if (a.ctrl->status != ST_RUNNING) return;
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<Acc>(smem_t, tp);
-    double q[3] = {0.0, 0.0, 0.0};
+    double q[ADAPT ? 5 : 3] = {};
     double mx[1] = {0.0};
-    auto epi = make_epi<T, V, PRIMAL, GEN, AVG>(a, q);
+    auto epi = make_epi<T, V, PRIMAL, GEN, AVG, ADAPT>(a, q);
     // streamed arrays: tile base + 32-bit offset; the gather: a plain 64-bit
     // address, measured 12-18 % faster than the base + offset form on
     // 4096- and 8192-nonzero tiles
@@ -466,8 +514,23 @@ __global__ __launch_bounds__(kBlock) void k_iter_tiled(IterArgs<T, V> a, TilePla
         return ld_val_at(a.val + b, j) * (Acc)a.gather[(int64_t)ld_at_nt(a.col + b, j)];
     };
     tiled_rows<false, Acc, U, SORTED>(tp, own_tile(), L, prod, epi);
-    if (epi.running() && (a.flags & (F_FIRST | F_EVAL)))
-        block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+    if (epi.running() && (a.flags & (F_FIRST | F_EVAL))) {
+        if constexpr (ADAPT) {
+            double q3[3] = {q[0], q[1], q[2]};
+            block_reduce_store<3, 0>(q3, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+        } else {
+            block_reduce_store<3, 0>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
+        }
+    }
+    if constexpr (ADAPT) {
+        if (epi.running()) {
+            constexpr int NA = PRIMAL ? 1 : 2;
+            double qa[NA];
+            qa[0] = q[3];
+            if (!PRIMAL) qa[NA - 1] = q[4];
+            block_reduce_store<NA, 0>(qa, mx, a.apart + NA * blockIdx.x);
+        }
+    }
 }
 
 // The same step as a persistent launch: about one workgroup per resident slot,
@@ -1006,10 +1069,11 @@ __global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
     }
 }
 
-// on a restart: anchor <- restart point, state (relative to it) <- 0
+// on a restart: anchor <- restart point, state (relative to it) <- 0, and
+// with the adaptive step the kept A~ (x - x0) <- 0 (ax, else NULL)
 template <typename T>
 __global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t n, T* y, T* y0,
-                                const T* yh, int64_t m) {
+                                const T* yh, int64_t m, T* ax) {
     if (!c->restart_now) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1020,6 +1084,117 @@ __global__ void k_apply_restart(const Ctrl* c, T* x, T* x0, const T* xh, int64_t
          i += (int64_t)gridDim.x * blockDim.x) {
         y0[i] = yh[i];
         y[i] = (T)0;
+        if (ax) ax[i] = (T)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adaptive step with rejection (the step rule of PDLP)
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    Ctrl* ctrl;
+    const double* ap;  // [gp]: ||x^ - x||^2 per primal block
+    const double* ad;  // [gd][2]: ||y^ - y||^2, (y^ - y)^T A~ (x^ - x) per dual block
+    int gp, gd;
+    int32_t it;        // the attempt's index in its block
+};
+
+// One workgroup: the move's sums in fixed order, then the rule: eta_bar =
+// (omega ||dx||^2 + ||dy||^2 / omega) / (2 |dy^T A~ dx|) (infinite for a zero
+// product); the attempt is accepted when eta <= eta_bar; the next step is
+// min((1 - (t + 1)^-0.3) eta_bar, (1 + (t + 1)^-0.6) eta), t the attempt's
+// 1-based number.
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
+    Ctrl& c = *a.ctrl;
+    if (c.status != ST_RUNNING) return;
+    __shared__ double sh[2][kBlock];
+    double vp[1], vd[2];
+    fixed_cols<1, 1>(a.ap, a.gp, vp, sh);
+    fixed_cols<2, 2>(a.ad, a.gd, vd, sh);
+    if (threadIdx.x != 0) return;
+    const double om = c.omega, eta = c.eta;
+    const double mag = fabs(vd[1]);
+    const double bar = mag > 0.0 ? (om * vp[0] + vd[0] / om) / (2.0 * mag) : INFINITY;
+    const double t = (double)(c.t_base + a.it + 1);
+    const double nxt = fmin((1.0 - pow(t + 1.0, -0.3)) * bar, (1.0 + pow(t + 1.0, -0.6)) * eta);
+    const bool ok = eta <= bar;
+    c.accepted = ok ? 1 : 0;
+    if (!ok) c.rejected += 1;
+    c.eta = nxt;
+    c.tau = nxt / om;
+    c.sigma = nxt * om;
+}
+
+template <typename T>
+struct RestoreArgs {
+    const Ctrl* ctrl;
+    const T *u_in, *v_in, *ax_in;  // the attempt's inputs
+    T *u_out, *v_out, *ax_out;     // and outputs
+    const T *x0, *y0;
+    T *xhat, *yhat;                // F_HAT: the projected points the solve reports
+    double *xo, *yo;               // F_EVAL: the evaluated point, original space
+    const double *d_col, *d_row;
+    double *pp, *pd;               // F_EVAL: slot 2 of the evaluation partials
+    int64_t n, m;
+    int gp, gd;
+    int flags;
+};
+
+// After a rejected attempt: the outputs take the inputs back (the iterate
+// stays), and where the attempt stored its projected point for the solve
+// (F_HAT) or for the evaluation (F_EVAL) the current iterate replaces it,
+// with its distance to the anchor in the evaluation partials.  Block b
+// handles the b-th of gp chunks of the columns and of gd chunks of the rows,
+// one partial slot each.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adapt_restore(RestoreArgs<T> a) {
+    if (a.ctrl->status != ST_RUNNING || a.ctrl->accepted) return;
+    const int b = blockIdx.x;
+    double q[1] = {0.0};
+    double mx[1] = {0.0};
+    if (b < a.gp) {
+        const int64_t ch = (a.n + a.gp - 1) / a.gp, i0 = (int64_t)b * ch, i1 = min(a.n, i0 + ch);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+            const T u = a.u_in[i];
+            a.u_out[i] = u;
+            const double h = (double)a.x0[i] + (double)u;
+            if (a.flags & F_HAT) a.xhat[i] = (T)h;
+            if (a.flags & F_EVAL) {
+                a.xo[i] = a.d_col[i] * h;
+                q[0] += (double)u * (double)u;
+            }
+        }
+    }
+    if (a.flags & F_EVAL) {
+        if (b < a.gp) block_reduce_store<1, 0>(q, mx, a.pp + 3 * b + 2);
+        __syncthreads();
+        q[0] = 0.0;
+    }
+    if (b < a.gd) {
+        const int64_t ch = (a.m + a.gd - 1) / a.gd, i0 = (int64_t)b * ch, i1 = min(a.m, i0 + ch);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+            const T v = a.v_in[i];
+            a.v_out[i] = v;
+            a.ax_out[i] = a.ax_in[i];
+            const double h = (double)a.y0[i] + (double)v;
+            if (a.flags & F_HAT) a.yhat[i] = (T)h;
+            if (a.flags & F_EVAL) {
+                a.yo[i] = a.d_row[i] * h;
+                q[0] += (double)v * (double)v;
+            }
+        }
+    }
+    if ((a.flags & F_EVAL) && b < a.gd) block_reduce_store<1, 0>(q, mx, a.pd + 3 * b + 2);
+}
+
+// dst <- src for the three arrays of an iterate (u, v, A~ (x - x0))
+template <typename T>
+__global__ void k_copy_iterate(const T* u, T* u2, int64_t n, const T* v, T* v2, const T* ax, T* ax2, int64_t m) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        u2[i] = u[i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        v2[i] = v[i];
+        ax2[i] = ax[i];
     }
 }
 
@@ -1233,13 +1408,13 @@ uint64_t state_fingerprint(const mipdhg_lp& lp, const mipdhg_options& o) {
     };
     const int64_t sz[4] = {lp.m, lp.n, lp.nnz, (has_bounds(lp) ? 1 : 0) | (has_sense(lp) ? 2 : 0)};
     mix(sz, sizeof(sz));
-    const int32_t iv[20] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
+    const int32_t iv[21] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters, o.eval_every, o.halpern,
                             o.restarts, iter_kind(o, lp.m, lp.n), tile_nnz_of(o), tile_rows_of(o), short_row_of(o),
                             o.gather_order, o.lanes_a, o.lanes_at, o.long_row, tile_nnz_at_of(o),
-                            tile_rows_at_of(o), short_row_at_of(o), o.restart_avg, o.panel_width};
+                            tile_rows_at_of(o), short_row_at_of(o), o.restart_avg, o.panel_width, o.step_rule};
     mix(iv, sizeof(iv));
-    const double dv[8] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
-                          o.pw_kd};
+    const double dv[9] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta, o.pw_ki,
+                          o.pw_kd, o.step0};
     mix(dv, sizeof(dv));
     return h;
 }
@@ -1284,13 +1459,17 @@ struct PlainWs {
     double *xprev, *yprev;      // infeasibility certificates: previous evaluated point
     double *axprev, *atyprev;   // and its A x, A^T y
     void *x_avg, *y_avg;        // restart to average: the epoch's means
+    // adaptive step: the other buffer of the pairs (u, v, A~ (x - x0)) that
+    // attempts alternate between, A~ (x - x0) itself, and the move's sums
+    void *x_alt, *y_alt, *ax, *ax_alt;
+    double *ap, *ad;
     PanelLayout pl;             // spmv_kind 3: A's panel layout (dual step)
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
                      int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds,
-                     bool avg, bool panel) {
+                     bool avg, bool panel, bool adapt) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -1340,6 +1519,12 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
     w.hi_t = bounds ? cv.take<char>(n * ts) : nullptr;
     w.x_avg = avg ? cv.take<char>(n * ts) : nullptr;
     w.y_avg = avg ? cv.take<char>(m * ts) : nullptr;
+    w.x_alt = adapt ? cv.take<char>(n * ts) : nullptr;
+    w.y_alt = adapt ? cv.take<char>(m * ts) : nullptr;
+    w.ax = adapt ? cv.take<char>(m * ts) : nullptr;
+    w.ax_alt = adapt ? cv.take<char>(m * ts) : nullptr;
+    w.ap = adapt ? cv.take<double>((size_t)w.gcap) : nullptr;
+    w.ad = adapt ? cv.take<double>((size_t)w.gcap * 2) : nullptr;
     memset(&w.pl, 0, sizeof(w.pl));
     if (panel) {
         const int64_t sc = panel_seg_cap(m, nnz), cc = panel_chunk_cap(nnz), ec = panel_elem_cap(nnz);
@@ -1398,6 +1583,12 @@ int check_options(const mipdhg_options* o) {
         return set_error("tile_rows_at must be in [0, %d]", kMaxTileRows), MIPDHG_ERR_INVALID_ARG;
     if (o->short_row_at < -1) return set_error("short_row_at must be >= -1"), MIPDHG_ERR_INVALID_ARG;
     if (o->restart_avg < 0 || o->restart_avg > 1) return set_error("restart_avg must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (o->step_rule < 0 || o->step_rule > 1) return set_error("step_rule must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
+    if (!(o->step0 >= 0.0) || !std::isfinite(o->step0))
+        return set_error("step0 must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;
+    if (o->step_rule == 1 && (o->halpern != 0 || o->reflect_rho != 0.0 || o->restart_avg != 0))
+        return set_error("step_rule 1 needs plain PDHG: halpern 0, reflect_rho 0, restart_avg 0"),
+               MIPDHG_ERR_INVALID_ARG;
     for (int L : {o->lanes_a, o->lanes_at})
         if (L != 0 && L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
             return set_error("lanes must be 0 or a power of two in [2, 64]"), MIPDHG_ERR_INVALID_ARG;
@@ -1437,7 +1628,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
                    tile_rows_of(*opt), tile_nnz_at_of(*opt), tile_rows_at_of(*opt), sorted_layout(*opt, lp->m, lp->n),
-                   has_bounds(*lp), opt->restart_avg != 0, opt->spmv_kind == 3).bytes;
+                   has_bounds(*lp), opt->restart_avg != 0, opt->spmv_kind == 3, opt->step_rule == 1).bytes;
     return 0;
 }
 
@@ -1493,8 +1684,17 @@ struct Solver {
         (const void*)k_iter_tiled<T, V, Acc, false, 8, true, G, true>,                                        \
         (const void*)k_iter_tiled<T, V, Acc, true, 16, true, G, true>,                                        \
         (const void*)k_iter_tiled<T, V, Acc, false, 16, true, G, true>
+#define MIP_ADAPT_KERNELS(G)                                                                                 \
+    (const void*)k_iter_tiled<T, V, Acc, true, 8, false, G, false, true>,                                     \
+        (const void*)k_iter_tiled<T, V, Acc, false, 8, false, G, false, true>,                                \
+        (const void*)k_iter_tiled<T, V, Acc, true, 16, false, G, false, true>,                                \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, false, G, false, true>,                               \
+        (const void*)k_iter_tiled<T, V, Acc, true, 8, true, G, false, true>,                                  \
+        (const void*)k_iter_tiled<T, V, Acc, false, 8, true, G, false, true>,                                 \
+        (const void*)k_iter_tiled<T, V, Acc, true, 16, true, G, false, true>,                                 \
+        (const void*)k_iter_tiled<T, V, Acc, false, 16, true, G, false, true>
             const void* ks[] = {MIP_ITER_KERNELS(false), MIP_ITER_KERNELS(true), MIP_AVG_KERNELS(false),
-                                MIP_AVG_KERNELS(true),
+                                MIP_AVG_KERNELS(true), MIP_ADAPT_KERNELS(false), MIP_ADAPT_KERNELS(true),
                                 (const void*)k_eval<true, false>, (const void*)k_eval<false, false>,
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
@@ -1502,6 +1702,7 @@ struct Solver {
                                 (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
 #undef MIP_ITER_KERNELS
 #undef MIP_AVG_KERNELS
+#undef MIP_ADAPT_KERNELS
             for (const void* k : ks)
                 if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
                     return set_error("tile shape needs %d bytes of LDS per workgroup, more than the device allows", lim),
@@ -1589,7 +1790,25 @@ struct Solver {
         a.halpern = o.halpern;
         a.it = it;
         a.flags = flags;
+        a.state_out = a.state;
+        a.ax_in = nullptr;
+        a.ax_out = nullptr;
+        a.apart = nullptr;
+        if (adaptive()) {  // even attempts go from the first buffers to the second, odd ones back
+            const bool odd = (it & 1) != 0;
+            void* const xin = odd ? w.x_alt : w.x;
+            void* const xout = odd ? w.x : w.x_alt;
+            void* const yin = odd ? w.y_alt : w.y;
+            void* const yout = odd ? w.y : w.y_alt;
+            a.state = (T*)(primal ? xin : yin);
+            a.state_out = (T*)(primal ? xout : yout);
+            if (primal) a.gather = (const T*)yin;
+            a.ax_in = (const T*)(odd ? w.ax_alt : w.ax);
+            a.ax_out = (T*)(odd ? w.ax : w.ax_alt);
+            a.apart = primal ? w.ap : w.ad;
+        }
     }
+    bool adaptive() const { return o.step_rule == 1; }
     // One of the tile kernels: one workgroup per tile or persistent, 8 or 16
     // products in flight per thread, row-major or sorted layout.
     template <bool PRIMAL>
@@ -1598,12 +1817,15 @@ struct Solver {
         if (o.restart_avg) {  // one workgroup per tile only (checked with the options)
             if (g) launch_tiles_g<PRIMAL, true, true>(a, tp, gpersist);
             else launch_tiles_g<PRIMAL, false, true>(a, tp, gpersist);
+        } else if (adaptive()) {  // likewise
+            if (g) launch_tiles_g<PRIMAL, true, false, true>(a, tp, gpersist);
+            else launch_tiles_g<PRIMAL, false, false, true>(a, tp, gpersist);
         } else {
             if (g) launch_tiles_g<PRIMAL, true, false>(a, tp, gpersist);
             else launch_tiles_g<PRIMAL, false, false>(a, tp, gpersist);
         }
     }
-    template <bool PRIMAL, bool G, bool AVG>
+    template <bool PRIMAL, bool G, bool AVG, bool ADAPT = false>
     void launch_tiles_g(const IterArgs<T, V>& a, TilePlan tp, int gpersist) {
         const size_t lds = tile_lds_bytes(tp, sizeof(Acc));
         const bool big = tp.tile_nnz > 8 * kBlock;
@@ -1613,7 +1835,18 @@ struct Solver {
     hipLaunchKernelGGL((K<T, V, Acc, PRIMAL, U, SRT, G>), grid, dim3(kBlock), lds, stream, a, tp)
 #define MIP_AVG_LAUNCH(U, SRT) \
     hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, PRIMAL, U, SRT, G, true>), grid, dim3(kBlock), lds, stream, a, tp)
-        if constexpr (AVG) {
+#define MIP_ADAPT_LAUNCH(U, SRT)                                                                              \
+    hipLaunchKernelGGL((k_iter_tiled<T, V, Acc, PRIMAL, U, SRT, G, false, true>), grid, dim3(kBlock), lds, stream, \
+                       a, tp)
+        if constexpr (ADAPT) {
+            if (big) {
+                if (sorted()) MIP_ADAPT_LAUNCH(16, true);
+                else MIP_ADAPT_LAUNCH(16, false);
+            } else {
+                if (sorted()) MIP_ADAPT_LAUNCH(8, true);
+                else MIP_ADAPT_LAUNCH(8, false);
+            }
+        } else if constexpr (AVG) {
             if (big) {
                 if (sorted()) MIP_AVG_LAUNCH(16, true);
                 else MIP_AVG_LAUNCH(16, false);
@@ -1640,6 +1873,7 @@ struct Solver {
         }
 #undef MIP_TILE_LAUNCH
 #undef MIP_AVG_LAUNCH
+#undef MIP_ADAPT_LAUNCH
     }
     int launch_primal(int it, int flags) {
         IterArgs<T, V> a;
@@ -1757,7 +1991,7 @@ struct Solver {
         const T* ry = (const T*)(o.restart_avg ? w.y_avg : w.yhat);
         hipLaunchKernelGGL((k_apply_restart<T>), dim3(grid_for(mx)), dim3(kBlock), 0, stream,
                            (const Ctrl*)w.ctrl, (T*)w.x, (T*)w.x0, rx, (int64_t)lp.n, (T*)w.y, (T*)w.y0, ry,
-                           (int64_t)lp.m);
+                           (int64_t)lp.m, (T*)w.ax);
         MIP_LAUNCH_CHECK();
         return launch_anchor_resid(0);
     }
@@ -1778,6 +2012,39 @@ struct Solver {
         MIP_LAUNCH_CHECK();
         return 0;
     }
+    // The adaptive step's decision on attempt it, and the rollback of a
+    // rejected attempt
+    int launch_step(int it, int flags) {
+        StepArgs sa{w.ctrl, w.ap, w.ad, grid_primal(), grid_dual(), it};
+        hipLaunchKernelGGL(k_step, dim3(1), dim3(kBlock), 0, stream, sa);
+        const bool odd = (it & 1) != 0;
+        RestoreArgs<T> ra;
+        ra.ctrl = w.ctrl;
+        ra.u_in = (const T*)(odd ? w.x_alt : w.x);
+        ra.u_out = (T*)(odd ? w.x : w.x_alt);
+        ra.v_in = (const T*)(odd ? w.y_alt : w.y);
+        ra.v_out = (T*)(odd ? w.y : w.y_alt);
+        ra.ax_in = (const T*)(odd ? w.ax_alt : w.ax);
+        ra.ax_out = (T*)(odd ? w.ax : w.ax_alt);
+        ra.x0 = (const T*)w.x0;
+        ra.y0 = (const T*)w.y0;
+        ra.xhat = (T*)w.xhat;
+        ra.yhat = (T*)w.yhat;
+        ra.xo = xo;
+        ra.yo = yo;
+        ra.d_col = w.d_col;
+        ra.d_row = w.d_row;
+        ra.pp = w.pp;
+        ra.pd = w.pd;
+        ra.n = lp.n;
+        ra.m = lp.m;
+        ra.gp = grid_primal();
+        ra.gd = grid_dual();
+        ra.flags = flags;
+        hipLaunchKernelGGL((k_adapt_restore<T>), dim3(std::max(ra.gp, ra.gd)), dim3(kBlock), 0, stream, ra);
+        MIP_LAUNCH_CHECK();
+        return 0;
+    }
     // One block of nit iterations ending in an evaluation.  With trace, the
     // scaled iterates after iteration t_first + i are exported.
     int enqueue_block(int nit, int64_t t_first, bool trace) {
@@ -1790,16 +2057,29 @@ struct Solver {
             if (timing) MIP_HIP(hipEventRecord(tev[3 * it + 1], stream));
             if ((rc = launch_dual(it, flags))) return rc;
             if (timing) MIP_HIP(hipEventRecord(tev[3 * it + 2], stream));
+            if (adaptive()) {
+                if ((rc = launch_step(it, flags))) return rc;
+                if (last && (nit & 1)) {  // an odd block ends in the second buffers
+                    hipLaunchKernelGGL((k_copy_iterate<T>), dim3(grid_for(std::max(lp.m, lp.n))), dim3(kBlock), 0,
+                                       stream, (const T*)w.x_alt, (T*)w.x, (int64_t)lp.n, (const T*)w.y_alt, (T*)w.y,
+                                       (const T*)w.ax_alt, (T*)w.ax, (int64_t)lp.m);
+                    MIP_LAUNCH_CHECK();
+                }
+            }
             if (last && (rc = launch_eval_and_decide(nit))) return rc;
             const int64_t t = t_first + it;  // 1-based iteration number
             if (trace && t <= o.trace_iters) {
                 const int64_t off_n = (t - 1) * (int64_t)lp.n, off_m = (t - 1) * (int64_t)lp.m;
+                // the adaptive step's even attempts (but a block's last) leave the iterate in the second buffers
+                const bool second = adaptive() && !last && (it & 1) == 0;
                 if (o.trace_x)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
-                                       (const T*)w.x, (const T*)w.x0, o.trace_x + off_n, (int64_t)lp.n);
+                                       (const T*)(second ? w.x_alt : w.x), (const T*)w.x0, o.trace_x + off_n,
+                                       (int64_t)lp.n);
                 if (o.trace_y)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.m)), dim3(kBlock), 0, stream,
-                                       (const T*)w.y, (const T*)w.y0, o.trace_y + off_m, (int64_t)lp.m);
+                                       (const T*)(second ? w.y_alt : w.y), (const T*)w.y0, o.trace_y + off_m,
+                                       (int64_t)lp.m);
                 if (o.trace_xhat)
                     hipLaunchKernelGGL((k_export<T>), dim3(grid_for(lp.n)), dim3(kBlock), 0, stream,
                                        (const T*)w.xhat, (const T*)nullptr, o.trace_xhat + off_n, (int64_t)lp.n);
@@ -1834,7 +2114,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                 tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                o.restart_avg != 0, o.spmv_kind == 3);
+                o.restart_avg != 0, o.spmv_kind == 3, o.step_rule == 1);
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -1977,8 +2257,9 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         MIP_LAUNCH_CHECK();
     }
 
-    // --- power iteration for sigma_hat = ||D_r A D_c||_2
-    {
+    // --- power iteration for sigma_hat = ||D_r A D_c||_2 (not for the
+    // adaptive step, which starts from the largest scaled entry instead)
+    if (!S.adaptive()) {
         const double v0 = 1.0 / sqrt((double)n);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.pv, n, v0);
         // on the scaled iteration copies (tile plans with their layout)
@@ -2013,17 +2294,28 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         }
         MIP_LAUNCH_CHECK();
     }
-    std::vector<double> hist(o.power_iters + 1);
-    double red[4];
-    MIP_HIP(hipMemcpyAsync(hist.data(), w.hist, hist.size() * 8, hipMemcpyDeviceToHost, stream));
-    MIP_HIP(hipMemcpyAsync(red, w.red, 4 * 8, hipMemcpyDeviceToHost, stream));
+    if (S.adaptive()) {  // max_ij |A~_ij| from the row maxima of the scaled matrix
+        hipLaunchKernelGGL((k_scale_stat<true>), dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta,
+                           lp.a_col, lp.a_val, (const double*)w.d_row, (const double*)w.d_col, w.stat_r);
+        const int gmx = grid_for(m);
+        hipLaunchKernelGGL(k_max_part, dim3(gmx), dim3(kBlock), 0, stream, (const double*)w.stat_r, m, w.psetup);
+        hipLaunchKernelGGL(k_max_part, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, (int64_t)gmx,
+                           w.red + 4);
+        MIP_LAUNCH_CHECK();
+    }
+    std::vector<double> hist(S.adaptive() ? 1 : o.power_iters + 1, 0.0);
+    double red[5];
+    if (!S.adaptive()) MIP_HIP(hipMemcpyAsync(hist.data(), w.hist, hist.size() * 8, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipMemcpyAsync(red, w.red, 5 * 8, hipMemcpyDeviceToHost, stream));
     MIP_HIP(hipStreamSynchronize(stream));
     bn2 = red[0];
     cn2 = red[1];
     for (auto& h : hist) h = sqrt(h);
     const double sigma_hat = hist.back();
     double eta;
-    if (sigma_hat <= 0.0) {
+    if (S.adaptive()) {
+        eta = o.step0 > 0.0 ? o.step0 : (red[4] > 0.0 ? 1.0 / red[4] : 1.0);
+    } else if (sigma_hat <= 0.0) {
         eta = o.step_safety;
     } else if (o.pock_chambolle && hist.size() > 10 &&
                fabs(hist.back() - hist[hist.size() - 11]) > 1e-3 * hist.back()) {
@@ -2042,7 +2334,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         MIP_HIP(hipStreamSynchronize(stream));
         // the data, by the norms of b and c and the step size that setup has
         // just recomputed (setup leaves the iterates and the control block)
-        if (cur.b_norm != sqrt(bn2) || cur.c_norm != sqrt(cn2) || cur.eta != eta)
+        if (cur.b_norm != sqrt(bn2) || cur.c_norm != sqrt(cn2) || cur.eta0 != eta)
             return set_error("resume: the workspace holds the state of another LP of these sizes"),
                    MIPDHG_ERR_INVALID_ARG;
         // a solve that stopped at an evaluation (optimal or at its iteration
@@ -2088,6 +2380,10 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     c0.fingerprint = fp;
     c0.have_prev = 0;
     c0.infeas_tol = o.infeas_tol;
+    c0.eta0 = eta;
+    c0.step_rule = o.step_rule;
+    c0.accepted = 1;
+    c0.rejected = 0;
     if (!o.resume) {
         MIP_HIP(hipMemcpyAsync(w.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, o.x_init,
@@ -2098,6 +2394,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         if ((rc = S.launch_anchor_resid(1))) return rc;
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.xprev, n, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.yprev, m, 0.0);
+        if (S.adaptive())  // x = x0: A~ (x - x0) = 0
+            hipLaunchKernelGGL((k_fill_t<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, (T*)w.ax, m, (T)0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.atyprev, n, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, w.axprev, m, 0.0);
         MIP_LAUNCH_CHECK();
@@ -2267,7 +2565,8 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         info->xz = cf.xz;
         info->max_violation = std::max(std::max(cf.rp_inf, cf.rd_inf), cf.xz / (1.0 + fabs(cf.pobj)));
         info->sigma_hat = sigma_hat;
-        info->eta = eta;
+        info->eta = o.step_rule == 1 ? cf.eta : eta;
+        info->rejected = cf.rejected;
         info->omega0 = omega0;
         info->omega = cf.omega;
         info->ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -2306,7 +2605,7 @@ static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp,
     char* const base = reinterpret_cast<char*>(uintptr_t(4096));  // layout only, never dereferenced
     const PlainWs w = carve(base, 0, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                             tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                            o.restart_avg != 0, o.spmv_kind == 3);
+                            o.restart_avg != 0, o.spmv_kind == 3, o.step_rule == 1);
     const size_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
     const size_t m = (size_t)lp.m, n = (size_t)lp.n, G = (size_t)w.gcap;
     auto at = [&](const void* p, size_t bytes) { return std::make_pair((size_t)((const char*)p - base), bytes); };
@@ -2321,6 +2620,7 @@ static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp,
         r.push_back(at(w.x_avg, n * ts));
         r.push_back(at(w.y_avg, m * ts));
     }
+    if (o.step_rule == 1) r.push_back(at(w.ax, m * ts));  // between blocks the iterate is in the first buffers
     return r;
 }
 
@@ -2387,6 +2687,9 @@ extern "C" int mipdhg_solve(const mipdhg_lp* lp, const mipdhg_options* opt, doub
         return set_error("the general form runs on the tile kernels (spmv_kind 0 or 2)"), MIPDHG_ERR_UNSUPPORTED;
     if (opt->restart_avg && opt->spmv_kind != 0)
         return set_error("restart to average runs on the one-workgroup-per-tile kernels (spmv_kind 0)"),
+               MIPDHG_ERR_UNSUPPORTED;
+    if (opt->step_rule == 1 && opt->spmv_kind != 0)
+        return set_error("the adaptive step runs on the one-workgroup-per-tile kernels (spmv_kind 0)"),
                MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {

@@ -500,8 +500,8 @@ static int check_unrolled(const mipdhg_batch* bt, const mipdhg_options* o, int K
     if (o->resume) return set_error("resume is a single-LP solve option"), MIPDHG_ERR_UNSUPPORTED;
     if (is_general(bt->whole))
         return set_error("the general form (bounds, inequality rows) is a single-LP option"), MIPDHG_ERR_UNSUPPORTED;
-    if (o->pw_ki != 0.0 || o->pw_kd != 0.0 || o->restart_avg)
-        return set_error("the PID primal weight and restart to average are single-LP options"),
+    if (o->pw_ki != 0.0 || o->pw_kd != 0.0 || o->restart_avg || o->step_rule)
+        return set_error("the PID primal weight, restart to average and the adaptive step are single-LP options"),
                MIPDHG_ERR_UNSUPPORTED;
     const int B = bt->count;
     if (bt->row_off[0] != 0 || bt->col_off[0] != 0 || bt->nnz_off[0] != 0 || bt->row_off[B] != bt->whole.m ||
