@@ -9,6 +9,8 @@ Contents
   pdhg.py       scaling, step size, PDHG iteration, evaluation, restarts,
                 the differentiable unrolled map and its reverse/tangent modes
   centering.py  the centered warm-start map of Algorithm 1
+  ipm.py        the interior-point consumer of that start (Mehrotra's
+                predictor-corrector on the scaled LP, dense direct solves)
 
 Parity status of each function is stated in its module header.
 """
