@@ -418,8 +418,8 @@ int mipdhg_center_start_noalloc(int32_t n, const double *x, const double *z, con
 int mipdhg_center_reclamp(int32_t n, double alpha_min, void *stream, double *x_io, double *z_io);
 
 /* sizeof of the public structs, for bindings that mirror them:
- * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info, 3 mipdhg_batch;
- * 0 for anything else. */
+ * which = 0 mipdhg_lp, 1 mipdhg_options, 2 mipdhg_info, 3 mipdhg_batch,
+ * 4 mipdhg_ipm_options, 5 mipdhg_ipm_info; 0 for anything else. */
 size_t mipdhg_sizeof(int which);
 
 /* Times every candidate shape of the two iteration SpMVs on this LP (lane
@@ -460,6 +460,68 @@ int mipdhg_autotune(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, voi
 int mipdhg_autotune_cached(const mipdhg_lp *lp, mipdhg_options *opt, int32_t iters, const char *cache_path,
                            void *workspace, size_t workspace_bytes, void *stream, double *x, double *y, double *z,
                            double *r_p, double *r_d, double *best_ms, int32_t *hit);
+
+/* ------------------------------------------------------------------------
+ * Interior-point consumer of the centered start (Section 3.1).  The paper
+ * warm-starts a barrier solver from Algorithm 1's point and counts its
+ * iterations (Section 4.6).  This one is Mehrotra's primal-dual
+ * predictor-corrector on the scaled LP min c~^T x, A~ x = b~, x >= 0
+ * (A~ = D_r A D_c, b~ = D_r b, c~ = D_c c; D_r, D_c as mipdhg_solve returns
+ * them, NULL for ones): normal equations (A~ X Z^-1 A~^T) dy = rhs formed
+ * dense on the device and factored by Cholesky (a pivot that is not positive
+ * is replaced by 1e128 and counted), the predictor and corrector sharing the
+ * factor, steps step_frac of the way to the boundary (at most 1), separate
+ * for x and for (y, z); it stops when the three relative tests of Section 2
+ * hold at tol on the scaled LP.  Standard form, m <= 16384 (the dense matrix);
+ * A's rows must list their columns in increasing order.  Device pointers,
+ * float64; the workspace is 256-byte aligned, of mipdhg_ipm_workspace_size()
+ * bytes or more.  Returns the status (MIPDHG_OPTIMAL, MIPDHG_ITER_LIMIT,
+ * MIPDHG_NUMERICAL) or a negative error. */
+typedef struct mipdhg_ipm_options {
+    double tol;           /* the relative tests of Section 2 on the scaled LP   [1e-8]   */
+    int32_t max_iter;     /* Newton steps                                        [100]    */
+    int32_t max_lifts;    /* warm start: tenfold raises of alpha_min at most     [12]     */
+    double step_frac;     /* fraction of the step to the boundary, in (0, 1)     [0.9995] */
+    double min_step;      /* warm start: a first step min(a_p, a_d) below this
+                             raises alpha_min (Section 3.1: 1e-6)                [1e-6]   */
+    double mu_min, delta_max, alpha_min; /* Algorithm 1's parameters   [1e-6, 1e-4, 1e-6] */
+} mipdhg_ipm_options;
+
+typedef struct mipdhg_ipm_info {
+    int32_t status;       /* as returned                                                 */
+    int32_t iters;        /* Newton steps of the run that was kept                       */
+    int32_t lifts;        /* warm start: tenfold raises of alpha_min                     */
+    int32_t pivots_replaced;
+    double alpha_min;     /* warm start: the value the kept run started from             */
+    double mu_target;     /* warm start: Algorithm 1's mu_target                         */
+    double first_step_p, first_step_d; /* the first iteration's steps                   */
+    double rel_rp, rel_rd, rel_gap;    /* the three relative measures at the end (scaled) */
+    double pobj, dobj;    /* c~^T x~ = c^T x and b~^T y~ = b^T y at the end              */
+    double mu;            /* x^T z / n at the end (scaled)                               */
+    double ms_total;      /* wall time of the call                                       */
+} mipdhg_ipm_info;
+
+void mipdhg_ipm_default_options(mipdhg_ipm_options *opt);
+int mipdhg_ipm_workspace_size(const mipdhg_lp *lp, size_t *bytes);
+
+/* From the scaled-space point (x_start, y_start, z_start), x, z > 0, or from
+ * Mehrotra's heuristic point when all three are NULL (cold start).  Outputs
+ * x, y, z (n, m, n) in the original space: x = D_c x~, y = D_r y~,
+ * z = z~ / D_c. */
+int mipdhg_ipm_solve(const mipdhg_lp *lp, const double *d_row, const double *d_col, const double *x_start,
+                     const double *y_start, const double *z_start, const mipdhg_ipm_options *opt, void *workspace,
+                     size_t workspace_bytes, void *stream, double *x, double *y, double *z, mipdhg_ipm_info *info);
+
+/* The hybrid of Section 3.1 from a PDHG solution (x, y, z) in the original
+ * space (as mipdhg_solve returns it, with its d_row, d_col): Algorithm 1's
+ * centered point (x', y / D_r, z') of the scaled point, then the
+ * interior-point method from it; while the first step of a run is below
+ * min_step, alpha_min grows tenfold (at most max_lifts times), x' and z' are
+ * lifted to it, and the method runs again from the lifted point.  Outputs
+ * and result as for mipdhg_ipm_solve. */
+int mipdhg_ipm_warm(const mipdhg_lp *lp, const double *d_row, const double *d_col, const double *x_pdhg,
+                    const double *y_pdhg, const double *z_pdhg, const mipdhg_ipm_options *opt, void *workspace,
+                    size_t workspace_bytes, void *stream, double *x, double *y, double *z, mipdhg_ipm_info *info);
 
 /* Not an operation of the method: a plain streaming read of `bytes` bytes of
  * device memory at buf (16-byte aligned, a positive multiple of 16), with the

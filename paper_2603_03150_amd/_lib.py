@@ -64,6 +64,21 @@ class InfoStruct(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class IpmOptionsStruct(C.Structure):
+    _fields_ = [("tol", _f64), ("max_iter", _i32), ("max_lifts", _i32), ("step_frac", _f64), ("min_step", _f64),
+                ("mu_min", _f64), ("delta_max", _f64), ("alpha_min", _f64)]
+
+
+class IpmInfoStruct(C.Structure):
+    _fields_ = [("status", _i32), ("iters", _i32), ("lifts", _i32), ("pivots_replaced", _i32),
+                ("alpha_min", _f64), ("mu_target", _f64), ("first_step_p", _f64), ("first_step_d", _f64),
+                ("rel_rp", _f64), ("rel_rd", _f64), ("rel_gap", _f64), ("pobj", _f64), ("dobj", _f64),
+                ("mu", _f64), ("ms_total", _f64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BatchStruct(C.Structure):
     _fields_ = [("count", _i32), ("row_off", _p), ("col_off", _p), ("nnz_off", _p), ("whole", LPStruct)]
 
@@ -90,6 +105,12 @@ SIGNATURES = {
     "mipdhg_center_reclamp": (C.c_int, [_i32, _f64, _p, _p, _p]),
     "mipdhg_center_noalloc_max_n": (_i32, []),
     "mipdhg_read_probe": (C.c_int, [_p, C.c_size_t, _i32, _p, _p]),
+    "mipdhg_ipm_default_options": (None, [C.POINTER(IpmOptionsStruct)]),
+    "mipdhg_ipm_workspace_size": (C.c_int, [C.POINTER(LPStruct), C.POINTER(C.c_size_t)]),
+    "mipdhg_ipm_solve": (C.c_int, [C.POINTER(LPStruct), _p, _p, _p, _p, _p, C.POINTER(IpmOptionsStruct), _p,
+                                   C.c_size_t, _p, _p, _p, _p, C.POINTER(IpmInfoStruct)]),
+    "mipdhg_ipm_warm": (C.c_int, [C.POINTER(LPStruct), _p, _p, _p, _p, _p, C.POINTER(IpmOptionsStruct), _p,
+                                  C.c_size_t, _p, _p, _p, _p, C.POINTER(IpmInfoStruct)]),
     "mipdhg_center_start_noalloc": (C.c_int, [_i32, _p, _p, _p, _f64, _f64, _f64, _p, _p, _p, C.POINTER(_f64)]),
     "mipdhg_autotune": (C.c_int, [C.POINTER(LPStruct), C.POINTER(OptionsStruct), _i32, _p, C.c_size_t, _p,
                                   _p, _p, _p, _p, _p, C.POINTER(_f64)]),

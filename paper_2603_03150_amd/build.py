@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmipdhg.so")
 
 SOURCES = ["capi.cpp", "validate.hip", "plain.hip", "panel.hip", "batched.hip", "unrolled.hip", "center.hip",
-           "autotune.cpp", "probe.hip"]
+           "autotune.cpp", "probe.hip", "ipm.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

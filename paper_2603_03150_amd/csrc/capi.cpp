@@ -70,6 +70,8 @@ extern "C" size_t mipdhg_sizeof(int which) {
         case 1: return sizeof(mipdhg_options);
         case 2: return sizeof(mipdhg_info);
         case 3: return sizeof(mipdhg_batch);
+        case 4: return sizeof(mipdhg_ipm_options);
+        case 5: return sizeof(mipdhg_ipm_info);
         default: return 0;
     }
 }

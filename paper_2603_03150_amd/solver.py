@@ -356,3 +356,58 @@ def read_probe(buf: torch.Tensor, blocks: int = 2048) -> torch.Tensor:
     _lib.check(lib.mipdhg_read_probe(buf.data_ptr(), buf.numel() * buf.element_size(), int(blocks),
                                      torch.cuda.current_stream(buf.device).cuda_stream, out.data_ptr()))
     return out
+
+
+@dataclass
+class IpmSolution:
+    status: int
+    status_name: str
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    info: dict
+
+
+def ipm_options(**kw) -> _lib.IpmOptionsStruct:
+    lib = _lib.load()
+    o = _lib.IpmOptionsStruct()
+    lib.mipdhg_ipm_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown interior-point option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ipm_call(dlp: DeviceLP, fn: str, d_row, d_col, point, **opts) -> IpmSolution:
+    lib = _lib.load()
+    o = ipm_options(**opts)
+    lps = dlp.struct()
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_ipm_workspace_size(C.byref(lps), C.byref(nb)))
+    d = dlp.device
+    f64 = dict(dtype=torch.float64, device=d)
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    x, y, z = torch.empty(dlp.n, **f64), torch.empty(dlp.m, **f64), torch.empty(dlp.n, **f64)
+    keep = [None if v is None else v.to(**f64).contiguous() for v in (d_row, d_col, *point)]
+    ptr = [None if v is None else v.data_ptr() for v in keep]
+    info = _lib.IpmInfoStruct()
+    rc = getattr(lib, fn)(C.byref(lps), *ptr, C.byref(o), ws.data_ptr(), ws.numel(),
+                          torch.cuda.current_stream(d).cuda_stream, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                          C.byref(info))
+    _lib.check(rc)
+    return IpmSolution(rc, lib.mipdhg_status_string(rc).decode(), x, y, z, info.as_dict())
+
+
+def ipm_solve(dlp: DeviceLP, d_row=None, d_col=None, start=None, **opts) -> IpmSolution:
+    """mipdhg_ipm_solve: the interior-point method on the LP scaled by
+    (d_row, d_col) (None: unscaled), from the scaled-space point
+    start = (x, y, z), or from Mehrotra's point when start is None."""
+    return _ipm_call(dlp, "mipdhg_ipm_solve", d_row, d_col, start if start is not None else (None, None, None),
+                     **opts)
+
+
+def ipm_warm(dlp: DeviceLP, sol: "Solution", **opts) -> IpmSolution:
+    """mipdhg_ipm_warm: Algorithm 1 from a PDHG solution of dlp (its x, y, z
+    and scaling), then the interior-point method with the alpha_min loop."""
+    return _ipm_call(dlp, "mipdhg_ipm_warm", sol.d_row, sol.d_col, (sol.x, sol.y, sol.z), **opts)

@@ -44,6 +44,8 @@ def test_struct_layouts_and_defaults():
     assert lib.mipdhg_sizeof(0) == C.sizeof(_lib.LPStruct)
     assert lib.mipdhg_sizeof(1) == C.sizeof(_lib.OptionsStruct)
     assert lib.mipdhg_sizeof(2) == C.sizeof(_lib.InfoStruct)
+    assert lib.mipdhg_sizeof(4) == C.sizeof(_lib.IpmOptionsStruct)
+    assert lib.mipdhg_sizeof(5) == C.sizeof(_lib.IpmInfoStruct)
     d = P.default_options()
     assert d["ruiz_iters"] == 10 and d["eval_every"] == 64 and abs(d["beta_art"] - 0.36) < 1e-15
     assert lib.mipdhg_status_string(0) == b"OPTIMAL"
