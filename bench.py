@@ -22,9 +22,10 @@ Also reported, on the same JSON line:
                     sources match it;
   cpu_baseline      the float64 NumPy/SciPy oracle on the host, single thread,
                     on a bounded sample of the same workload;
-  power_law, tolerance_ratios, differentiation, batched, general: the other
-                    workloads (see their docstrings below), each with its
-                    error against the float64 oracle or the closed-form optimum.
+  power_law, tolerance_ratios, differentiation, batched, general, ipm_hybrid:
+                    the other workloads (see their docstrings below), each
+                    with its error against the float64 oracle or the
+                    closed-form optimum.
 """
 from __future__ import annotations
 
@@ -69,6 +70,7 @@ def parse():
     ap.add_argument("--no-ratios", action="store_true", help="skip the tolerance-ratio leg")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-general", action="store_true", help="skip the general-form LP leg")
+    ap.add_argument("--no-ipm", action="store_true", help="skip the PDHG / interior-point hybrid leg")
     ap.add_argument("--profile", action="store_true",
                     help="only a short capped solve (256 iterations) of --workload (for hardware counters)")
     ap.add_argument("--shape", default="",
@@ -260,6 +262,7 @@ def kernel_roofline(P, dlp, ws, precision: str, iters: int, workload_key: str, s
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec["bytes_per_launch"] if rec else None,
             "kernel": name, "bytes_per_launch": b, "ms_per_launch": ms, "launches_timed": int(ti["n_primal"]),
+            "ms_primal": ti["ms_primal"], "ms_dual": ti["ms_dual"],
             "ms_per_launch_events_each": each["ms_" + dom],
             "traffic_source": f"profiles/traffic_{workload_key}.json" if rec else None,
             "other_kernel": {names[k]: {"bytes": v[0], "ms": v[1], "GBs": v[0] / (v[1] * 1e-3) / 1e9,
@@ -360,10 +363,7 @@ def general_leg(P, torch, eps: float, precision: str) -> dict:
            "rel_obj_err_vs_planted": abs(inf["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star)),
            "rel_rp": inf["rel_rp"], "rel_rd": inf["rel_rd"], "rel_gap": inf["rel_gap"],
            "max_violation": inf["max_violation"], "generate_s": gen_s, "roofline": roof,
-           "standard_kernels_same_matrix": {"ms_primal": sroof["ms_per_launch"] if sroof["kernel"].endswith("primal>")
-                                            else sroof["other_kernel"]["primal"]["ms"],
-                                            "ms_dual": sroof["ms_per_launch"] if sroof["kernel"].endswith("dual>")
-                                            else sroof["other_kernel"]["dual"]["ms"]},
+           "standard_kernels_same_matrix": {"ms_primal": sroof["ms_primal"], "ms_dual": sroof["ms_dual"]},
            "spmv_shape": shape, "autotune_s": tune_s}
     del dlp, std, ws
     torch.cuda.empty_cache()
@@ -590,6 +590,42 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
                         "FP32 iterates, FP64 per-instance tests"}
 
 
+def ipm_leg(P, torch, eps: float = 1e-4) -> dict:
+    """The hybrid of Section 3.1 on synthetic LPs: the GPU PDHG solve to
+    eps_rel (float64), Algorithm 1's centered start and the GPU interior-point
+    method from it (mipdhg_ipm_warm, with the alpha_min loop), against the same
+    interior-point method from Mehrotra's point on the same scaled LP.  Reports
+    the Newton-step counts, their ratio (the quantity of the paper's Section
+    4.6 tables), how many warm runs finish within 10 steps, and the objective
+    error against the planted optimum."""
+    import math
+    import lpgen
+    cases = [(f"cfg1 seed {s} (200 x 500)", lpgen.cfg1(s)) for s in range(4)] + \
+            [(f"power-law 1/100 seed {s} (1,000 x 4,000)", lpgen.cfg2_sub(s, 100)) for s in range(4)] + \
+            [("power-law 1/25 seed 0 (4,000 x 16,000)", lpgen.cfg2_sub(0, 25))]
+    rows = []
+    for name, lp in cases:
+        dlp = P.DeviceLP.from_lp(lp)
+        pd = P.solve(dlp, eps, "fp64")
+        torch.cuda.synchronize()
+        warm = P.ipm_warm(dlp, pd)
+        cold = P.ipm_solve(dlp, pd.d_row, pd.d_col)
+        wi, ci = warm.info, cold.info
+        rows.append({"lp": name, "pdhg_iters": int(pd.info["iters"]), "pdhg_ms": pd.info["ms_total"],
+                     "warm_status": warm.status_name, "warm_iters": wi["iters"], "lifts": wi["lifts"],
+                     "cold_status": cold.status_name, "cold_iters": ci["iters"],
+                     "ratio": wi["iters"] / max(1, ci["iters"]), "warm_ms": wi["ms_total"], "cold_ms": ci["ms_total"],
+                     "rel_obj_err_vs_planted": abs(wi["pobj"] - lp.p_star) / max(1.0, abs(lp.p_star))})
+        del dlp, pd, warm, cold
+        torch.cuda.empty_cache()
+    ok = [r for r in rows if r["warm_status"] == "OPTIMAL" and r["cold_status"] == "OPTIMAL"]
+    return {"pdhg_eps_rel": eps, "ipm_tol": 1e-8, "instances": len(rows), "solved": len(ok),
+            "ratio_geomean": math.exp(sum(math.log(max(r["ratio"], 1e-12)) for r in ok) / max(1, len(ok))),
+            "warm_le_10_rate": sum(1 for r in ok if r["warm_iters"] <= 10) / max(1, len(rows)),
+            "max_rel_obj_err_vs_planted": max((r["rel_obj_err_vs_planted"] for r in ok), default=None),
+            "runs": rows}
+
+
 def _counter_rows(folder: str) -> dict:
     """Per kernel symbol of a rocprofv3 --pmc csv output: {counter: mean per
     dispatch} (rows of one dispatch and counter are added first)."""
@@ -634,7 +670,7 @@ def counter_summary(folder: str, workload: str, precision: str, shape_text: str)
                   "--output-format csv -- python3 bench.py --calibrate-copy",
         "trace": f"rocprofv3 --kernel-trace --stats -d {folder}/profb_{workload} -o run --output-format csv -- "
                  f"python3 bench.py --workload {workload} --precision {precision} --shape {shape_text} --steps 2 "
-                 "--warmup 1 --no-batched --no-ratios --no-diff --no-cpu-baseline --no-other --no-general",
+                 "--warmup 1 --no-batched --no-ratios --no-diff --no-cpu-baseline --no-other --no-general --no-ipm",
     }
     fetch = _counter_rows(f"{folder}/pmc_{workload}_FETCH_SIZE")
     write = _counter_rows(f"{folder}/pmc_{workload}_WRITE_SIZE")
@@ -848,6 +884,9 @@ def main() -> int:
     if not args.no_general:
         print("# general-form leg", file=sys.stderr, flush=True)
         out["general"] = general_leg(P, torch, args.eps, args.precision)
+    if not args.no_ipm:
+        print("# hybrid leg (PDHG, centered start, interior point)", file=sys.stderr, flush=True)
+        out["ipm_hybrid"] = ipm_leg(P, torch)
     if not args.no_batched:
         print("# batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(P, torch, args.batch_count, args.plain_sample, args.eps)
