@@ -2233,10 +2233,24 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
                            lp.at_rowptr, lp.at_col, lp.at_val, (const double*)w.d_col, (const double*)w.d_row, lp.n,
                            (V*)w.at_vs);
     }
-    if (S.panel()) {  // A's panel layout for the dual step (same scaled values as the copies)
-        rc = panel_build<V>(rpa, lp.m, lp.n, nnz, lp.a_rowptr, lp.a_col, lp.a_val, (const double*)w.d_row,
-                            (const double*)w.d_col, S.panel_w(), sizeof(T), w.pl, stream);
-        if (rc) return rc;
+    // A's panel layout for the dual step (same scaled values as the copies) is
+    // built on a second stream, so that its host-side steps overlap the power
+    // iteration; the first stream waits for it before the loop
+    struct SideStream {
+        hipStream_t s = nullptr;
+        hipEvent_t scaled = nullptr, built = nullptr;
+        ~SideStream() {
+            if (scaled) (void)hipEventDestroy(scaled);
+            if (built) (void)hipEventDestroy(built);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } side;
+    if (S.panel()) {
+        MIP_HIP(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        MIP_HIP(hipEventCreateWithFlags(&side.scaled, hipEventDisableTiming));
+        MIP_HIP(hipEventCreateWithFlags(&side.built, hipEventDisableTiming));
+        MIP_HIP(hipEventRecord(side.scaled, stream));
+        MIP_HIP(hipStreamWaitEvent(side.s, side.scaled, 0));
     }
     {
         const int gm = grid_for(m, 1024), gn = grid_for(n, 1024);
@@ -2293,6 +2307,17 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
             MIP_LAUNCH_CHECK();
         }
         MIP_LAUNCH_CHECK();
+    }
+    if (S.panel()) {
+        rc = panel_build<V>(rpa, lp.m, lp.n, nnz, lp.a_rowptr, lp.a_col, lp.a_val, (const double*)w.d_row,
+                            (const double*)w.d_col, S.panel_w(), sizeof(T), w.pl, side.s);
+        if (rc) {
+            (void)hipStreamSynchronize(side.s);
+            (void)hipStreamSynchronize(stream);
+            return rc;
+        }
+        MIP_HIP(hipEventRecord(side.built, side.s));
+        MIP_HIP(hipStreamWaitEvent(stream, side.built, 0));
     }
     if (S.adaptive()) {  // max_ij |A~_ij| from the row maxima of the scaled matrix
         hipLaunchKernelGGL((k_scale_stat<true>), dim3(gta), dim3(kBlock), tile_lds_bytes(S.ta, 8), stream, S.ta,
