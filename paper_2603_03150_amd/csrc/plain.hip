@@ -253,27 +253,31 @@ __global__ __launch_bounds__(kBlock) void k_scale_vec(const double* v, const dou
 // iteration actually applies, with one gather per nonzero (scaling the
 // float64 original on the fly would gather the column factor as well).
 // Products and sums in float64.
-template <typename V, bool SORTED>
+// The power iteration's SpMV on the scaled copy: vectors of type X (the
+// iterate type: float64, or float32 in the FP32 modes, whose scaled matrix is
+// itself rounded to float32 or BF16), products and row sums in float64.
+template <typename V, bool SORTED, typename X, int U>
 __global__ __launch_bounds__(kBlock) void k_spmv_copy(TilePlan p, const int32_t* col, const V* vals,
-                                                      const double* x, double* y, double* partials) {
+                                                      const X* x, X* y, double* partials) {
     extern __shared__ __align__(16) unsigned char smem_t[];
     const auto L = tile_lds<double>(smem_t, p);
     double s[1] = {0.0};
     double mx[1] = {0.0};
     auto prod = [&](int b, int j) {
-        return (double)ld_val_at(vals + b, j) * x[ld_at_nt(col + b, j)];
+        return (double)ld_val_at(vals + b, j) * (double)x[ld_at_nt(col + b, j)];
     };
     auto epi = [&](int r, double a) {
-        y[r] = a;
+        y[r] = (X)a;
         s[0] += a * a;
     };
     auto le = lepi(epi);
-    tiled_rows<false, double, 8, SORTED>(p, own_tile(), L, prod, le);
+    tiled_rows<false, double, U, SORTED>(p, own_tile(), L, prod, le);
     block_reduce_store<1, 0>(s, mx, partials + blockIdx.x);
 }
 
 // v = u / sqrt(sum of G partials), identical sum order in every workgroup
-__global__ __launch_bounds__(kBlock) void k_normalize(const double* u, double* v, int64_t n,
+template <typename X>
+__global__ __launch_bounds__(kBlock) void k_normalize(const X* u, X* v, int64_t n,
                                                       const double* partials, int G) {
     __shared__ double sh[kBlock];
     double s = 0.0;
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_normalize(const double* u, double* v
     const double nrm = sqrt(sh[0]);
     if (nrm == 0.0) return;  // u = 0: keep v
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        v[i] = u[i] / nrm;
+        v[i] = (X)((double)u[i] / nrm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1699,7 +1703,8 @@ struct Solver {
                                 (const void*)k_eval<true, true>, (const void*)k_eval<false, true>,
                                 (const void*)k_scale_stat<true>, (const void*)k_scale_stat<false>,
                                 (const void*)k_anchor_resid<T>,
-                                (const void*)k_spmv_copy<V, true>, (const void*)k_spmv_copy<V, false>};
+                                (const void*)k_spmv_copy<V, true, T, 8>, (const void*)k_spmv_copy<V, false, T, 8>,
+                                (const void*)k_spmv_copy<V, true, T, 16>, (const void*)k_spmv_copy<V, false, T, 16>};
 #undef MIP_ITER_KERNELS
 #undef MIP_AVG_KERNELS
 #undef MIP_ADAPT_KERNELS
@@ -2275,7 +2280,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     // adaptive step, which starts from the largest scaled entry instead)
     if (!S.adaptive()) {
         const double v0 = 1.0 / sqrt((double)n);
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, w.pv, n, v0);
+        hipLaunchKernelGGL((k_fill_t<T>), dim3(grid_for(n)), dim3(kBlock), 0, stream, (T*)w.pv, n, (T)v0);
         // on the scaled iteration copies (tile plans with their layout)
         TilePlan pa = S.ta, pat = S.tat;
         const bool srt = S.sorted();
@@ -2285,25 +2290,29 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
         }
         const int32_t* ca = srt ? w.col_a : lp.a_col;
         const int32_t* cat = srt ? w.col_at : lp.at_col;
-        auto spmv = [&](const TilePlan& tp, const int32_t* col, const void* vals, const double* x, double* y,
+        // vectors in the iterate type T (the buffers hold float64 room)
+        auto spmv = [&](const TilePlan& tp, const int32_t* col, const void* vals, const void* xv, void* yv,
                         double* part) {
-            if (srt)
-                hipLaunchKernelGGL((k_spmv_copy<V, true>), dim3(tp.ntiles), dim3(kBlock), tile_lds_bytes(tp, 8), stream,
-                                   tp, col, (const V*)vals, x, y, part);
-            else
-                hipLaunchKernelGGL((k_spmv_copy<V, false>), dim3(tp.ntiles), dim3(kBlock), tile_lds_bytes(tp, 8),
-                                   stream, tp, col, (const V*)vals, x, y, part);
+            const T* x = (const T*)xv;
+            T* y = (T*)yv;
+            const bool big = tp.tile_nnz > 8 * kBlock;
+            const dim3 g(tp.ntiles), b(kBlock);
+            const size_t lds = tile_lds_bytes(tp, 8);
+            if (srt && big) hipLaunchKernelGGL((k_spmv_copy<V, true, T, 16>), g, b, lds, stream, tp, col, (const V*)vals, x, y, part);
+            else if (srt) hipLaunchKernelGGL((k_spmv_copy<V, true, T, 8>), g, b, lds, stream, tp, col, (const V*)vals, x, y, part);
+            else if (big) hipLaunchKernelGGL((k_spmv_copy<V, false, T, 16>), g, b, lds, stream, tp, col, (const V*)vals, x, y, part);
+            else hipLaunchKernelGGL((k_spmv_copy<V, false, T, 8>), g, b, lds, stream, tp, col, (const V*)vals, x, y, part);
         };
         for (int k = 0; k <= o.power_iters; ++k) {
             // av = A~ v, hist[k] = ||av||^2
-            spmv(pa, ca, w.a_vs, (const double*)w.pv, w.pav, w.psetup);
+            spmv(pa, ca, w.a_vs, w.pv, w.pav, w.psetup);
             hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(kBlock), 0, stream, (const double*)w.psetup, gta, 1,
                                w.hist + k);
             if (k == o.power_iters) break;
             // u = A~^T av, v = u / ||u||
-            spmv(pat, cat, w.at_vs, (const double*)w.pav, w.pu, w.psetup + G);
-            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n, 1024)), dim3(kBlock), 0, stream, (const double*)w.pu,
-                               w.pv, n, (const double*)(w.psetup + G), gtat);
+            spmv(pat, cat, w.at_vs, w.pav, w.pu, w.psetup + G);
+            hipLaunchKernelGGL((k_normalize<T>), dim3(grid_for(n, 1024)), dim3(kBlock), 0, stream, (const T*)w.pu,
+                               (T*)w.pv, n, (const double*)(w.psetup + G), gtat);
             MIP_LAUNCH_CHECK();
         }
         MIP_LAUNCH_CHECK();
