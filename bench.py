@@ -162,20 +162,23 @@ def kernel_names(shape: dict) -> dict:
     """Names of the kernels of one primal and one dual step for an SpMV
     shape; the panel layout's dual step is two kernels."""
     kind = int(shape.get("spmv_kind", 0))
-    base = {0: "k_iter_tiled", 1: "k_iter", 2: "k_iter_persist", 3: "k_iter_tiled"}[kind]
-    return {"primal": f"{base}<primal>", "dual": PANEL_DUAL if kind == 3 else f"{base}<dual>"}
+    base = {0: "k_iter_tiled", 1: "k_iter", 2: "k_iter_persist", 3: "k_iter_tiled", 4: "k_rowpanel_primal"}[kind]
+    return {"primal": f"{base}<primal>", "dual": PANEL_DUAL if kind >= 3 else f"{base}<dual>"}
 
 
 def short_kernel(symbol: str):
     """The name kernel_names() uses for a kernel symbol of a profile (the
     panel kernels under their own names), or None for other kernels."""
     import re
-    m = re.search(r"mip::(k_iter_tiled|k_iter_persist|k_iter|k_panel_spmv|k_panel_rows)<([^()]*)>", symbol)
+    m = re.search(r"mip::(k_iter_tiled|k_iter_persist|k_iter|k_panel_spmv|k_panel_rows|k_rowpanel_primal)<([^()]*)>",
+                  symbol)
     if not m:
         return None
     name, targs = m.group(1), [t.strip() for t in m.group(2).split(",")]
     if name.startswith("k_panel"):
         return name
+    if name == "k_rowpanel_primal":
+        return "k_rowpanel_primal<primal>"
     primal = targs[4 if name == "k_iter" else 3] == "true"
     return f"{name}<{'primal' if primal else 'dual'}>"
 
@@ -202,7 +205,9 @@ def traffic_record(workload_key: str, kernel: str, shape: dict):
     with open(path) as fh:
         rec = json.load(fh)
     # the kernel's own side of the shape: A's tiles (or panels) for the dual, A^T's tiles for the primal
-    if kernel.endswith("<primal>"):
+    if kernel.startswith("k_rowpanel_primal"):
+        side = ("spmv_kind", "panel_width")
+    elif kernel.endswith("<primal>"):
         side = ("spmv_kind", "tile_nnz_at", "tile_rows_at", "short_row_at")
     elif kernel == PANEL_DUAL:
         side = ("spmv_kind", "panel_width")

@@ -141,8 +141,17 @@ typedef struct mipdhg_options {
                                groups of narrow column span, each panel of the
                                gathered vector staged in LDS, row sums per
                                panel added in panel order), the primal step on
-                               A^T's LDS tiles as with 0; UNSUPPORTED when A
-                               does not fit the layout's limits            [0] */
+                               A^T's LDS tiles as with 0; 4 = the dual step as
+                               with 3 and the primal step on a row-panel
+                               layout of A^T (groups of rows whose columns,
+                               apart from a short common tail such as a
+                               block-angular LP's linking rows, fit one
+                               panel of LDS; every row summed whole and its
+                               epilogue run where its sum ends; its layout
+                               takes longer to build than 3's, so it pays on
+                               long solves and the autotuner does not try
+                               it); UNSUPPORTED when the matrix does not fit
+                               the layouts                                 [0] */
     int32_t tile_nnz;       /* LDS tiles: nonzeros per tile, 256..8192 (0 = 2048) */
     int32_t tile_rows;      /* LDS tiles: rows per tile, 1..512 (0 = 512)           */
     int32_t short_row;      /* LDS tile row sums: 0 or -1 = every thread reduces an equal chunk of

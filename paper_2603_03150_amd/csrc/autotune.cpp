@@ -40,6 +40,8 @@ std::vector<Cand> candidates() {
     // the dual on A's panel layout, which has no tile shape; its primal step
     // is kind 0's, so kind 0's fastest primal shape goes with it
     c.push_back({3, kDefNnz, kDefRows, kDefShort, kDefNnz, kDefRows, kDefShort});
+    // (kind 4, both steps on panel layouts, is not a candidate: its layout
+    // costs more setup than its primal saves on a solve of ordinary length)
     return c;
 }
 
@@ -89,7 +91,7 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
         double ms = 1e300;
         Cand c{0, 0, 0, 0, 0, 0, 0};
     };
-    constexpr int kKinds = 4;
+    constexpr int kKinds = 5;
     Best dual[kKinds], primal[kKinds], dual_def[kKinds], primal_def[kKinds];
     bool first = true;
     const bool general = lp->lo || lp->hi || lp->sense;  // runs on the tile kernels only
@@ -148,15 +150,16 @@ extern "C" int mipdhg_autotune(const mipdhg_lp* lp, mipdhg_options* opt, int32_t
     }
     if (kind < 0) return mip::set_error("no candidate shape could be timed"), MIPDHG_ERR_UNSUPPORTED;
     opt->spmv_kind = kind;
-    // kind 3 still runs the power iteration and the evaluations on A's tiles:
-    // the shape of kind 0's fastest dual
-    const Cand& ac = (kind == 3 && dual[0].ms < 1e300) ? dual[0].c : dual[kind].c;
+    // kinds 3 and 4 still run the power iteration and the evaluations on the
+    // tiles: the shapes of kind 0's fastest dual (A) and, for kind 4, primal (A^T)
+    const Cand& ac = ((kind == 3 || kind == 4) && dual[0].ms < 1e300) ? dual[0].c : dual[kind].c;
+    const Cand& pc = (kind == 4 && primal[0].ms < 1e300) ? primal[0].c : primal[kind].c;
     opt->tile_nnz = ac.tile_nnz;
     opt->tile_rows = ac.tile_rows;
     opt->short_row = ac.short_row;
-    opt->tile_nnz_at = primal[kind].c.tile_nnz_at;
-    opt->tile_rows_at = primal[kind].c.tile_rows_at;
-    opt->short_row_at = primal[kind].c.short_row_at;
+    opt->tile_nnz_at = pc.tile_nnz_at;
+    opt->tile_rows_at = pc.tile_rows_at;
+    opt->short_row_at = pc.short_row_at;
     if (best_ms) *best_ms = best;
     return 0;
 }

@@ -139,10 +139,10 @@ __device__ __forceinline__ T group_max_rt(T v, int L) {
 // Block-wide reduction of NS sums and NM maxima, in a fixed order, written to
 // out[q] for q in [0, NS+NM) whose bit is set in `mask`.  Every thread of the
 // block must call it.
-template <int NS, int NM>
+template <int NS, int NM, int BS = kBlock>
 __device__ __forceinline__ void block_reduce_store(double (&s)[NS], double (&mx)[NM > 0 ? NM : 1],
                                                    double* out, unsigned mask = ~0u) {
-    __shared__ double sh[(NS + NM) > 0 ? (NS + NM) : 1][kBlock / kWave];
+    __shared__ double sh[(NS + NM) > 0 ? (NS + NM) : 1][BS / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
 #pragma unroll
@@ -161,7 +161,7 @@ __device__ __forceinline__ void block_reduce_store(double (&s)[NS], double (&mx)
     if (threadIdx.x < NS + NM) {
         const int q = threadIdx.x;
         double v = sh[q][0];
-        for (int w = 1; w < kBlock / kWave; ++w) v = (q < NS) ? v + sh[q][w] : fmax(v, sh[q][w]);
+        for (int w = 1; w < BS / kWave; ++w) v = (q < NS) ? v + sh[q][w] : fmax(v, sh[q][w]);
         if (mask & (1u << q)) out[q] = v;
     }
 }

@@ -45,7 +45,7 @@ struct PanelChunk {
     int32_t start;      // first element (a multiple of 8)
     int32_t count;      // nonzeros (the chunk is padded to a multiple of 8)
     int32_t row0;       // first row (global)
-    int32_t unit;
+    int32_t unit;       // the unit (panel layout); the row count (row-panel layout)
 };
 
 // Device arrays of the layout (inside the solver's workspace) and sizes.
@@ -82,5 +82,64 @@ template <typename V>
 int panel_build(const std::vector<int32_t>& rp, int32_t nrows, int32_t ncols, int64_t nnz, const int32_t* rowptr,
                 const int32_t* col, const double* val, const double* d_self, const double* d_other, int width,
                 size_t partial_elem_bytes, PanelLayout& L, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Row-panel layout of A^T for the primal step: every row of A^T is summed
+// whole inside one workgroup, so no partial sums are written.  The rows are
+// cut into groups of consecutive rows whose columns, apart from a common tail
+// [t0, ncols) (the rows of A that span the whole matrix, e.g. the linking rows
+// of a block-angular LP), fall in a window [lo, lo + ml); a workgroup stages
+// that window and the tail (together at most one panel) in LDS and the row's
+// elements carry their column's place in it.  A group's rows are split into
+// units (one workgroup each) of about the same number of nonzeros, units into
+// chunks as in the panel layout; a row without nonzeros gets one element of
+// value 0 so that its epilogue runs.
+constexpr int kRowPanelMaxUnits = 2048;
+constexpr int kRowPanelChunkRows = 128;  // rows of a chunk at most (their sums wait in LDS)
+
+struct RowPanelGroup {
+    int32_t lo, ml;     // staged window [lo, lo + ml), ml a multiple of 8; the tail follows at ml
+};
+
+struct RowPanelUnit {
+    int32_t group;
+    int32_t c0, c1;     // chunks [c0, c1)
+};
+
+struct RowPanelLayout {
+    RowPanelGroup* groups;
+    RowPanelUnit* units;
+    PanelChunk* chunks;
+    void* val;            // [elems] scaled values, type V
+    uint16_t* col;        // [elems] place in the staged window and tail
+    uint16_t* rid;        // [elems] row inside the chunk
+    int32_t* row_group;   // [nrows] (build)
+    int32_t* row_off;     // [nrows] first element of the row (build)
+    uint16_t* row_rid;    // [nrows] (build)
+    int32_t* span;        // [2 max(nrows, ncols)] (build)
+    int32_t t0, tail;     // tail [t0, t0 + tail) of the gathered vector
+    int32_t ngroups, nunits, nchunks;
+    int64_t nelem;
+};
+
+inline int64_t rowpanel_chunk_cap(int64_t nrows, int64_t nnz) {
+    return 2 * (nnz + nrows) / kPanelChunk + nrows / kRowPanelChunkRows + 2 * (int64_t)kRowPanelMaxUnits + 16;
+}
+inline int64_t rowpanel_elem_cap(int64_t nrows, int64_t nnz) {
+    return nnz + nrows + 8 * rowpanel_chunk_cap(nrows, nnz) + kPanelChunk;
+}
+
+// Builds the row-panel layout of the matrix whose rows are rp/rowptr/col/val
+// (A^T: nrows = n, ncols = m), from the host row pointers of both the matrix
+// and its transpose (rp_t, the rows of A, used to find the tail): values
+// d_self[r] * val * d_other[col] rounded to V, exactly as the tile copies.
+// Returns 0, MIPDHG_ERR_UNSUPPORTED when the matrix does not have this
+// structure (a row's window wider than the panel, a wide row of A outside a
+// short final run, a row longer than a chunk), or a HIP error.
+template <typename V>
+int rowpanel_build(const std::vector<int32_t>& rp, int32_t nrows, int32_t ncols, int64_t nnz, const int32_t* rowptr,
+                   const int32_t* col, const double* val, const int32_t* rowptr_t, const int32_t* col_t,
+                   const double* d_self, const double* d_other, int width, int cus, RowPanelLayout& L,
+                   hipStream_t stream);
 
 }  // namespace mip

@@ -330,4 +330,222 @@ template int panel_build<uint16_t>(const std::vector<int32_t>&, int32_t, int32_t
                                    const int32_t*, const double*, const double*, const double*, int, size_t,
                                    PanelLayout&, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// row-panel layout (panel.h)
+// ---------------------------------------------------------------------------
+namespace {
+
+// smallest and largest column below t0 of every row (none: lo > hi)
+__global__ void k_row_span_below(const int32_t* rowptr, const int32_t* col, int32_t nrows, int32_t t0,
+                                 int32_t* span) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0x7fffffff, hi = -1;
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+            const int32_t c = col[k];
+            if (c >= t0) continue;
+            lo = c < lo ? c : lo;
+            hi = c > hi ? c : hi;
+        }
+        span[2 * r] = lo;
+        span[2 * r + 1] = hi;
+    }
+}
+
+// every row's elements at their places: scaled value, place in the staged
+// window or tail, row inside the chunk; an empty row's one element is 0
+template <typename V>
+__global__ void k_rowpanel_scatter(const int32_t* rowptr, const int32_t* col, const double* val, const double* d_self,
+                                   const double* d_other, int32_t nrows, const int32_t* row_group,
+                                   const RowPanelGroup* groups, int32_t t0, const int32_t* row_off,
+                                   const uint16_t* row_rid, V* out, uint16_t* colv, uint16_t* rid) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
+        const RowPanelGroup g = groups[row_group[r]];
+        const int64_t b = row_off[r];
+        const uint16_t rr = row_rid[r];
+        const int k0 = rowptr[r], k1 = rowptr[r + 1];
+        if (k0 == k1) {
+            out[b] = (V)0;
+            colv[b] = 0;
+            rid[b] = rr;
+            continue;
+        }
+        const double ds = d_self[r];
+        for (int k = k0; k < k1; ++k) {
+            const int32_t cc = col[k];
+            const double v = ds * val[k] * d_other[cc];  // the tile copies' expression
+            const int64_t pos = b + (k - k0);
+            if constexpr (sizeof(V) == 2) {
+                out[pos] = f32_to_bf16_rne((float)v);
+            } else {
+                out[pos] = (V)v;
+            }
+            colv[pos] = (uint16_t)(cc < t0 ? cc - g.lo : g.ml + (cc - t0));
+            rid[pos] = rr;
+        }
+    }
+}
+
+}  // namespace
+
+template <typename V>
+int rowpanel_build(const std::vector<int32_t>& rp, int32_t nrows, int32_t ncols, int64_t nnz, const int32_t* rowptr,
+                   const int32_t* col, const double* val, const int32_t* rowptr_t, const int32_t* col_t,
+                   const double* d_self, const double* d_other, int width, int cus, RowPanelLayout& L,
+                   hipStream_t stream) {
+    // --- the tail: the rows of the transpose that span more than half of its
+    // columns and more than half a panel (the rows that couple everything,
+    // such as linking rows) must be a final run of at most a quarter panel
+    hipLaunchKernelGGL(k_row_span, dim3(grid_for(ncols)), dim3(kBlock), 0, stream, rowptr_t, col_t, ncols, L.span);
+    MIP_LAUNCH_CHECK();
+    std::vector<int32_t> span(2 * (size_t)std::max(nrows, ncols));
+    MIP_HIP(hipMemcpyAsync(span.data(), L.span, 2 * (size_t)ncols * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    int32_t t0 = ncols;
+    for (int32_t i = 0; i < ncols; ++i)
+        if (span[2 * i + 1] >= span[2 * i] &&
+            (int64_t)span[2 * i + 1] - span[2 * i] + 1 > std::max<int64_t>(width / 2, nrows / 2)) {
+            t0 = i;
+            break;
+        }
+    if (ncols - t0 > width / 4)
+        return set_error("row-panel layout: %d wide rows from row %d of A, more than a quarter panel (%d)", ncols - t0,
+                         t0, width / 4),
+               MIPDHG_ERR_UNSUPPORTED;
+    t0 &= ~7;
+    const int32_t tail = ncols - t0;
+    const int32_t ml_max = (width - tail) & ~7;
+    // --- every row's window below the tail
+    hipLaunchKernelGGL(k_row_span_below, dim3(grid_for(nrows)), dim3(kBlock), 0, stream, rowptr, col, nrows, t0,
+                       L.span);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipMemcpyAsync(span.data(), L.span, 2 * (size_t)nrows * 4, hipMemcpyDeviceToHost, stream));
+    MIP_HIP(hipStreamSynchronize(stream));
+    // --- groups of consecutive rows whose windows fit together
+    std::vector<RowPanelGroup> groups;
+    std::vector<int32_t> row_group(nrows), group_r0;
+    int64_t glo = 0, ghi = -1;  // the open group's window (ghi < glo: none yet)
+    auto flush = [&]() {
+        RowPanelGroup g;
+        if (ghi >= glo) {
+            g.lo = (int32_t)(glo & ~7);
+            g.ml = (int32_t)(((ghi - g.lo + 1) + 7) & ~7);
+        } else {
+            g.lo = 0;
+            g.ml = 0;
+        }
+        groups.push_back(g);
+    };
+    for (int32_t r = 0; r < nrows; ++r) {
+        const int32_t lo = span[2 * r], hi = span[2 * r + 1];
+        if (r == 0) group_r0.push_back(0);
+        if (hi >= lo) {
+            if ((int64_t)hi - (lo & ~7) + 1 > ml_max)
+                return set_error("row-panel layout: row %d spans %d columns below the tail, more than %d", r,
+                                 hi - lo + 1, ml_max),
+                       MIPDHG_ERR_UNSUPPORTED;
+            const int64_t nlo = ghi >= glo ? std::min<int64_t>(glo, lo) : lo;
+            const int64_t nhi = ghi >= glo ? std::max<int64_t>(ghi, hi) : hi;
+            if (nhi - (nlo & ~7) + 1 > ml_max) {
+                flush();
+                group_r0.push_back(r);
+                glo = lo;
+                ghi = hi;
+            } else {
+                glo = nlo;
+                ghi = nhi;
+            }
+        }
+        row_group[r] = (int32_t)groups.size();
+    }
+    flush();
+    group_r0.push_back(nrows);
+    // --- units of about the same number of elements (an empty row counts one)
+    int64_t total = 0;
+    for (int32_t r = 0; r < nrows; ++r) total += std::max(1, rp[r + 1] - rp[r]);
+    const int64_t target = std::max<int64_t>(4096, (total + 2 * (int64_t)cus - 1) / (2 * (int64_t)cus));
+    std::vector<RowPanelUnit> units;
+    std::vector<PanelChunk> chunks;
+    std::vector<int32_t> row_off(nrows);
+    std::vector<uint16_t> row_rid(nrows);
+    int64_t e = 0;
+    for (size_t gi = 0; gi + 1 < group_r0.size(); ++gi) {
+        const int32_t r0 = group_r0[gi], r1 = group_r0[gi + 1];
+        int32_t r = r0;
+        while (r < r1) {  // one unit
+            RowPanelUnit u;
+            u.group = (int32_t)gi;
+            u.c0 = (int32_t)chunks.size();
+            int64_t acc = 0;
+            int cnt = 0, row0 = -1;
+            int64_t cstart = e;
+            int nrow = 0;
+            auto close = [&]() {
+                if (cnt == 0) return;
+                // a row-panel chunk's last field holds its row count
+                chunks.push_back(PanelChunk{(int32_t)cstart, cnt, row0, nrow});
+                nrow = 0;
+                e = cstart + ((cnt + 7) & ~7);
+                cnt = 0;
+                row0 = -1;
+            };
+            while (r < r1 && (acc < target || r == r0)) {
+                const int len = std::max(1, rp[r + 1] - rp[r]);
+                if (len > kPanelChunk)
+                    return set_error("row-panel layout: row %d has %d nonzeros, more than a chunk (%d)", r, len,
+                                     kPanelChunk),
+                           MIPDHG_ERR_UNSUPPORTED;
+                if (cnt + len > kPanelChunk || (row0 >= 0 && r - row0 >= kRowPanelChunkRows)) close();
+                if (row0 < 0) {
+                    row0 = r;
+                    cstart = e;
+                }
+                row_off[r] = (int32_t)(cstart + cnt);
+                row_rid[r] = (uint16_t)(r - row0);
+                ++nrow;
+                cnt += len;
+                acc += len;
+                ++r;
+                if (acc >= target) break;
+            }
+            close();
+            u.c1 = (int32_t)chunks.size();
+            units.push_back(u);
+        }
+    }
+    if ((int64_t)units.size() > kRowPanelMaxUnits || (int64_t)chunks.size() > rowpanel_chunk_cap(nrows, nnz) ||
+        e > rowpanel_elem_cap(nrows, nnz) || e >= INT32_MAX)
+        return set_error("row-panel layout: %zu units, %zu chunks or %lld elements exceed the workspace's capacity",
+                         units.size(), chunks.size(), (long long)e),
+               MIPDHG_ERR_UNSUPPORTED;
+    L.t0 = t0;
+    L.tail = tail;
+    L.ngroups = (int32_t)groups.size();
+    L.nunits = (int32_t)units.size();
+    L.nchunks = (int32_t)chunks.size();
+    L.nelem = e;
+    MIP_HIP(hipMemcpyAsync(L.groups, groups.data(), groups.size() * sizeof(RowPanelGroup), hipMemcpyHostToDevice,
+                           stream));
+    MIP_HIP(hipMemcpyAsync(L.units, units.data(), units.size() * sizeof(RowPanelUnit), hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(L.chunks, chunks.data(), chunks.size() * sizeof(PanelChunk), hipMemcpyHostToDevice,
+                           stream));
+    MIP_HIP(hipMemcpyAsync(L.row_group, row_group.data(), (size_t)nrows * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(L.row_off, row_off.data(), (size_t)nrows * 4, hipMemcpyHostToDevice, stream));
+    MIP_HIP(hipMemcpyAsync(L.row_rid, row_rid.data(), (size_t)nrows * 2, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL((k_rowpanel_scatter<V>), dim3(grid_for(nrows)), dim3(kBlock), 0, stream, rowptr, col, val,
+                       d_self, d_other, nrows, (const int32_t*)L.row_group, (const RowPanelGroup*)L.groups, t0,
+                       (const int32_t*)L.row_off, (const uint16_t*)L.row_rid, (V*)L.val, L.col, L.rid);
+    MIP_LAUNCH_CHECK();
+    MIP_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
+    return 0;
+}
+
+#define MIP_ROWPANEL_INST(V)                                                                                       \
+    template int rowpanel_build<V>(const std::vector<int32_t>&, int32_t, int32_t, int64_t, const int32_t*,         \
+                                   const int32_t*, const double*, const int32_t*, const int32_t*, const double*,  \
+                                   const double*, int, int, RowPanelLayout&, hipStream_t);
+MIP_ROWPANEL_INST(double)
+MIP_ROWPANEL_INST(float)
+MIP_ROWPANEL_INST(uint16_t)
+#undef MIP_ROWPANEL_INST
+
 }  // namespace mip

@@ -627,69 +627,73 @@ __device__ __forceinline__ int u16_at(const pu4& w, int j) {
     return (int)((j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xffffu));
 }
 
-// One workgroup per unit: the panel's slice of the gathered vector is staged
-// in LDS (every load of a thread issued before its LDS writes), then every
-// wave takes chunks of up to 512 nonzeros, 8 per lane (vector loads, the next
-// chunk's issued before the current one is summed), and sums each row's
-// products in float64 in the row order of the matrix: a lane adds its own run
-// of elements, a segmented scan over the lanes adds the runs of rows that
-// cross lanes, and the lane holding a row's last element writes the row's sum
-// to its partial.
-template <typename T, typename V>
-__global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
-    if (a.ctrl->status != ST_RUNNING) return;
-    __shared__ T xs[panel_width<T>()];
-    const int W = a.width;
-    const PanelUnit un = a.units[blockIdx.x];
-    const PanelGroup g = a.groups[un.group];
-    const int64_t c0 = (int64_t)g.lo + (int64_t)un.panel * W;  // a multiple of 8
-    {
-        constexpr int kVec = 16 / (int)sizeof(T);
-        typedef T VT __attribute__((ext_vector_type(kVec)));
-        constexpr int kPer = panel_width<T>() / (kPanelBlock * kVec);
-        VT buf[kPer];
+// Stages gather[c0 .. c0 + len) into xs[x0 ..) (zero past ncols): every
+// 16-byte load of a thread issued before its LDS writes.  c0 and x0 are
+// multiples of 8 elements.
+template <typename T>
+__device__ __forceinline__ void panel_stage(T* xs, int x0, const T* gather, int64_t c0, int len, int64_t ncols) {
+    constexpr int kVec = 16 / (int)sizeof(T);
+    typedef T VT __attribute__((ext_vector_type(kVec)));
+    constexpr int kPer = panel_width<T>() / (kPanelBlock * kVec);
+    VT buf[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
-            if (i < W) {
-                const int64_t c = c0 + i;
-                if (c + kVec <= a.ncols) {
-                    buf[k] = *(const VT*)(a.gather + c);
-                } else {
+    for (int k = 0; k < kPer; ++k) {
+        const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
+        if (i < len) {
+            const int64_t c = c0 + i;
+            if (c + kVec <= ncols) {
+                buf[k] = *(const VT*)(gather + c);
+            } else {
 #pragma unroll
-                    for (int e = 0; e < kVec; ++e) buf[k][e] = c + e < a.ncols ? a.gather[c + e] : (T)0;
-                }
+                for (int e = 0; e < kVec; ++e) buf[k][e] = c + e < ncols ? gather[c + e] : (T)0;
             }
         }
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
-            if (i < W) *(VT*)&xs[i] = buf[k];
-        }
     }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = (k * kPanelBlock + (int)threadIdx.x) * kVec;
+        if (i < len) *(VT*)&xs[x0 + i] = buf[k];
+    }
+}
+
+// The waves of the workgroup take chunks c0 + wave, c0 + wave + 16, ... of
+// up to 512 nonzeros, 8 per lane (vector loads, the next chunk's issued
+// before the current one is summed), and sum each row's products with the
+// staged vector xs in float64 in the row order of the matrix: a lane adds its
+// own run of elements, a segmented scan over the lanes adds the runs of rows
+// that cross lanes, and the lane holding a row's last element calls
+// emit(global row, sum).  W: the staged width (a power of two).
+// body: fetch(chunk) as soon as the chunk's descriptor is known (a chunk
+// ahead of its processing), begin(chunk) when its processing starts,
+// emit(row, sum), end(chunk).
+template <typename T, typename V, typename Body>
+__device__ __forceinline__ void panel_chunks(const PanelChunk* chunks, int32_t c_begin, int32_t c_end, const V* valp,
+                                             const uint16_t* colp, const uint16_t* ridp, const T* xs, int W,
+                                             Body& body) {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int64_t pbase = g.seg_base + (int64_t)un.panel * (g.r1 - g.r0) - g.r0;
     constexpr int kStride = kPanelBlock / kWave;
-    int c = un.c0 + wave;
+    int c = c_begin + wave;
     PanelChunk ch{0, 0, 0, 0};
     PanelRaw<V> raw;
-    if (c < un.c1) {
-        ch = a.chunks[c];
+    if (c < c_end) {
+        ch = chunks[c];
         if (ch.count > lane * 8) {
             const int64_t e0 = (int64_t)ch.start + lane * 8;
-            raw.load(a.val + e0, a.col + e0, a.rid + e0);
+            raw.load(valp + e0, colp + e0, ridp + e0);
         }
+        body.fetch(ch);
     }
-    for (; c < un.c1; c += kStride) {
+    for (; c < c_end; c += kStride) {
         const PanelChunk cur = ch;
         const PanelRaw<V> rc = raw;
-        if (c + kStride < un.c1) {  // the next chunk's loads go out first
-            ch = a.chunks[c + kStride];
+        body.begin(cur);
+        if (c + kStride < c_end) {  // the next chunk's loads go out first
+            ch = chunks[c + kStride];
             if (ch.count > lane * 8) {
                 const int64_t e0 = (int64_t)ch.start + lane * 8;
-                raw.load(a.val + e0, a.col + e0, a.rid + e0);
+                raw.load(valp + e0, colp + e0, ridp + e0);
             }
+            body.fetch(ch);
         }
         const int n = cur.count - lane * 8;  // this lane's elements (may be <= 0 or > 8)
         int rr[8];
@@ -731,9 +735,107 @@ __global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
             head = head && rr[j] == rr[0];
             const bool last = (j == 7) ? (lane == kWave - 1 || next_n <= 0 || next_r0 != rr[7])
                                        : (j + 1 >= n || rr[j + 1] != rr[j]);
-            if (last) a.partial[pbase + cur.row0 + rr[j]] = (T)(s[j] + (head ? carry : 0.0));
+            if (last) body.emit(cur.row0 + rr[j], s[j] + (head ? carry : 0.0));
         }
+        body.end(cur);
     }
+}
+
+// One workgroup per unit: the panel's slice of the gathered vector is staged
+// in LDS, then the unit's chunks are summed (panel_chunks) and each row's sum
+// over the panel goes to its partial.
+template <typename T, typename V>
+__global__ __launch_bounds__(kPanelBlock) void k_panel_spmv(PanelArgs<T, V> a) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    __shared__ __align__(16) T xs[panel_width<T>()];
+    const int W = a.width;
+    const PanelUnit un = a.units[blockIdx.x];
+    const PanelGroup g = a.groups[un.group];
+    const int64_t c0 = (int64_t)g.lo + (int64_t)un.panel * W;  // a multiple of 8
+    panel_stage<T>(xs, 0, a.gather, c0, W, a.ncols);
+    __syncthreads();
+    struct Body {
+        T* partial;
+        __device__ __forceinline__ void fetch(const PanelChunk&) {}
+        __device__ __forceinline__ void begin(const PanelChunk&) {}
+        __device__ __forceinline__ void emit(int32_t r, double sum) { partial[r] = (T)sum; }
+        __device__ __forceinline__ void end(const PanelChunk&) {}
+    } body{a.partial + g.seg_base + (int64_t)un.panel * (g.r1 - g.r0) - g.r0};
+    panel_chunks<T, V>(a.chunks, un.c0, un.c1, a.val, a.col, a.rid, xs, W, body);
+}
+
+template <typename V>
+struct RowPanelArgs {
+    int32_t width;
+    const RowPanelGroup* groups;
+    const RowPanelUnit* units;
+    const PanelChunk* chunks;
+    const V* val;
+    const uint16_t* col;
+    const uint16_t* rid;
+    int32_t t0, tail;
+    int64_t ncols;
+};
+
+// The primal step on A^T's row-panel layout: a workgroup per unit stages its
+// group's window of v and the common tail in LDS and sums every row of the
+// unit whole (panel_chunks).  A row-panel chunk holds at most
+// kRowPanelChunkRows rows, its row count in the descriptor's last field: a
+// chunk ahead of its processing, lane l issues the epilogue loads of the
+// chunk's rows l and l + 64 (consecutive rows on consecutive lanes); the row
+// sums go to the wave's slice of LDS; then each lane finishes its rows.
+template <typename T, typename V, bool GEN>
+__global__ __launch_bounds__(kPanelBlock) void k_rowpanel_primal(IterArgs<T, V> a, RowPanelArgs<V> pa) {
+    if (a.ctrl->status != ST_RUNNING) return;
+    __shared__ __align__(16) T xs[panel_width<T>()];
+    __shared__ double rsum[kPanelBlock / kWave][kRowPanelChunkRows];
+    double q[3] = {0.0, 0.0, 0.0};
+    double mx[1] = {0.0};
+    auto epi = make_epi<T, V, true, GEN>(a, q);
+    epi.ready();
+    const RowPanelUnit un = pa.units[blockIdx.x];
+    const RowPanelGroup g = pa.groups[un.group];
+    panel_stage<T>(xs, 0, a.gather, g.lo, g.ml, pa.t0);
+    panel_stage<T>(xs, g.ml, a.gather, pa.t0, pa.tail, pa.ncols);
+    __syncthreads();
+    typedef typename decltype(epi)::Pre Pre;
+    constexpr int kPer = kRowPanelChunkRows / kWave;
+    struct Body {
+        decltype(epi)& epi;
+        double* rs;  // the wave's row sums, by row inside the chunk
+        int lane;
+        int32_t row0 = 0;
+        Pre pre[kPer], nxt[kPer];
+        __device__ __forceinline__ void fetch(const PanelChunk& ch) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int j = lane + k * kWave;
+                if (j < ch.unit) nxt[k] = epi.load(ch.row0 + j, 0);
+            }
+        }
+        __device__ __forceinline__ void begin(const PanelChunk& ch) {
+            row0 = ch.row0;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) pre[k] = nxt[k];
+        }
+        __device__ __forceinline__ void emit(int32_t r, double sum) { rs[r - row0] = sum; }
+        __device__ __forceinline__ void end(const PanelChunk& ch) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int j = lane + k * kWave;
+                if (j < ch.unit) epi.apply(ch.row0 + j, 0, pre[k], rs[j]);
+            }
+            __builtin_amdgcn_wave_barrier();  // the next chunk's sums overwrite rs
+        }
+    };
+    const int wave = threadIdx.x / kWave;
+    Body body{epi, &rsum[wave][0], (int)(threadIdx.x & (kWave - 1))};
+    panel_chunks<T, V>(pa.chunks, un.c0, un.c1, pa.val, pa.col, pa.rid, xs, pa.width, body);
+    if (a.flags & (F_FIRST | F_EVAL))
+        block_reduce_store<3, 0, kPanelBlock>(q, mx, a.partials + 3 * blockIdx.x, iter_store_mask(a.flags));
 }
 
 struct PanelRows {
@@ -1467,13 +1569,14 @@ struct PlainWs {
     // attempts alternate between, A~ (x - x0) itself, and the move's sums
     void *x_alt, *y_alt, *ax, *ax_alt;
     double *ap, *ad;
-    PanelLayout pl;             // spmv_kind 3: A's panel layout (dual step)
+    PanelLayout pl;             // spmv_kind 3, 4: A's panel layout (dual step)
+    RowPanelLayout rl;          // spmv_kind 4: A^T's row-panel layout (primal step)
     size_t bytes;
 };
 
 static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, int prec, int power_iters,
                      int64_t tnz, int64_t trows, int64_t tnz_t, int64_t trows_t, bool sorted, bool bounds,
-                     bool avg, bool panel, bool adapt) {
+                     bool avg, bool panel, bool adapt, bool rowpanel) {
     Carver cv(base, cap);
     PlainWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
@@ -1545,6 +1648,20 @@ static PlainWs carve(void* base, size_t cap, int64_t m, int64_t n, int64_t nnz, 
         w.pl.rid = cv.take<uint16_t>(ec);
         w.pl.partial = cv.take<char>(sc * ts);
     }
+    memset(&w.rl, 0, sizeof(w.rl));
+    if (rowpanel) {  // rows of A^T: n
+        const int64_t cc = rowpanel_chunk_cap(n, nnz), ec = rowpanel_elem_cap(n, nnz);
+        w.rl.groups = cv.take<RowPanelGroup>(kRowPanelMaxUnits);
+        w.rl.units = cv.take<RowPanelUnit>(kRowPanelMaxUnits);
+        w.rl.chunks = cv.take<PanelChunk>(cc);
+        w.rl.val = cv.take<char>(ec * vs);
+        w.rl.col = cv.take<uint16_t>(ec);
+        w.rl.rid = cv.take<uint16_t>(ec);
+        w.rl.row_group = cv.take<int32_t>(n);
+        w.rl.row_off = cv.take<int32_t>(n);
+        w.rl.row_rid = cv.take<uint16_t>(n);
+        w.rl.span = cv.take<int32_t>(2 * std::max(m, n));
+    }
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -1561,7 +1678,7 @@ int check_options(const mipdhg_options* o) {
     if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return set_error("pw_theta must be in [0,1]"), MIPDHG_ERR_INVALID_ARG;
     if (!std::isfinite(o->pw_ki) || !std::isfinite(o->pw_kd))
         return set_error("pw_ki and pw_kd must be finite"), MIPDHG_ERR_INVALID_ARG;
-    if (o->spmv_kind < 0 || o->spmv_kind > 3) return set_error("spmv_kind must be 0, 1, 2 or 3"), MIPDHG_ERR_INVALID_ARG;
+    if (o->spmv_kind < 0 || o->spmv_kind > 4) return set_error("spmv_kind must be 0 to 4"), MIPDHG_ERR_INVALID_ARG;
     if (o->panel_width != 0) {
         const int maxw = kPanelBytes / ((o->precision == MIPDHG_FP64 || o->precision == MIPDHG_FP32_A) ? 8 : 4);
         if (o->panel_width < 64 || o->panel_width > maxw || (o->panel_width & (o->panel_width - 1)))
@@ -1632,7 +1749,7 @@ extern "C" int mipdhg_workspace_size(const mipdhg_lp* lp, const mipdhg_options* 
     if ((rc = check_options(opt))) return rc;
     *bytes = carve(nullptr, 0, lp->m, lp->n, lp->nnz, opt->precision, opt->power_iters, tile_nnz_of(*opt),
                    tile_rows_of(*opt), tile_nnz_at_of(*opt), tile_rows_at_of(*opt), sorted_layout(*opt, lp->m, lp->n),
-                   has_bounds(*lp), opt->restart_avg != 0, opt->spmv_kind == 3, opt->step_rule == 1).bytes;
+                   has_bounds(*lp), opt->restart_avg != 0, opt->spmv_kind >= 3, opt->step_rule == 1, opt->spmv_kind == 4).bytes;
     return 0;
 }
 
@@ -1725,9 +1842,13 @@ struct Solver {
     }
     bool sorted() const { return sorted_layout(o, lp.m, lp.n); }
     // spmv_kind 3: the dual step on A's panel layout, the primal on A^T's tiles
-    bool panel() const { return o.spmv_kind == 3; }
+    bool panel() const { return o.spmv_kind == 3 || o.spmv_kind == 4; }
+    bool rowpanel() const { return o.spmv_kind == 4; }
     int panel_w() const { return o.panel_width > 0 ? o.panel_width : panel_width<T>(); }
-    int grid_primal() const { return persistent() ? gp_persist : tiled() ? tat.ntiles : hpat.grid(); }
+    int grid_primal() const {
+        if (rowpanel()) return w.rl.nunits;
+        return persistent() ? gp_persist : tiled() ? tat.ntiles : hpat.grid();
+    }
     int grid_dual() const {
         if (panel())
             return (int)((lp.m + kBlock - 1) / kBlock + (w.pl.nwide + kBlock / kWave - 1) / (kBlock / kWave));
@@ -1883,7 +2004,27 @@ struct Solver {
     int launch_primal(int it, int flags) {
         IterArgs<T, V> a;
         fill_iter(a, true, it, flags);
-        if (tiled()) {
+        if (rowpanel()) {
+            RowPanelArgs<V> ra;
+            ra.width = panel_w();
+            ra.groups = w.rl.groups;
+            ra.units = w.rl.units;
+            ra.chunks = w.rl.chunks;
+            ra.val = (const V*)w.rl.val;
+            ra.col = w.rl.col;
+            ra.rid = w.rl.rid;
+            ra.t0 = w.rl.t0;
+            ra.tail = w.rl.tail;
+            ra.ncols = lp.m;
+            if (w.rl.nunits > 0) {
+                if (gen_primal())
+                    hipLaunchKernelGGL((k_rowpanel_primal<T, V, true>), dim3(w.rl.nunits), dim3(kPanelBlock), 0,
+                                       stream, a, ra);
+                else
+                    hipLaunchKernelGGL((k_rowpanel_primal<T, V, false>), dim3(w.rl.nunits), dim3(kPanelBlock), 0,
+                                       stream, a, ra);
+            }
+        } else if (tiled()) {
             launch_tiles<true>(a, tat, gp_persist);
         } else {
             MIP_DISPATCH_L(pat.lanes, hipLaunchKernelGGL((k_iter<T, V, Acc, L, true>), dim3(hpat.grid()), dim3(kBlock),
@@ -2119,7 +2260,7 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
     Solver<T, V, Acc> S(lp, o, stream);
     S.w = carve(ws, ws_bytes, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                 tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                o.restart_avg != 0, o.spmv_kind == 3, o.step_rule == 1);
+                o.restart_avg != 0, o.spmv_kind >= 3, o.step_rule == 1, o.spmv_kind == 4);
     if (S.w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, S.w.bytes),
                MIPDHG_ERR_WORKSPACE;
@@ -2324,6 +2465,19 @@ static int solve_impl(const mipdhg_lp& lp, const mipdhg_options& o, double eps, 
             (void)hipStreamSynchronize(side.s);
             (void)hipStreamSynchronize(stream);
             return rc;
+        }
+        if (S.rowpanel()) {
+            int dev = 0, cus = 256;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            rc = rowpanel_build<V>(rpat, lp.n, lp.m, nnz, lp.at_rowptr, lp.at_col, lp.at_val, lp.a_rowptr, lp.a_col,
+                                   (const double*)w.d_col, (const double*)w.d_row, S.panel_w(), cus, w.rl, side.s);
+            if (rc) {
+                (void)hipStreamSynchronize(side.s);
+                (void)hipStreamSynchronize(stream);
+                return rc;
+            }
         }
         MIP_HIP(hipEventRecord(side.built, side.s));
         MIP_HIP(hipStreamWaitEvent(stream, side.built, 0));
@@ -2639,7 +2793,7 @@ static std::vector<std::pair<size_t, size_t>> state_regions(const mipdhg_lp& lp,
     char* const base = reinterpret_cast<char*>(uintptr_t(4096));  // layout only, never dereferenced
     const PlainWs w = carve(base, 0, lp.m, lp.n, lp.nnz, o.precision, o.power_iters, tile_nnz_of(o), tile_rows_of(o),
                             tile_nnz_at_of(o), tile_rows_at_of(o), sorted_layout(o, lp.m, lp.n), has_bounds(lp),
-                            o.restart_avg != 0, o.spmv_kind == 3, o.step_rule == 1);
+                            o.restart_avg != 0, o.spmv_kind >= 3, o.step_rule == 1, o.spmv_kind == 4);
     const size_t ts = (o.precision == MIPDHG_FP64 || o.precision == MIPDHG_FP32_A) ? 8 : 4;
     const size_t m = (size_t)lp.m, n = (size_t)lp.n, G = (size_t)w.gcap;
     auto at = [&](const void* p, size_t bytes) { return std::make_pair((size_t)((const char*)p - base), bytes); };

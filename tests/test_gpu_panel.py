@@ -34,9 +34,9 @@ def _small_block_angular(seed=0):
     return lpgen.cfg3(seed, nblocks=4, bm=300, bn=1200, nlink=20, link_nnz=60)
 
 
-def _trace(lp, T=100, eval_every=64, **kw):
+def _trace(lp, T=100, eval_every=64, spmv_kind=3, **kw):
     sol = P.solve(P.DeviceLP.from_lp(lp), 1e-12, "fp64", trace_iters=T, max_iter=T, eval_every=eval_every,
-                  spmv_kind=3, **kw)
+                  spmv_kind=spmv_kind, **kw)
     ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-12, opts=OracleOptions(max_iter=T, eval_every=eval_every),
                        trace_iters=T, lo=lp.lo, hi=lp.hi, sense=lp.sense)
     assert sol.status == ref.status
@@ -126,3 +126,56 @@ def test_row_longer_than_a_chunk_in_one_panel_is_unsupported():
     assert e.value.code == -6 and "chunk" in str(e.value) or "nonzeros in one panel" in str(e.value)
     with pytest.raises(P.MipdhgError):
         P.solve(lp, 1e-4, "fp64", spmv_kind=3, panel_width=100)  # not a power of two
+
+
+# --- spmv_kind 4: the primal step on A^T's row-panel layout as well
+
+def _six_blocks():
+    # 6 blocks 300 x 400 (6 per column) + 20 linking rows of 60: with 1,024-entry panels the
+    # linking rows (span 2,400 > 512) are the tail, the block rows (span 400) are not, and
+    # A^T's windows (300 rows a block) group three blocks at a time
+    return lpgen.cfg3(0, nblocks=6, bm=300, bn=400, nlink=20, link_nnz=60)
+
+
+@pytest.mark.parametrize("width", [0, 1024])
+def test_row_panels_trace_parity_block_angular(width):
+    _trace(_six_blocks(), panel_width=width, spmv_kind=4)
+
+
+def _with_empty_columns(lp, k=5):
+    # k columns of A without nonzeros (rows of A^T that get one zero element), cost 1
+    from types import SimpleNamespace
+    import scipy.sparse as sp
+    A = sp.hstack([lp.A, sp.csr_matrix((lp.m, k))]).tocsr()
+    A.sort_indices()
+    return SimpleNamespace(A=A, AT=sp.csr_matrix(A.T), b=lp.b, c=np.concatenate([lp.c, np.ones(k)]), lo=None,
+                           hi=None, sense=None)
+
+
+def test_row_panels_trace_parity_random_general_and_empty_columns():
+    _trace(lpgen.cfg1(0), spmv_kind=4)
+    _trace(lpgen.general_cfg1(1), T=70, eval_every=16, spmv_kind=4)
+    _trace(_with_empty_columns(lpgen.cfg1(2)), T=70, spmv_kind=4)
+    _trace(lpgen.cfg2_sub(3, scale=400), T=70, spmv_kind=4, tile_nnz_at=512, tile_rows_at=64)
+
+
+def test_row_panels_full_solve_and_float32():
+    lp = _six_blocks()
+    dlp = P.DeviceLP.from_lp(lp)
+    a = P.solve(dlp, 1e-8, "fp64", spmv_kind=4, panel_width=1024)
+    ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-8)
+    assert a.status == ref.status == 0 and a.info["iters"] == ref.iters
+    s = P.solve(dlp, 1e-6, "fp32", spmv_kind=4, panel_width=1024, max_iter=200_000)
+    b = P.solve(dlp, 1e-6, "fp32", spmv_kind=4, panel_width=1024, use_graph=0)
+    assert s.status == 0 and torch.equal(s.x, b.x) and torch.equal(s.y, b.y)
+    assert abs(s.info["pobj"] - ref.meas.pobj) <= 1e-4 * abs(ref.meas.pobj)
+    for prec in ("bf16", "fp32"):
+        c = P.solve(dlp, 1e-4, prec, spmv_kind=4)
+        assert c.status == 0
+
+
+def test_row_panels_refuse_a_matrix_without_the_structure():
+    # 64-entry panels: every row of cfg1's A (up to 500 columns) is wide, not a short tail
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve(P.DeviceLP.from_lp(lpgen.cfg1(0)), 1e-4, "fp64", spmv_kind=4, panel_width=64)
+    assert e.value.code == -6 and "row-panel" in str(e.value)
