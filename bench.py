@@ -720,7 +720,7 @@ def counter_summary(folder: str, workload: str, precision: str, shape_text: str)
              "```", cmds["trace"] + f" > {folder}/bench_{workload}.json", "```", "",
              "| kernel | calls | avg us | min us | max us | total ms |", "|---|---|---|---|---|---|"]
     for r in stats[:12]:
-        lines.append(f"| `{r['Name'].split('(')[0]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+        lines.append(f"| `{r['Name'].replace('(anonymous namespace)::', '').split('(')[0]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
     bj = os.path.join(folder, f"bench_{workload}.json")
