@@ -118,3 +118,28 @@ def test_one_step_parity_full_block_angular(prec, tol):
 def test_one_step_parity_full_general_power_law(prec, tol):
     # the general-form leg of the benchmark: bounds and row senses on the power-law shape
     _one_step_check(_lp("general"), prec, _tuned("general", prec), tol)
+
+
+@pytest.mark.parametrize("name", ["power_law", "block_angular"])
+def test_full_solve_remeasured_on_the_host(name):
+    """A full-size FP32 solve to 1e-4 at the tuned shape, its point re-measured
+    in float64 on the host (SciPy, original model): the three tests of
+    Section 2 hold, and the GPU's own evaluation (k_eval, and k_decide's
+    fixed-order reduction over thousands of partial rows) reports the same
+    measures."""
+    lp = _lp(name)
+    sol = P.solve(P.DeviceLP.from_lp(lp), 1e-4, "fp32", **_tuned(name, "fp32"))
+    assert sol.status == 0
+    x, y = _np(sol.x), _np(sol.y)
+    g = lp.c - lp.AT @ y
+    z = np.maximum(g, 0.0)
+    rp, rd = lp.b - lp.A @ x, g - z
+    p, d = float(lp.c @ x), float(lp.b @ y)
+    rel = (np.linalg.norm(rp) / (1 + np.linalg.norm(lp.b)), np.linalg.norm(rd) / (1 + np.linalg.norm(lp.c)),
+           abs(p - d) / (1 + abs(p) + abs(d)))
+    assert max(rel) <= 1e-4
+    info = sol.info
+    for got, ref in zip((info["rel_rp"], info["rel_rd"], info["rel_gap"]), rel):
+        assert abs(got - ref) <= 1e-8 * ref + 1e-15, (got, ref)
+    assert abs(info["pobj"] - p) <= 1e-12 * (1 + abs(p)) and abs(info["dobj"] - d) <= 1e-12 * (1 + abs(d))
+    assert np.allclose(_np(sol.z), z, rtol=0, atol=1e-12 * (1 + np.abs(z).max()))
