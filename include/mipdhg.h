@@ -248,6 +248,13 @@ typedef struct mipdhg_options {
     int32_t step_rule;
     /* step_rule 1: the first step, > 0 (0 = 1 / max |A~_ij|)              [0] */
     double step0;
+    /* Batched solve: LDS bytes per workgroup of a first launch for the
+     * instances whose y and x_bar (the vectors kept in LDS) fit in it, at the
+     * occupancy that size allows; the others follow in a second launch sized
+     * by the largest instance.  0 = one launch sized by the largest instance.
+     * Every instance's result is the same either way; mipdhg_autotune_batched
+     * picks the fastest.                                                    [0] */
+    int32_t batch_split;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */
@@ -542,6 +549,19 @@ int mipdhg_ipm_warm(const mipdhg_lp *lp, const double *d_row, const double *d_co
  * a hardware counter it gives the counter's reading for a known number of
  * bytes read.  Asynchronous; INVALID_ARG on a bad argument. */
 int mipdhg_read_probe(const void *buf, size_t bytes, int32_t blocks, void *stream, uint32_t *out);
+
+/* Times mipdhg_solve_batched on this batch with each candidate LDS budget of
+ * the first launch (batch_split 0, 4, 8, 16, 32 KB: one launch sized by the
+ * largest instance, or the instances whose vectors fit the budget in a
+ * launch at the occupancy it allows, beside a launch of the others) and
+ * writes the fastest into opt->batch_split (0 kept unless another is more
+ * than 3 % faster).  Every candidate gives every instance the same result;
+ * the outputs hold the last candidate's.  Arguments as for
+ * mipdhg_solve_batched; best_ms (host, nullable) receives the chosen
+ * candidate's kernel time. */
+int mipdhg_autotune_batched(const mipdhg_batch *bt, mipdhg_options *opt, const double *eps_rel, void *workspace,
+                            size_t workspace_bytes, void *stream, double *x, double *y, double *z, double *r_p,
+                            double *r_d, double *best_ms);
 
 /* Text for a status or error code. */
 const char *mipdhg_status_string(int code);

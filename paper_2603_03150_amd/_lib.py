@@ -45,7 +45,8 @@ class OptionsStruct(C.Structure):
                 ("x_init", _p), ("y_init", _p), ("gather_order", _i32), ("resume", _i32),
                 ("infeas_tol", _f64), ("pw_ki", _f64), ("pw_kd", _f64),
                 ("tile_nnz_at", _i32), ("tile_rows_at", _i32), ("short_row_at", _i32), ("restart_avg", _i32),
-                ("panel_width", _i32), ("step_rule", _i32), ("step0", _f64)]
+                ("panel_width", _i32), ("step_rule", _i32), ("step0", _f64),
+                ("batch_split", _i32)]
 
 
 class InfoStruct(C.Structure):
@@ -93,6 +94,8 @@ SIGNATURES = {
                                               C.POINTER(C.c_size_t)]),
     "mipdhg_solve_batched": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _p, _p, C.c_size_t,
                                        _p, _p, _p, _p, _p, _p, _p]),
+    "mipdhg_autotune_batched": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _p, _p, C.c_size_t,
+                                          _p, _p, _p, _p, _p, _p, C.POINTER(_f64)]),
     "mipdhg_unrolled_tape_size": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32,
                                             C.POINTER(C.c_size_t)]),
     "mipdhg_unrolled_forward": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32, _i32,

@@ -446,12 +446,28 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     for (int i = 0; i <= B; ++i)
         if (rpa[bt.row_off[i]] != bt.nnz_off[i] || rpat[bt.col_off[i]] != bt.nnz_off[i])
             return set_error("nnz_off does not match the row pointers at instance %d", i), MIPDHG_ERR_BAD_CSR;
-    // largest instances first
+    // largest instances first; with a split, the instances whose vectors
+    // exceed the first launch's LDS come first in the order array (the second
+    // launch), each class largest first
     std::vector<int32_t> order(B);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
         return bt.nnz_off[p + 1] - bt.nnz_off[p] > bt.nnz_off[q + 1] - bt.nnz_off[q];
     });
+    auto inst_lds = [&](int i) {
+        return lds_bytes_for(bt.row_off[i + 1] - bt.row_off[i], bt.col_off[i + 1] - bt.col_off[i], sizeof(T));
+    };
+    int n_big = B, sm_m = 0, sm_n = 0;  // the second launch's instance count; the first's largest sizes
+    if (o.batch_split > 0) {
+        std::stable_partition(order.begin(), order.end(), [&](int i) { return inst_lds(i) > o.batch_split; });
+        n_big = 0;
+        for (int i : order)
+            if (inst_lds(i) > o.batch_split) ++n_big;
+        for (int k = n_big; k < B; ++k) {
+            sm_m = std::max(sm_m, bt.row_off[order[k] + 1] - bt.row_off[order[k]]);
+            sm_n = std::max(sm_n, bt.col_off[order[k] + 1] - bt.col_off[order[k]]);
+        }
+    }
     MIP_HIP(hipMemcpyAsync(w.order, order.data(), B * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.eps, eps, (size_t)B * 8, hipMemcpyHostToDevice, stream));
@@ -510,21 +526,68 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     a.eval_every = o.eval_every;
     a.halpern = o.halpern;
     a.restarts = o.restarts;
-    // persistent grid: as many workgroups as fit, never more than instances
-    int dev = 0, cus = 256, per_cu = 1;
+    // persistent grids: as many workgroups as fit, never more than instances
+    int dev = 0, cus = 256;
     MIP_HIP(hipGetDevice(&dev));
     MIP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     MIP_HIP(hipFuncSetAttribute((const void*)k_batched<T, V, Acc>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V, Acc>, kBatchBlock, lds));
-    const int grid = std::max(1, std::min(B, cus * std::max(per_cu, 1)));
+    auto grid_for_lds = [&](int bytes, int count, int* g) {
+        int per_cu = 1;
+        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V, Acc>, kBatchBlock, bytes));
+        *g = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
+        return 0;
+    };
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, w.counter, 64);
     const auto t1 = clk::now();
     hipEvent_t e0, e1;
     MIP_HIP(hipEventCreate(&e0));
     MIP_HIP(hipEventCreate(&e1));
     MIP_HIP(hipEventRecord(e0, stream));
-    hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
-    MIP_LAUNCH_CHECK();
+    if (n_big == B) {
+        int grid = 1;
+        if ((rc = grid_for_lds(lds, B, &grid))) return rc;
+        hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+        MIP_LAUNCH_CHECK();
+    } else {
+        // the small instances on a side stream at their occupancy, the others
+        // (if any) on the caller's stream at the largest instance's; both
+        // persistent launches run at once and share the CUs
+        struct Side {
+            hipStream_t s = nullptr;
+            hipEvent_t fork = nullptr, join = nullptr;
+            ~Side() {
+                if (fork) (void)hipEventDestroy(fork);
+                if (join) (void)hipEventDestroy(join);
+                if (s) (void)hipStreamDestroy(s);
+            }
+        } side;
+        MIP_HIP(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+        MIP_HIP(hipEventCreateWithFlags(&side.fork, hipEventDisableTiming));
+        MIP_HIP(hipEventCreateWithFlags(&side.join, hipEventDisableTiming));
+        MIP_HIP(hipEventRecord(side.fork, stream));
+        MIP_HIP(hipStreamWaitEvent(side.s, side.fork, 0));
+        BArgs<T, V> as = a;
+        as.B = B - n_big;
+        as.order = w.order + n_big;
+        as.counter = w.counter + 1;
+        as.lds_m = sm_m;
+        as.lds_n = sm_n;
+        const int lds_sm = lds_bytes_for(sm_m, sm_n, sizeof(T));
+        int grid = 1;
+        if ((rc = grid_for_lds(lds_sm, as.B, &grid))) return rc;
+        hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds_sm, side.s, as);
+        MIP_LAUNCH_CHECK();
+        if (n_big > 0) {
+            BArgs<T, V> ab = a;
+            ab.B = n_big;
+            if ((rc = grid_for_lds(lds, n_big, &grid))) return rc;
+            hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, ab);
+            MIP_LAUNCH_CHECK();
+        }
+        MIP_HIP(hipEventRecord(side.join, side.s));
+        MIP_HIP(hipStreamWaitEvent(stream, side.join, 0));
+        MIP_HIP(hipStreamSynchronize(side.s));
+    }
     MIP_HIP(hipEventRecord(e1, stream));
     std::vector<BInst> res(B);
     MIP_HIP(hipMemcpyAsync(res.data(), w.info, sizeof(BInst) * B, hipMemcpyDeviceToHost, stream));
@@ -623,4 +686,39 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
             return batched_impl<float, float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                      r_d, info);
     }
+}
+
+extern "C" int mipdhg_autotune_batched(const mipdhg_batch* bt, mipdhg_options* opt, const double* eps_rel,
+                                       void* workspace, size_t workspace_bytes, void* stream, double* x, double* y,
+                                       double* z, double* r_p, double* r_d, double* best_ms) {
+    clear_error();
+    int rc = check_batch(bt);
+    if (rc) return rc;
+    if (!opt) return set_error("options are NULL"), MIPDHG_ERR_INVALID_ARG;
+    std::vector<mipdhg_info> info((size_t)bt->count);
+    // LDS budgets of the first launch (0: one launch); the default stays
+    // unless another is more than 3 % faster, so that the choice is stable
+    const int32_t cands[] = {0, 4096, 8192, 16384, 32768};
+    double best = 1e300, def = 1e300;
+    int32_t pick = 0;
+    for (int32_t c : cands) {
+        mipdhg_options o = *opt;
+        o.batch_split = c;
+        const int r = mipdhg_solve_batched(bt, &o, eps_rel, workspace, workspace_bytes, stream, x, y, z, r_p, r_d,
+                                           info.data());
+        if (r < 0) return r;
+        const double ms = info[0].ms_iter;  // the launches, timed by events on the stream
+        if (c == 0) def = ms;
+        if (ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    if (best * 1.03 >= def) {
+        pick = 0;
+        best = def;
+    }
+    opt->batch_split = pick;
+    if (best_ms) *best_ms = best;
+    return 0;
 }

@@ -307,6 +307,27 @@ def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
     return BatchSolution(rc, x, y, z, r_p, r_d, [infos[i].as_dict() for i in range(batch.count)])
 
 
+def autotune_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32", **opts) -> dict:
+    """mipdhg_autotune_batched: the fastest batch_split for this batch (one
+    timed batched solve per candidate); returns the option and its time."""
+    lib = _lib.load()
+    o = make_options(precision, **opts)
+    st = batch.struct()
+    nb = C.c_size_t(0)
+    _lib.check(lib.mipdhg_batch_workspace_size(C.byref(st), C.byref(o), C.byref(nb)))
+    d = batch.lp.device
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+    f64 = dict(dtype=torch.float64, device=d)
+    m, n = batch.lp.m, batch.lp.n
+    bufs = [torch.empty(k, **f64) for k in (n, m, n, m, n)]
+    eps_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (batch.count,)))
+    best = C.c_double(0.0)
+    _lib.check(lib.mipdhg_autotune_batched(C.byref(st), C.byref(o), eps_arr.ctypes.data, ws.data_ptr(), ws.numel(),
+                                           torch.cuda.current_stream(d).cuda_stream, *[b.data_ptr() for b in bufs],
+                                           C.byref(best)))
+    return {"batch_split": o.batch_split, "ms": best.value}
+
+
 def batch_workspace_bytes(batch: DeviceBatch, precision: str = "fp32", **opts) -> int:
     lib = _lib.load()
     o = make_options(precision, **opts)

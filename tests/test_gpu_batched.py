@@ -182,3 +182,32 @@ def test_batched_per_instance_tolerances():
     # a tolerance per instance is required, each finite and >= 0
     with pytest.raises(P.MipdhgError):
         P.solve_batched(P.DeviceBatch.from_lps([lp, lp]), [1e-4, float("nan")], "fp64")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_launch_split_gives_every_instance_the_same_result(prec):
+    # sizes 20..2,000 rows: the 4, 8, 16 KB budgets put instances in both launches,
+    # 48 KB (above the largest instance's vectors) puts them all in the first
+    lps = [lpgen.cfg4_instance(700 + i, m) for i, m in enumerate(_sizes(48, 20, 2000, seed=5))]
+    batch = P.DeviceBatch.from_lps(lps)
+    ref = P.solve_batched(batch, 1e-4, prec)
+    for split in (4096, 8192, 16384, 49152):
+        got = P.solve_batched(batch, 1e-4, prec, batch_split=split)
+        assert got.status == ref.status
+        assert torch.equal(got.x, ref.x) and torch.equal(got.y, ref.y) and torch.equal(got.z, ref.z)
+        assert [i["iters"] for i in got.infos] == [i["iters"] for i in ref.infos]
+
+
+def test_batched_autotuner_choice_is_parity_equal():
+    lps = [lpgen.cfg4_instance(800 + i, m) for i, m in enumerate(_sizes(64, 20, 2000, seed=6))]
+    batch = P.DeviceBatch.from_lps(lps)
+    best = P.autotune_batched(batch, 1e-4, "fp32")
+    assert best["batch_split"] in (0, 4096, 8192, 16384, 32768) and best["ms"] > 0
+    a = P.solve_batched(batch, 1e-4, "fp32", batch_split=best["batch_split"])
+    b = P.solve_batched(batch, 1e-4, "fp32")
+    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
+    # and the chosen run against the oracle on a few instances
+    for i in (0, 31, 63):
+        lp = lps[i]
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-4)
+        assert abs(a.infos[i]["pobj"] - ref.meas.pobj) <= 1e-3 * (1 + abs(ref.meas.pobj))
