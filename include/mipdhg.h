@@ -248,12 +248,15 @@ typedef struct mipdhg_options {
     int32_t step_rule;
     /* step_rule 1: the first step, > 0 (0 = 1 / max |A~_ij|)              [0] */
     double step0;
-    /* Batched solve: LDS bytes per workgroup of a first launch for the
-     * instances whose y and x_bar (the vectors kept in LDS) fit in it, at the
-     * occupancy that size allows; the others follow in a second launch sized
-     * by the largest instance.  0 = one launch sized by the largest instance.
-     * Every instance's result is the same either way; mipdhg_autotune_batched
-     * picks the fastest.                                                    [0] */
+    /* Batched solve, > 0: two concurrent launches.  Instances whose y and
+     * x_bar (the vectors kept in LDS) fit in batch_split bytes run in
+     * 256-thread workgroups at the occupancy that size allows; the others
+     * run in 1024-thread workgroups (four times the threads on each row and
+     * column).  0 = one launch of 256-thread workgroups sized by the largest
+     * instance.  The narrow class's results are bitwise those of the single
+     * launch; the wide class sums over other thread partitions, so its
+     * iterates agree to rounding.  mipdhg_autotune_batched picks the
+     * fastest.                                                              [0] */
     int32_t batch_split;
 } mipdhg_options;
 
@@ -550,13 +553,12 @@ int mipdhg_ipm_warm(const mipdhg_lp *lp, const double *d_row, const double *d_co
  * bytes read.  Asynchronous; INVALID_ARG on a bad argument. */
 int mipdhg_read_probe(const void *buf, size_t bytes, int32_t blocks, void *stream, uint32_t *out);
 
-/* Times mipdhg_solve_batched on this batch with each candidate LDS budget of
- * the first launch (batch_split 0, 4, 8, 16, 32 KB: one launch sized by the
- * largest instance, or the instances whose vectors fit the budget in a
- * launch at the occupancy it allows, beside a launch of the others) and
+/* Times mipdhg_solve_batched on this batch with each candidate batch_split
+ * (0, 2, 4, 8, 16, 32 KB: one launch, or the instances whose vectors fit the
+ * budget in narrow workgroups beside wide workgroups for the others) and
  * writes the fastest into opt->batch_split (0 kept unless another is more
- * than 3 % faster).  Every candidate gives every instance the same result;
- * the outputs hold the last candidate's.  Arguments as for
+ * than 3 % faster).  The candidates' results agree to rounding (bitwise for
+ * the narrow class); the outputs hold the last candidate's.  Arguments as for
  * mipdhg_solve_batched; best_ms (host, nullable) receives the chosen
  * candidate's kernel time. */
 int mipdhg_autotune_batched(const mipdhg_batch *bt, mipdhg_options *opt, const double *eps_rel, void *workspace,

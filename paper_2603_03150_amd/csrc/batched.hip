@@ -45,6 +45,7 @@ struct BArgs {
     const double* at_val;
     const double *b, *c;
     V *a_vs, *at_vs;
+    uint16_t *a_cl, *at_cl;  // instance-local columns of A, A^T
     T *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
     double *d_row, *d_col, *pv, *pu, *pav;
     double *xo, *yo, *zo, *rpo, *rdo;
@@ -56,7 +57,7 @@ struct BArgs {
     int32_t ruiz, pc, power_iters, eval_every, halpern, restarts;
 };
 
-template <typename T, typename V, typename Acc>
+template <typename T, typename V, typename Acc, int BS>
 __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, double* sh) {
     const int tid = threadIdx.x;
     const int r0 = a.row_off[inst], r1 = a.row_off[inst + 1];
@@ -64,7 +65,8 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     const int m = r1 - r0, n = c1 - c0;
     double nomax[1] = {0.0};
     const InstMat M{a.a_rowptr, a.a_col, a.a_val, a.at_rowptr, a.at_col, a.at_val, a.b, a.c};
-    const InstSetup su = inst_setup<T, V>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs, a.at_vs,
+    const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs, a.at_vs,
+                                          a.a_cl, a.at_cl,
                                           a.bt, a.ct, a.ruiz, a.pc, a.power_iters, a.step_safety, sh);
     const double b_norm = su.b_norm, c_norm = su.c_norm, sigma_hat = su.sigma_hat, eta = su.eta,
                  omega0 = su.omega0;
@@ -72,11 +74,11 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     const double eps = a.eps[inst];
 
     // initial point (0, 0)
-    for (int j = tid; j < n; j += kBatchBlock) {
+    for (int j = tid; j < n; j += BS) {
         a.x[c0 + j] = (T)0;
         a.x0[c0 + j] = (T)0;
     }
-    for (int i = tid; i < m; i += kBatchBlock) {
+    for (int i = tid; i < m; i += BS) {
         yL[i] = (T)0;
         a.y0[r0 + i] = (T)0;
     }
@@ -110,19 +112,19 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             nx0 = a.x0[g];
             nct = a.ct[g];
         }
-        for (int j = tid; j < n; j += kBatchBlock) {
+        for (int j = tid; j < n; j += BS) {
             const int g = c0 + j;
             const int b0 = nb0, b1 = nb1;
             const double o = (double)nx, an = (double)nx0, ctg = (double)nct;
             {
-                const int gn = c0 + min(j + kBatchBlock, n - 1);
+                const int gn = c0 + min(j + BS, n - 1);
                 nb0 = a.at_rowptr[gn];
                 nb1 = a.at_rowptr[gn + 1];
                 nx = a.x[gn];
                 nx0 = a.x0[gn];
                 nct = a.ct[gn];
             }
-            const Acc s = row_dot4<Acc>(a.at_vs, a.at_col, yL, r0, b0, b1);
+            const Acc s = row_dot4<Acc>(a.at_vs, a.at_cl, yL, b0, b1);
             double hh = o - tau * (ctg - (double)s);
             hh = hh < 0.0 ? 0.0 : hh;
             xbL[j] = (T)(2.0 * hh - o);
@@ -149,18 +151,18 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             my0 = a.y0[g];
             mbt = a.bt[g];
         }
-        for (int i = tid; i < m; i += kBatchBlock) {
+        for (int i = tid; i < m; i += BS) {
             const int g = r0 + i;
             const int b0 = mb0, b1 = mb1;
             const double an = (double)my0, btg = (double)mbt;
             {
-                const int gn = r0 + min(i + kBatchBlock, m - 1);
+                const int gn = r0 + min(i + BS, m - 1);
                 mb0 = a.a_rowptr[gn];
                 mb1 = a.a_rowptr[gn + 1];
                 my0 = a.y0[gn];
                 mbt = a.bt[gn];
             }
-            const Acc s = row_dot4<Acc>(a.a_vs, a.a_col, xbL, c0, b0, b1);
+            const Acc s = row_dot4<Acc>(a.a_vs, a.a_cl, xbL, b0, b1);
             const double o = (double)yL[i];
             const double hh = o + sig * (btg - (double)s);
             yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
@@ -180,7 +182,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             ++k;
             continue;
         }
-        wg_reduce<4, 0>(q, nomax, sh);
+        wg_reduce<4, 0, BS>(q, nomax, sh);
         if (first) R0 = sqrt(omega * q[0] + q[2] / omega);
         ++k;
         if (!is_eval) continue;
@@ -188,7 +190,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         // evaluation on the original block, float64
         for (int q5 = 0; q5 < 5; ++q5) ev[q5] = 0.0;
         evm[0] = evm[1] = 0.0;
-        for (int i = tid; i < m; i += kBatchBlock) {
+        for (int i = tid; i < m; i += BS) {
             const int g = r0 + i;
             double s = 0.0;
             for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz) s += a.a_val[kz] * a.xo[a.a_col[kz]];
@@ -198,7 +200,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             ev[1] += a.b[g] * a.yo[g];
             evm[0] = fmax(evm[0], fabs(rp));
         }
-        for (int j = tid; j < n; j += kBatchBlock) {
+        for (int j = tid; j < n; j += BS) {
             const int g = c0 + j;
             double s = 0.0;
             for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz) s += a.at_val[kz] * a.yo[a.at_col[kz]];
@@ -213,7 +215,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
             ev[4] += xv * z;
             evm[1] = fmax(evm[1], fabs(rd));
         }
-        wg_reduce<5, 2>(ev, evm, sh);
+        wg_reduce<5, 2, BS>(ev, evm, sh);
         const double rp = sqrt(ev[0]), rd = sqrt(ev[2]), pobj = ev[3], dobj = ev[1];
         const double gap = fabs(pobj - dobj);
         if (!(isfinite(ev[0]) && isfinite(ev[2]) && isfinite(pobj) && isfinite(dobj))) status = MIPDHG_NUMERICAL;
@@ -233,12 +235,12 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
                 tau = eta / omega;
                 sig = eta * omega;
             }
-            for (int j = tid; j < n; j += kBatchBlock) {
+            for (int j = tid; j < n; j += BS) {
                 const T v = a.xhat[c0 + j];
                 a.x[c0 + j] = v;
                 a.x0[c0 + j] = v;
             }
-            for (int i = tid; i < m; i += kBatchBlock) {
+            for (int i = tid; i < m; i += BS) {
                 const T v = a.yhat[r0 + i];
                 yL[i] = v;
                 a.y0[r0 + i] = v;
@@ -273,12 +275,16 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     __syncthreads();
 }
 
-template <typename T, typename V, typename Acc>
-__global__ __launch_bounds__(kBatchBlock) void k_batched(BArgs<T, V> a) {
+// Workgroup size of the split's launch of large instances: twice the
+// threads on each instance's rows and columns.
+constexpr int kBatchWide = 512;
+
+template <typename T, typename V, typename Acc, int BS>
+__global__ __launch_bounds__(BS) void k_batched(BArgs<T, V> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* yL = (T*)smem;
     T* xbL = yL + a.lds_m;
-    __shared__ double sh[8 * (kBatchBlock / kWave)];
+    __shared__ double sh[8 * (BS / kWave)];
     __shared__ int next;
     while (true) {
         if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batched(BArgs<T, V> a) {
         const int qi = next;
         __syncthreads();
         if (qi >= a.B) break;  // uniform: every wave leaves once the queue is empty
-        solve_instance<T, V, Acc>(a, a.order[qi], yL, xbL, sh);
+        solve_instance<T, V, Acc, BS>(a, a.order[qi], yL, xbL, sh);
     }
 }
 
@@ -355,6 +361,7 @@ struct BatchWs {
     BInst* info;
     double *d_row, *d_col, *pv, *pu, *pav, *partials, *red, *eps;
     void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
+    uint16_t *a_cl, *at_cl;
     size_t bytes;
 };
 
@@ -381,6 +388,8 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.red = cv.take<double>(16);
     w.a_vs = cv.take<char>(nnz * vs);
     w.at_vs = cv.take<char>(nnz * vs);
+    w.a_cl = cv.take<uint16_t>(nnz);
+    w.at_cl = cv.take<uint16_t>(nnz);
     w.x = cv.take<char>(n * ts);
     w.x0 = cv.take<char>(n * ts);
     w.xhat = cv.take<char>(n * ts);
@@ -432,7 +441,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
         max_n = std::max(max_n, bt.col_off[i + 1] - bt.col_off[i]);
     }
     const int lds = lds_bytes_for(max_m, max_n, sizeof(T));
-    if (lds > 150 * 1024)
+    if (lds > 150 * 1024 || max_m > kInstMaxDim || max_n > kInstMaxDim)
         return set_error("largest instance needs %d bytes of LDS (limit 150 KiB): m + n too large", lds),
                MIPDHG_ERR_UNSUPPORTED;
     // host checks of the row pointers against the instance offsets
@@ -447,8 +456,8 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
         if (rpa[bt.row_off[i]] != bt.nnz_off[i] || rpat[bt.col_off[i]] != bt.nnz_off[i])
             return set_error("nnz_off does not match the row pointers at instance %d", i), MIPDHG_ERR_BAD_CSR;
     // largest instances first; with a split, the instances whose vectors
-    // exceed the first launch's LDS come first in the order array (the second
-    // launch), each class largest first
+    // need more than batch_split bytes come first in the order array (the
+    // wide launch), each class largest first
     std::vector<int32_t> order(B);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
@@ -457,7 +466,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     auto inst_lds = [&](int i) {
         return lds_bytes_for(bt.row_off[i + 1] - bt.row_off[i], bt.col_off[i + 1] - bt.col_off[i], sizeof(T));
     };
-    int n_big = B, sm_m = 0, sm_n = 0;  // the second launch's instance count; the first's largest sizes
+    int n_big = B, sm_m = 0, sm_n = 0;  // the wide launch's instance count; the narrow one's largest sizes
     if (o.batch_split > 0) {
         std::stable_partition(order.begin(), order.end(), [&](int i) { return inst_lds(i) > o.batch_split; });
         n_big = 0;
@@ -493,6 +502,8 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     a.c = lp.c;
     a.a_vs = (V*)w.a_vs;
     a.at_vs = (V*)w.at_vs;
+    a.a_cl = w.a_cl;
+    a.at_cl = w.at_cl;
     a.x = (T*)w.x;
     a.x0 = (T*)w.x0;
     a.xhat = (T*)w.xhat;
@@ -530,10 +541,14 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     int dev = 0, cus = 256;
     MIP_HIP(hipGetDevice(&dev));
     MIP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MIP_HIP(hipFuncSetAttribute((const void*)k_batched<T, V, Acc>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    auto grid_for_lds = [&](int bytes, int count, int* g) {
+    auto* k_narrow = k_batched<T, V, Acc, kBatchBlock>;
+    auto* k_wide = k_batched<T, V, Acc, kBatchWide>;
+    MIP_HIP(hipFuncSetAttribute((const void*)k_narrow, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    MIP_HIP(hipFuncSetAttribute((const void*)k_wide, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    auto grid_for_lds = [&](bool wide, int bytes, int count, int* g) {
         int per_cu = 1;
-        MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<T, V, Acc>, kBatchBlock, bytes));
+        if (wide) MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wide, kBatchWide, bytes));
+        else MIP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_narrow, kBatchBlock, bytes));
         *g = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
         return 0;
     };
@@ -543,15 +558,16 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     MIP_HIP(hipEventCreate(&e0));
     MIP_HIP(hipEventCreate(&e1));
     MIP_HIP(hipEventRecord(e0, stream));
-    if (n_big == B) {
+    if (o.batch_split == 0) {
         int grid = 1;
-        if ((rc = grid_for_lds(lds, B, &grid))) return rc;
-        hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
+        if ((rc = grid_for_lds(false, lds, B, &grid))) return rc;
+        hipLaunchKernelGGL((k_batched<T, V, Acc, kBatchBlock>), dim3(grid), dim3(kBatchBlock), lds, stream, a);
         MIP_LAUNCH_CHECK();
     } else {
         // the small instances on a side stream at their occupancy, the others
-        // (if any) on the caller's stream at the largest instance's; both
-        // persistent launches run at once and share the CUs
+        // (if any) on the caller's stream in wide workgroups at the largest
+        // instance's occupancy; both persistent launches run at once and share
+        // the CUs
         struct Side {
             hipStream_t s = nullptr;
             hipEvent_t fork = nullptr, join = nullptr;
@@ -573,15 +589,34 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
         as.lds_m = sm_m;
         as.lds_n = sm_n;
         const int lds_sm = lds_bytes_for(sm_m, sm_n, sizeof(T));
-        int grid = 1;
-        if ((rc = grid_for_lds(lds_sm, as.B, &grid))) return rc;
-        hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds_sm, side.s, as);
-        MIP_LAUNCH_CHECK();
+        // grids sized to be resident together: at most one wide workgroup
+        // per CU, the narrow launch in what that leaves of the CU's threads
+        // and LDS (neither launch waits on the other, so this is for speed
+        // only)
+        int max_thr = 2048, cu_lds = 160 * 1024;
+        MIP_HIP(hipDeviceGetAttribute(&max_thr, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev));
+        MIP_HIP(hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+        const bool shared = n_big > 0 && as.B > 0;
         if (n_big > 0) {
             BArgs<T, V> ab = a;
             ab.B = n_big;
-            if ((rc = grid_for_lds(lds, n_big, &grid))) return rc;
-            hipLaunchKernelGGL((k_batched<T, V, Acc>), dim3(grid), dim3(kBatchBlock), lds, stream, ab);
+            int grid = 1;
+            if ((rc = grid_for_lds(true, lds, n_big, &grid))) return rc;
+            if (shared) grid = std::min(grid, cus);
+            hipLaunchKernelGGL((k_batched<T, V, Acc, kBatchWide>), dim3(grid), dim3(kBatchWide), lds, stream, ab);
+            MIP_LAUNCH_CHECK();
+        }
+        if (as.B > 0) {
+            int grid = 1;
+            if ((rc = grid_for_lds(false, lds_sm, as.B, &grid))) return rc;
+            if (shared) {
+                const int by_thr = (max_thr - kBatchWide) / kBatchBlock;
+                const int by_lds = lds_sm > 0 ? (cu_lds - lds) / lds_sm : by_thr;
+                const int per_cu = std::max(1, std::min(grid / std::max(cus, 1), std::min(by_thr, by_lds)));
+                grid = std::max(1, std::min(as.B, cus * per_cu));
+            }
+            hipLaunchKernelGGL((k_batched<T, V, Acc, kBatchBlock>), dim3(grid), dim3(kBatchBlock), lds_sm, side.s,
+                               as);
             MIP_LAUNCH_CHECK();
         }
         MIP_HIP(hipEventRecord(side.join, side.s));
@@ -698,7 +733,7 @@ extern "C" int mipdhg_autotune_batched(const mipdhg_batch* bt, mipdhg_options* o
     std::vector<mipdhg_info> info((size_t)bt->count);
     // LDS budgets of the first launch (0: one launch); the default stays
     // unless another is more than 3 % faster, so that the choice is stable
-    const int32_t cands[] = {0, 4096, 8192, 16384, 32768};
+    const int32_t cands[] = {0, 2048, 4096, 8192, 16384, 32768};
     double best = 1e300, def = 1e300;
     int32_t pick = 0;
     for (int32_t c : cands) {

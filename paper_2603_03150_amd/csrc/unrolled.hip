@@ -48,6 +48,7 @@ struct UArgs {
     // tape: scaling, scaled values, schedule, checkpoints
     double *d_row, *d_col, *pv, *pu, *pav;
     V *a_vs, *at_vs;
+    uint16_t *a_cl, *at_cl;  // instance-local columns of A, A^T
     T *bt, *ct;
     double *eta, *omega0, *taus, *sigmas;
     int8_t* restart;
@@ -108,7 +109,7 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
             nx0 = a.x0[gn];
             nct = a.ct[gn];
         }
-        const Acc s = row_dot4<Acc>(a.at_vs, a.M.at_col, yL, u.r0, b0, b1);
+        const Acc s = row_dot4<Acc>(a.at_vs, a.at_cl, yL, b0, b1);
         const double v = o - tau * (ctg - (double)s);
         const double hh = v < 0.0 ? 0.0 : v;
         if (maskrow) {
@@ -146,7 +147,7 @@ __device__ __forceinline__ void u_iterate(const UArgs<T, V>& a, const UInst<T, V
             my0 = a.y0[gn];
             mbt = a.bt[gn];
         }
-        const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, xbL, u.c0, b0, b1);
+        const Acc s = row_dot4<Acc>(a.a_vs, a.a_cl, xbL, b0, b1);
         const double o = (double)yL[i];
         const double hh = o + sig * (btg - (double)s);
         yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
@@ -180,7 +181,8 @@ template <typename T, typename V, typename Acc>
 __device__ void forward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* yL, T* xbL, double* sh) {
     const int tid = threadIdx.x, i = u.inst, B = a.B;
     const InstSetup su = inst_setup<T, V>(a.M, u.r0, u.r1, u.c0, u.c1, a.d_row, a.d_col, a.pv, a.pu, a.pav,
-                                          a.a_vs, a.at_vs, a.bt, a.ct, a.ruiz, a.pc, a.power_iters,
+                                          a.a_vs, a.at_vs, a.a_cl, a.at_cl, a.bt, a.ct, a.ruiz, a.pc,
+                                          a.power_iters,
                                           a.step_safety, sh);
     double omega = su.omega0;
     int epoch = 0;
@@ -348,7 +350,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
             for (int j = tid; j < u.n; j += kBatchBlock) {
                 const int g = u.c0 + j;
                 const Acc s =
-                    row_dot4<Acc>(a.at_vs, a.M.at_col, lyhL, u.r0, a.M.at_rowptr[g], a.M.at_rowptr[g + 1]);
+                    row_dot4<Acc>(a.at_vs, a.at_cl, lyhL, a.M.at_rowptr[g], a.M.at_rowptr[g + 1]);
                 const double lxbar = -sig * (double)s;
                 const double lx = (double)a.lx[g], lx0 = (double)a.lx0[g];
                 double lxh = (rs ? lx + lx0 : w * opr * lx) + 2.0 * lxbar;
@@ -365,7 +367,7 @@ __device__ void backward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T*
             // (R2) rows: lam_y -= A~ lam_g
             for (int r = tid; r < u.m; r += kBatchBlock) {
                 const int g = u.r0 + r;
-                const Acc s = row_dot4<Acc>(a.a_vs, a.M.a_col, lgL, u.c0, a.M.a_rowptr[g], a.M.a_rowptr[g + 1]);
+                const Acc s = row_dot4<Acc>(a.a_vs, a.a_cl, lgL, a.M.a_rowptr[g], a.M.a_rowptr[g + 1]);
                 a.ly[g] = (T)((double)a.ly[g] - (double)s);
             }
             __syncthreads();
@@ -414,6 +416,7 @@ struct TapeLayout {
     int32_t *row_off, *col_off, *word_off, *counter;
     double *d_row, *d_col, *pv, *pu, *pav, *eta, *omega0, *taus, *sigmas;
     void *a_vs, *at_vs, *bt, *ct;
+    uint16_t *a_cl, *at_cl;
     int8_t* restart;
     void *cp_x, *cp_x0, *cp_y, *cp_y0;
     int32_t *cp_k, *cp_ep;
@@ -455,6 +458,8 @@ static TapeLayout carve_tape(void* base, size_t cap, const mipdhg_batch& bt, int
     t.sigmas = cv.take<double>((size_t)t.nep * B);
     t.a_vs = cv.take<char>(nnz * vs);
     t.at_vs = cv.take<char>(nnz * vs);
+    t.a_cl = cv.take<uint16_t>(nnz);
+    t.at_cl = cv.take<uint16_t>(nnz);
     t.bt = cv.take<char>(m * ts);
     t.ct = cv.take<char>(n * ts);
     t.restart = cv.take<int8_t>((size_t)K * B);
@@ -528,7 +533,8 @@ static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K,
         max_n = std::max(max_n, bt.col_off[i + 1] - bt.col_off[i]);
     }
     const int lds = (int)(((size_t)max_m + (size_t)max_n) * sizeof(T) + 16);
-    if (lds > 150 * 1024) return set_error("instance too large for LDS (%d bytes)", lds), MIPDHG_ERR_UNSUPPORTED;
+    if (lds > 150 * 1024 || max_m > kInstMaxDim || max_n > kInstMaxDim)
+        return set_error("instance too large for LDS (%d bytes)", lds), MIPDHG_ERR_UNSUPPORTED;
     const mipdhg_lp& lp = bt.whole;
     if (!backward) {
         std::vector<int32_t> rpa(lp.m + 1), rpat(lp.n + 1);
@@ -581,6 +587,8 @@ static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K,
     a.pav = t.pav;
     a.a_vs = (V*)t.a_vs;
     a.at_vs = (V*)t.at_vs;
+    a.a_cl = t.a_cl;
+    a.at_cl = t.at_cl;
     a.bt = (T*)t.bt;
     a.ct = (T*)t.ct;
     a.eta = t.eta;

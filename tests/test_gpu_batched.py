@@ -56,11 +56,13 @@ def _tests_hold(lp, x, y, eps):
             and abs(p - d) <= eps * (1 + abs(p) + abs(d)))
 
 
-def test_batched_fp64_matches_oracle_per_instance():
+@pytest.mark.parametrize("split", [0, 2048])
+def test_batched_fp64_matches_oracle_per_instance(split):
+    # split 2048: instances with m + n > 254 run in the wide workgroups
     lps = [lpgen.cfg4_instance(i, m) for i, m in enumerate(_sizes(24))]
     batch = P.DeviceBatch.from_lps(lps)
     eps = 1e-6
-    sol = P.solve_batched(batch, eps, "fp64", max_iter=100_000)
+    sol = P.solve_batched(batch, eps, "fp64", max_iter=100_000, batch_split=split)
     for i, lp in enumerate(lps):
         ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, eps, opts=OracleOptions(max_iter=100_000))
         got = sol.split(batch, i)
@@ -87,16 +89,18 @@ def test_batched_fp64_iteration_limit_and_options():
         assert _rel(_np(got["x"]), ref.meas.x) <= 1e-10
 
 
+@pytest.mark.parametrize("split", [0, 4096])
 @pytest.mark.parametrize("T", [1, 64, 100, 257])
-def test_batched_fp64_iterates_match_oracle_at_default_options(T):
+def test_batched_fp64_iterates_match_oracle_at_default_options(T, split):
     """Per-iterate parity with the default options (Halpern, reflection 1,
     restarts): cut at iteration T by the iteration limit, every instance's
     evaluated point equals the oracle's after T iterations, on sizes up to
-    m = 2,000 (LDS-resident instances of every size the batch holds)."""
+    m = 2,000 (LDS-resident instances of every size the batch holds); with
+    split 4096 the three larger instances run in the wide workgroups."""
     sizes = [20, 150, 700, 2000]
     lps = [lpgen.cfg4_instance(600 + i, m) for i, m in enumerate(sizes)]
     batch = P.DeviceBatch.from_lps(lps)
-    sol = P.solve_batched(batch, 1e-14, "fp64", max_iter=T)
+    sol = P.solve_batched(batch, 1e-14, "fp64", max_iter=T, batch_split=split)
     for i, lp in enumerate(lps):
         ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-14, opts=OracleOptions(max_iter=T))
         got = sol.split(batch, i)
@@ -185,29 +189,42 @@ def test_batched_per_instance_tolerances():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_launch_split_gives_every_instance_the_same_result(prec):
+def test_launch_split_narrow_class_bitwise_wide_class_to_tolerance(prec):
     # sizes 20..2,000 rows: the 4, 8, 16 KB budgets put instances in both launches,
-    # 48 KB (above the largest instance's vectors) puts them all in the first
+    # 48 KB (above the largest instance's vectors) puts them all in the narrow one
     lps = [lpgen.cfg4_instance(700 + i, m) for i, m in enumerate(_sizes(48, 20, 2000, seed=5))]
     batch = P.DeviceBatch.from_lps(lps)
-    ref = P.solve_batched(batch, 1e-4, prec)
+    ts = 8 if prec == "fp64" else 4
+    eps = 1e-4
+    ref = P.solve_batched(batch, eps, prec)
     for split in (4096, 8192, 16384, 49152):
-        got = P.solve_batched(batch, 1e-4, prec, batch_split=split)
-        assert got.status == ref.status
-        assert torch.equal(got.x, ref.x) and torch.equal(got.y, ref.y) and torch.equal(got.z, ref.z)
-        assert [i["iters"] for i in got.infos] == [i["iters"] for i in ref.infos]
+        got = P.solve_batched(batch, eps, prec, batch_split=split)
+        assert got.status == ref.status == 0
+        for i, lp in enumerate(lps):
+            g, r = got.split(batch, i), ref.split(batch, i)
+            if (lp.m + lp.n) * ts + 16 <= split:  # narrow: the single launch's arithmetic
+                assert torch.equal(g["x"], r["x"]) and torch.equal(g["y"], r["y"]), (split, i)
+                assert g["info"]["iters"] == r["info"]["iters"], (split, i)
+            else:  # wide: other sum partitions, the same tests met
+                assert g["info"]["status"] == 0
+                assert _tests_hold(lp, _np(g["x"]), _np(g["y"]), eps), (split, i)
+                err, bound = objective_bound(lp, _np(g["x"]), _np(g["y"]))
+                assert err <= bound * (1 + 1e-9) + 1e-12, (split, i)
 
 
 def test_batched_autotuner_choice_is_parity_equal():
     lps = [lpgen.cfg4_instance(800 + i, m) for i, m in enumerate(_sizes(64, 20, 2000, seed=6))]
     batch = P.DeviceBatch.from_lps(lps)
-    best = P.autotune_batched(batch, 1e-4, "fp32")
-    assert best["batch_split"] in (0, 4096, 8192, 16384, 32768) and best["ms"] > 0
-    a = P.solve_batched(batch, 1e-4, "fp32", batch_split=best["batch_split"])
-    b = P.solve_batched(batch, 1e-4, "fp32")
-    assert torch.equal(a.x, b.x) and torch.equal(a.y, b.y)
+    eps = 1e-4
+    best = P.autotune_batched(batch, eps, "fp32")
+    assert best["batch_split"] in (0, 2048, 4096, 8192, 16384, 32768) and best["ms"] > 0
+    a = P.solve_batched(batch, eps, "fp32", batch_split=best["batch_split"])
+    assert a.status == 0
+    for i, lp in enumerate(lps):
+        x, y = _np(a.split(batch, i)["x"]), _np(a.split(batch, i)["y"])
+        assert _tests_hold(lp, x, y, eps), i
     # and the chosen run against the oracle on a few instances
     for i in (0, 31, 63):
         lp = lps[i]
-        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, 1e-4)
+        ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, eps)
         assert abs(a.infos[i]["pobj"] - ref.meas.pobj) <= 1e-3 * (1 + abs(ref.meas.pobj))
