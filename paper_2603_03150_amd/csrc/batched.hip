@@ -68,10 +68,20 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs, a.at_vs,
                                           a.a_cl, a.at_cl,
                                           a.bt, a.ct, a.ruiz, a.pc, a.power_iters, a.step_safety, sh);
-    const double b_norm = su.b_norm, c_norm = su.c_norm, sigma_hat = su.sigma_hat, eta = su.eta,
-                 omega0 = su.omega0;
-    double omega = omega0, tau = eta / omega, sig = eta * omega;
+    // the report's set-up fields are written now, so that they do not stay
+    // live (in registers) across the iterations
+    if (tid == 0) {
+        BInst& r = a.info[inst];
+        r.b_norm = su.b_norm;
+        r.c_norm = su.c_norm;
+        r.sigma_hat = su.sigma_hat;
+        r.eta = su.eta;
+        r.omega0 = su.omega0;
+    }
+    const double eta = su.eta;
+    double omega = su.omega0, tau = eta / omega, sig = eta * omega;
     const double eps = a.eps[inst];
+    const double tol_p = eps * (1.0 + su.b_norm), tol_d = eps * (1.0 + su.c_norm);
 
     // initial point (0, 0)
     for (int j = tid; j < n; j += BS) {
@@ -91,7 +101,6 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     int restarts = 0;
     int status = -1;
     int64_t t = 0;
-    double ev[5], evm[2];
     while (status < 0) {
         ++t;
         const bool is_eval = (t % E == 0) || (t == a.max_iter);
@@ -188,8 +197,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         if (!is_eval) continue;
         const double R = sqrt(omega * q[0] + q[2] / omega);
         // evaluation on the original block, float64
-        for (int q5 = 0; q5 < 5; ++q5) ev[q5] = 0.0;
-        evm[0] = evm[1] = 0.0;
+        double ev[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, evm[2] = {0.0, 0.0};
         for (int i = tid; i < m; i += BS) {
             const int g = r0 + i;
             double s = 0.0;
@@ -219,10 +227,19 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         const double rp = sqrt(ev[0]), rd = sqrt(ev[2]), pobj = ev[3], dobj = ev[1];
         const double gap = fabs(pobj - dobj);
         if (!(isfinite(ev[0]) && isfinite(ev[2]) && isfinite(pobj) && isfinite(dobj))) status = MIPDHG_NUMERICAL;
-        else if (rp <= eps * (1.0 + b_norm) && rd <= eps * (1.0 + c_norm) &&
-                 gap <= eps * (1.0 + fabs(pobj) + fabs(dobj)))
+        else if (rp <= tol_p && rd <= tol_d && gap <= eps * (1.0 + fabs(pobj) + fabs(dobj)))
             status = MIPDHG_OPTIMAL;
         else if (t >= a.max_iter) status = MIPDHG_ITER_LIMIT;
+        if (tid == 0) {  // the latest evaluation's measures
+            BInst& r = a.info[inst];
+            r.rp2 = ev[0];
+            r.rd2 = ev[2];
+            r.pobj = ev[3];
+            r.dobj = ev[1];
+            r.xz = ev[4];
+            r.rp_inf = evm[0];
+            r.rd_inf = evm[1];
+        }
         if (status >= 0) break;
         bool restart = false;
         if (a.restarts)
@@ -258,18 +275,6 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         r.status = status;
         r.restarts = restarts;
         r.iters = t;
-        r.rp2 = ev[0];
-        r.rd2 = ev[2];
-        r.pobj = ev[3];
-        r.dobj = ev[1];
-        r.xz = ev[4];
-        r.rp_inf = evm[0];
-        r.rd_inf = evm[1];
-        r.b_norm = b_norm;
-        r.c_norm = c_norm;
-        r.sigma_hat = sigma_hat;
-        r.eta = eta;
-        r.omega0 = omega0;
         r.omega = omega;
     }
     __syncthreads();
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(BS) void k_batched(BArgs<T, V> a) {
     while (true) {
         if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
         __syncthreads();
-        const int qi = next;
+        const int qi = __builtin_amdgcn_readfirstlane(next);  // uniform: scalar loads of the offsets
         __syncthreads();
         if (qi >= a.B) break;  // uniform: every wave leaves once the queue is empty
         solve_instance<T, V, Acc, BS>(a, a.order[qi], yL, xbL, sh);

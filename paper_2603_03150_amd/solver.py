@@ -7,6 +7,7 @@ libmipdhg.
 from __future__ import annotations
 
 import ctypes as C
+from collections.abc import Sequence
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -304,7 +305,27 @@ def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
                                   stream, x.data_ptr(), y.data_ptr(), z.data_ptr(), r_p.data_ptr(),
                                   r_d.data_ptr(), infos)
     _lib.check(rc)
-    return BatchSolution(rc, x, y, z, r_p, r_d, [infos[i].as_dict() for i in range(batch.count)])
+    return BatchSolution(rc, x, y, z, r_p, r_d, _InfoList(infos))
+
+
+class _InfoList(Sequence):
+    """The per-instance reports as dicts, converted when read (a batch holds
+    thousands; converting all of them costs milliseconds)."""
+
+    def __init__(self, raw):
+        self._raw = raw
+
+    def __len__(self) -> int:
+        return len(self._raw)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self._raw[k].as_dict() for k in range(*i.indices(len(self._raw)))]
+        if i < 0:
+            i += len(self._raw)
+        if not 0 <= i < len(self._raw):
+            raise IndexError(i)
+        return self._raw[i].as_dict()
 
 
 def autotune_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32", **opts) -> dict:
