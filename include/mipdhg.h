@@ -63,6 +63,11 @@ extern "C" {
                                     infeas_tol)                                */
 #define MIPDHG_DUAL_INFEASIBLE 5   /* the change of the evaluated x is a
                                     recession direction with c^T d < 0        */
+#define MIPDHG_IN_PROGRESS 6       /* batched solve: the instance used up this
+                                    call's block of iterations
+                                    (batch_block_iters); its state is in the
+                                    workspace and a call with resume = 1
+                                    continues it                              */
 /* errors (< 0) */
 #define MIPDHG_ERR_INVALID_ARG -1   /* null pointer, bad size or option       */
 #define MIPDHG_ERR_BAD_CSR -2       /* row pointers or column indices invalid */
@@ -193,8 +198,9 @@ typedef struct mipdhg_options {
      * so pass the same output arrays.  A state that does not match (other
      * sizes, options, b or c norms or step size) is INVALID_ARG, and so is
      * one that stopped on non-finite values.  Not with x_init, y_init or
-     * tracing; a kernel_timing = 2 solve is not resumable.  Single-LP solve
-     * only (UNSUPPORTED in the batched and unrolled entry points).          [0] */
+     * tracing; a kernel_timing = 2 solve is not resumable.  The batched
+     * solve resumes too (see batch_block_iters); the unrolled entry points
+     * do not (UNSUPPORTED).                                                 [0] */
     int32_t resume;
     /* Infeasibility certificates (the paper does not treat infeasible LPs;
      * this is the library's own test).  At every evaluation after the first,
@@ -258,6 +264,17 @@ typedef struct mipdhg_options {
      * iterates agree to rounding.  mipdhg_autotune_batched picks the
      * fastest.                                                              [0] */
     int32_t batch_split;
+    /* Batched solve, > 0: iterations per call.  Each unfinished instance
+     * stops at its first evaluation at least batch_block_iters iterations
+     * after it started in this call, saves its state (iterates, anchors,
+     * primal weight, steps, restart bookkeeping, iteration count) in the
+     * workspace and reports MIPDHG_IN_PROGRESS.  A call with resume = 1 on
+     * the same batch, workspace, output arrays and options (eps_rel and
+     * max_iter may change) continues every instance in progress, skips the
+     * finished ones (their outputs and reports stand) and gives bitwise the
+     * result of one uninterrupted solve.  A resumed call skips the device
+     * validation the first call did.  0 = run every instance to the end.  [0] */
+    int32_t batch_block_iters;
 } mipdhg_options;
 
 /* Per-solve report (host struct). */
@@ -362,7 +379,9 @@ int mipdhg_batch_workspace_size(const mipdhg_batch *batch, const mipdhg_options 
  * largest status over the instances (0 when all are OPTIMAL) or an error.
  * An instance needs (m_i + n_i) * sizeof(iterate) bytes of LDS, at most
  * 150 KiB; larger instances return MIPDHG_ERR_UNSUPPORTED.  Tracing, warm
- * starts and kernel timing are not available here. */
+ * starts and kernel timing are not available here.  With batch_block_iters
+ * the solve runs in resumable blocks: the return value is
+ * MIPDHG_IN_PROGRESS while any instance is unfinished. */
 int mipdhg_solve_batched(const mipdhg_batch *batch, const mipdhg_options *opt, const double *eps_rel,
                          void *workspace, size_t workspace_bytes, void *stream,
                          double *x, double *y, double *z, double *r_p, double *r_d,

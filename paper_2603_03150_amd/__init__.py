@@ -1,7 +1,7 @@
 """MI355X (gfx950) restarted PDHG for standard-form LPs, behind the C ABI of
 include/mipdhg.h.  The Python layer only marshals device pointers."""
 from ._lib import (  # noqa: F401
-    OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE, MipdhgError, load,
+    OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE, IN_PROGRESS, MipdhgError, load,
 )
 from .solver import (  # noqa: F401
     BatchSolution, DeviceBatch, autotune, DeviceLP, Solution, batch_workspace_bytes, default_options, make_options,

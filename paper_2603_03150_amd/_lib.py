@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmipdhg.so")
 
 # status / error codes
-OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 0, 1, 2, 3, 4, 5
+OPTIMAL, ITER_LIMIT, TIME_LIMIT, NUMERICAL, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE, IN_PROGRESS = 0, 1, 2, 3, 4, 5, 6
 ERR_INVALID_ARG, ERR_BAD_CSR, ERR_TRANSPOSE, ERR_HIP = -1, -2, -3, -4
 ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_NONFINITE = -5, -6, -7
 
@@ -46,7 +46,7 @@ class OptionsStruct(C.Structure):
                 ("infeas_tol", _f64), ("pw_ki", _f64), ("pw_kd", _f64),
                 ("tile_nnz_at", _i32), ("tile_rows_at", _i32), ("short_row_at", _i32), ("restart_avg", _i32),
                 ("panel_width", _i32), ("step_rule", _i32), ("step0", _f64),
-                ("batch_split", _i32)]
+                ("batch_split", _i32), ("batch_block_iters", _i32)]
 
 
 class InfoStruct(C.Structure):

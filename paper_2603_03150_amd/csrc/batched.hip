@@ -32,6 +32,12 @@ struct BInst {  // per-instance result, device side
     double b_norm, c_norm, sigma_hat, eta, omega0, omega;
 };
 
+struct BState {  // an instance's solve state between resumable calls
+    int64_t t, k;
+    double omega, tau, sig, R0, R_prev;
+    int32_t restarts, phase;  // phase: 1 suspended, 2 finished
+};
+
 template <typename T, typename V>
 struct BArgs {
     int32_t B;
@@ -50,8 +56,11 @@ struct BArgs {
     double *d_row, *d_col, *pv, *pu, *pav;
     double *xo, *yo, *zo, *rpo, *rdo;
     BInst* info;
+    BState* state;
+    T* ysave;  // y of suspended instances
     int32_t* counter;
     const double* eps;  // per-instance eps_rel
+    int32_t resume, block_iters;
     double step_safety, rho, beta_suff, beta_nec, beta_art, theta;
     int64_t max_iter;
     int32_t ruiz, pc, power_iters, eval_every, halpern, restarts;
@@ -64,43 +73,76 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     const int c0 = a.col_off[inst], c1 = a.col_off[inst + 1];
     const int m = r1 - r0, n = c1 - c0;
     double nomax[1] = {0.0};
-    const InstMat M{a.a_rowptr, a.a_col, a.a_val, a.at_rowptr, a.at_col, a.at_val, a.b, a.c};
-    const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs, a.at_vs,
-                                          a.a_cl, a.at_cl,
-                                          a.bt, a.ct, a.ruiz, a.pc, a.power_iters, a.step_safety, sh);
-    // the report's set-up fields are written now, so that they do not stay
-    // live (in registers) across the iterations
-    if (tid == 0) {
-        BInst& r = a.info[inst];
-        r.b_norm = su.b_norm;
-        r.c_norm = su.c_norm;
-        r.sigma_hat = su.sigma_hat;
-        r.eta = su.eta;
-        r.omega0 = su.omega0;
-    }
-    const double eta = su.eta;
-    double omega = su.omega0, tau = eta / omega, sig = eta * omega;
+    BState& st = a.state[inst];
+    // phase of this instance in the workspace: 0 fresh, 1 suspended at the
+    // end of a block, 2 finished (read by every thread: uniform)
+    const int phase = a.resume ? st.phase : 0;
+    if (phase == 2) return;  // finished in an earlier call: its outputs and report stand
     const double eps = a.eps[inst];
-    const double tol_p = eps * (1.0 + su.b_norm), tol_d = eps * (1.0 + su.c_norm);
-
-    // initial point (0, 0)
-    for (int j = tid; j < n; j += BS) {
-        a.x[c0 + j] = (T)0;
-        a.x0[c0 + j] = (T)0;
-    }
-    for (int i = tid; i < m; i += BS) {
-        yL[i] = (T)0;
-        a.y0[r0 + i] = (T)0;
+    double eta, omega, tau, sig, tol_p, tol_d;
+    int64_t k, t;
+    double R0, R_prev;
+    int restarts;
+    if (phase == 0) {
+        const InstMat M{a.a_rowptr, a.a_col, a.a_val, a.at_rowptr, a.at_col, a.at_val, a.b, a.c};
+        const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs,
+                                                  a.at_vs, a.a_cl, a.at_cl, a.bt, a.ct, a.ruiz, a.pc,
+                                                  a.power_iters, a.step_safety, sh);
+        // the report's set-up fields are written now, so that they do not
+        // stay live (in registers) across the iterations
+        if (tid == 0) {
+            BInst& r = a.info[inst];
+            r.b_norm = su.b_norm;
+            r.c_norm = su.c_norm;
+            r.sigma_hat = su.sigma_hat;
+            r.eta = su.eta;
+            r.omega0 = su.omega0;
+        }
+        eta = su.eta;
+        omega = su.omega0;
+        tau = eta / omega;
+        sig = eta * omega;
+        tol_p = eps * (1.0 + su.b_norm);
+        tol_d = eps * (1.0 + su.c_norm);
+        k = 0;
+        t = 0;
+        R0 = NAN;
+        R_prev = INFINITY;
+        restarts = 0;
+        // initial point (0, 0)
+        for (int j = tid; j < n; j += BS) {
+            a.x[c0 + j] = (T)0;
+            a.x0[c0 + j] = (T)0;
+        }
+        for (int i = tid; i < m; i += BS) {
+            yL[i] = (T)0;
+            a.y0[r0 + i] = (T)0;
+        }
+    } else {
+        // resume: the scaled matrix, b~, c~, the scaling, x, the anchors and
+        // the report's set-up fields are still in the workspace; y and the
+        // scalars were saved when the block ended
+        const BInst& r = a.info[inst];
+        eta = r.eta;
+        tol_p = eps * (1.0 + r.b_norm);
+        tol_d = eps * (1.0 + r.c_norm);
+        omega = st.omega;
+        tau = st.tau;
+        sig = st.sig;
+        k = st.k;
+        t = st.t;
+        R0 = st.R0;
+        R_prev = st.R_prev;
+        restarts = st.restarts;
+        for (int i = tid; i < m; i += BS) yL[i] = a.ysave[r0 + i];
     }
     __syncthreads();
 
     const double rho = a.rho, opr = 1.0 + a.rho;
     const int E = a.eval_every;
-    int64_t k = 0;
-    double R0 = NAN, R_prev = INFINITY;
-    int restarts = 0;
+    const int64_t t_begin = t;
+    bool suspended = false;
     int status = -1;
-    int64_t t = 0;
     while (status < 0) {
         ++t;
         const bool is_eval = (t % E == 0) || (t == a.max_iter);
@@ -269,8 +311,27 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         } else {
             R_prev = R;
         }
+        // end of this call's block: the state after an evaluation and its
+        // restart decision is what the next iteration starts from
+        if (a.block_iters > 0 && t - t_begin >= a.block_iters) {
+            suspended = true;
+            break;
+        }
+    }
+    if (suspended) {
+        for (int i = tid; i < m; i += BS) a.ysave[r0 + i] = yL[i];
+        status = MIPDHG_IN_PROGRESS;
     }
     if (tid == 0) {
+        st.phase = suspended ? 1 : 2;
+        st.t = t;
+        st.k = k;
+        st.omega = omega;
+        st.tau = tau;
+        st.sig = sig;
+        st.R0 = R0;
+        st.R_prev = R_prev;
+        st.restarts = restarts;
         BInst& r = a.info[inst];
         r.status = status;
         r.restarts = restarts;
@@ -364,8 +425,9 @@ int64_t blockdiag_tile_slots(int64_t m, int64_t n, int64_t nnz) {
 struct BatchWs {
     int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
+    BState* state;
     double *d_row, *d_col, *pv, *pu, *pav, *partials, *red, *eps;
-    void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
+    void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt, *ysave;
     uint16_t *a_cl, *at_cl;
     size_t bytes;
 };
@@ -383,6 +445,7 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.tiles_a = cv.take<int32_t>(4 * max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault));
     w.tiles_at = cv.take<int32_t>(4 * max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault));
     w.info = cv.take<BInst>(B);
+    w.state = cv.take<BState>(B);
     w.eps = cv.take<double>(B);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
@@ -402,6 +465,7 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.y0 = cv.take<char>(m * ts);
     w.yhat = cv.take<char>(m * ts);
     w.bt = cv.take<char>(m * ts);
+    w.ysave = cv.take<char>(m * ts);
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
@@ -486,7 +550,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.eps, eps, (size_t)B * 8, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.col_off, bt.col_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
-    if (o.validate &&
+    if (o.validate && !o.resume &&
         (rc = validate_blockdiag(bt, rpa, rpat, w.tiles_a, w.tiles_at, w.row_off, w.col_off, w.flags, w.partials,
                                  w.red, stream)))
         return rc;
@@ -527,6 +591,10 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     a.rpo = r_p;
     a.rdo = r_d;
     a.info = w.info;
+    a.state = w.state;
+    a.ysave = (T*)w.ysave;
+    a.resume = o.resume;
+    a.block_iters = o.batch_block_iters;
     a.counter = w.counter;
     a.eps = w.eps;
     a.step_safety = o.step_safety;
@@ -706,9 +774,8 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
     if (opt->pw_ki != 0.0 || opt->pw_kd != 0.0 || opt->restart_avg || opt->step_rule)
         return set_error("the PID primal weight, restart to average and the adaptive step are single-LP options"),
                MIPDHG_ERR_UNSUPPORTED;
-    if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing || opt->resume)
-        return set_error("tracing, warm starts, kernel timing and resume are single-LP options"),
-               MIPDHG_ERR_UNSUPPORTED;
+    if (opt->trace_iters || opt->x_init || opt->y_init || opt->kernel_timing)
+        return set_error("tracing, warm starts and kernel timing are single-LP options"), MIPDHG_ERR_UNSUPPORTED;
     if (opt->precision == MIPDHG_FP32_A)
         return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
@@ -736,7 +803,7 @@ extern "C" int mipdhg_autotune_batched(const mipdhg_batch* bt, mipdhg_options* o
     if (rc) return rc;
     if (!opt) return set_error("options are NULL"), MIPDHG_ERR_INVALID_ARG;
     std::vector<mipdhg_info> info((size_t)bt->count);
-    // LDS budgets of the first launch (0: one launch); the default stays
+    // LDS budgets of the narrow launch (0: one launch); the default stays
     // unless another is more than 3 % faster, so that the choice is stable
     const int32_t cands[] = {0, 2048, 4096, 8192, 16384, 32768};
     double best = 1e300, def = 1e300;
@@ -744,6 +811,8 @@ extern "C" int mipdhg_autotune_batched(const mipdhg_batch* bt, mipdhg_options* o
     for (int32_t c : cands) {
         mipdhg_options o = *opt;
         o.batch_split = c;
+        o.resume = 0;  // whole solves from the start
+        o.batch_block_iters = 0;
         const int r = mipdhg_solve_batched(bt, &o, eps_rel, workspace, workspace_bytes, stream, x, y, z, r_p, r_d,
                                            info.data());
         if (r < 0) return r;

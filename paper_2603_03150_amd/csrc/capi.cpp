@@ -51,6 +51,7 @@ extern "C" const char* mipdhg_status_string(int code) {
         case MIPDHG_NUMERICAL: return "NUMERICAL";
         case MIPDHG_PRIMAL_INFEASIBLE: return "PRIMAL_INFEASIBLE";
         case MIPDHG_DUAL_INFEASIBLE: return "DUAL_INFEASIBLE";
+        case MIPDHG_IN_PROGRESS: return "IN_PROGRESS";
         case MIPDHG_ERR_INVALID_ARG: return "ERR_INVALID_ARG";
         case MIPDHG_ERR_BAD_CSR: return "ERR_BAD_CSR";
         case MIPDHG_ERR_TRANSPOSE: return "ERR_TRANSPOSE";

@@ -1706,6 +1706,7 @@ int check_options(const mipdhg_options* o) {
     if (o->restart_avg < 0 || o->restart_avg > 1) return set_error("restart_avg must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (o->batch_split < 0 || o->batch_split > 150 * 1024)
         return set_error("batch_split must be in [0, 153600] bytes"), MIPDHG_ERR_INVALID_ARG;
+    if (o->batch_block_iters < 0) return set_error("batch_block_iters must be >= 0"), MIPDHG_ERR_INVALID_ARG;
     if (o->step_rule < 0 || o->step_rule > 1) return set_error("step_rule must be 0 or 1"), MIPDHG_ERR_INVALID_ARG;
     if (!(o->step0 >= 0.0) || !std::isfinite(o->step0))
         return set_error("step0 must be finite and >= 0"), MIPDHG_ERR_INVALID_ARG;

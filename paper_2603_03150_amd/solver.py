@@ -274,6 +274,7 @@ class BatchSolution:
     r_p: torch.Tensor
     r_d: torch.Tensor
     infos: list
+    workspace: torch.Tensor | None = None  # holds the state a resumed call continues
 
     def split(self, batch: DeviceBatch, i: int) -> dict:
         r0, r1 = batch.row_off[i], batch.row_off[i + 1]
@@ -283,21 +284,34 @@ class BatchSolution:
 
 
 def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
-                  workspace: torch.Tensor | None = None, **opts) -> BatchSolution:
+                  workspace: torch.Tensor | None = None, resume: "BatchSolution | None" = None,
+                  **opts) -> BatchSolution:
     """Run mipdhg_solve_batched on every instance of the batch; eps is one
-    tolerance for all instances or a sequence of one per instance."""
+    tolerance for all instances or a sequence of one per instance.
+
+    resume: the BatchSolution of an earlier call on this batch with the same
+    options (batch_block_iters > 0) whose instances in progress this call
+    continues; its workspace and output tensors are reused and written in
+    place."""
     lib = _lib.load()
     o = make_options(precision, **opts)
     st = batch.struct()
     nb = C.c_size_t(0)
     _lib.check(lib.mipdhg_batch_workspace_size(C.byref(st), C.byref(o), C.byref(nb)))
     d = batch.lp.device
-    if workspace is None or workspace.numel() < nb.value:
-        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
     f64 = dict(dtype=torch.float64, device=d)
     m, n = batch.lp.m, batch.lp.n
-    x, y, z = torch.empty(n, **f64), torch.empty(m, **f64), torch.empty(n, **f64)
-    r_p, r_d = torch.empty(m, **f64), torch.empty(n, **f64)
+    if resume is not None:
+        o.resume = 1
+        workspace = resume.workspace
+        if workspace is None or workspace.numel() < nb.value:
+            raise ValueError("resume: the solution's workspace does not fit these options")
+        x, y, z, r_p, r_d = resume.x, resume.y, resume.z, resume.r_p, resume.r_d
+    else:
+        if workspace is None or workspace.numel() < nb.value:
+            workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=d)
+        x, y, z = torch.empty(n, **f64), torch.empty(m, **f64), torch.empty(n, **f64)
+        r_p, r_d = torch.empty(m, **f64), torch.empty(n, **f64)
     infos = (_lib.InfoStruct * batch.count)()
     stream = torch.cuda.current_stream(d).cuda_stream
     eps_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (batch.count,)))
@@ -305,7 +319,7 @@ def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
                                   stream, x.data_ptr(), y.data_ptr(), z.data_ptr(), r_p.data_ptr(),
                                   r_d.data_ptr(), infos)
     _lib.check(rc)
-    return BatchSolution(rc, x, y, z, r_p, r_d, _InfoList(infos))
+    return BatchSolution(rc, x, y, z, r_p, r_d, _InfoList(infos), workspace)
 
 
 class _InfoList(Sequence):

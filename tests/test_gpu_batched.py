@@ -228,3 +228,32 @@ def test_batched_autotuner_choice_is_parity_equal():
         lp = lps[i]
         ref = oracle.solve(lp.A, lp.AT, lp.b, lp.c, eps)
         assert abs(a.infos[i]["pobj"] - ref.meas.pobj) <= 1e-3 * (1 + abs(ref.meas.pobj))
+
+
+@pytest.mark.parametrize("prec,split", [("fp32", 0), ("fp64", 0), ("fp32", 4096)])
+def test_resumable_blocks_give_the_one_shot_result(prec, split):
+    # blocks of 128 iterations (two evaluations), resumed until every instance
+    # has finished: bitwise the uninterrupted solve, instance by instance
+    lps = [lpgen.cfg4_instance(900 + i, m) for i, m in enumerate(_sizes(32, 20, 1500, seed=7))]
+    batch = P.DeviceBatch.from_lps(lps)
+    eps = 1e-4
+    ref = P.solve_batched(batch, eps, prec, batch_split=split)
+    assert ref.status == 0
+    sol = P.solve_batched(batch, eps, prec, batch_split=split, batch_block_iters=128)
+    assert sol.status == P.IN_PROGRESS
+    first = [inf["status"] for inf in sol.infos]
+    assert first.count(P.IN_PROGRESS) > 0 and all(s in (0, P.IN_PROGRESS) for s in first)
+    for inf in sol.infos:  # a suspended instance stopped at the first evaluation past the block
+        assert inf["status"] == 0 or inf["iters"] == 128
+    calls = 1
+    while sol.status == P.IN_PROGRESS:
+        sol = P.solve_batched(batch, eps, prec, resume=sol, batch_split=split, batch_block_iters=128)
+        calls += 1
+        assert calls <= 200
+    assert calls == 1 + (max(inf["iters"] for inf in ref.infos) - 1) // 128
+    assert sol.status == 0
+    for key in ("x", "y", "z", "r_p", "r_d"):
+        assert torch.equal(getattr(sol, key), getattr(ref, key)), key
+    for a, b in zip(sol.infos, ref.infos):
+        assert (a["status"], a["iters"], a["restarts"]) == (b["status"], b["iters"], b["restarts"])
+        assert a["omega"] == b["omega"] and a["pobj"] == b["pobj"]
