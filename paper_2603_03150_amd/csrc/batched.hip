@@ -53,7 +53,7 @@ struct BArgs {
     V *a_vs, *at_vs;
     uint16_t *a_cl, *at_cl;  // instance-local columns of A, A^T
     T *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
-    double *d_row, *d_col, *pv, *pu, *pav;
+    double *d_row, *d_col, *pu, *pav;
     double *xo, *yo, *zo, *rpo, *rdo;
     BInst* info;
     BState* state;
@@ -85,9 +85,9 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
     int restarts;
     if (phase == 0) {
         const InstMat M{a.a_rowptr, a.a_col, a.a_val, a.at_rowptr, a.at_col, a.at_val, a.b, a.c};
-        const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pv, a.pu, a.pav, a.a_vs,
+        const InstSetup su = inst_setup<T, V, BS>(M, r0, r1, c0, c1, a.d_row, a.d_col, a.pu, a.pav, a.a_vs,
                                                   a.at_vs, a.a_cl, a.at_cl, a.bt, a.ct, a.ruiz, a.pc,
-                                                  a.power_iters, a.step_safety, sh);
+                                                  a.power_iters, a.step_safety, xbL, yL, sh);
         // the report's set-up fields are written now, so that they do not
         // stay live (in registers) across the iterations
         if (tid == 0) {
@@ -426,7 +426,7 @@ struct BatchWs {
     int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
     BState* state;
-    double *d_row, *d_col, *pv, *pu, *pav, *partials, *red, *eps;
+    double *d_row, *d_col, *pu, *pav, *partials, *red, *eps;
     void *a_vs, *at_vs, *x, *x0, *xhat, *ct, *y0, *yhat, *bt, *ysave;
     uint16_t *a_cl, *at_cl;
     size_t bytes;
@@ -449,7 +449,6 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.eps = cv.take<double>(B);
     w.d_row = cv.take<double>(m);
     w.d_col = cv.take<double>(n);
-    w.pv = cv.take<double>(n);
     w.pu = cv.take<double>(n);
     w.pav = cv.take<double>(m);
     w.partials = cv.take<double>((size_t)std::max(max_tiles(m, nnz, kTileNnzDefault, kTileRowsDefault), max_tiles(n, nnz, kTileNnzDefault, kTileRowsDefault)) + 16);
@@ -582,7 +581,6 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     a.bt = (T*)w.bt;
     a.d_row = w.d_row;
     a.d_col = w.d_col;
-    a.pv = w.pv;
     a.pu = w.pu;
     a.pav = w.pav;
     a.xo = x;

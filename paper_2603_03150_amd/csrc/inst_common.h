@@ -88,13 +88,14 @@ struct InstSetup {
 // threads.  Writes D_r, D_c (float64), the
 // scaled values of the instance's entries of A and A^T (type V) with their
 // instance-local columns (a_cl: col - c0, at_cl: row - r0), b~ and c~ (type T),
-// and returns the norms, sigma_hat, eta and omega_0.  pv, pu, pav are float64
-// scratch vectors indexed like x, x, y.
+// and returns the norms, sigma_hat, eta and omega_0.  pu, pav are float64
+// scratch vectors indexed like x, y; xl[n] and yl[m] are LDS vectors of the
+// workgroup, free during the set-up.
 template <typename T, typename V, int BS = kBatchBlock>
 __device__ InstSetup inst_setup(const InstMat& M, int r0, int r1, int c0, int c1, double* d_row, double* d_col,
-                                double* pv, double* pu, double* pav, V* a_vs, V* at_vs, uint16_t* a_cl,
+                                double* pu, double* pav, V* a_vs, V* at_vs, uint16_t* a_cl,
                                 uint16_t* at_cl, T* bt, T* ct, int ruiz, int pc, int power_iters,
-                                double step_safety, double* sh) {
+                                double step_safety, T* xl, T* yl, double* sh) {
     const int tid = threadIdx.x;
     const int m = r1 - r0, n = c1 - c0;
     double nn[2] = {0.0, 0.0}, nomax[1] = {0.0};
@@ -176,21 +177,20 @@ __device__ InstSetup inst_setup(const InstMat& M, int r0, int r1, int c0, int c1
     wg_reduce<2, 0, BS>(tn, nomax, sh);
     const double nbt = sqrt(tn[0]), nct = sqrt(tn[1]);
 
-    // power iteration in float64 with the scaling applied on the fly
-    for (int j = tid; j < n; j += BS) pv[c0 + j] = 1.0 / sqrt((double)n);
+    // power iteration on the scaled iteration copy (the values and 16-bit
+    // columns the iterations apply), as in the single-LP solve: vectors in
+    // the iterate type, held in LDS (v in xl, A~ v in yl), products and sums
+    // in float64.  u = A~^T (A~ v) overwrites v, which it no longer needs.
+    __syncthreads();  // the scaled copies above are read by other threads
+    for (int j = tid; j < n; j += BS) xl[j] = (T)(1.0 / sqrt((double)n));
     __syncthreads();
     double h = 0.0, h_m10 = 0.0;
     for (int kk = 0; kk <= power_iters; ++kk) {
         double s1[1] = {0.0};
         for (int i = tid; i < m; i += BS) {
             const int g = r0 + i;
-            double acc = 0.0;
-            for (int k = M.a_rowptr[g]; k < M.a_rowptr[g + 1]; ++k) {
-                const int j = M.a_col[k];
-                acc += M.a_val[k] * (d_col[j] * pv[j]);
-            }
-            const double t = d_row[g] * acc;
-            pav[g] = t;
+            const double t = row_dot4<double>(a_vs, a_cl, xl, M.a_rowptr[g], M.a_rowptr[g + 1]);
+            yl[i] = (T)t;
             s1[0] += t * t;
         }
         wg_reduce<1, 0, BS>(s1, nomax, sh);
@@ -200,19 +200,14 @@ __device__ InstSetup inst_setup(const InstMat& M, int r0, int r1, int c0, int c1
         double s2[1] = {0.0};
         for (int j = tid; j < n; j += BS) {
             const int g = c0 + j;
-            double acc = 0.0;
-            for (int k = M.at_rowptr[g]; k < M.at_rowptr[g + 1]; ++k) {
-                const int i = M.at_col[k];
-                acc += M.at_val[k] * (d_row[i] * pav[i]);
-            }
-            const double t = d_col[g] * acc;
-            pu[g] = t;
+            const double t = row_dot4<double>(at_vs, at_cl, yl, M.at_rowptr[g], M.at_rowptr[g + 1]);
+            xl[j] = (T)t;
             s2[0] += t * t;
         }
         wg_reduce<1, 0, BS>(s2, nomax, sh);
         const double nu = sqrt(s2[0]);
         if (nu != 0.0)
-            for (int j = tid; j < n; j += BS) pv[c0 + j] = pu[c0 + j] / nu;
+            for (int j = tid; j < n; j += BS) xl[j] = (T)((double)xl[j] / nu);
         __syncthreads();
     }
     const double sigma_hat = h;

@@ -46,7 +46,7 @@ struct UArgs {
     const int32_t *row_off, *col_off, *word_off;
     InstMat M;
     // tape: scaling, scaled values, schedule, checkpoints
-    double *d_row, *d_col, *pv, *pu, *pav;
+    double *d_row, *d_col, *pu, *pav;
     V *a_vs, *at_vs;
     uint16_t *a_cl, *at_cl;  // instance-local columns of A, A^T
     T *bt, *ct;
@@ -180,10 +180,9 @@ __device__ __forceinline__ void u_restart(const UArgs<T, V>& a, const UInst<T, V
 template <typename T, typename V, typename Acc>
 __device__ void forward_instance(const UArgs<T, V>& a, const UInst<T, V>& u, T* yL, T* xbL, double* sh) {
     const int tid = threadIdx.x, i = u.inst, B = a.B;
-    const InstSetup su = inst_setup<T, V>(a.M, u.r0, u.r1, u.c0, u.c1, a.d_row, a.d_col, a.pv, a.pu, a.pav,
+    const InstSetup su = inst_setup<T, V>(a.M, u.r0, u.r1, u.c0, u.c1, a.d_row, a.d_col, a.pu, a.pav,
                                           a.a_vs, a.at_vs, a.a_cl, a.at_cl, a.bt, a.ct, a.ruiz, a.pc,
-                                          a.power_iters,
-                                          a.step_safety, sh);
+                                          a.power_iters, a.step_safety, xbL, yL, sh);
     double omega = su.omega0;
     int epoch = 0;
     double tau, sig;
@@ -414,7 +413,7 @@ __global__ void k_zero_bytes(uint8_t* p, int64_t n) {
 // ---------------------------------------------------------------------------
 struct TapeLayout {
     int32_t *row_off, *col_off, *word_off, *counter;
-    double *d_row, *d_col, *pv, *pu, *pav, *eta, *omega0, *taus, *sigmas;
+    double *d_row, *d_col, *pu, *pav, *eta, *omega0, *taus, *sigmas;
     void *a_vs, *at_vs, *bt, *ct;
     uint16_t *a_cl, *at_cl;
     int8_t* restart;
@@ -449,7 +448,6 @@ static TapeLayout carve_tape(void* base, size_t cap, const mipdhg_batch& bt, int
     t.counter = cv.take<int32_t>(64);
     t.d_row = cv.take<double>(m);
     t.d_col = cv.take<double>(n);
-    t.pv = cv.take<double>(n);
     t.pu = cv.take<double>(n);
     t.pav = cv.take<double>(m);
     t.eta = cv.take<double>(B);
@@ -582,7 +580,6 @@ static int unrolled_impl(const mipdhg_batch& bt, const mipdhg_options& o, int K,
     a.M = InstMat{lp.a_rowptr, lp.a_col, lp.a_val, lp.at_rowptr, lp.at_col, lp.at_val, lp.b, lp.c};
     a.d_row = t.d_row;
     a.d_col = t.d_col;
-    a.pv = t.pv;
     a.pu = t.pu;
     a.pav = t.pav;
     a.a_vs = (V*)t.a_vs;
