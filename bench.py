@@ -75,13 +75,15 @@ def parse():
                     help="only a short capped solve (256 iterations) of --workload (for hardware counters)")
     ap.add_argument("--shape", default="",
                     help="SpMV shape instead of the autotuner's, e.g. spmv_kind=0,tile_nnz=4096,tile_rows=512,short_row=-1")
-    ap.add_argument("--workload", default="block_angular", choices=["power_law", "block_angular"],
-                    help="LP of the main line (the other one runs as a leg)")
+    ap.add_argument("--workload", default="block_angular", choices=["power_law", "block_angular", "batched"],
+                    help="LP of the main line (the other one runs as a leg); batched: only with --counter-summary")
     ap.add_argument("--infeas-tol", type=float, default=None,
                     help="infeasibility-certificate tolerance of the main-line solves (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only a plain device copy and a streaming read of known sizes (to calibrate hardware "
                          "byte counters)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="only one batched solve of the 4,096-LP workload (for hardware counters)")
     ap.add_argument("--counter-summary", default="",
                     help="no GPU: write profiles/traffic_<workload>.json and the profile summary of --workload "
                          "from the rocprofv3 outputs under this folder (see counter_summary)")
@@ -183,15 +185,33 @@ def short_kernel(symbol: str):
     return f"{name}<{'primal' if primal else 'dual'}>"
 
 
-def kernel_source_sha() -> str:
+BATCHED_SOURCES = ("paper_2603_03150_amd/csrc/common.h", "paper_2603_03150_amd/csrc/inst_common.h",
+                   "paper_2603_03150_amd/csrc/batched.hip")
+
+
+def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
     """Hash of the sources that define the iteration kernels: a stored
     hardware-counter record is used only while they are unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def batched_traffic_record(split: int):
+    """Measured HBM bytes of the batched launch on the 4,096-LP workload,
+    from profiles/traffic_batched.json, or None if there is none, or the
+    batched kernel's sources or the launch split differ from its own."""
+    path = os.path.join(ROOT, "profiles", "traffic_batched.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_sha(BATCHED_SOURCES) or rec.get("batch_split") != split:
+        return None
+    return rec
 
 
 def traffic_record(workload_key: str, kernel: str, shape: dict):
@@ -452,8 +472,11 @@ def diff_leg(P, torch) -> dict:
 
         def rel(a, b):
             return float(np.linalg.norm(a - b) / max(1e-300, np.linalg.norm(b)))
+        # coordinates whose final projection mask (x_j > 0) differs from the
+        # oracle's: the map is piecewise linear, its piece fixed by the masks
+        flips = int(np.count_nonzero((xk[c0:c1] > 0) != (rx > 0)))
         errs.append({"instance": i, "x_K": rel(xk[c0:c1], rx), "dL_dc": rel(gc[c0:c1], rc),
-                     "dL_db": rel(gb[r0:r1], rb)})
+                     "dL_db": rel(gb[r0:r1], rb), "final_mask_flips": flips, "n": int(c1 - c0)})
     return {"instances": 256, "K": 2000, "ckpt_every": 100, "precision": "fp32", "forward_s": t1 - t0,
             "backward_s": t2 - t1, "tape_bytes": umap.tape_bytes,
             "error_vs_fp64_oracle": {"instances": errs,
@@ -563,6 +586,7 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
     alg = sum(int(inf["iters"]) * (12.0 * lp.nnz + 28.0 * lp.n + 24.0 * lp.m) for inf, lp in zip(sol.infos, lps))
     mat_mb = 12.0 * sum(lp.nnz for lp in lps) / 1e6
     gbs = alg / dt / 1e9
+    trec = batched_traffic_record(split)
     # objectives: every instance against its planted optimum, and a sample of
     # 16 (spread over the sizes) against the oracle run to 1e-8
     x = sol.x.cpu().numpy()
@@ -581,7 +605,10 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
     return {"metric": "batched LPs/s to eps_rel=1e-4", "value": count / dt, "unit": "LPs/s",
             "cpu_baseline": cpu,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batched",
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": None if trec is None else trec["bytes_per_launch"],
+                         "traffic_over_algorithmic": None if trec is None else trec["bytes_per_launch"] / alg,
+                         "kernel": "k_batched",
                          "bytes_total": alg, "seconds": dt,
                          "note": "algorithmic bytes summed over every instance's iterations (12 nnz + 28 n + 24 m "
                                  f"each, FP32) over the launch; the batch's iteration copy of A and A^T is {mat_mb:.0f} MB "
@@ -655,6 +682,84 @@ def _counter_rows(folder: str) -> dict:
         d = out.setdefault(kern, {}).setdefault(ctr, [])
         d.append(v)
     return {k: {c: (sum(v) / len(v), len(v)) for c, v in cs.items()} for k, cs in out.items()}
+
+
+def batched_counter_summary(folder: str) -> int:
+    """Write profiles/traffic_batched.json and profiles/batched_kernels_4096.md
+    from the rocprofv3 outputs of the commands listed in them (run from the
+    repository root, outputs under `folder`): FETCH_SIZE and WRITE_SIZE of
+    the batched launch (bench.py --profile-batched, the default launch
+    split), calibrated like the plain kernels' (bench.py --calibrate-copy),
+    and the launch's kernel statistics."""
+    import csv
+    import glob
+    prof = "python3 bench.py --profile-batched"
+    cmds = {
+        "fetch": f"timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE -d {folder}/pmc_batched_FETCH_SIZE -o run "
+                 f"--output-format csv -- {prof}",
+        "write": f"timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE -d {folder}/pmc_batched_WRITE_SIZE -o run "
+                 f"--output-format csv -- {prof}",
+        "cfetch": f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d {folder}/pmc_copy_FETCH_SIZE -o run "
+                  "--output-format csv -- python3 bench.py --calibrate-copy",
+        "cwrite": f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d {folder}/pmc_copy_WRITE_SIZE -o run "
+                  "--output-format csv -- python3 bench.py --calibrate-copy",
+        "trace": f"rocprofv3 --kernel-trace --stats -d {folder}/profb_batched -o run --output-format csv -- {prof}",
+    }
+    fetch = _counter_rows(f"{folder}/pmc_batched_FETCH_SIZE")
+    write = _counter_rows(f"{folder}/pmc_batched_WRITE_SIZE")
+    cf = _counter_rows(f"{folder}/pmc_copy_FETCH_SIZE")
+    cw = _counter_rows(f"{folder}/pmc_copy_WRITE_SIZE")
+    gib = float(1 << 30)
+    probe_f = [v["FETCH_SIZE"][0] for k, v in cf.items() if "k_read_probe" in k]
+    copy_w = [v["WRITE_SIZE"][0] for k, v in cw.items() if "copyBuffer" in k]
+    if not probe_f or not copy_w:
+        raise RuntimeError("calibration kernels not found in the copy profiles")
+    ff, wf = gib / (probe_f[0] * 1024.0), gib / (copy_w[0] * 1024.0)
+    kernels = {}
+    for sym, cs in fetch.items():
+        if "k_batched" not in sym or "FETCH_SIZE" not in cs or sym not in write:
+            continue
+        fk, nd = cs["FETCH_SIZE"]
+        wk = write[sym]["WRITE_SIZE"][0]
+        kernels[sym.split("(")[0]] = {"dispatches": nd, "fetch_kib": fk, "write_kib": wk,
+                                      "bytes_per_launch": fk * 1024.0 * ff + wk * 1024.0 * wf}
+    if not kernels:
+        raise RuntimeError("k_batched not found in the counter profiles")
+    total = sum(v["bytes_per_launch"] for v in kernels.values())
+    rec = {"workload": "4096 LPs, m log-uniform [20,2000], n=2.5m, 4 nnz/col, FP32 iterates, eps_rel=1e-4",
+           "batch_split": 0, "source_sha256": kernel_source_sha(BATCHED_SOURCES),
+           "kernel_sources": list(BATCHED_SOURCES), "fetch_factor": ff, "write_factor": wf,
+           "calibration": (f"FETCH_SIZE {probe_f[0]:.1f} KiB per 1 GiB streaming read (k_read_probe), WRITE_SIZE "
+                           f"{copy_w[0]:.1f} KiB per 1 GiB device copy (__amd_rocclr_copyBuffer), bench.py "
+                           "--calibrate-copy"),
+           "commands": [cmds["fetch"], cmds["write"], cmds["cfetch"], cmds["cwrite"]], "kernels": kernels,
+           "bytes_per_launch": total}
+    with open(os.path.join(ROOT, "profiles", "traffic_batched.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    stats = []
+    for f in glob.glob(os.path.join(folder, "profb_batched", "**", "*kernel_stats.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            stats += list(csv.DictReader(fh))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Batched kernel, 4,096 LPs, FP32 iterates, eps_rel 1e-4, one launch", "",
+             "Kernel statistics (rocprofv3 --kernel-trace --stats):", "", "```", cmds["trace"], "```", "",
+             "| kernel | calls | avg ms | total ms |", "|---|---|---|---|"]
+    for r in stats[:6]:
+        lines.append(f"| `{r['Name'].split('(')[0]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    lines += ["", "## HBM-side traffic (rocprofv3 --pmc, one counter per run)", "", "```"]
+    lines += [cmds[k] for k in ("fetch", "write", "cfetch", "cwrite")]
+    lines += ["```", "", rec["calibration"] + f": factors {ff:.3f} (FETCH_SIZE) and {wf:.3f} (WRITE_SIZE).", "",
+              "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated GB per launch |", "|---|---|---|---|"]
+    for k, v in kernels.items():
+        lines.append(f"| `{k}` | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['bytes_per_launch'] / 1e9:.1f} |")
+    lines += ["", f"Kernel sources sha256 {rec['source_sha256']} ({', '.join(BATCHED_SOURCES)}); the bench's "
+              "batched leg uses this record while they are unchanged and its launch split is 0."]
+    with open(os.path.join(ROOT, "profiles", "batched_kernels_4096.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"wrote": ["profiles/traffic_batched.json", "profiles/batched_kernels_4096.md"],
+                      "bytes_per_launch": total}))
+    return 0
 
 
 def counter_summary(folder: str, workload: str, precision: str, shape_text: str) -> int:
@@ -768,7 +873,12 @@ def counter_summary(folder: str, workload: str, precision: str, shape_text: str)
 def main() -> int:
     args = parse()
     if args.counter_summary:
+        if args.workload == "batched":
+            return batched_counter_summary(args.counter_summary)
         return counter_summary(args.counter_summary, args.workload, args.precision, args.shape)
+    if args.workload == "batched":
+        print("--workload batched is for --counter-summary only", file=sys.stderr)
+        return 2
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the solver runs on a single GPU; how it would shard is described, not built)", file=sys.stderr)
@@ -782,6 +892,15 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.profile_batched:
+        lps = [lpgen.cfg4_instance(i, int(m)) for i, m in enumerate(lpgen.cfg4_sizes(args.batch_count))]
+        batch = P.DeviceBatch.from_lps(lps, "cuda:0")
+        sol = P.solve_batched(batch, args.eps, "fp32", max_iter=100_000)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_batched_count": args.batch_count, "status": sol.status,
+                          "instance_iterations": sum(int(i["iters"]) for i in sol.infos),
+                          "ms_kernel": sol.infos[0]["ms_iter"]}))
+        return 0
     if args.calibrate_copy:
         # 1 GiB read + 1 GiB written per copy, four copies; then four 1 GiB
         # streaming reads with the SpMV kernels' loads (mipdhg_read_probe)
