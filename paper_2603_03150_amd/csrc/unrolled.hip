@@ -500,7 +500,7 @@ static int check_unrolled(const mipdhg_batch* bt, const mipdhg_options* o, int K
     if (rc) return rc;
     if ((rc = check_options(o))) return rc;
     if (K < 1 || ckpt < 1) return set_error("K >= 1 and ckpt_every >= 1 required"), MIPDHG_ERR_INVALID_ARG;
-    if (o->resume) return set_error("resume is a single-LP solve option"), MIPDHG_ERR_UNSUPPORTED;
+    if (o->resume) return set_error("the unrolled map has no state to resume"), MIPDHG_ERR_UNSUPPORTED;
     if (is_general(bt->whole))
         return set_error("the general form (bounds, inequality rows) is a single-LP option"), MIPDHG_ERR_UNSUPPORTED;
     if (o->pw_ki != 0.0 || o->pw_kd != 0.0 || o->restart_avg || o->step_rule)

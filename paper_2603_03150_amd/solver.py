@@ -302,6 +302,8 @@ def solve_batched(batch: DeviceBatch, eps=1e-4, precision: str = "fp32",
     f64 = dict(dtype=torch.float64, device=d)
     m, n = batch.lp.m, batch.lp.n
     if resume is not None:
+        if not isinstance(resume, BatchSolution):
+            raise TypeError("resume takes the BatchSolution of an earlier call")
         o.resume = 1
         workspace = resume.workspace
         if workspace is None or workspace.numel() < nb.value:

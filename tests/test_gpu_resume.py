@@ -96,11 +96,15 @@ def test_resume_refuses_another_state():
         P.solve(dlp, 1e-12, "fp64", max_iter=128, resume=a, x_init=torch.zeros(lp.n))
 
 
-def test_resume_is_a_single_lp_option():
+def test_resume_is_refused_by_the_unrolled_map():
+    # the batched solve resumes its blocks (test_gpu_batched.py); the unrolled
+    # map has no state to continue
     batch = P.DeviceBatch.from_lps([lpgen.tiny(6, 15, 3, 0)])
     with pytest.raises(P.MipdhgError) as e:
-        P.solve_batched(batch, 1e-4, "fp32", resume=1)
+        P.UnrolledMap(batch, K=8, ckpt_every=4, precision="fp32", resume=1)
     assert e.value.code == -6
+    with pytest.raises(TypeError):
+        P.solve_batched(batch, 1e-4, "fp32", resume=1)
 
 
 def test_time_limit_stops_at_a_block_and_resumes_bitwise():
