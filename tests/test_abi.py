@@ -74,3 +74,36 @@ def test_host_side_argument_errors():
     # solve rejects a NULL workspace before touching any device memory
     assert lib.mipdhg_solve(C.byref(s), C.byref(o), 1e-4, None, 0, None, None, None, None, None, None,
                             None, None, None) == -1
+
+
+def test_batched_option_errors_on_the_host():
+    # a two-instance batch described on the host (device pointers never
+    # dereferenced by the workspace query); the batched options are checked
+    from paper_2603_03150_amd import _lib
+    lib = _lib.load()
+    o = _lib.OptionsStruct()
+    lib.mipdhg_default_options(C.byref(o))
+    assert o.batch_split == 0 and o.batch_block_iters == 0
+    row_off = (C.c_int32 * 3)(0, 2, 5)
+    col_off = (C.c_int32 * 3)(0, 4, 9)
+    nnz_off = (C.c_int64 * 3)(0, 6, 14)
+    bt = _lib.BatchStruct()
+    bt.count = 2
+    bt.row_off, bt.col_off, bt.nnz_off = (C.cast(v, C.c_void_p) for v in (row_off, col_off, nnz_off))
+    w = bt.whole
+    w.m, w.n, w.nnz = 5, 9, 14
+    w.a_rowptr = w.at_rowptr = w.a_col = w.a_val = w.at_col = w.at_val = w.b = w.c = 8
+    nb = C.c_size_t(0)
+    assert lib.mipdhg_batch_workspace_size(C.byref(bt), C.byref(o), C.byref(nb)) == 0 and nb.value > 0
+    for field, bad in (("batch_block_iters", -1), ("batch_split", -1), ("batch_split", 150 * 1024 + 1)):
+        lib.mipdhg_default_options(C.byref(o))
+        setattr(o, field, bad)
+        assert lib.mipdhg_batch_workspace_size(C.byref(bt), C.byref(o), C.byref(nb)) == -1, field
+        assert field.encode() in lib.mipdhg_last_error()
+    lib.mipdhg_default_options(C.byref(o))
+    o.batch_block_iters, o.batch_split = 128, 4096
+    assert lib.mipdhg_batch_workspace_size(C.byref(bt), C.byref(o), C.byref(nb)) == 0
+    # the instance offsets must end at the whole matrix's sizes
+    nnz_off[2] = 13
+    assert lib.mipdhg_batch_workspace_size(C.byref(bt), C.byref(o), C.byref(nb)) == -1
+    assert lib.mipdhg_status_string(6) == b"IN_PROGRESS"
