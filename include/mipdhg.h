@@ -272,8 +272,11 @@ typedef struct mipdhg_options {
      * the same batch, workspace, output arrays and options (eps_rel and
      * max_iter may change) continues every instance in progress, skips the
      * finished ones (their outputs and reports stand) and gives bitwise the
-     * result of one uninterrupted solve.  A resumed call skips the device
-     * validation the first call did.  0 = run every instance to the end.  [0] */
+     * result of one uninterrupted solve.  A workspace that does not hold
+     * this batch's state under these options (checked by a fingerprint of
+     * the offsets and options) is INVALID_ARG, and the state is left as it
+     * was.  A resumed call skips the device validation the first call did.
+     * 0 = run every instance to the end.                                    [0] */
     int32_t batch_block_iters;
 } mipdhg_options;
 

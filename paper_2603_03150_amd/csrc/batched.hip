@@ -423,6 +423,7 @@ int64_t blockdiag_tile_slots(int64_t m, int64_t n, int64_t nnz) {
 }
 
 struct BatchWs {
+    uint64_t* hdr;  // {marker, fingerprint} of the state the workspace holds
     int32_t *order, *row_off, *col_off, *counter, *flags, *tiles_a, *tiles_at;
     BInst* info;
     BState* state;
@@ -437,6 +438,7 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     BatchWs w;
     const size_t vs = prec == MIPDHG_FP64 ? 8 : (prec == MIPDHG_FP32_BF16A ? 2 : 4);
     const size_t ts = prec == MIPDHG_FP64 ? 8 : 4;
+    w.hdr = cv.take<uint64_t>(4);
     w.order = cv.take<int32_t>(B);
     w.row_off = cv.take<int32_t>(B + 1);
     w.col_off = cv.take<int32_t>(B + 1);
@@ -468,6 +470,30 @@ static BatchWs carve_batch(void* base, size_t cap, int64_t B, int64_t m, int64_t
     w.bytes = (cv.off + 255) & ~size_t(255);
     return w;
 }
+
+// Identity of a batched solve's state in its workspace: the batch's sizes
+// and offsets and every option the iterations depend on (not eps_rel,
+// max_iter, batch_block_iters, validate or resume).  FNV-1a over the fields.
+static uint64_t batch_fingerprint(const mipdhg_batch& bt, const mipdhg_options& o) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t nb) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < nb; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    const int64_t sz[4] = {bt.count, bt.whole.m, bt.whole.n, bt.whole.nnz};
+    mix(sz, sizeof(sz));
+    mix(bt.row_off, ((size_t)bt.count + 1) * sizeof(int32_t));
+    mix(bt.col_off, ((size_t)bt.count + 1) * sizeof(int32_t));
+    mix(bt.nnz_off, ((size_t)bt.count + 1) * sizeof(int64_t));
+    const int32_t iv[8] = {o.precision, o.ruiz_iters, o.pock_chambolle, o.power_iters,
+                           o.eval_every, o.halpern, o.restarts, o.batch_split};
+    mix(iv, sizeof(iv));
+    const double dv[6] = {o.step_safety, o.reflect_rho, o.beta_suff, o.beta_nec, o.beta_art, o.pw_theta};
+    mix(dv, sizeof(dv));
+    return h;
+}
+
+constexpr uint64_t kBatchStateMarker = 0x6d69706468672d62ull;
 
 static int check_batch(const mipdhg_batch* bt) {
     if (!bt) return set_error("batch is NULL"), MIPDHG_ERR_INVALID_ARG;
@@ -503,6 +529,18 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
     if (w.bytes > ws_bytes)
         return set_error("workspace too small: %zu bytes given, %zu needed", ws_bytes, w.bytes), MIPDHG_ERR_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return set_error("workspace must be 256-byte aligned"), MIPDHG_ERR_INVALID_ARG;
+    // a resume continues only the state of this batch under these options;
+    // the header is invalid while a call runs and valid once it returns
+    const uint64_t fp = batch_fingerprint(bt, o);
+    uint64_t hdr_in[2] = {0, 0};
+    const uint64_t hdr_running[2] = {0, 0}, hdr_done[2] = {kBatchStateMarker, fp};
+    if (o.resume) {
+        MIP_HIP(hipMemcpyAsync(hdr_in, w.hdr, sizeof(hdr_in), hipMemcpyDeviceToHost, stream));
+        MIP_HIP(hipStreamSynchronize(stream));
+        if (hdr_in[0] != kBatchStateMarker || hdr_in[1] != fp)
+            return set_error("resume: the workspace does not hold the state of this batch with these options"),
+                   MIPDHG_ERR_INVALID_ARG;
+    }
     int max_m = 0, max_n = 0;
     for (int i = 0; i < B; ++i) {
         max_m = std::max(max_m, bt.row_off[i + 1] - bt.row_off[i]);
@@ -545,6 +583,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
             sm_n = std::max(sm_n, bt.col_off[order[k] + 1] - bt.col_off[order[k]]);
         }
     }
+    MIP_HIP(hipMemcpyAsync(w.hdr, hdr_running, sizeof(hdr_running), hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.order, order.data(), B * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.row_off, bt.row_off, (B + 1) * 4, hipMemcpyHostToDevice, stream));
     MIP_HIP(hipMemcpyAsync(w.eps, eps, (size_t)B * 8, hipMemcpyHostToDevice, stream));
@@ -695,6 +734,7 @@ static int batched_impl(const mipdhg_batch& bt, const mipdhg_options& o, const d
         MIP_HIP(hipStreamSynchronize(side.s));
     }
     MIP_HIP(hipEventRecord(e1, stream));
+    MIP_HIP(hipMemcpyAsync(w.hdr, hdr_done, sizeof(hdr_done), hipMemcpyHostToDevice, stream));
     std::vector<BInst> res(B);
     MIP_HIP(hipMemcpyAsync(res.data(), w.info, sizeof(BInst) * B, hipMemcpyDeviceToHost, stream));
     MIP_HIP(hipStreamSynchronize(stream));

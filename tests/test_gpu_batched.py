@@ -257,3 +257,29 @@ def test_resumable_blocks_give_the_one_shot_result(prec, split):
     for a, b in zip(sol.infos, ref.infos):
         assert (a["status"], a["iters"], a["restarts"]) == (b["status"], b["iters"], b["restarts"])
         assert a["omega"] == b["omega"] and a["pobj"] == b["pobj"]
+
+
+def test_resume_refuses_a_workspace_without_this_batchs_state():
+    lps = [lpgen.cfg4_instance(950 + i, m) for i, m in enumerate([30, 80, 200])]
+    batch = P.DeviceBatch.from_lps(lps)
+    ref = P.solve_batched(batch, 1e-4, "fp64")
+    first = P.solve_batched(batch, 1e-4, "fp64", batch_block_iters=64)
+    assert first.status == P.IN_PROGRESS
+    # a zeroed workspace holds no state
+    blank = P.BatchSolution(0, first.x.clone(), first.y.clone(), first.z.clone(), first.r_p.clone(),
+                            first.r_d.clone(), [], torch.zeros_like(first.workspace))
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp64", resume=blank, batch_block_iters=64)
+    assert e.value.code == -1
+    # the state of the batch under other options
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, 1e-4, "fp64", resume=first, batch_block_iters=64, ruiz_iters=5)
+    assert e.value.code == -1
+    # the refused calls left the state as it was: resuming it gives the one-shot result
+    sol, calls = first, 1
+    while sol.status == P.IN_PROGRESS:
+        sol = P.solve_batched(batch, 1e-4, "fp64", resume=sol, batch_block_iters=64)
+        calls += 1
+        assert calls <= 500
+    assert torch.equal(sol.x, ref.x) and torch.equal(sol.y, ref.y)
+    assert [i["iters"] for i in sol.infos] == [i["iters"] for i in ref.infos]
