@@ -184,7 +184,7 @@ def test_step_size_hand_histories():
     assert step_size(1000.0, _hist(down(999.0), 1000.0), pc) == 0.95
     # the change is taken against the entry ten iterations back, in either direction
     assert step_size(1000.0, _hist(up(1001.0), 1000.0), pc) == 0.95
-    # too short a history to judge, and a zero estimate
+    # too short a history to decide, and a zero estimate
     assert step_size(0.8, [0.1, 0.8], pc) == 0.95 / 0.8
     assert step_size(0.0, _hist(0.0, 0.0), pc) == 0.95
     assert step_size(0.8, _hist(1.0 - 2.0 ** -9, 1.0), OracleOptions(step_safety=0.5)) == 0.5
