@@ -283,3 +283,21 @@ def test_resume_refuses_a_workspace_without_this_batchs_state():
         assert calls <= 500
     assert torch.equal(sol.x, ref.x) and torch.equal(sol.y, ref.y)
     assert [i["iters"] for i in sol.infos] == [i["iters"] for i in ref.infos]
+
+
+def test_resume_takes_a_new_tolerance():
+    # eps_rel may change between calls: a first block at 1e-4 in which no
+    # instance finishes, then the rest at 1e-6, is the one-shot 1e-6 solve
+    lps = [lpgen.cfg4_instance(980 + i, m) for i, m in enumerate(_sizes(12, 100, 600, seed=8))]
+    batch = P.DeviceBatch.from_lps(lps)
+    ref = P.solve_batched(batch, 1e-6, "fp64")
+    assert ref.status == 0
+    sol = P.solve_batched(batch, 1e-4, "fp64", batch_block_iters=64)
+    assert all(inf["status"] == P.IN_PROGRESS and inf["iters"] == 64 for inf in sol.infos)
+    calls = 1
+    while sol.status == P.IN_PROGRESS:
+        sol = P.solve_batched(batch, 1e-6, "fp64", resume=sol, batch_block_iters=256)
+        calls += 1
+        assert calls <= 500
+    assert torch.equal(sol.x, ref.x) and torch.equal(sol.y, ref.y) and torch.equal(sol.z, ref.z)
+    assert [i["iters"] for i in sol.infos] == [i["iters"] for i in ref.infos]
