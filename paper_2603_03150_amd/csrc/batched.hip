@@ -816,6 +816,12 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
         return set_error("tracing, warm starts and kernel timing are single-LP options"), MIPDHG_ERR_UNSUPPORTED;
     if (opt->precision == MIPDHG_FP32_A)
         return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
+    // the batched iterations keep x and y themselves (not relative to an
+    // anchor whose residuals are taken in float64), so their fixed point is
+    // that of the rounded matrix; BF16 rounding of the values leaves the
+    // original LP's residuals near 2e-3, above any useful tolerance
+    if (opt->precision == MIPDHG_FP32_BF16A)
+        return set_error("BF16 matrix values are a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
@@ -824,9 +830,6 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
         case MIPDHG_FP32:
             return batched_impl<float, float, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                       r_d, info);
-        case MIPDHG_FP32_BF16A:
-            return batched_impl<float, uint16_t, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
-                                                         r_p, r_d, info);
         default:
             return batched_impl<float, float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                      r_d, info);

@@ -301,3 +301,31 @@ def test_resume_takes_a_new_tolerance():
         assert calls <= 500
     assert torch.equal(sol.x, ref.x) and torch.equal(sol.y, ref.y) and torch.equal(sol.z, ref.z)
     assert [i["iters"] for i in sol.infos] == [i["iters"] for i in ref.infos]
+
+
+def test_batched_all_fp32_mode_reaches_tolerance():
+    # FP32 sums as well as FP32 storage: every instance meets the Section 2
+    # tests when re-measured in float64 on the host, with the planted-KKT
+    # objective bound
+    prec = "fp32acc32"
+    lps = [lpgen.cfg4_instance(1100 + i, m) for i, m in enumerate(_sizes(24, 20, 1000, seed=9))]
+    batch = P.DeviceBatch.from_lps(lps)
+    eps = 1e-4
+    sol = P.solve_batched(batch, eps, prec, max_iter=200_000)
+    assert sol.status == 0
+    for i, lp in enumerate(lps):
+        got = sol.split(batch, i)
+        x, y = _np(got["x"]), _np(got["y"])
+        assert _tests_hold(lp, x, y, eps), (prec, i)
+        err, bound = objective_bound(lp, x, y)
+        assert err <= bound * (1 + 1e-9) + 1e-12, (prec, i, err, bound)
+
+
+def test_batched_refuses_bf16_values():
+    # the batched iterations are not anchor-relative: with BF16 values every
+    # instance of this batch stalled near rel r_P 2e-3 (the rounding floor)
+    batch = P.DeviceBatch.from_lps([lpgen.cfg4_instance(1200, 40)])
+    for prec in ("bf16", "fp32a"):
+        with pytest.raises(P.MipdhgError) as e:
+            P.solve_batched(batch, 1e-4, prec)
+        assert e.value.code == -6, prec
