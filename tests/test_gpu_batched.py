@@ -329,3 +329,25 @@ def test_batched_refuses_bf16_values():
         with pytest.raises(P.MipdhgError) as e:
             P.solve_batched(batch, 1e-4, prec)
         assert e.value.code == -6, prec
+
+
+def test_batched_extreme_instance_sizes():
+    # a one-row simplex LP (optimum min_j c_j), a dense 4 x 10 instance and one
+    # of 10,000 x 25,000 (140 KB of vectors in LDS, near the 150 KB limit) in
+    # one FP32 launch; the same batch in FP64 needs twice that LDS: refused
+    simplex = lpgen.simplex_lp(np.array([0.7, -0.3, 1.2, 0.4]))
+    lps = [simplex, lpgen.cfg4_instance(1300, 4), lpgen.cfg4_instance(1301, 10000)]
+    batch = P.DeviceBatch.from_lps(lps)
+    eps = 1e-4
+    sol = P.solve_batched(batch, eps, "fp32", max_iter=200_000)
+    assert sol.status == 0
+    for i, lp in enumerate(lps):
+        got = sol.split(batch, i)
+        x, y = _np(got["x"]), _np(got["y"])
+        assert _tests_hold(lp, x, y, eps), i
+        err, bound = objective_bound(lp, x, y)
+        assert err <= bound * (1 + 1e-9) + 1e-12, (i, err, bound)
+    assert abs(sol.infos[0]["pobj"] - (-0.3)) <= 1e-3
+    with pytest.raises(P.MipdhgError) as e:
+        P.solve_batched(batch, eps, "fp64")
+    assert e.value.code == -6
