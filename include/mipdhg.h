@@ -381,11 +381,11 @@ int mipdhg_batch_workspace_size(const mipdhg_batch *batch, const mipdhg_options 
  * (nullable) is a HOST array of `count` reports.  The return value is the
  * largest status over the instances (0 when all are OPTIMAL) or an error.
  * An instance needs (m_i + n_i) * sizeof(iterate) bytes of LDS, at most
- * 150 KiB; larger instances return MIPDHG_ERR_UNSUPPORTED.  Precision
- * FP64, FP32 or FP32_ACC32: the batched iterations hold x and y themselves,
- * not relative to an anchor with float64 residuals, so BF16 values (whose
- * rounding leaves the original LP's residuals near 2e-3) and FP32_A are
- * UNSUPPORTED.  Tracing, warm starts and kernel timing are not available here.  With batch_block_iters
+ * 150 KiB; larger instances return MIPDHG_ERR_UNSUPPORTED.  Every precision
+ * but FP32_A (UNSUPPORTED); as in the single-LP solve, each instance's
+ * iteration is held relative to its epoch's anchor, whose residuals are
+ * formed in float64 on `whole`.  Tracing, warm starts and kernel timing are
+ * not available here.  With batch_block_iters
  * the solve runs in resumable blocks: the return value is
  * MIPDHG_IN_PROGRESS while any instance is unfinished. */
 int mipdhg_solve_batched(const mipdhg_batch *batch, const mipdhg_options *opt, const double *eps_rel,

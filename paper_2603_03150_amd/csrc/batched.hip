@@ -52,6 +52,9 @@ struct BArgs {
     const double *b, *c;
     V *a_vs, *at_vs;
     uint16_t *a_cl, *at_cl;  // instance-local columns of A, A^T
+    // the state relative to the epoch's anchor (x0, y0): x holds u = x - x0
+    // (y's v = y - y0 is in LDS), ct and bt the anchor's residuals
+    // c~ - A~^T y0 and b~ - A~ x0
     T *x, *x0, *xhat, *ct, *y0, *yhat, *bt;
     double *d_row, *d_col, *pu, *pav;
     double *xo, *yo, *zo, *rpo, *rdo;
@@ -148,7 +151,6 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         const bool is_eval = (t % E == 0) || (t == a.max_iter);
         const bool first = (k == 0);
         const double w = a.halpern ? (double)(k + 1) / (double)(k + 2) : 1.0;
-        const double omw = 1.0 - w;
         double q[4] = {0.0, 0.0, 0.0, 0.0};
         // primal step over the columns (rows of A^T); float64 arithmetic,
         // stored in T.  The next row's bounds and vector entries are loaded
@@ -166,7 +168,7 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
         for (int j = tid; j < n; j += BS) {
             const int g = c0 + j;
             const int b0 = nb0, b1 = nb1;
-            const double o = (double)nx, an = (double)nx0, ctg = (double)nct;
+            const double u = (double)nx, x0 = (double)nx0, rc = (double)nct;
             {
                 const int gn = c0 + min(j + BS, n - 1);
                 nb0 = a.at_rowptr[gn];
@@ -175,57 +177,58 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
                 nx0 = a.x0[gn];
                 nct = a.ct[gn];
             }
+            // u = x - x0, v = y - y0 (in LDS), rc = c~ - A~^T y0:
+            // x_hat = x0 + max(u - tau (rc - A~^T v), -x0)
             const Acc s = row_dot4<Acc>(a.at_vs, a.at_cl, yL, b0, b1);
-            double hh = o - tau * (ctg - (double)s);
-            hh = hh < 0.0 ? 0.0 : hh;
-            xbL[j] = (T)(2.0 * hh - o);
-            a.x[g] = (T)(w * (opr * hh - rho * o) + omw * an);
+            double uh = u - tau * (rc - (double)s);
+            uh = uh < -x0 ? -x0 : uh;
+            xbL[j] = (T)(2.0 * uh - u);  // x_bar - x0
+            a.x[g] = (T)(w * (opr * uh - rho * u));
             if (first || is_eval) {
-                const double d = o - hh;
+                const double d = u - uh;
                 q[0] += d * d;
             }
             if (is_eval) {
-                const double d = hh - an;
-                q[1] += d * d;
-                a.xhat[g] = (T)hh;
-                a.xo[g] = a.d_col[g] * hh;
+                q[1] += uh * uh;
+                const double xh = x0 + uh;
+                a.xhat[g] = (T)xh;
+                a.xo[g] = a.d_col[g] * xh;
             }
         }
         __syncthreads();
         // dual step over the rows of A, with the same prefetch
         int mb0 = 0, mb1 = 0;
-        T my0 = 0, mbt = 0;
+        T mbt = 0;
         if (m > 0) {
             const int g = r0 + min(tid, m - 1);
             mb0 = a.a_rowptr[g];
             mb1 = a.a_rowptr[g + 1];
-            my0 = a.y0[g];
             mbt = a.bt[g];
         }
         for (int i = tid; i < m; i += BS) {
             const int g = r0 + i;
             const int b0 = mb0, b1 = mb1;
-            const double an = (double)my0, btg = (double)mbt;
+            const double rb = (double)mbt;
             {
                 const int gn = r0 + min(i + BS, m - 1);
                 mb0 = a.a_rowptr[gn];
                 mb1 = a.a_rowptr[gn + 1];
-                my0 = a.y0[gn];
                 mbt = a.bt[gn];
             }
+            // rb = b~ - A~ x0: y_hat = y0 + v + sigma (rb - A~ (x_bar - x0))
             const Acc s = row_dot4<Acc>(a.a_vs, a.a_cl, xbL, b0, b1);
-            const double o = (double)yL[i];
-            const double hh = o + sig * (btg - (double)s);
-            yL[i] = (T)(w * (opr * hh - rho * o) + omw * an);
+            const double v = (double)yL[i];
+            const double vh = v + sig * (rb - (double)s);
+            yL[i] = (T)(w * (opr * vh - rho * v));
             if (first || is_eval) {
-                const double d = o - hh;
+                const double d = v - vh;
                 q[2] += d * d;
             }
             if (is_eval) {
-                const double d = hh - an;
-                q[3] += d * d;
-                a.yhat[g] = (T)hh;
-                a.yo[g] = a.d_row[g] * hh;
+                q[3] += vh * vh;
+                const double yh = (double)a.y0[g] + vh;
+                a.yhat[g] = (T)yh;
+                a.yo[g] = a.d_row[g] * yh;
             }
         }
         __syncthreads();
@@ -294,15 +297,35 @@ __device__ void solve_instance(const BArgs<T, V>& a, int inst, T* yL, T* xbL, do
                 tau = eta / omega;
                 sig = eta * omega;
             }
+            // the anchor moves to (x_hat, y_hat), the state to 0, and the new
+            // anchor's residuals are formed in float64 on the caller's
+            // matrix: rb = D_r (b - A D_c x0), rc = D_c (c - A^T D_r y0)
             for (int j = tid; j < n; j += BS) {
-                const T v = a.xhat[c0 + j];
-                a.x[c0 + j] = v;
-                a.x0[c0 + j] = v;
+                a.x0[c0 + j] = a.xhat[c0 + j];
+                a.x[c0 + j] = (T)0;
             }
             for (int i = tid; i < m; i += BS) {
-                const T v = a.yhat[r0 + i];
-                yL[i] = v;
-                a.y0[r0 + i] = v;
+                a.y0[r0 + i] = a.yhat[r0 + i];
+                yL[i] = (T)0;
+            }
+            __syncthreads();
+            for (int i = tid; i < m; i += BS) {
+                const int g = r0 + i;
+                double sa = 0.0;
+                for (int kz = a.a_rowptr[g]; kz < a.a_rowptr[g + 1]; ++kz) {
+                    const int jc = a.a_col[kz];
+                    sa += a.a_val[kz] * (a.d_col[jc] * (double)a.x0[jc]);
+                }
+                a.bt[g] = (T)(a.d_row[g] * (a.b[g] - sa));
+            }
+            for (int j = tid; j < n; j += BS) {
+                const int g = c0 + j;
+                double sa = 0.0;
+                for (int kz = a.at_rowptr[g]; kz < a.at_rowptr[g + 1]; ++kz) {
+                    const int ir = a.at_col[kz];
+                    sa += a.at_val[kz] * (a.d_row[ir] * (double)a.y0[ir]);
+                }
+                a.ct[g] = (T)(a.d_col[g] * (a.c[g] - sa));
             }
             k = 0;
             R_prev = INFINITY;
@@ -816,12 +839,6 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
         return set_error("tracing, warm starts and kernel timing are single-LP options"), MIPDHG_ERR_UNSUPPORTED;
     if (opt->precision == MIPDHG_FP32_A)
         return set_error("FP32_A is a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
-    // the batched iterations keep x and y themselves (not relative to an
-    // anchor whose residuals are taken in float64), so their fixed point is
-    // that of the rounded matrix; BF16 rounding of the values leaves the
-    // original LP's residuals near 2e-3, above any useful tolerance
-    if (opt->precision == MIPDHG_FP32_BF16A)
-        return set_error("BF16 matrix values are a single-LP precision mode"), MIPDHG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     switch (opt->precision) {
         case MIPDHG_FP64:
@@ -830,6 +847,9 @@ extern "C" int mipdhg_solve_batched(const mipdhg_batch* bt, const mipdhg_options
         case MIPDHG_FP32:
             return batched_impl<float, float, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                       r_d, info);
+        case MIPDHG_FP32_BF16A:
+            return batched_impl<float, uint16_t, double>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z,
+                                                         r_p, r_d, info);
         default:
             return batched_impl<float, float, float>(*bt, *opt, eps_rel, workspace, workspace_bytes, s, x, y, z, r_p,
                                                      r_d, info);
