@@ -567,6 +567,22 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
     dt = time.perf_counter() - t0
     iters = np.array([inf["iters"] for inf in sol.infos])
     solved = sum(1 for inf in sol.infos if inf["status"] == 0)
+    # the same batch with BF16 matrix values (a side record, not the headline)
+    ws16 = torch.empty(P.batch_workspace_bytes(batch, "bf16"), dtype=torch.uint8, device="cuda:0")
+    P.solve_batched(batch, eps, "bf16", workspace=ws16, max_iter=100_000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol16 = P.solve_batched(batch, eps, "bf16", workspace=ws16, max_iter=100_000)
+    torch.cuda.synchronize()
+    dt16 = time.perf_counter() - t1
+    x16 = sol16.x.cpu().numpy()
+    err16 = max(abs(float(lp.c @ x16[batch.col_off[i]:batch.col_off[i + 1]]) - lp.p_star) / max(1.0, abs(lp.p_star))
+                for i, lp in enumerate(lps))
+    bf16_rec = {"value": count / dt16, "unit": "LPs/s", "seconds": dt16,
+                "solved": sum(1 for inf in sol16.infos if inf["status"] == 0),
+                "iters_p50": float(np.median([inf["iters"] for inf in sol16.infos])),
+                "max_rel_obj_err_vs_planted": err16}
+    del ws16
     # plain FP64 path, one LP at a time, on every (count/sample)-th instance by size
     order = np.argsort(sizes, kind="stable")
     pick = order[np.linspace(0, count - 1, sample).round().astype(int)]
@@ -620,6 +636,7 @@ def batched_leg(P, torch, count: int, sample: int, eps: float) -> dict:
                                      "oracle_status": [int(st) for st, _ in refs],
                                      "reference": "objective of the oracle run to 1e-8"},
             "count": count, "solved": solved, "seconds": dt, "batch_split": split, "autotune_s": tune_s,
+            "bf16_values": bf16_rec,
             "iters_p50": float(np.percentile(iters, 50)), "iters_p99": float(np.percentile(iters, 99)),
             "plain_fp64_lps_per_s": plain_lps, "plain_sample": int(sample),
             "speedup_vs_plain": (count / dt) / plain_lps, "generate_s": gen_s,
