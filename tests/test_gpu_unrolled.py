@@ -179,10 +179,11 @@ def test_fp64_gradient_matches_oracle_at_the_timed_size():
     # the differentiation workload's own instances (500 x 1,500) and K = 2,000
     # with checkpoints every 100, in FP64, against the oracle's reverse mode.
     # Measured: x_K agrees to about 1e-12 and dL/db to about 1e-14 on all
-    # three; dL/dc to 7e-12 on instance 255 but to 2.9e-7 and 6.5e-6 on
-    # instances 0 and 85, the difference spread over many columns (entries
-    # reach 2e4).  The cause is not established; cancellation in the
-    # 2,000-term sum for c would fit.  The bounds are 1e-9 and 1e-4.
+    # three; dL/dc (norm about 1e5, against 25 for dL/db) to 7e-12 on
+    # instance 255 but to 2.9e-7 and 6.5e-6 on instances 0 and 85, the
+    # difference spread over many columns.  Its cause is open: the sum for
+    # dL/dc has no cancellation, and a 1e-14 change of c flips no projection
+    # mask in the oracle.  The bounds are 1e-9 and 1e-4.
     lps, ws = [], []
     for i in (0, 85, 255):
         lp, w = lpgen.cfg5_instance(i)
