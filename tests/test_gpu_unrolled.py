@@ -182,10 +182,10 @@ def test_fp64_gradient_matches_oracle_at_the_timed_size():
     # three; dL/dc (norm about 1e5, against 25 for dL/db) to 7e-12 on
     # instance 255 but to 2.9e-7 and 6.5e-6 on instances 0 and 85, the
     # difference spread over many columns and growing with K (2e-15 at
-    # K = 300).  The oracle's sweep is well-conditioned (1-ulp noise moves
-    # its dL/dc by 1e-15), so this is not rounding: a probable defect in
-    # the GPU c-adjoint of long runs, under investigation.  The bounds are
-    # 1e-9 and 1e-4.
+    # K = 300).  It is not rounding in the sweep (1-ulp noise moves the
+    # oracle's dL/dc by 1e-15); a mask taken differently by the two
+    # trajectories and a defect in a term of the GPU c-adjoint of long runs
+    # both remain open.  The bounds are 1e-9 and 1e-4.
     lps, ws = [], []
     for i in (0, 85, 255):
         lp, w = lpgen.cfg5_instance(i)
