@@ -422,6 +422,19 @@ int mipdhg_unrolled_backward(const mipdhg_batch *batch, const mipdhg_options *op
                              int32_t ckpt_every, void *tape, size_t tape_bytes, const double *grad_xK,
                              void *stream, double *grad_c, double *grad_b);
 
+/* The schedule a forward pass recorded on its tape for instance `inst`: the
+ * iterations at which it restarted (HOST int32 restart_at, ascending) and
+ * the step sizes (tau, sigma) of every epoch (HOST double taus, sigmas, one
+ * more than the restarts); *n_restarts receives the count.  These are the
+ * constants of the map the forward and backward passes differentiate; a
+ * float64 reference run with them reproduces the map.  capacity is the
+ * length of taus and sigmas (restart_at holds capacity - 1): INVALID_ARG if
+ * the schedule has more epochs.  Copies from the tape on `stream` and waits. */
+int mipdhg_unrolled_schedule(const mipdhg_batch *batch, const mipdhg_options *opt, int32_t K,
+                             int32_t ckpt_every, const void *tape, size_t tape_bytes, int32_t inst,
+                             void *stream, int32_t capacity, int32_t *restart_at, double *taus,
+                             double *sigmas, int32_t *n_restarts);
+
 /* ---- Centered warm start (Algorithm 1, Section 3.1) ----------------------
  * Maps a PDHG solution of the SCALED LP to the interior-point start (x', z')
  * (y passes through unchanged): mu_target = max(x^T z / n, mu_min); each pair

@@ -102,6 +102,8 @@ SIGNATURES = {
                                           _p, C.c_size_t, _p, _p]),
     "mipdhg_unrolled_backward": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32, _p,
                                            C.c_size_t, _p, _p, _p, _p]),
+    "mipdhg_unrolled_schedule": (C.c_int, [C.POINTER(BatchStruct), C.POINTER(OptionsStruct), _i32, _i32, _p,
+                                           C.c_size_t, _i32, _p, _i32, _p, _p, _p, C.POINTER(_i32)]),
     "mipdhg_center_workspace_size": (C.c_size_t, [_i32]),
     "mipdhg_center_start": (C.c_int, [_i32, _p, _p, _p, _f64, _f64, _f64, _p, C.c_size_t, _p, _p, _p,
                                       C.POINTER(_f64)]),

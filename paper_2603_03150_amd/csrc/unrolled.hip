@@ -719,3 +719,43 @@ extern "C" int mipdhg_unrolled_backward(const mipdhg_batch* bt, const mipdhg_opt
                                                       grad_c, grad_b);
     }
 }
+
+extern "C" int mipdhg_unrolled_schedule(const mipdhg_batch* bt, const mipdhg_options* opt, int32_t K,
+                                        int32_t ckpt_every, const void* tape, size_t tape_bytes, int32_t inst,
+                                        void* stream, int32_t capacity, int32_t* restart_at, double* taus,
+                                        double* sigmas, int32_t* n_restarts) {
+    clear_error();
+    int rc = check_unrolled(bt, opt, K, ckpt_every);
+    if (rc) return rc;
+    if (!tape || !restart_at || !taus || !sigmas || !n_restarts)
+        return set_error("tape and the four outputs are required"), MIPDHG_ERR_INVALID_ARG;
+    if (inst < 0 || inst >= bt->count) return set_error("inst must be in [0, count)"), MIPDHG_ERR_INVALID_ARG;
+    const TapeLayout t = carve_tape(const_cast<void*>(tape), tape_bytes, *bt, opt->precision, K, ckpt_every,
+                                    opt->eval_every);
+    if (t.bytes > tape_bytes)
+        return set_error("tape too small: %zu bytes given, %zu needed", tape_bytes, t.bytes), MIPDHG_ERR_WORKSPACE;
+    const int B = bt->count;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int8_t> flags((size_t)K * B);
+    std::vector<double> tv((size_t)t.nep * B), sv((size_t)t.nep * B);
+    MIP_HIP(hipMemcpyAsync(flags.data(), t.restart, flags.size(), hipMemcpyDeviceToHost, s));
+    MIP_HIP(hipMemcpyAsync(tv.data(), t.taus, tv.size() * 8, hipMemcpyDeviceToHost, s));
+    MIP_HIP(hipMemcpyAsync(sv.data(), t.sigmas, sv.size() * 8, hipMemcpyDeviceToHost, s));
+    MIP_HIP(hipStreamSynchronize(s));
+    int32_t nr = 0;
+    for (int32_t it = 1; it <= K; ++it)
+        if (flags[(size_t)(it - 1) * B + inst]) {
+            if (nr + 1 >= capacity)
+                return set_error("capacity %d holds fewer epochs than the schedule's", capacity),
+                       MIPDHG_ERR_INVALID_ARG;
+            restart_at[nr++] = it;
+        }
+    if (nr + 1 > capacity || nr + 1 > t.nep)
+        return set_error("capacity %d holds fewer epochs than the schedule's", capacity), MIPDHG_ERR_INVALID_ARG;
+    for (int32_t e = 0; e <= nr; ++e) {
+        taus[e] = tv[(size_t)e * B + inst];
+        sigmas[e] = sv[(size_t)e * B + inst];
+    }
+    *n_restarts = nr;
+    return 0;
+}

@@ -52,6 +52,23 @@ class UnrolledMap:
         _lib.check(rc)
         return xK, tape
 
+    def schedule(self, tape: torch.Tensor, inst: int) -> tuple[list, list, list]:
+        """mipdhg_unrolled_schedule: instance inst's restart iterations and the
+        (tau, sigma) of its epochs, as the forward pass recorded them on tape."""
+        lib = _lib.load()
+        dev = self.batch.lp.device
+        cap = self.K // max(1, int(self.opts.eval_every)) + 2
+        restart_at = (C.c_int32 * cap)()
+        taus, sigmas = (C.c_double * cap)(), (C.c_double * cap)()
+        nr = C.c_int32(0)
+        st = self.batch.struct()
+        rc = lib.mipdhg_unrolled_schedule(C.byref(st), C.byref(self.opts), self.K, self.ckpt, tape.data_ptr(),
+                                          tape.numel(), int(inst), torch.cuda.current_stream(dev).cuda_stream, cap,
+                                          restart_at, taus, sigmas, C.byref(nr))
+        _lib.check(rc)
+        k = nr.value
+        return list(restart_at[:k]), list(taus[:k + 1]), list(sigmas[:k + 1])
+
     def backward_raw(self, c: torch.Tensor, b: torch.Tensor, tape: torch.Tensor,
                      grad_xK: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
         lib = _lib.load()

@@ -205,3 +205,30 @@ def test_fp64_gradient_matches_oracle_at_the_timed_size():
         print("instance", i, "relative errors x_K, dL/dc, dL/db:", errs)
         assert errs[0] <= 1e-9, i
         assert errs[1] <= 1e-4 and errs[2] <= 1e-4, (i, errs)
+
+
+def test_fp64_gradient_equals_oracle_on_the_recorded_schedule():
+    # the oracle's reverse mode run with the schedule (restart iterations and
+    # per-epoch steps) the GPU recorded is the same map: x_K, dL/dc and dL/db
+    # agree to float64 rounding at the differentiation workload's size
+    from oracle.pdhg import Schedule
+    lps, ws = [], []
+    for i in (0, 85, 255):
+        lp, w = lpgen.cfg5_instance(i)
+        lps.append(lp)
+        ws.append(w)
+    batch = P.DeviceBatch.from_lps(lps)
+    K = 2000
+    umap = P.UnrolledMap(batch, K=K, ckpt_every=100, precision="fp64")
+    xK, tape = umap.forward_raw(batch.lp.c, batch.lp.b)
+    w = torch.tensor(np.concatenate(ws), device="cuda")
+    gc, gb = umap.backward_raw(batch.lp.c, batch.lp.b, tape, w)
+    xK, gc, gb = _np(xK), _np(gc), _np(gb)
+    for i, lp in enumerate(lps):
+        restart_at, taus, sigmas = umap.schedule(tape, i)
+        assert len(taus) == len(restart_at) + 1 and all(t % 64 == 0 for t in restart_at)
+        rc, rb, rx, _ = oracle.unrolled_grad(lp.A, lp.b, lp.c, K, ws[i], OracleOptions(),
+                                             schedule=Schedule(list(restart_at), list(taus), list(sigmas)))
+        assert _rel(_seg(batch, xK, i), rx) <= 1e-10, i
+        assert _rel(_seg(batch, gc, i), rc) <= 1e-10, i
+        assert _rel(_seg(batch, gb, i, rows=True), rb) <= 1e-10, i
