@@ -449,7 +449,7 @@ def diff_leg(P, torch) -> dict:
 
     import lpgen
     import oracle
-    from oracle.pdhg import OracleOptions
+    from oracle.pdhg import OracleOptions, Schedule
     lps, ws = lpgen.cfg5_batch(256)
     batch = P.DeviceBatch.from_lps(lps, "cuda:0")
     umap = P.UnrolledMap(batch, K=2000, ckpt_every=100, precision="fp32")
@@ -468,6 +468,11 @@ def diff_leg(P, torch) -> dict:
     errs = []
     for i in (0, 85, 170, 255):
         rc, rb, rx, _ = oracle.unrolled_grad(lps[i].A, lps[i].b, lps[i].c, 2000, ws[i], OracleOptions())
+        # the float64 oracle on the schedule this FP32 run recorded (restart
+        # iterations and steps): what remains is FP32 arithmetic
+        ra, ta, sa = umap.schedule(tape, i)
+        sc, _, _, _ = oracle.unrolled_grad(lps[i].A, lps[i].b, lps[i].c, 2000, ws[i], OracleOptions(),
+                                           schedule=Schedule(list(ra), list(ta), list(sa)))
         c0, c1, r0, r1 = batch.col_off[i], batch.col_off[i + 1], batch.row_off[i], batch.row_off[i + 1]
 
         def rel(a, b):
@@ -476,7 +481,8 @@ def diff_leg(P, torch) -> dict:
         # oracle's: the map is piecewise linear, its piece fixed by the masks
         flips = int(np.count_nonzero((xk[c0:c1] > 0) != (rx > 0)))
         errs.append({"instance": i, "x_K": rel(xk[c0:c1], rx), "dL_dc": rel(gc[c0:c1], rc),
-                     "dL_db": rel(gb[r0:r1], rb), "final_mask_flips": flips, "n": int(c1 - c0)})
+                     "dL_db": rel(gb[r0:r1], rb), "final_mask_flips": flips, "n": int(c1 - c0),
+                     "dL_dc_vs_oracle_on_this_schedule": rel(gc[c0:c1], sc)})
     return {"instances": 256, "K": 2000, "ckpt_every": 100, "precision": "fp32", "forward_s": t1 - t0,
             "backward_s": t2 - t1, "tape_bytes": umap.tape_bytes,
             "error_vs_fp64_oracle": {"instances": errs,
