@@ -232,3 +232,25 @@ def test_fp64_gradient_equals_oracle_on_the_recorded_schedule():
         assert _rel(_seg(batch, xK, i), rx) <= 1e-10, i
         assert _rel(_seg(batch, gc, i), rc) <= 1e-10, i
         assert _rel(_seg(batch, gb, i, rows=True), rb) <= 1e-10, i
+
+
+def test_schedule_export_refuses_small_capacity_and_bad_instance():
+    import ctypes as C
+    from paper_2603_03150_amd import _lib
+    lps, ws = _fd_set(2)
+    batch = P.DeviceBatch.from_lps(lps)
+    umap = P.UnrolledMap(batch, K=300, ckpt_every=100, precision="fp64")
+    _, tape = umap.forward_raw(batch.lp.c, batch.lp.b)
+    restart_at, taus, sigmas = umap.schedule(tape, 0)
+    assert len(restart_at) >= 1 and len(taus) == len(restart_at) + 1
+    lib = _lib.load()
+    st = batch.struct()
+    stream = torch.cuda.current_stream().cuda_stream
+    ra, tv, sv, nr = (C.c_int32 * 1)(), (C.c_double * 1)(), (C.c_double * 1)(), C.c_int32(0)
+    # one slot holds a single epoch: the schedule has more
+    rc = lib.mipdhg_unrolled_schedule(C.byref(st), C.byref(umap.opts), umap.K, umap.ckpt, tape.data_ptr(),
+                                      tape.numel(), 0, stream, 1, ra, tv, sv, C.byref(nr))
+    assert rc == -1 and b"capacity" in lib.mipdhg_last_error()
+    rc = lib.mipdhg_unrolled_schedule(C.byref(st), C.byref(umap.opts), umap.K, umap.ckpt, tape.data_ptr(),
+                                      tape.numel(), 2, stream, 1, ra, tv, sv, C.byref(nr))
+    assert rc == -1 and b"inst" in lib.mipdhg_last_error()
